@@ -1,0 +1,71 @@
+"""Input generators: determinism and the statistics each workload promises."""
+import hashlib
+
+import numpy as np
+
+import seqgen
+
+
+def test_scoring_data_sanity():
+    M = seqgen.BLOSUM62
+    assert M.shape == (24, 24)
+    assert (M == M.T).all()
+    assert (np.diag(M)[:20] > 0).all()      # X-X is -1 in the published table
+    assert abs(seqgen.BACKGROUND.sum() - 1.0) < 1e-12
+    assert len(seqgen.BACKGROUND) == 20
+    # a few table entries (Henikoff & Henikoff 1992)
+    A = seqgen.PROTEIN_ALPHABET
+    assert M[A.index("W"), A.index("W")] == 11
+    assert M[A.index("C"), A.index("C")] == 9
+    assert M[A.index("I"), A.index("V")] == 3
+    assert M[A.index("D"), A.index("E")] == 2
+
+
+def test_generators_are_deterministic():
+    a1, b1 = seqgen.workload0(1000, 900)
+    a2, b2 = seqgen.workload0(1000, 900)
+    assert hashlib.sha256(a1.tobytes()).hexdigest() == hashlib.sha256(a2.tobytes()).hexdigest()
+    assert (b1 == b2).all() and len(a1) == 1000 and len(b1) == 900
+    assert set(np.unique(a1).tobytes()) <= set(b"ACGT")
+
+
+def test_long_pair_mutation_rates():
+    q, t = seqgen.workload1(200_000, flank=5_000)
+    core_len = len(t) - 10_000
+    # 0.5% indel events, half insertions/half deletions, mean length 3: net length change ~0
+    assert abs(core_len - len(q)) < 0.003 * len(q)
+    # the core starts with the query's first bases unless a mutation hit them
+    assert (t[5000:5100] == q[:100]).mean() > 0.9
+
+
+def test_protein_db_lengths():
+    cat, off = seqgen.protein_db(20_000)
+    L = np.diff(off)
+    assert L.min() >= 25 and L.max() <= 35_000
+    assert 280 <= np.median(L) <= 320
+    assert 340 <= L.mean() <= 380          # calibrated to Swiss-Prot's mean length (~361)
+    freq = np.bincount(np.searchsorted(np.frombuffer(b"ACDEFGHIKLMNPQRSTVWY", np.uint8), cat),
+                       minlength=20)
+    assert freq.sum() == len(cat)
+
+
+def test_query_lengths_range():
+    qs = seqgen.queries(20)
+    L = [len(q) for q in qs]
+    assert len(L) == 20 and min(L) >= 100 and max(L) <= 5000
+
+
+def test_read_pairs_window():
+    rng = seqgen.rng_for(4, 9)
+    for L in (150, 1000, 5000):
+        r, ref = seqgen.read_pair(rng, L)
+        assert len(r) == L
+        assert abs(len(ref) - round(1.2 * L)) <= 0.2 * L + 10
+
+
+def test_mutate_identity():
+    rng = np.random.default_rng(3)
+    q = seqgen.random_protein(rng, 20_000)
+    t = seqgen.mutate(rng, q, 0.3, 0.0, protein=True)
+    assert len(t) == len(q)
+    assert abs((t != q).mean() - 0.3) < 0.02

@@ -1,0 +1,131 @@
+/*
+ * swh.h -- C ABI of the MI355X Smith-Waterman engine (libswh.so).
+ *
+ * The library computes optimal local alignments with affine gaps
+ * (Smith-Waterman with Gotoh's three-state recurrences), the method whose
+ * "resolution" phase (find the maximum score) and "reconstruction" phase
+ * (find the optimal path with space-efficient methods) the paper describes in
+ * its Background section, "SW# suite".  Scoring follows the same paragraph:
+ * a substitution matrix plus gap open / gap extension penalties.
+ *
+ * Conventions shared by every entry point
+ *  - Sequences are ASCII; a symbol is looked up case-insensitively in the
+ *    scoring alphabet.  Any other byte fails with SWH_E_ALPHABET and the last
+ *    error names the sequence and the position.
+ *  - A gap of length k costs gap_open + (k-1) * gap_extend.
+ *  - Coordinates are 0-based and inclusive.  The query indexes rows, the
+ *    target columns.
+ *  - The end of an alignment is the first cell in row-major order (smallest
+ *    query position, then smallest target position) that holds the optimal
+ *    score; the start is the largest start (query first, then target) of an
+ *    optimal alignment with that end.  A score of 0 means "no alignment":
+ *    all coordinates are -1 and the CIGAR is empty.
+ *  - CIGAR: run-length M (aligned pair), I (query residue against a gap),
+ *    D (target residue against a gap).  Among co-optimal paths the one
+ *    returned is the greedy backward walk of the global DP over the aligned
+ *    rectangle that prefers, at an H cell, the diagonal, then I, then D, and
+ *    inside a gap prefers closing it over extending it.
+ *  - The caller owns every buffer.  Nothing keeps a caller pointer after the
+ *    call returns.  Host-pointer calls are synchronous.
+ *  - Every call returns a status; on failure swh_last_error() describes it.
+ *    No entry point aborts, exits or throws.
+ *  - A context belongs to one host thread at a time.
+ */
+#ifndef SWH_H
+#define SWH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SWH_OK = 0,
+    SWH_E_INVAL = -1,      /* bad argument (null pointer, bad size, bad scoring) */
+    SWH_E_ALPHABET = -2,   /* a sequence byte is not in the alphabet */
+    SWH_E_NOMEM = -3,      /* device or host allocation failed */
+    SWH_E_RANGE = -4,      /* output buffer too small, or input beyond a documented limit */
+    SWH_E_DEVICE = -5,     /* HIP runtime error */
+    SWH_E_TIMEOUT = -6,    /* a kernel's bounded wait expired (internal error) */
+    SWH_E_CANCELLED = -7
+} swh_status;
+
+typedef struct swh_ctx swh_ctx;
+
+/* Scoring scheme.  matrix is alphabet_size x alphabet_size int8, row-major,
+ * matrix[q * alphabet_size + t] = s(query symbol q, target symbol t).
+ * Limits: 1 <= alphabet_size <= 32, 0 < gap_extend <= gap_open <= 65535. */
+typedef struct {
+    const char   *alphabet;
+    int32_t       alphabet_size;
+    const int8_t *matrix;
+    int32_t       gap_open;
+    int32_t       gap_extend;
+} swh_scoring;
+
+typedef struct {
+    int32_t  score;
+    uint32_t flags;            /* SWH_F_* */
+    int64_t  q_begin, q_end;   /* -1 when score == 0 */
+    int64_t  t_begin, t_end;
+} swh_alignment;
+
+#define SWH_F_NONE 0u
+
+enum { SWH_MODE_SCORE = 0,   /* score and end coordinates (forward pass only) */
+       SWH_MODE_COORDS = 1,  /* + start coordinates (reverse pass) */
+       SWH_MODE_CIGAR = 2 }; /* + CIGAR (linear-space traceback) */
+
+/* Per-call statistics; set struct_size = sizeof(swh_stats) before the call. */
+typedef struct {
+    uint32_t struct_size;
+    uint32_t reserved;
+    double   cells_forward;     /* n * m of the forward pass */
+    double   ms_forward;        /* device time of the forward pass */
+    double   ms_reverse;        /* device time of the reverse pass */
+    double   ms_traceback;      /* wall time of the traceback */
+    double   cells_traceback;   /* DP cells evaluated by the traceback */
+} swh_stats;
+
+/* Context on HIP device `device` (ordinal).  Allocates nothing large; device
+ * buffers grow on demand and are kept until swh_destroy. */
+swh_status  swh_create(int device, swh_ctx **out);
+void        swh_destroy(swh_ctx *ctx);
+/* Text of the last failure on ctx; valid until the next call on ctx. */
+const char *swh_last_error(const swh_ctx *ctx);
+
+/*
+ * One local alignment of query q (qlen bytes) against target t (tlen bytes),
+ * host pointers.  Resolution: forward score pass (score, end).  mode >=
+ * COORDS adds the reverse pass over the reversed prefixes ending at the end
+ * cell, which gives the start.  mode == CIGAR adds the reconstruction.
+ *
+ * cigar: caller buffer of cigar_cap bytes, NUL-terminated on success; may be
+ * NULL when mode < CIGAR.  *cigar_len (may be NULL) receives the CIGAR
+ * length without the NUL; when cigar_cap is too small the call fails with
+ * SWH_E_RANGE and *cigar_len holds the required length.
+ * Limits: qlen, tlen < 2^31; min(qlen, tlen) * max|s| < 2^28;
+ * for mode CIGAR also (max s + gap_extend) * (qlen + tlen) + gap_open < 2^27.
+ * stats may be NULL.
+ */
+swh_status swh_align(swh_ctx *ctx, const char *q, int64_t qlen, const char *t, int64_t tlen,
+                     const swh_scoring *scoring, int mode, swh_alignment *out,
+                     char *cigar, int64_t cigar_cap, int64_t *cigar_len, swh_stats *stats);
+
+/*
+ * Same as swh_align with q and t in device memory (for example torch tensor
+ * data pointers).  stream is a hipStream_t (NULL = the default stream); the
+ * call orders its work after prior work on that stream and returns when the
+ * result is on the host.  Inputs must stay valid until the call returns.
+ */
+swh_status swh_align_dev(swh_ctx *ctx, const char *q_dev, int64_t qlen, const char *t_dev,
+                         int64_t tlen, const swh_scoring *scoring, int mode, void *stream,
+                         swh_alignment *out, char *cigar, int64_t cigar_cap,
+                         int64_t *cigar_len, swh_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWH_H */

@@ -1,0 +1,71 @@
+"""ctypes binding of libswh.so (declarations mirror include/swh.h).
+
+Argument marshalling only: every step of the alignment runs in the HIP
+library.  Importing this module fails loudly when the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswh.so")
+
+SWH_OK = 0
+STATUS_NAMES = {0: "SWH_OK", -1: "SWH_E_INVAL", -2: "SWH_E_ALPHABET", -3: "SWH_E_NOMEM",
+                -4: "SWH_E_RANGE", -5: "SWH_E_DEVICE", -6: "SWH_E_TIMEOUT", -7: "SWH_E_CANCELLED"}
+MODE_SCORE, MODE_COORDS, MODE_CIGAR = 0, 1, 2
+
+
+class swh_scoring(ctypes.Structure):
+    _fields_ = [("alphabet", ctypes.c_char_p), ("alphabet_size", ctypes.c_int32),
+                ("matrix", ctypes.c_void_p), ("gap_open", ctypes.c_int32),
+                ("gap_extend", ctypes.c_int32)]
+
+
+class swh_alignment(ctypes.Structure):
+    _fields_ = [("score", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("q_begin", ctypes.c_int64), ("q_end", ctypes.c_int64),
+                ("t_begin", ctypes.c_int64), ("t_end", ctypes.c_int64)]
+
+
+class swh_stats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("cells_forward", ctypes.c_double), ("ms_forward", ctypes.c_double),
+                ("ms_reverse", ctypes.c_double), ("ms_traceback", ctypes.c_double),
+                ("cells_traceback", ctypes.c_double)]
+
+
+# name -> (restype, argtypes); the C-ABI surface declared in include/swh.h
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I64P = ctypes.POINTER(ctypes.c_int64)
+SIGNATURES = {
+    "swh_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_P)]),
+    "swh_destroy": (None, [_P]),
+    "swh_last_error": (ctypes.c_char_p, [_P]),
+    "swh_align": (ctypes.c_int, [_P, _P, _I64, _P, _I64, ctypes.POINTER(swh_scoring), ctypes.c_int,
+                                 ctypes.POINTER(swh_alignment), ctypes.c_char_p, _I64, _I64P,
+                                 ctypes.POINTER(swh_stats)]),
+    "swh_align_dev": (ctypes.c_int, [_P, _P, _I64, _P, _I64, ctypes.POINTER(swh_scoring), ctypes.c_int,
+                                     _P, ctypes.POINTER(swh_alignment), ctypes.c_char_p, _I64, _I64P,
+                                     ctypes.POINTER(swh_stats)]),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libswh.so; raises RuntimeError if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib

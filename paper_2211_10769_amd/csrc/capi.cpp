@@ -1,0 +1,190 @@
+// capi.cpp -- the extern "C" entry points of libswh.so (declared in
+// include/swh.h): argument validation, context lifetime, error text.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "context.h"
+
+namespace swh {
+
+swh_status fail(swh_ctx *ctx, swh_status st, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+swh_status hip_fail(swh_ctx *ctx, hipError_t e, const char *what)
+{
+    return fail(ctx, SWH_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+swh_status ensure(swh_ctx *ctx, DevBuf &buf, size_t bytes, const char *what)
+{
+    if (buf.cap >= bytes && buf.p) return SWH_OK;
+    if (buf.p) {
+        hipDeviceSynchronize();
+        hipFree(buf.p);
+        buf.p = nullptr;
+        buf.cap = 0;
+    }
+    size_t want = bytes < 4096 ? 4096 : bytes + bytes / 8;
+    hipError_t e = hipMalloc(&buf.p, want);
+    if (e != hipSuccess) {
+        buf.p = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, SWH_E_NOMEM, std::string("cannot allocate ") + std::to_string(want) + " bytes for " + what);
+    }
+    buf.cap = want;
+    return SWH_OK;
+}
+
+swh_status make_scoring(swh_ctx *ctx, const swh_scoring *in, Scoring &out)
+{
+    if (!in) return fail(ctx, SWH_E_INVAL, "scoring is NULL");
+    if (!in->alphabet || !in->matrix) return fail(ctx, SWH_E_INVAL, "scoring alphabet or matrix is NULL");
+    if (in->alphabet_size < 1 || in->alphabet_size > 32)
+        return fail(ctx, SWH_E_INVAL, "alphabet_size must be in 1..32");
+    if (in->gap_open <= 0 || in->gap_extend <= 0 || in->gap_extend > in->gap_open || in->gap_open > 65535)
+        return fail(ctx, SWH_E_INVAL, "gap penalties must satisfy 0 < gap_extend <= gap_open <= 65535");
+    std::memset(out.lut, 0xFF, sizeof(out.lut));
+    for (int k = 0; k < in->alphabet_size; ++k) {
+        unsigned char c = (unsigned char)in->alphabet[k];
+        if (c == 0) return fail(ctx, SWH_E_INVAL, "alphabet shorter than alphabet_size");
+        unsigned char up = (c >= 'a' && c <= 'z') ? (unsigned char)(c - 'a' + 'A') : c;
+        if (out.lut[up] != 0xFF) return fail(ctx, SWH_E_INVAL, "alphabet repeats a symbol");
+        out.lut[up] = (uint8_t)k;
+        if (up >= 'A' && up <= 'Z') out.lut[up - 'A' + 'a'] = (uint8_t)k;
+    }
+    out.asize = in->alphabet_size;
+    out.smax = -128;
+    out.smin = 127;
+    for (int k = 0; k < out.asize * out.asize; ++k) {
+        out.mat[k] = in->matrix[k];
+        out.smax = out.smax > in->matrix[k] ? out.smax : in->matrix[k];
+        out.smin = out.smin < in->matrix[k] ? out.smin : in->matrix[k];
+    }
+    out.o = in->gap_open;
+    out.e = in->gap_extend;
+    return SWH_OK;
+}
+
+namespace {
+
+swh_status check_pair(swh_ctx *ctx, const void *q, int64_t qlen, const void *t, int64_t tlen, const Scoring &sc,
+                      int mode, swh_alignment *out)
+{
+    if (!out) return fail(ctx, SWH_E_INVAL, "out is NULL");
+    if (qlen < 0 || tlen < 0) return fail(ctx, SWH_E_INVAL, "negative sequence length");
+    if ((qlen && !q) || (tlen && !t)) return fail(ctx, SWH_E_INVAL, "sequence pointer is NULL");
+    if (mode < SWH_MODE_SCORE || mode > SWH_MODE_CIGAR) return fail(ctx, SWH_E_INVAL, "unknown mode");
+    if (qlen >= (int64_t)1 << 31 || tlen >= (int64_t)1 << 31)
+        return fail(ctx, SWH_E_RANGE, "sequence longer than 2^31 - 1");
+    const int64_t smax = sc.smax > 0 ? sc.smax : 1;
+    const int64_t sabs = sc.smax > -sc.smin ? sc.smax : -sc.smin;
+    if ((qlen < tlen ? qlen : tlen) * (sabs > 0 ? sabs : 1) >= ((int64_t)1 << 28))
+        return fail(ctx, SWH_E_RANGE, "min(qlen, tlen) * max|s| must stay below 2^28");
+    if (mode == SWH_MODE_CIGAR && (smax + sc.e) * (qlen + tlen) + sc.o >= ((int64_t)1 << 27))
+        return fail(ctx, SWH_E_RANGE, "(max s + gap_extend) * (qlen + tlen) + gap_open must stay below 2^27");
+    return SWH_OK;
+}
+
+}  // namespace
+
+}  // namespace swh
+
+using namespace swh;
+
+extern "C" {
+
+swh_status swh_create(int device, swh_ctx **out)
+{
+    if (!out) return SWH_E_INVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        return SWH_E_DEVICE;
+    }
+    if (device < 0 || device >= count) return SWH_E_INVAL;
+    swh_ctx *ctx = new (std::nothrow) swh_ctx();
+    if (!ctx) return SWH_E_NOMEM;
+    ctx->device = device;
+    if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete ctx;
+        return SWH_E_DEVICE;
+    }
+    for (auto &ev : ctx->ev) {
+        if (hipEventCreate(&ev) != hipSuccess) {
+            swh_destroy(ctx);
+            return SWH_E_DEVICE;
+        }
+    }
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) == hipSuccess) ctx->num_cu = p.multiProcessorCount;
+    *out = ctx;
+    return SWH_OK;
+}
+
+void swh_destroy(swh_ctx *ctx)
+{
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    if (ctx->own_stream) hipStreamSynchronize(ctx->own_stream);
+    for (DevBuf *b : ctx->all())
+        if (b->p) hipFree(b->p);
+    for (auto &ev : ctx->ev)
+        if (ev) hipEventDestroy(ev);
+    if (ctx->own_stream) hipStreamDestroy(ctx->own_stream);
+    delete ctx;
+}
+
+const char *swh_last_error(const swh_ctx *ctx)
+{
+    if (!ctx) return "no context";
+    return ctx->err.c_str();
+}
+
+swh_status swh_align(swh_ctx *ctx, const char *q, int64_t qlen, const char *t, int64_t tlen,
+                     const swh_scoring *scoring, int mode, swh_alignment *out, char *cigar, int64_t cigar_cap,
+                     int64_t *cigar_len, swh_stats *stats)
+{
+    if (!ctx) return SWH_E_INVAL;
+    ctx->err.clear();
+    Scoring sc;
+    swh_status s = make_scoring(ctx, scoring, sc);
+    if (s != SWH_OK) return s;
+    if ((s = check_pair(ctx, q, qlen, t, tlen, sc, mode, out)) != SWH_OK) return s;
+    if (stats && stats->struct_size < sizeof(swh_stats)) return fail(ctx, SWH_E_INVAL, "stats->struct_size too small");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SWH_E_DEVICE, "hipSetDevice failed");
+    hipStream_t st = ctx->own_stream;
+    if ((s = ensure(ctx, ctx->qraw, (size_t)qlen + 1, "query copy")) != SWH_OK) return s;
+    if ((s = ensure(ctx, ctx->traw, (size_t)tlen + 1, "target copy")) != SWH_OK) return s;
+    hipError_t e;
+    if (qlen && (e = hipMemcpyAsync(ctx->qraw.p, q, (size_t)qlen, hipMemcpyHostToDevice, st)) != hipSuccess)
+        return hip_fail(ctx, e, "hipMemcpyAsync(query)");
+    if (tlen && (e = hipMemcpyAsync(ctx->traw.p, t, (size_t)tlen, hipMemcpyHostToDevice, st)) != hipSuccess)
+        return hip_fail(ctx, e, "hipMemcpyAsync(target)");
+    return align_device(ctx, (const char *)ctx->qraw.p, qlen, (const char *)ctx->traw.p, tlen, sc, mode, st, out,
+                        cigar, cigar_cap, cigar_len, stats);
+}
+
+swh_status swh_align_dev(swh_ctx *ctx, const char *q_dev, int64_t qlen, const char *t_dev, int64_t tlen,
+                         const swh_scoring *scoring, int mode, void *stream, swh_alignment *out, char *cigar,
+                         int64_t cigar_cap, int64_t *cigar_len, swh_stats *stats)
+{
+    if (!ctx) return SWH_E_INVAL;
+    ctx->err.clear();
+    Scoring sc;
+    swh_status s = make_scoring(ctx, scoring, sc);
+    if (s != SWH_OK) return s;
+    if ((s = check_pair(ctx, q_dev, qlen, t_dev, tlen, sc, mode, out)) != SWH_OK) return s;
+    if (stats && stats->struct_size < sizeof(swh_stats)) return fail(ctx, SWH_E_INVAL, "stats->struct_size too small");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SWH_E_DEVICE, "hipSetDevice failed");
+    return align_device(ctx, q_dev, qlen, t_dev, tlen, sc, mode, (hipStream_t)stream, out, cigar, cigar_cap,
+                        cigar_len, stats);
+}
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+// context.h -- the opaque swh_ctx and its grow-only device buffers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/swh.h"
+#include "engine.h"
+
+namespace swh {
+
+// A device allocation that only grows; freed with the context.
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+// Validated scoring with the symbol lookup table and the device copy of the matrix.
+struct Scoring {
+    uint8_t lut[256];          // byte -> code, 0xFF = not in the alphabet
+    int asize = 0;
+    int8_t mat[32 * 32];
+    int o = 0, e = 0;
+    int smax = 0, smin = 0;    // extreme matrix entries
+};
+
+}  // namespace swh
+
+struct swh_ctx {
+    int device = 0;
+    hipStream_t own_stream = nullptr;
+    int num_cu = 0;
+    std::string err;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+
+    // pairwise buffers
+    swh::DevBuf qraw, traw;        // ASCII copies of host inputs
+    swh::DevBuf qc, tc;            // codes
+    swh::DevBuf qr, tr;            // reversed codes
+    swh::DevBuf border, flags, misc, strip_best, mat, lut;
+    // traceback buffers
+    swh::DevBuf tb_fwd, tb_bwd, tb_front, tb_codes_q, tb_codes_t, tb_leaf, tb_misc;
+    std::vector<swh::DevBuf *> all() {
+        return {&qraw, &traw, &qc, &tc, &qr, &tr, &border, &flags, &misc, &strip_best, &mat, &lut,
+                &tb_fwd, &tb_bwd, &tb_front, &tb_codes_q, &tb_codes_t, &tb_leaf, &tb_misc};
+    }
+};
+
+namespace swh {
+
+// Status helpers: set ctx->err and return the status.
+swh_status fail(swh_ctx *ctx, swh_status st, const std::string &msg);
+swh_status hip_fail(swh_ctx *ctx, hipError_t e, const char *what);
+// Make sure buf holds at least bytes; on failure sets the error and returns SWH_E_NOMEM.
+swh_status ensure(swh_ctx *ctx, DevBuf &buf, size_t bytes, const char *what);
+swh_status make_scoring(swh_ctx *ctx, const swh_scoring *in, Scoring &out);
+
+// Pairwise alignment on device-resident ASCII inputs (engine.cpp).
+swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const char *t_dev, int64_t tlen,
+                        const Scoring &sc, int mode, hipStream_t st, swh_alignment *out, char *cigar,
+                        int64_t cigar_cap, int64_t *cigar_len, swh_stats *stats);
+
+}  // namespace swh

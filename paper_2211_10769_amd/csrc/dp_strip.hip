@@ -1,0 +1,426 @@
+// dp_strip.hip -- the score pass of the alignment DP on CDNA4 (gfx950).
+//
+// One wave64 owns a strip of 64*R consecutive query rows; lane l owns rows
+// [l*R, l*R + R) of the strip.  The wave sweeps the target columns with a
+// skew of one column per lane: at step t lane l works on column t - l + 1,
+// all R of its rows at that column, the vertical dependency inside the lane
+// carried in registers.  Lane l-1's last row (H and the F it passes down)
+// reaches lane l through a whole-wave DPP shift (wave_shr:1); lane 0 reads the
+// previous strip's last row from a border buffer in HBM, lane 63's last row is
+// collected 64 columns at a time (wave_shl:1) and written back to the same
+// buffer, in place.  Strips are taken in order from an atomic ticket and
+// hand over the border one 64-column chunk at a time through per-chunk
+// counters, so a strip only ever waits on a strip with a smaller ticket that
+// is already running: the wavefront cannot deadlock whatever the grid size.
+//
+// Recurrences (paper, Background: Smith-Waterman with affine open/extension
+// penalties, the "resolution" phase of SW#):
+//   E(i,j) = max(E(i,j-1) - e, H(i,j-1) - o)
+//   F(i,j) = max(F(i-1,j) - e, H(i-1,j) - o)
+//   H(i,j) = max(floor, H(i-1,j-1) + s(a_i,b_j), E(i,j), F(i,j))
+// LOCAL: floor = 0 and E, F are stored clamped at 0 -- max(E,0) obeys the
+// same recurrence clamped at 0, and H = max3(diag + s, E', F') then needs no
+// extra operation.  GLOBAL (traceback passes): floor = kNeg, no clamp.
+//
+// Substitution scores come from a per-strip query profile in LDS,
+// prof[code][k/4][lane] as int4, read with four ds_read_b128 per step (R=16)
+// with no bank conflicts whatever code each lane holds.
+#include <hip/hip_runtime.h>
+
+#include "engine.h"
+
+namespace swh {
+
+namespace {
+
+constexpr int kDppWaveShl1 = 0x130;   // lane i reads lane i+1 (lane 63: keeps old)
+constexpr int kDppWaveShr1 = 0x138;   // lane i reads lane i-1 (lane 0: keeps old)
+
+__device__ __forceinline__ int shr1(int old, int src)
+{
+    return __builtin_amdgcn_update_dpp(old, src, kDppWaveShr1, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ int shl1(int old, int src)
+{
+    return __builtin_amdgcn_update_dpp(old, src, kDppWaveShl1, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ int max3i(int a, int b, int c) { return max(max(a, b), c); }
+
+// Border traffic goes through agent-scope relaxed atomics (coherent across
+// the XCDs' L2s per location); ordering is explicit: stores are drained with
+// s_waitcnt vmcnt(0) before the chunk counter is published.
+__device__ __forceinline__ void store_border(Border *p, int h, int f)
+{
+    uint64_t v = (uint64_t)(uint32_t)h | ((uint64_t)(uint32_t)f << 32);
+    __hip_atomic_store((uint64_t *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void load_border(const Border *p, int &h, int &f)
+{
+    uint64_t v = __hip_atomic_load((const uint64_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    h = (int)(uint32_t)v;
+    f = (int)(uint32_t)(v >> 32);
+}
+
+__device__ __forceinline__ void drain_stores()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0x0F70);     // vmcnt(0), expcnt/lgkmcnt untouched
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Wait until chunk counter >= need.  Every value that decides a branch is
+// made wave-uniform (readfirstlane) so that no loop exit can diverge: the
+// kernel's lane shifts assume all 64 lanes execute together.  Bounded: on
+// expiry (or when another wave has given up) sets/observes abort and returns
+// false.
+__device__ __forceinline__ bool wait_chunk(const StripArgs &a, int chunk, int need)
+{
+    int spins = 0;
+    for (;;) {
+        const int v = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(a.flags + chunk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (v >= need) return true;
+        const int ab = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (ab) return false;
+        if (++spins > a.spin_limit) {
+            __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+template <int R>
+struct Prof {
+    static constexpr int R4 = R / 4;
+};
+
+// One DP step for the lane's R rows at one column.
+//   dg   : H(row0-1, j-1)                f    : F handed down into row0 (in), out of row R-1 (out)
+//   hp[] : H(row, j-1) in, H(row, j) out E[]  : E(row, j) in (already the value for this column), E(row, j+1) out
+// PASS: rows with index >= nreal copy the row above (pass-through), so the
+// wave's last row reproduces the last real row (global mode, ragged strip).
+template <int R, bool LOCAL, bool PASS>
+__device__ __forceinline__ void dp_step(int (&hp)[R], int (&E)[R], const int (&sc)[R], int dg, int hup,
+                                        int &f, int o, int e, int nreal)
+{
+    constexpr int B = LOCAL ? 0 : kNeg;
+    int habove = hup;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        int h = max3i(dg + sc[k], E[k], f);
+        int hop = h - o;
+        int fn = max3i(f - e, hop, B);
+        E[k] = max3i(E[k] - e, hop, B);
+        dg = hp[k];
+        if (PASS) {
+            const bool real = k < nreal;
+            h = real ? h : habove;
+            fn = real ? fn : f;
+            habove = h;
+        }
+        f = fn;
+        hp[k] = h;
+    }
+}
+
+template <int R, bool LOCAL>
+__global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
+{
+    extern __shared__ int4 prof4[];
+    constexpr int R4 = Prof<R>::R4;
+    constexpr int B = LOCAL ? 0 : kNeg;
+    const int lane = threadIdx.x;
+    const int pad = a.asize;
+    const int A1 = a.asize + 1;
+    const int o = a.o, e = a.e;
+    int *prof = reinterpret_cast<int *>(prof4);
+
+    for (;;) {
+        // every lane takes part in the atomic (lane 0 adds 1, the others 0), so no
+        // lane-dependent branch precedes the readfirstlane that broadcasts the ticket
+        const int sv = __hip_atomic_fetch_add(a.ticket, lane == 0 ? 1 : 0, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+        const int s = __builtin_amdgcn_readfirstlane(sv);
+        if (s >= a.nstrips) break;
+        const int64_t row0 = (int64_t)s * 64 * R + (int64_t)lane * R;   // 0-based
+
+        // ---- query profile for this lane's rows (written and read by this lane only)
+        for (int k = 0; k < R; ++k) {
+            const int q = a.qc[row0 + k];
+            for (int c = 0; c < A1; ++c) {
+                int v = (q >= a.asize || c >= a.asize) ? kNeg : (int)a.mat[q * a.asize + c];
+                prof[((c * R4 + (k >> 2)) * 64 + lane) * 4 + (k & 3)] = v;
+            }
+        }
+        int nreal = (int)min<int64_t>(max<int64_t>(a.n - row0, 0), R);
+        const bool ragged = !LOCAL && __builtin_amdgcn_readfirstlane(
+                                          (int)((int64_t)(s + 1) * 64 * R > a.n));
+
+        int hp[R], E[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) { hp[k] = B; E[k] = B; }
+        int hup_prev = B;          // H(row0-1, j-1): diag of the first row
+        int hbot = B, fbot = B;    // this lane's last row output of the previous step
+        int oh = B, of = B;        // collected outputs of lane 63
+        int bv = 0, br = 0, bc = 0, thr = 1;   // best cell (local)
+
+        // block 0 inputs
+        int code = lane == 0 ? (int)a.tc[0] : pad;       // current column's code
+        int tfeed = a.tc[1 + lane];                       // lane 0 = code of column t+2
+        int fh = B, ff = B;
+        bool ok = true;
+        if (ok && !wait_chunk(a, 0, s)) ok = false;
+        if (ok) load_border(a.border + lane, fh, ff);
+
+        int sc[R];
+        {
+            const int4 *pr = prof4 + (code * R4) * 64 + lane;
+#pragma unroll
+            for (int q4 = 0; q4 < R4; ++q4) {
+                int4 v = pr[q4 * 64];
+                sc[4 * q4] = v.x; sc[4 * q4 + 1] = v.y; sc[4 * q4 + 2] = v.z; sc[4 * q4 + 3] = v.w;
+            }
+        }
+
+        for (int b = 0; b < a.nblocks && ok; ++b) {
+            // prefetch the next block's target codes and border chunk
+            const int tfeed_n = a.tc[64 * (b + 1) + 1 + lane];
+            int fh_n = B, ff_n = B;
+            if (64 * (b + 1) < a.m) {
+                if (!wait_chunk(a, b + 1, s)) { ok = false; break; }
+                load_border(a.border + 64 * (b + 1) + lane, fh_n, ff_n);
+            }
+
+            const int tbase = 64 * b;
+#pragma unroll 2
+            for (int u = 0; u < 64; ++u) {
+                // next column's code (lane 0 from the feed, others from the lane above)
+                const int code_n = shr1(tfeed, code);
+                tfeed = shl1(tfeed, tfeed);
+                int sc_n[R];
+                {
+                    const int4 *pr = prof4 + (code_n * R4) * 64 + lane;
+#pragma unroll
+                    for (int q4 = 0; q4 < R4; ++q4) {
+                        int4 v = pr[q4 * 64];
+                        sc_n[4 * q4] = v.x; sc_n[4 * q4 + 1] = v.y;
+                        sc_n[4 * q4 + 2] = v.z; sc_n[4 * q4 + 3] = v.w;
+                    }
+                }
+                // row above this lane's first row at this column
+                const int hup = shr1(fh, hbot);
+                int f = shr1(ff, fbot);
+                fh = shl1(fh, fh);
+                ff = shl1(ff, ff);
+
+                if (LOCAL || !ragged)
+                    dp_step<R, LOCAL, false>(hp, E, sc, hup_prev, hup, f, o, e, nreal);
+                else
+                    dp_step<R, LOCAL, true>(hp, E, sc, hup_prev, hup, f, o, e, nreal);
+                hup_prev = hup;
+                hbot = hp[R - 1];
+                fbot = f;
+                oh = shl1(hbot, oh);
+                of = shl1(fbot, of);
+
+                if (LOCAL) {
+                    int mx = hp[0];
+#pragma unroll
+                    for (int k = 1; k < R; ++k) mx = max(mx, hp[k]);
+                    if (mx >= thr) {
+                        const int j = tbase + u - lane + 1;      // 1-based column
+                        if (j >= 1 && j <= a.m) {
+#pragma unroll
+                            for (int k = 0; k < R; ++k) {
+                                const int row = (int)(row0 + k + 1);
+                                const bool take = k < nreal && (hp[k] > bv || (hp[k] == bv && row < br));
+                                bv = take ? hp[k] : bv;
+                                br = take ? row : br;
+                                bc = take ? j : bc;
+                            }
+                            thr = max(bv, 1);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < R; ++k) sc[k] = sc_n[k];
+                code = code_n;
+            }
+
+            // lane l holds lane 63's output of step 64b+l: column 64b+l-62 (1-based)
+            const int idx = 64 * b + lane - 63;
+            if (idx >= 0 && idx < a.m) store_border(a.border + idx, oh, of);
+            drain_stores();
+            // chunk b-1 (columns 64(b-1)+1 .. 64b) is now complete
+            if (lane == 0 && b >= 1)
+                __hip_atomic_store(a.flags + (b - 1), s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            tfeed = tfeed_n;
+            fh = fh_n;
+            ff = ff_n;
+        }
+        // publish the remaining chunks (also on abort, so that no waiter is left behind)
+        {
+            const int nchunks = (a.m + 63) / 64;
+            const int first = ok ? max(a.nblocks - 1, 0) : 0;
+            for (int c0 = first; c0 < nchunks; c0 += 64) {
+                const int c = c0 + lane;
+                if (c < nchunks)
+                    __hip_atomic_store(a.flags + c, s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+
+        if (LOCAL) {
+            // wave reduction: score desc, row asc, col asc
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const int ov = __shfl_xor(bv, off), orr = __shfl_xor(br, off), oc = __shfl_xor(bc, off);
+                const bool better = ov > bv || (ov == bv && (orr < br || (orr == br && oc < bc)));
+                bv = better ? ov : bv;
+                br = better ? orr : br;
+                bc = better ? oc : bc;
+            }
+            if (lane == 0) a.strip_best[s] = BestCell{bv, br, bc, 0};
+        }
+    }
+}
+
+__global__ void encode_kernel(const char *src, int64_t len, uint8_t *dst, int64_t padded_len,
+                              const uint8_t *lut, uint8_t pad, int32_t *bad_pos)
+{
+    __shared__ uint8_t tab[256];
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) tab[i] = lut[i];
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < padded_len; i += stride) {
+        uint8_t c = pad;
+        if (i < len) {
+            c = tab[(uint8_t)src[i]];
+            if (c == 0xFF) {
+                atomicMin(bad_pos, (int32_t)min<int64_t>(i, INT32_MAX - 1));
+                c = pad;
+            }
+        }
+        dst[i] = c;
+    }
+}
+
+__global__ void reverse_kernel(const uint8_t *src, int64_t len, uint8_t *dst, int64_t padded_len, uint8_t pad)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < padded_len; i += stride)
+        dst[i] = i < len ? src[len - 1 - i] : pad;
+}
+
+__global__ void fill_border_kernel(Border *b, int64_t count, Border v)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) b[i] = v;
+}
+
+__global__ void __launch_bounds__(1024) reduce_best_kernel(const BestCell *in, int32_t count, BestCell *out)
+{
+    __shared__ BestCell part[1024];
+    BestCell best{0, 0, 0, 0};
+    for (int i = threadIdx.x; i < count; i += blockDim.x) {
+        BestCell c = in[i];
+        const bool better = c.score > best.score ||
+                            (c.score == best.score && c.score > 0 &&
+                             (best.score == 0 || c.row < best.row || (c.row == best.row && c.col < best.col)));
+        if (better) best = c;
+    }
+    part[threadIdx.x] = best;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            BestCell x = part[threadIdx.x], y = part[threadIdx.x + w];
+            const bool better = y.score > x.score ||
+                                (y.score == x.score && y.score > 0 &&
+                                 (y.row < x.row || (y.row == x.row && y.col < x.col)));
+            if (better) part[threadIdx.x] = y;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = part[0];
+}
+
+int grid_for(int64_t work, int threads)
+{
+    int64_t g = (work + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > 4096) g = 4096;
+    return (int)g;
+}
+
+template <int R, bool LOCAL>
+hipError_t launch_strip_t(const StripArgs &a, int grid, hipStream_t st)
+{
+    const size_t lds = strip_lds_bytes(R, a.asize);
+    hipLaunchKernelGGL((strip_kernel<R, LOCAL>), dim3(grid), dim3(64), lds, st, a);
+    return hipGetLastError();
+}
+
+template <int R, bool LOCAL>
+int grid_limit_t(int device, int asize)
+{
+    int per_cu = 0;
+    hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(&strip_kernel<R, LOCAL>), 64, strip_lds_bytes(R, asize));
+    if (err != hipSuccess || per_cu < 1) per_cu = 1;
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) != hipSuccess) return per_cu * 64;
+    return per_cu * p.multiProcessorCount;
+}
+
+}  // namespace
+
+size_t strip_lds_bytes(int R, int asize) { return (size_t)(asize + 1) * R * 64 * 4; }
+
+hipError_t launch_encode(const char *src, int64_t len, uint8_t *dst, int64_t padded_len,
+                         const uint8_t *lut, uint8_t pad, int32_t *bad_pos, hipStream_t st)
+{
+    hipLaunchKernelGGL(encode_kernel, dim3(grid_for(padded_len, 256)), dim3(256), 0, st, src, len, dst,
+                       padded_len, lut, pad, bad_pos);
+    return hipGetLastError();
+}
+
+hipError_t launch_reverse(const uint8_t *src, int64_t len, uint8_t *dst, int64_t padded_len, uint8_t pad,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(reverse_kernel, dim3(grid_for(padded_len, 256)), dim3(256), 0, st, src, len, dst,
+                       padded_len, pad);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_border(Border *b, int64_t count, Border v, hipStream_t st)
+{
+    hipLaunchKernelGGL(fill_border_kernel, dim3(grid_for(count, 256)), dim3(256), 0, st, b, count, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_best(const BestCell *in, int32_t count, BestCell *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(reduce_best_kernel, dim3(1), dim3(1024), 0, st, in, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_strip(const StripArgs &a, int R, bool local, int grid, hipStream_t st)
+{
+    if (R == 16) return local ? launch_strip_t<16, true>(a, grid, st) : launch_strip_t<16, false>(a, grid, st);
+    if (R == 8) return local ? launch_strip_t<8, true>(a, grid, st) : launch_strip_t<8, false>(a, grid, st);
+    if (R == 4) return local ? launch_strip_t<4, true>(a, grid, st) : launch_strip_t<4, false>(a, grid, st);
+    return hipErrorInvalidValue;
+}
+
+int strip_grid_limit(int device, int R, bool local, int asize)
+{
+    if (R == 16) return local ? grid_limit_t<16, true>(device, asize) : grid_limit_t<16, false>(device, asize);
+    if (R == 8) return local ? grid_limit_t<8, true>(device, asize) : grid_limit_t<8, false>(device, asize);
+    return local ? grid_limit_t<4, true>(device, asize) : grid_limit_t<4, false>(device, asize);
+}
+
+}  // namespace swh

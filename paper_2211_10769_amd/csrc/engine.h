@@ -1,0 +1,64 @@
+// engine.h -- internal interface between the C ABI (capi.cpp), the host
+// orchestration (engine.cpp, traceback.cpp) and the HIP kernels (*.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace swh {
+
+// "Minus infinity" of the int32 DP.  Every reachable value of the global DP
+// stays well above it (input limits in swh.h), so sums of two of them never
+// overflow and no value derived from it can tie with a real one.
+constexpr int32_t kNeg = -(1 << 29);
+
+// Border record passed from one strip of rows to the next: the strip's last
+// row H and the F value it hands down to the row below.
+struct Border {
+    int32_t h;
+    int32_t f;
+};
+
+// Per strip of rows: best cell of the local DP (score, 1-based row, col).
+struct BestCell {
+    int32_t score, row, col, pad;
+};
+
+// Arguments of the strip-wavefront kernel (dp_strip.hip).
+struct StripArgs {
+    const uint8_t *qc;       // query codes, padded with the pad code to nstrips*64*R rows
+    const uint8_t *tc;       // target codes, >= 64*(nblocks+3) entries (pad code beyond m)
+    int32_t n, m;            // real rows and columns
+    int32_t nstrips;
+    int32_t nblocks;         // sweep_blocks(m)
+    const int8_t *mat;       // asize x asize substitution scores
+    int32_t asize;           // the pad code equals asize
+    int32_t o, e;            // gap open, gap extend (> 0)
+    Border *border;          // 64*(nblocks+3) entries: top row in, bottom row out
+    int32_t *flags;          // nblocks+3 chunk counters, zero on entry
+    int32_t *ticket;         // strip ticket, zero on entry
+    int32_t *abort_flag;     // set when a bounded wait expires
+    BestCell *strip_best;    // nstrips entries (local mode)
+    int32_t spin_limit;      // polls before a wait gives up
+};
+
+// Launchers (return hipSuccess or the launch error).
+hipError_t launch_encode(const char *src, int64_t len, uint8_t *dst, int64_t padded_len,
+                         const uint8_t *lut, uint8_t pad, int32_t *bad_pos, hipStream_t st);
+hipError_t launch_reverse(const uint8_t *src, int64_t len, uint8_t *dst, int64_t padded_len,
+                          uint8_t pad, hipStream_t st);
+hipError_t launch_fill_border(Border *b, int64_t count, Border v, hipStream_t st);
+hipError_t launch_strip(const StripArgs &a, int R, bool local, int grid, hipStream_t st);
+hipError_t launch_reduce_best(const BestCell *in, int32_t count, BestCell *out, hipStream_t st);
+
+// Blocks of 64 steps that sweep m columns with the 63-step lane skew:
+// ceil((m + 63) / 64).  Code and border buffers hold 64 * (blocks + 3) entries.
+inline int64_t sweep_blocks(int64_t m) { return (m + 63 + 63) / 64; }
+
+// Largest resident grid of the strip kernel for this R and alphabet (per device).
+int strip_grid_limit(int device, int R, bool local, int asize);
+size_t strip_lds_bytes(int R, int asize);
+
+}  // namespace swh

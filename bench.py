@@ -1,0 +1,139 @@
+"""Benchmark of the pairwise hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 5000000]
+
+Workload: the long DNA pair (5,000,000 bp query; target = mutated copy with
+2% substitutions, 0.5% indels of geometric length (mean 3) and 50 kbp random
+flanks on both sides, about 5.1 Mbp); match +1, mismatch -3, gap open 5,
+extend 2.  Inputs are generated on the host, copied to HBM once, and are
+resident before the timed region starts.
+
+One step = one complete pairwise alignment through the library: encode,
+forward score pass (score + end), reverse pass (start) and, when the mode is
+"cigar", the linear-space traceback.  value = forward DP cells per step x
+steps / timed seconds (GCUPS, the paper's metric: billion cell updates per
+second).  The JSON line also carries the forward kernel alone (HIP events on
+the stream it runs on), its roofline against the integer-VALU peak, and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz = 39.3e12 32-bit integer lane-ops/s.
+VALU_LANE_OPS = 256 * 64 * 2.4e9
+# Algorithmic integer operations per DP cell of the local pass:
+# add (diag + s), max3 (H), sub (H - o), sub + max3 (E), sub + max3 (F).
+OPS_PER_CELL = 7
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=2)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--n", type=int, default=5_000_000, help="query length of the long pair")
+    p.add_argument("--flank", type=int, default=50_000)
+    p.add_argument("--mode", default="coords", choices=["score", "coords", "cigar"])
+    p.add_argument("--cpu-rows", type=int, default=500,
+                   help="rows of the query used for the timed CPU-oracle sample")
+    p.add_argument("--no-cpu", action="store_true")
+    return p.parse_args()
+
+
+def cpu_baseline(q, t, rows):
+    import oracle
+    import seqgen
+    sc = seqgen.dna_scoring()
+    a = bytes(q[:rows])
+    b = bytes(t)
+    t0 = time.perf_counter()
+    oracle.sw_end(a, b, sc)
+    dt = time.perf_counter() - t0
+    cells = len(a) * len(b)
+    return {"value": cells / dt / 1e9, "unit": "GCUPS", "cores": 1, "kind": "oracle",
+            "sample": f"score pass of the first {rows} query rows against the full target "
+                      f"({cells:.3e} cells, {dt:.1f} s, single thread)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the pairwise path has no "
+              "multi-GPU mode in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2211_10769_amd as swh
+    import seqgen
+
+    q, t = seqgen.workload1(args.n, flank=args.flank)
+    sc = swh.Scoring(*seqgen.dna_scoring())
+    dev = torch.device("cuda:0")
+    qd = torch.from_numpy(np.ascontiguousarray(q)).to(dev)
+    td = torch.from_numpy(np.ascontiguousarray(t)).to(dev)
+    torch.cuda.synchronize()
+    eng = swh.Engine(0)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    for _ in range(args.warmup):
+        eng.align_dev(qd, td, sc, mode=args.mode, stream=stream)
+    torch.cuda.synchronize()
+
+    fwd_ms, rev_ms, tb_ms = [], [], []
+    t0 = time.perf_counter()
+    res = None
+    for _ in range(args.steps):
+        res = eng.align_dev(qd, td, sc, mode=args.mode, stream=stream, stats=True)
+        fwd_ms.append(res["stats"]["ms_forward"])
+        rev_ms.append(res["stats"]["ms_reverse"])
+        tb_ms.append(res["stats"]["ms_traceback"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    cells = float(len(q)) * float(len(t))
+    value = cells * args.steps / dt / 1e9
+    fwd_avg = sum(fwd_ms) / len(fwd_ms)
+    fwd_gcups = cells / (fwd_avg / 1e3) / 1e9
+    peak_gcups = VALU_LANE_OPS / OPS_PER_CELL / 1e9
+    out = {
+        "metric": "GCUPS (score-only SW, 1 MI355X) + prefilter search speedup at recall@10>=0.99",
+        "value": round(value, 2),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "long DNA pair: 5 Mbp query vs mutated copy with 50 kbp flanks "
+                               "(+1/-3, open 5, extend 2)",
+                   "query_bp": len(q), "target_bp": len(t), "mode": args.mode,
+                   "cells_per_step": cells},
+        "result": {k: res[k] for k in ("score", "q_begin", "q_end", "t_begin", "t_end")},
+        "forward_kernel": {"gcups": round(fwd_gcups, 2), "ms": round(fwd_avg, 2)},
+        "reverse_ms": round(sum(rev_ms) / len(rev_ms), 2),
+        "traceback_ms": round(sum(tb_ms) / len(tb_ms), 2),
+        "roofline": {"bound": "alu", "achieved": round(fwd_gcups, 2), "peak": round(peak_gcups, 1),
+                     "unit": "GCUPS", "frac": round(fwd_gcups / peak_gcups, 4), "traffic": None},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(q, t, args.cpu_rows)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -105,7 +105,7 @@ const char *swh_last_error(const swh_ctx *ctx);
  * NULL when mode < CIGAR.  *cigar_len (may be NULL) receives the CIGAR
  * length without the NUL; when cigar_cap is too small the call fails with
  * SWH_E_RANGE and *cigar_len holds the required length.
- * Limits: qlen, tlen < 2^31; min(qlen, tlen) * max|s| < 2^28;
+ * Limits: qlen, tlen < 2^31; min(qlen, tlen) * max|s| < 2^26;
  * for mode CIGAR also (max s + gap_extend) * (qlen + tlen) + gap_open < 2^27.
  * stats may be NULL.
  */

@@ -84,8 +84,8 @@ swh_status check_pair(swh_ctx *ctx, const void *q, int64_t qlen, const void *t, 
         return fail(ctx, SWH_E_RANGE, "sequence longer than 2^31 - 1");
     const int64_t smax = sc.smax > 0 ? sc.smax : 1;
     const int64_t sabs = sc.smax > -sc.smin ? sc.smax : -sc.smin;
-    if ((qlen < tlen ? qlen : tlen) * (sabs > 0 ? sabs : 1) >= ((int64_t)1 << 28))
-        return fail(ctx, SWH_E_RANGE, "min(qlen, tlen) * max|s| must stay below 2^28");
+    if ((qlen < tlen ? qlen : tlen) * (sabs > 0 ? sabs : 1) >= ((int64_t)1 << 26))
+        return fail(ctx, SWH_E_RANGE, "min(qlen, tlen) * max|s| must stay below 2^26");
     if (mode == SWH_MODE_CIGAR && (smax + sc.e) * (qlen + tlen) + sc.o >= ((int64_t)1 << 27))
         return fail(ctx, SWH_E_RANGE, "(max s + gap_extend) * (qlen + tlen) + gap_open must stay below 2^27");
     return SWH_OK;

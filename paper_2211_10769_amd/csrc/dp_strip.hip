@@ -22,9 +22,14 @@
 // same recurrence clamped at 0, and H = max3(diag + s, E', F') then needs no
 // extra operation.  GLOBAL (traceback passes): floor = kNeg, no clamp.
 //
-// Substitution scores come from a per-strip query profile in LDS,
-// prof[code][k/4][lane] as int4, read with four ds_read_b128 per step (R=16)
-// with no bank conflicts whatever code each lane holds.
+// Substitution scores come from a per-strip query profile in LDS: for each
+// symbol code, the lane's R int8 scores in R/4 consecutive words,
+// prof[code][lane][R/4].  One step reads them with a single ds_read_b128
+// (R=16), conflict-free whatever code each lane holds, and each byte enters
+// the add through an SDWA sign-extended byte select at no extra cost.  The
+// pad code scores -128: in a virtual column left of the sweep the diagonal
+// is the boundary value, so the pad can never raise H there; everything to
+// the right of the last column or below the last row is never read back.
 #include <hip/hip_runtime.h>
 
 #include "engine.h"
@@ -78,7 +83,7 @@ __device__ __forceinline__ void drain_stores()
 // false.
 __device__ __forceinline__ bool wait_chunk(const StripArgs &a, int chunk, int need)
 {
-    int spins = 0;
+    const uint64_t t0 = wall_clock64();
     for (;;) {
         const int v = __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(a.flags + chunk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
@@ -86,7 +91,7 @@ __device__ __forceinline__ bool wait_chunk(const StripArgs &a, int chunk, int ne
         const int ab = __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         if (ab) return false;
-        if (++spins > a.spin_limit) {
+        if (wall_clock64() - t0 > a.wait_ticks) {
             __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
         }
@@ -96,8 +101,32 @@ __device__ __forceinline__ bool wait_chunk(const StripArgs &a, int chunk, int ne
 
 template <int R>
 struct Prof {
-    static constexpr int R4 = R / 4;
+    static constexpr int W = R / 4;   // profile words per (code, lane)
 };
+
+template <int W>
+__device__ __forceinline__ void load_prof(const int *prof, int code, int lane, int (&w)[W])
+{
+    const int *p = prof + (code * 64 + lane) * W;
+    if constexpr (W == 8) {
+        const int4 x = reinterpret_cast<const int4 *>(p)[0], y = reinterpret_cast<const int4 *>(p)[1];
+        w[0] = x.x; w[1] = x.y; w[2] = x.z; w[3] = x.w; w[4] = y.x; w[5] = y.y; w[6] = y.z; w[7] = y.w;
+    } else if constexpr (W == 4) {
+        const int4 x = reinterpret_cast<const int4 *>(p)[0];
+        w[0] = x.x; w[1] = x.y; w[2] = x.z; w[3] = x.w;
+    } else if constexpr (W == 2) {
+        const int2 x = reinterpret_cast<const int2 *>(p)[0];
+        w[0] = x.x; w[1] = x.y;
+    } else {
+        w[0] = p[0];
+    }
+}
+
+template <int W>
+__device__ __forceinline__ int prof_score(const int (&w)[W], int k)
+{
+    return (int)(signed char)(w[k >> 2] >> (8 * (k & 3)));
+}
 
 // One DP step for the lane's R rows at one column.
 //   dg   : H(row0-1, j-1)                f    : F handed down into row0 (in), out of row R-1 (out)
@@ -105,14 +134,14 @@ struct Prof {
 // PASS: rows with index >= nreal copy the row above (pass-through), so the
 // wave's last row reproduces the last real row (global mode, ragged strip).
 template <int R, bool LOCAL, bool PASS>
-__device__ __forceinline__ void dp_step(int (&hp)[R], int (&E)[R], const int (&sc)[R], int dg, int hup,
+__device__ __forceinline__ void dp_step(int (&hp)[R], int (&E)[R], const int (&sc)[R / 4], int dg, int hup,
                                         int &f, int o, int e, int nreal)
 {
     constexpr int B = LOCAL ? 0 : kNeg;
     int habove = hup;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        int h = max3i(dg + sc[k], E[k], f);
+        int h = max3i(dg + prof_score<R / 4>(sc, k), E[k], f);
         int hop = h - o;
         int fn = max3i(f - e, hop, B);
         E[k] = max3i(E[k] - e, hop, B);
@@ -131,14 +160,13 @@ __device__ __forceinline__ void dp_step(int (&hp)[R], int (&E)[R], const int (&s
 template <int R, bool LOCAL>
 __global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
 {
-    extern __shared__ int4 prof4[];
-    constexpr int R4 = Prof<R>::R4;
+    extern __shared__ int prof[];
+    constexpr int W = Prof<R>::W;
     constexpr int B = LOCAL ? 0 : kNeg;
     const int lane = threadIdx.x;
     const int pad = a.asize;
     const int A1 = a.asize + 1;
     const int o = a.o, e = a.e;
-    int *prof = reinterpret_cast<int *>(prof4);
 
     for (;;) {
         // every lane takes part in the atomic (lane 0 adds 1, the others 0), so no
@@ -150,11 +178,17 @@ __global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
         const int64_t row0 = (int64_t)s * 64 * R + (int64_t)lane * R;   // 0-based
 
         // ---- query profile for this lane's rows (written and read by this lane only)
-        for (int k = 0; k < R; ++k) {
-            const int q = a.qc[row0 + k];
-            for (int c = 0; c < A1; ++c) {
-                int v = (q >= a.asize || c >= a.asize) ? kNeg : (int)a.mat[q * a.asize + c];
-                prof[((c * R4 + (k >> 2)) * 64 + lane) * 4 + (k & 3)] = v;
+        for (int c = 0; c < A1; ++c) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                unsigned word = 0;
+#pragma unroll
+                for (int b4 = 0; b4 < 4; ++b4) {
+                    const int q = a.qc[row0 + 4 * w + b4];
+                    const int v = (q >= a.asize || c >= a.asize) ? -128 : (int)a.mat[q * a.asize + c];
+                    word |= (unsigned)(v & 0xFF) << (8 * b4);
+                }
+                prof[(c * 64 + lane) * W + w] = (int)word;
             }
         }
         int nreal = (int)min<int64_t>(max<int64_t>(a.n - row0, 0), R);
@@ -167,7 +201,14 @@ __global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
         int hup_prev = B;          // H(row0-1, j-1): diag of the first row
         int hbot = B, fbot = B;    // this lane's last row output of the previous step
         int oh = B, of = B;        // collected outputs of lane 63
-        int bv = 0, br = 0, bc = 0, thr = 1;   // best cell (local)
+        // best cell (local): key = (H << log2 R) | (R-1-k) orders cells of one
+        // step by value, then smaller row; bkey keeps the largest key seen and
+        // bstep the first step that reached it, so (value desc, row asc, column
+        // asc) -- the first cell in row-major order -- falls out without any
+        // branch.  Cells right of the last column or below the last row only
+        // hold values derived from real cells minus a gap penalty, so they can
+        // never reach the optimum and need no mask.
+        int bkey = 0, bstep = 0;
 
         // block 0 inputs
         int code = lane == 0 ? (int)a.tc[0] : pad;       // current column's code
@@ -177,15 +218,8 @@ __global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
         if (ok && !wait_chunk(a, 0, s)) ok = false;
         if (ok) load_border(a.border + lane, fh, ff);
 
-        int sc[R];
-        {
-            const int4 *pr = prof4 + (code * R4) * 64 + lane;
-#pragma unroll
-            for (int q4 = 0; q4 < R4; ++q4) {
-                int4 v = pr[q4 * 64];
-                sc[4 * q4] = v.x; sc[4 * q4 + 1] = v.y; sc[4 * q4 + 2] = v.z; sc[4 * q4 + 3] = v.w;
-            }
-        }
+        int sc[W];
+        load_prof<W>(prof, code, lane, sc);
 
         for (int b = 0; b < a.nblocks && ok; ++b) {
             // prefetch the next block's target codes and border chunk
@@ -202,16 +236,11 @@ __global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
                 // next column's code (lane 0 from the feed, others from the lane above)
                 const int code_n = shr1(tfeed, code);
                 tfeed = shl1(tfeed, tfeed);
-                int sc_n[R];
-                {
-                    const int4 *pr = prof4 + (code_n * R4) * 64 + lane;
-#pragma unroll
-                    for (int q4 = 0; q4 < R4; ++q4) {
-                        int4 v = pr[q4 * 64];
-                        sc_n[4 * q4] = v.x; sc_n[4 * q4 + 1] = v.y;
-                        sc_n[4 * q4 + 2] = v.z; sc_n[4 * q4 + 3] = v.w;
-                    }
-                }
+                int sc_n[W];
+                load_prof<W>(prof, code_n, lane, sc_n);
+                // keep the profile read for the next column ahead of this column's
+                // arithmetic, so its LDS latency overlaps one whole step
+                __builtin_amdgcn_sched_barrier(0);
                 // row above this lane's first row at this column
                 const int hup = shr1(fh, hbot);
                 int f = shr1(ff, fbot);
@@ -229,26 +258,16 @@ __global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
                 of = shl1(fbot, of);
 
                 if (LOCAL) {
-                    int mx = hp[0];
+                    constexpr int LOGR = R == 32 ? 5 : R == 16 ? 4 : R == 8 ? 3 : 2;
+                    int mx = (hp[0] << LOGR) | (R - 1);
 #pragma unroll
-                    for (int k = 1; k < R; ++k) mx = max(mx, hp[k]);
-                    if (mx >= thr) {
-                        const int j = tbase + u - lane + 1;      // 1-based column
-                        if (j >= 1 && j <= a.m) {
-#pragma unroll
-                            for (int k = 0; k < R; ++k) {
-                                const int row = (int)(row0 + k + 1);
-                                const bool take = k < nreal && (hp[k] > bv || (hp[k] == bv && row < br));
-                                bv = take ? hp[k] : bv;
-                                br = take ? row : br;
-                                bc = take ? j : bc;
-                            }
-                            thr = max(bv, 1);
-                        }
-                    }
+                    for (int k = 1; k < R; ++k) mx = max(mx, (hp[k] << LOGR) | (R - 1 - k));
+                    const bool gt = mx > bkey;
+                    bkey = gt ? mx : bkey;
+                    bstep = gt ? tbase + u : bstep;
                 }
 #pragma unroll
-                for (int k = 0; k < R; ++k) sc[k] = sc_n[k];
+                for (int w = 0; w < W; ++w) sc[w] = sc_n[w];
                 code = code_n;
             }
 
@@ -275,6 +294,10 @@ __global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
         }
 
         if (LOCAL) {
+            constexpr int LOGR = R == 32 ? 5 : R == 16 ? 4 : R == 8 ? 3 : 2;
+            int bv = bkey >> LOGR;
+            int br = bv > 0 ? (int)(row0 + (R - 1 - (bkey & (R - 1))) + 1) : 0;
+            int bc = bv > 0 ? bstep - lane + 1 : 0;
             // wave reduction: score desc, row asc, col asc
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) {
@@ -378,7 +401,7 @@ int grid_limit_t(int device, int asize)
 
 }  // namespace
 
-size_t strip_lds_bytes(int R, int asize) { return (size_t)(asize + 1) * R * 64 * 4; }
+size_t strip_lds_bytes(int R, int asize) { return (size_t)(asize + 1) * R * 64; }
 
 hipError_t launch_encode(const char *src, int64_t len, uint8_t *dst, int64_t padded_len,
                          const uint8_t *lut, uint8_t pad, int32_t *bad_pos, hipStream_t st)
@@ -410,6 +433,7 @@ hipError_t launch_reduce_best(const BestCell *in, int32_t count, BestCell *out, 
 
 hipError_t launch_strip(const StripArgs &a, int R, bool local, int grid, hipStream_t st)
 {
+    if (R == 32) return local ? launch_strip_t<32, true>(a, grid, st) : launch_strip_t<32, false>(a, grid, st);
     if (R == 16) return local ? launch_strip_t<16, true>(a, grid, st) : launch_strip_t<16, false>(a, grid, st);
     if (R == 8) return local ? launch_strip_t<8, true>(a, grid, st) : launch_strip_t<8, false>(a, grid, st);
     if (R == 4) return local ? launch_strip_t<4, true>(a, grid, st) : launch_strip_t<4, false>(a, grid, st);
@@ -418,6 +442,7 @@ hipError_t launch_strip(const StripArgs &a, int R, bool local, int grid, hipStre
 
 int strip_grid_limit(int device, int R, bool local, int asize)
 {
+    if (R == 32) return local ? grid_limit_t<32, true>(device, asize) : grid_limit_t<32, false>(device, asize);
     if (R == 16) return local ? grid_limit_t<16, true>(device, asize) : grid_limit_t<16, false>(device, asize);
     if (R == 8) return local ? grid_limit_t<8, true>(device, asize) : grid_limit_t<8, false>(device, asize);
     return local ? grid_limit_t<4, true>(device, asize) : grid_limit_t<4, false>(device, asize);

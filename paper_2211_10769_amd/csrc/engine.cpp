@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -18,13 +19,48 @@ namespace {
 // misc buffer layout (int32 words)
 enum { kTicket = 0, kAbort = 1, kBadQ = 2, kBadT = 3, kResult = 4, kMiscWords = 8 };
 
-constexpr int kSpinLimit = 1 << 22;   // polls (a few microseconds each) before a wait gives up
+// A single chunk wait longer than this is a bug (the wavefront cannot
+// deadlock); the kernel then drains and the call fails with SWH_E_TIMEOUT.
+constexpr double kWaitSeconds = 30.0;
+
+uint64_t wait_ticks(int device)
+{
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || khz <= 0)
+        khz = 100000;   // 100 MHz constant clock
+    return (uint64_t)(kWaitSeconds * 1e3 * khz);
+}
+
+// Tuning knobs (environment): SWH_ROWS forces the rows per lane (4, 8, 16,
+// 32), SWH_GRID the persistent grid of the strip kernel.
+int env_int(const char *name, int dflt)
+{
+    const char *v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    return std::atoi(v);
+}
 
 int pick_rows_per_lane(int64_t n)
 {
+    const int forced = env_int("SWH_ROWS", 0);
+    if (forced == 4 || forced == 8 || forced == 16 || forced == 32) return forced;
     if (n >= 200000) return 16;
     if (n >= 20000) return 8;
     return 4;
+}
+
+// Persistent grid: a whole number of waves per SIMD (every strip waits on the
+// previous one, so the wavefront runs at the pace of the most loaded SIMD and
+// an uneven spread of waves over SIMDs slows everything down).  Waves per
+// SIMD by strip height, from sweeps on the long DNA pair: 8 for R=4, 4 for
+// R=8, 2 for R=16 and R=32.
+int strip_grid(int nstrips, int R, int limit, int num_cu)
+{
+    const int forced = env_int("SWH_GRID", 0);
+    if (forced > 0) return std::min(forced, nstrips);
+    const int per_simd = R <= 4 ? 8 : R <= 8 ? 4 : 2;
+    const int want = std::min(limit, per_simd * 4 * std::max(num_cu, 1));
+    return std::max(1, std::min(nstrips, want));
 }
 
 struct LocalPass {
@@ -70,8 +106,8 @@ swh_status local_pass(swh_ctx *ctx, const uint8_t *qc, int64_t n, const uint8_t 
     a.ticket = misc + kTicket;
     a.abort_flag = misc + kAbort;
     a.strip_best = (BestCell *)ctx->strip_best.p;
-    a.spin_limit = kSpinLimit;
-    const int grid = std::max(1, std::min<int>(nstrips, strip_grid_limit(ctx->device, R, true, sc.asize)));
+    a.wait_ticks = wait_ticks(ctx->device);
+    const int grid = strip_grid(nstrips, R, strip_grid_limit(ctx->device, R, true, sc.asize), ctx->num_cu);
 
     hipEventRecord(ctx->ev[0], st);
     if ((e = launch_strip(a, R, true, grid, st)) != hipSuccess) return hip_fail(ctx, e, "strip kernel launch");

@@ -41,7 +41,7 @@ struct StripArgs {
     int32_t *ticket;         // strip ticket, zero on entry
     int32_t *abort_flag;     // set when a bounded wait expires
     BestCell *strip_best;    // nstrips entries (local mode)
-    int32_t spin_limit;      // polls before a wait gives up
+    uint64_t wait_ticks;     // wall-clock ticks one wait may last before it gives up
 };
 
 // Launchers (return hipSuccess or the launch error).

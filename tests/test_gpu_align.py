@@ -92,3 +92,17 @@ def test_bad_symbol(eng):
         eng.align("ACGN", "ACGT", seqgen.dna_scoring(), mode="score")
     assert ei.value.status == -2
     assert "position 3" in str(ei.value)
+
+
+@pytest.mark.parametrize("rows,grid", [(4, 0), (8, 0), (16, 0), (32, 0), (16, 1), (8, 3), (32, 2)])
+def test_forced_strip_shapes(eng, rows, grid, monkeypatch):
+    # every strip height and tiny persistent grids (one wave doing every strip in turn)
+    monkeypatch.setenv("SWH_ROWS", str(rows))
+    monkeypatch.setenv("SWH_GRID", str(grid))
+    rng = np.random.default_rng(rows * 100 + grid)
+    sc = seqgen.dna_scoring()
+    a = seqgen.random_dna(rng, 6000)
+    b = np.concatenate([seqgen.random_dna(rng, 700), seqgen.mutate(rng, a, 0.04, 0.01),
+                        seqgen.random_dna(rng, 333)])
+    _cmp(eng, bytes(a), bytes(b), sc)
+    _cmp(eng, bytes(seqgen.random_dna(rng, 2100)), bytes(seqgen.random_dna(rng, 1900)), sc)

@@ -41,10 +41,15 @@ struct swh_ctx {
     swh::DevBuf qc, tc;            // codes
     swh::DevBuf qr, tr;            // reversed codes
     swh::DevBuf border, flags, misc, strip_best, mat, lut;
+    // strip-kernel problem tables
+    swh::DevBuf probs, strip_prob, prob_best, sync;
+    std::vector<swh::Problem> h_probs;
+    std::vector<int32_t> h_strip_prob;
     // traceback buffers
     swh::DevBuf tb_fwd, tb_bwd, tb_front, tb_codes_q, tb_codes_t, tb_leaf, tb_misc;
     std::vector<swh::DevBuf *> all() {
         return {&qraw, &traw, &qc, &tc, &qr, &tr, &border, &flags, &misc, &strip_best, &mat, &lut,
+                &probs, &strip_prob, &prob_best, &sync,
                 &tb_fwd, &tb_bwd, &tb_front, &tb_codes_q, &tb_codes_t, &tb_leaf, &tb_misc};
     }
 };

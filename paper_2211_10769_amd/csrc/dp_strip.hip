@@ -81,12 +81,12 @@ __device__ __forceinline__ void drain_stores()
 // kernel's lane shifts assume all 64 lanes execute together.  Bounded: on
 // expiry (or when another wave has given up) sets/observes abort and returns
 // false.
-__device__ __forceinline__ bool wait_chunk(const StripArgs &a, int chunk, int need)
+__device__ __forceinline__ bool wait_chunk(const StripArgs &a, const int32_t *flags, int chunk, int need)
 {
     const uint64_t t0 = wall_clock64();
     for (;;) {
         const int v = __builtin_amdgcn_readfirstlane(
-            __hip_atomic_load(a.flags + chunk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            __hip_atomic_load(flags + chunk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         if (v >= need) return true;
         const int ab = __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
@@ -173,8 +173,11 @@ __global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
         // lane-dependent branch precedes the readfirstlane that broadcasts the ticket
         const int sv = __hip_atomic_fetch_add(a.ticket, lane == 0 ? 1 : 0, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
-        const int s = __builtin_amdgcn_readfirstlane(sv);
-        if (s >= a.nstrips) break;
+        const int sg = __builtin_amdgcn_readfirstlane(sv);
+        if (sg >= a.total_strips) break;
+        const int pi = a.strip_prob ? __builtin_amdgcn_readfirstlane((int)a.strip_prob[sg]) : 0;
+        const Problem P = a.probs[pi];
+        const int s = sg - P.strip0;                                      // strip within the problem
         const int64_t row0 = (int64_t)s * 64 * R + (int64_t)lane * R;   // 0-based
 
         // ---- query profile for this lane's rows (written and read by this lane only)
@@ -184,16 +187,16 @@ __global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
                 unsigned word = 0;
 #pragma unroll
                 for (int b4 = 0; b4 < 4; ++b4) {
-                    const int q = a.qc[row0 + 4 * w + b4];
+                    const int q = P.qc[row0 + 4 * w + b4];
                     const int v = (q >= a.asize || c >= a.asize) ? -128 : (int)a.mat[q * a.asize + c];
                     word |= (unsigned)(v & 0xFF) << (8 * b4);
                 }
                 prof[(c * 64 + lane) * W + w] = (int)word;
             }
         }
-        int nreal = (int)min<int64_t>(max<int64_t>(a.n - row0, 0), R);
+        int nreal = (int)min<int64_t>(max<int64_t>(P.n - row0, 0), R);
         const bool ragged = !LOCAL && __builtin_amdgcn_readfirstlane(
-                                          (int)((int64_t)(s + 1) * 64 * R > a.n));
+                                          (int)((int64_t)(s + 1) * 64 * R > P.n));
 
         int hp[R], E[R];
 #pragma unroll
@@ -211,23 +214,23 @@ __global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
         int bkey = 0, bstep = 0;
 
         // block 0 inputs
-        int code = lane == 0 ? (int)a.tc[0] : pad;       // current column's code
-        int tfeed = a.tc[1 + lane];                       // lane 0 = code of column t+2
+        int code = lane == 0 ? (int)P.tc[0] : pad;       // current column's code
+        int tfeed = P.tc[1 + lane];                       // lane 0 = code of column t+2
         int fh = B, ff = B;
         bool ok = true;
-        if (ok && !wait_chunk(a, 0, s)) ok = false;
-        if (ok) load_border(a.border + lane, fh, ff);
+        if (ok && !wait_chunk(a, P.flags, 0, s)) ok = false;
+        if (ok) load_border(P.border + lane, fh, ff);
 
         int sc[W];
         load_prof<W>(prof, code, lane, sc);
 
-        for (int b = 0; b < a.nblocks && ok; ++b) {
+        for (int b = 0; b < P.nblocks && ok; ++b) {
             // prefetch the next block's target codes and border chunk
-            const int tfeed_n = a.tc[64 * (b + 1) + 1 + lane];
+            const int tfeed_n = P.tc[64 * (b + 1) + 1 + lane];
             int fh_n = B, ff_n = B;
-            if (64 * (b + 1) < a.m) {
-                if (!wait_chunk(a, b + 1, s)) { ok = false; break; }
-                load_border(a.border + 64 * (b + 1) + lane, fh_n, ff_n);
+            if (64 * (b + 1) < P.m) {
+                if (!wait_chunk(a, P.flags, b + 1, s)) { ok = false; break; }
+                load_border(P.border + 64 * (b + 1) + lane, fh_n, ff_n);
             }
 
             const int tbase = 64 * b;
@@ -273,23 +276,23 @@ __global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
 
             // lane l holds lane 63's output of step 64b+l: column 64b+l-62 (1-based)
             const int idx = 64 * b + lane - 63;
-            if (idx >= 0 && idx < a.m) store_border(a.border + idx, oh, of);
+            if (idx >= 0 && idx < P.m) store_border(P.border + idx, oh, of);
             drain_stores();
             // chunk b-1 (columns 64(b-1)+1 .. 64b) is now complete
             if (lane == 0 && b >= 1)
-                __hip_atomic_store(a.flags + (b - 1), s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(P.flags + (b - 1), s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             tfeed = tfeed_n;
             fh = fh_n;
             ff = ff_n;
         }
         // publish the remaining chunks (also on abort, so that no waiter is left behind)
         {
-            const int nchunks = (a.m + 63) / 64;
-            const int first = ok ? max(a.nblocks - 1, 0) : 0;
+            const int nchunks = (P.m + 63) / 64;
+            const int first = ok ? max(P.nblocks - 1, 0) : 0;
             for (int c0 = first; c0 < nchunks; c0 += 64) {
                 const int c = c0 + lane;
                 if (c < nchunks)
-                    __hip_atomic_store(a.flags + c, s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(P.flags + c, s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
 
@@ -307,7 +310,7 @@ __global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
                 br = better ? orr : br;
                 bc = better ? oc : bc;
             }
-            if (lane == 0) a.strip_best[s] = BestCell{bv, br, bc, 0};
+            if (lane == 0) a.strip_best[sg] = BestCell{bv, br, bc, 0};
         }
     }
 }
@@ -371,6 +374,39 @@ __global__ void __launch_bounds__(1024) reduce_best_kernel(const BestCell *in, i
     if (threadIdx.x == 0) *out = part[0];
 }
 
+// One block per problem: the problem's best cell over its strips
+// (score desc, row asc, col asc).
+__global__ void __launch_bounds__(256) reduce_best_multi_kernel(const BestCell *strip_best, const Problem *probs,
+                                                                  int32_t nprobs, BestCell *out)
+{
+    __shared__ BestCell part[256];
+    for (int p = blockIdx.x; p < nprobs; p += gridDim.x) {
+        const int s0 = probs[p].strip0, ns = probs[p].nstrips;
+        BestCell best{0, 0, 0, 0};
+        for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+            const BestCell c = strip_best[s0 + i];
+            const bool better = c.score > best.score ||
+                                (c.score == best.score && c.score > 0 &&
+                                 (c.row < best.row || (c.row == best.row && c.col < best.col)));
+            if (better) best = c;
+        }
+        part[threadIdx.x] = best;
+        __syncthreads();
+        for (int w = blockDim.x / 2; w >= 1; w >>= 1) {
+            if ((int)threadIdx.x < w) {
+                const BestCell x = part[threadIdx.x], y = part[threadIdx.x + w];
+                const bool better = y.score > x.score ||
+                                    (y.score == x.score && y.score > 0 &&
+                                     (y.row < x.row || (y.row == x.row && y.col < x.col)));
+                if (better) part[threadIdx.x] = y;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[p] = part[0];
+        __syncthreads();
+    }
+}
+
 int grid_for(int64_t work, int threads)
 {
     int64_t g = (work + threads - 1) / threads;
@@ -428,6 +464,14 @@ hipError_t launch_fill_border(Border *b, int64_t count, Border v, hipStream_t st
 hipError_t launch_reduce_best(const BestCell *in, int32_t count, BestCell *out, hipStream_t st)
 {
     hipLaunchKernelGGL(reduce_best_kernel, dim3(1), dim3(1024), 0, st, in, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_best_multi(const BestCell *strip_best, const Problem *probs, int32_t nprobs,
+                                    BestCell *out, hipStream_t st)
+{
+    const int grid = nprobs < 4096 ? (nprobs > 0 ? nprobs : 1) : 4096;
+    hipLaunchKernelGGL(reduce_best_multi_kernel, dim3(grid), dim3(256), 0, st, strip_best, probs, nprobs, out);
     return hipGetLastError();
 }
 

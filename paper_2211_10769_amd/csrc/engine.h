@@ -26,22 +26,34 @@ struct BestCell {
     int32_t score, row, col, pad;
 };
 
-// Arguments of the strip-wavefront kernel (dp_strip.hip).
-struct StripArgs {
-    const uint8_t *qc;       // query codes, padded with the pad code to nstrips*64*R rows
-    const uint8_t *tc;       // target codes, >= 64*(nblocks+3) entries (pad code beyond m)
+// One DP problem of the strip-wavefront kernel: a rows x m-columns matrix
+// swept by strips of 64*R rows.  Many problems can share one launch: their
+// strips share one ticket space, and strips of different problems never wait
+// on each other.
+struct Problem {
+    const uint8_t *qc;       // row codes, padded with the pad code to nstrips*64*R rows
+    const uint8_t *tc;       // column codes, 64*(nblocks+3) entries (pad code beyond m)
+    Border *border;          // 64*(nblocks+3) entries: top row in, bottom row out
+    int32_t *flags;          // nblocks+3 chunk counters, zero on entry
     int32_t n, m;            // real rows and columns
     int32_t nstrips;
     int32_t nblocks;         // sweep_blocks(m)
-    const int8_t *mat;       // asize x asize substitution scores
-    int32_t asize;           // the pad code equals asize
-    int32_t o, e;            // gap open, gap extend (> 0)
-    Border *border;          // 64*(nblocks+3) entries: top row in, bottom row out
-    int32_t *flags;          // nblocks+3 chunk counters, zero on entry
-    int32_t *ticket;         // strip ticket, zero on entry
-    int32_t *abort_flag;     // set when a bounded wait expires
-    BestCell *strip_best;    // nstrips entries (local mode)
-    uint64_t wait_ticks;     // wall-clock ticks one wait may last before it gives up
+    int32_t strip0;          // global index of this problem's first strip
+    int32_t pad_;
+};
+
+// Arguments of the strip-wavefront kernel (dp_strip.hip).
+struct StripArgs {
+    const Problem *probs;
+    const int32_t *strip_prob;   // global strip -> problem index (NULL: single problem)
+    int32_t total_strips;
+    const int8_t *mat;           // asize x asize substitution scores
+    int32_t asize;               // the pad code equals asize
+    int32_t o, e;                // gap open, gap extend (> 0)
+    int32_t *ticket;             // strip ticket, zero on entry
+    int32_t *abort_flag;         // set when a bounded wait expires
+    BestCell *strip_best;        // one entry per global strip (local mode)
+    uint64_t wait_ticks;         // wall-clock ticks one wait may last before it gives up
 };
 
 // Launchers (return hipSuccess or the launch error).
@@ -52,6 +64,9 @@ hipError_t launch_reverse(const uint8_t *src, int64_t len, uint8_t *dst, int64_t
 hipError_t launch_fill_border(Border *b, int64_t count, Border v, hipStream_t st);
 hipError_t launch_strip(const StripArgs &a, int R, bool local, int grid, hipStream_t st);
 hipError_t launch_reduce_best(const BestCell *in, int32_t count, BestCell *out, hipStream_t st);
+// Per problem: best cell over its strips (strip_best indexed by global strip).
+hipError_t launch_reduce_best_multi(const BestCell *strip_best, const Problem *probs, int32_t nprobs,
+                                    BestCell *out, hipStream_t st);
 
 // Blocks of 64 steps that sweep m columns with the 63-step lane skew:
 // ceil((m + 63) / 64).  Code and border buffers hold 64 * (blocks + 3) entries.

@@ -1,0 +1,150 @@
+// strips.cpp -- host side of the strip-wavefront kernel: runs one launch over
+// a table of independent DP problems (one pairwise pass, the passes of one
+// traceback level, or a batch of pairs).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "context.h"
+#include "engine.h"
+#include "strips.h"
+
+namespace swh {
+
+namespace {
+
+// A single chunk wait longer than this is a bug (the wavefront cannot
+// deadlock); the kernel then drains and the call fails with SWH_E_TIMEOUT.
+constexpr double kWaitSeconds = 30.0;
+
+uint64_t wait_ticks(int device)
+{
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || khz <= 0)
+        khz = 100000;   // 100 MHz constant clock
+    return (uint64_t)(kWaitSeconds * 1e3 * khz);
+}
+
+}  // namespace
+
+int env_int(const char *name, int dflt)
+{
+    const char *v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    return std::atoi(v);
+}
+
+int pick_rows_per_lane(int64_t n)
+{
+    const int forced = env_int("SWH_ROWS", 0);
+    if (forced == 4 || forced == 8 || forced == 16 || forced == 32) return forced;
+    if (n >= 200000) return 16;
+    if (n >= 20000) return 8;
+    return 4;
+}
+
+// Persistent grid: a whole number of waves per SIMD (every strip waits on the
+// previous one of its problem, so a wavefront runs at the pace of the most
+// loaded SIMD and an uneven spread of waves over SIMDs slows it down).  Waves
+// per SIMD by strip height, from sweeps on the long DNA pair: 8 for R=4, 4
+// for R=8, 2 for R=16 and R=32.
+int strip_grid(int64_t nstrips, int R, int limit, int num_cu)
+{
+    const int forced = env_int("SWH_GRID", 0);
+    if (forced > 0) return (int)std::min<int64_t>(forced, nstrips);
+    const int per_simd = R <= 4 ? 8 : R <= 8 ? 4 : 2;
+    const int want = std::min(limit, per_simd * 4 * std::max(num_cu, 1));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(nstrips, want));
+}
+
+swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, const Scoring &sc, int R, bool local,
+                      hipStream_t st, std::vector<BestCell> *best, float *ms)
+{
+    const int np = (int)probs.size();
+    if (np == 0) return SWH_OK;
+    std::vector<Problem> &tab = ctx->h_probs;
+    std::vector<int32_t> &sp = ctx->h_strip_prob;
+    tab.resize(np);
+    sp.clear();
+    int64_t total_strips = 0, total_flags = 0;
+    for (int i = 0; i < np; ++i) {
+        const StripProblem &q = probs[i];
+        Problem &P = tab[i];
+        P.qc = q.qc;
+        P.tc = q.tc;
+        P.border = q.border;
+        P.n = (int32_t)q.n;
+        P.m = (int32_t)q.m;
+        P.nstrips = (int32_t)((q.n + 64 * R - 1) / (64 * R));
+        P.nblocks = (int32_t)sweep_blocks(q.m);
+        P.strip0 = (int32_t)total_strips;
+        P.flags = (int32_t *)(intptr_t)total_flags;   // offset, fixed up below
+        P.pad_ = 0;
+        total_strips += P.nstrips;
+        total_flags += P.nblocks + 3;
+        if (np > 1)
+            for (int k = 0; k < P.nstrips; ++k) sp.push_back(i);
+    }
+    if (total_strips >= INT32_MAX) return fail(ctx, SWH_E_RANGE, "too many strips in one launch");
+    swh_status s;
+    if ((s = ensure(ctx, ctx->flags, (size_t)total_flags * 4, "chunk counters")) != SWH_OK) return s;
+    if ((s = ensure(ctx, ctx->strip_best, (size_t)total_strips * sizeof(BestCell), "strip results")) != SWH_OK)
+        return s;
+    if ((s = ensure(ctx, ctx->probs, (size_t)np * sizeof(Problem), "problem table")) != SWH_OK) return s;
+    if (np > 1 && (s = ensure(ctx, ctx->strip_prob, sp.size() * 4, "strip table")) != SWH_OK) return s;
+    if (local && (s = ensure(ctx, ctx->prob_best, (size_t)np * sizeof(BestCell), "problem results")) != SWH_OK)
+        return s;
+    if ((s = ensure(ctx, ctx->sync, 64, "ticket")) != SWH_OK) return s;
+    for (int i = 0; i < np; ++i)
+        tab[i].flags = (int32_t *)ctx->flags.p + (intptr_t)tab[i].flags;
+
+    hipError_t e;
+    if ((e = hipMemsetAsync(ctx->flags.p, 0, (size_t)total_flags * 4, st)) != hipSuccess ||
+        (e = hipMemsetAsync(ctx->sync.p, 0, 8, st)) != hipSuccess)
+        return hip_fail(ctx, e, "hipMemsetAsync(counters)");
+    if ((e = hipMemcpyAsync(ctx->probs.p, tab.data(), (size_t)np * sizeof(Problem), hipMemcpyHostToDevice, st)) !=
+            hipSuccess ||
+        (np > 1 &&
+         (e = hipMemcpyAsync(ctx->strip_prob.p, sp.data(), sp.size() * 4, hipMemcpyHostToDevice, st)) != hipSuccess))
+        return hip_fail(ctx, e, "hipMemcpyAsync(problem table)");
+
+    StripArgs a;
+    a.probs = (const Problem *)ctx->probs.p;
+    a.strip_prob = np > 1 ? (const int32_t *)ctx->strip_prob.p : nullptr;
+    a.total_strips = (int32_t)total_strips;
+    a.mat = (const int8_t *)ctx->mat.p;
+    a.asize = sc.asize;
+    a.o = sc.o;
+    a.e = sc.e;
+    a.ticket = (int32_t *)ctx->sync.p;
+    a.abort_flag = (int32_t *)ctx->sync.p + 1;
+    a.strip_best = (BestCell *)ctx->strip_best.p;
+    a.wait_ticks = wait_ticks(ctx->device);
+    const int grid = strip_grid(total_strips, R, strip_grid_limit(ctx->device, R, local, sc.asize), ctx->num_cu);
+
+    hipEventRecord(ctx->ev[0], st);
+    if ((e = launch_strip(a, R, local, grid, st)) != hipSuccess) return hip_fail(ctx, e, "strip kernel launch");
+    hipEventRecord(ctx->ev[1], st);
+    if (local && (e = launch_reduce_best_multi(a.strip_best, a.probs, np, (BestCell *)ctx->prob_best.p, st)) !=
+                     hipSuccess)
+        return hip_fail(ctx, e, "reduce kernel launch");
+    int32_t flags_host[2] = {0, 0};
+    if ((e = hipMemcpyAsync(flags_host, ctx->sync.p, 8, hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return hip_fail(ctx, e, "hipMemcpyAsync(abort flag)");
+    if (local && best) {
+        best->resize(np);
+        if ((e = hipMemcpyAsync(best->data(), ctx->prob_best.p, (size_t)np * sizeof(BestCell), hipMemcpyDeviceToHost,
+                                st)) != hipSuccess)
+            return hip_fail(ctx, e, "hipMemcpyAsync(results)");
+    }
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(ctx, e, "strip pass");
+    if (ms) hipEventElapsedTime(ms, ctx->ev[0], ctx->ev[1]);
+    if (flags_host[1]) return fail(ctx, SWH_E_TIMEOUT, "strip wavefront wait expired");
+    return SWH_OK;
+}
+
+}  // namespace swh

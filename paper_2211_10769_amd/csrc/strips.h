@@ -1,0 +1,36 @@
+// strips.h -- run the strip-wavefront kernel over a table of DP problems.
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "context.h"
+#include "engine.h"
+
+namespace swh {
+
+// One problem as the caller sees it.  qc holds rows_padded(n, R) codes and tc
+// cols_padded(m) codes (pad code beyond the real ones).  border holds
+// cols_padded(m) entries: the caller fills the top row (zeros for a local
+// pass) and finds the last row there afterwards.
+struct StripProblem {
+    const uint8_t *qc;
+    int64_t n;
+    const uint8_t *tc;
+    int64_t m;
+    Border *border;
+};
+
+inline int64_t rows_padded(int64_t n, int R) { return ((n + 64 * R - 1) / (64 * R)) * 64 * R; }
+inline int64_t cols_padded(int64_t m) { return 64 * (sweep_blocks(m) + 3); }
+
+int env_int(const char *name, int dflt);
+int pick_rows_per_lane(int64_t n);
+int strip_grid(int64_t nstrips, int R, int limit, int num_cu);
+
+// One launch over all problems; local mode fills best (one entry per problem).
+swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, const Scoring &sc, int R, bool local,
+                      hipStream_t st, std::vector<BestCell> *best, float *ms);
+
+}  // namespace swh

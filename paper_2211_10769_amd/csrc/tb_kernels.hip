@@ -1,0 +1,262 @@
+// tb_kernels.hip -- kernels of the reconstruction phase (the paper's SW#
+// "reconstruction": the optimal path, found with space-efficient methods).
+//
+// The traceback is a frontier-seeded divide and conquer over the aligned
+// rectangle (global Gotoh DP, no zero clamp).  A split runs a forward pass
+// from the subproblem's top frontier to the mid row and a backward pass from
+// its end node up to the row below (both on the strip kernel in global mode),
+// then the crossing scan below finds the frontier columns an optimal path can
+// cross at.  Leaves run the full DP with per-cell tie flags and walk back.
+#include <hip/hip_runtime.h>
+
+#include "tb_kernels.h"
+
+namespace swh {
+
+namespace {
+
+constexpr int kDppWaveShr1 = 0x138;   // lane i reads lane i-1 (lane 0: keeps old)
+
+__device__ __forceinline__ int shr1(int old, int src)
+{
+    return __builtin_amdgcn_update_dpp(old, src, kDppWaveShr1, 0xF, 0xF, false);
+}
+
+__global__ void gather_kernel(const GatherDesc *descs, uint8_t pad)
+{
+    const GatherDesc d = descs[blockIdx.x];
+    for (int64_t i = threadIdx.x; i < d.padded; i += blockDim.x) {
+        uint8_t v = pad;
+        const int64_t k = i - d.first_pad;
+        if (k >= 0 && k < d.count) v = d.src[d.start + (int64_t)d.step * k];
+        d.dst[i] = v;
+    }
+}
+
+__global__ void border_init_kernel(const BorderInit *descs, int32_t o, int32_t e)
+{
+    const BorderInit d = descs[blockIdx.x];
+    for (int64_t c = threadIdx.x; c < d.padded; c += blockDim.x) {
+        Border v{kNeg, kNeg};
+        if (c < d.count) {
+            if (d.kind == 0) {
+                v = d.src[c];
+            } else if (d.kind == 1) {
+                const int32_t g = c == 0 ? 0 : (int32_t)(-(int64_t)o - (c - 1) * (int64_t)e);
+                v = Border{g, g - o};
+            } else {
+                v = Border{kNeg, c == 0 ? -o : kNeg};
+            }
+        }
+        d.dst[c] = v;
+    }
+}
+
+__global__ void root_front_kernel(Border *dst, int64_t q, int32_t o, int32_t e)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j <= q; j += stride) {
+        const int32_t g = j == 0 ? 0 : (int32_t)(-(int64_t)o - (j - 1) * (int64_t)e);
+        dst[j] = Border{g, g - o};
+    }
+}
+
+// A path from the frontier to the end crosses from mid row r into row r+1
+// through exactly one edge: vertical into F(r+1, j) (forward value D(j),
+// backward value from F(r+1, j) = D'+o) or diagonal G(r, j-1) -> G(r+1, j).
+// The edge is on an optimal path iff forward + edge + backward == V.
+__global__ void __launch_bounds__(256) cross_kernel(const CrossDesc *descs, const int8_t *mat, int32_t asize,
+                                                    int32_t o, int32_t e, CrossOut *outs)
+{
+    __shared__ int32_t s_cmin, s_count, s_key;
+    const CrossDesc d = descs[blockIdx.x];
+    if (threadIdx.x == 0) {
+        s_cmin = INT32_MAX;
+        s_count = 0;
+        s_key = INT32_MAX;
+    }
+    __syncthreads();
+    const int64_t w = d.J - d.L + 1;
+    int cmin = INT32_MAX, count = 0, key = INT32_MAX;
+    for (int64_t k = threadIdx.x; k < w; k += blockDim.x) {
+        const int64_t j = d.L + k;
+        const Border fw = d.fwd[k];
+        const Border bw = d.bwd[w - 1 - k];
+        if ((int64_t)fw.f + bw.f + o == d.V) {
+            cmin = min(cmin, (int)j);
+            ++count;
+            key = min(key, (int)(j << 1) | 1);
+        }
+        if (k >= 1 && j >= 1) {
+            const int s = mat[d.arow * asize + d.bpad[j]];
+            if ((int64_t)d.fwd[k - 1].h + s + bw.h == d.V) {
+                cmin = min(cmin, (int)(j - 1));
+                ++count;
+                key = min(key, (int)(j << 1));
+            }
+        }
+    }
+    if (count) {
+        atomicMin(&s_cmin, cmin);
+        atomicAdd(&s_count, count);
+        atomicMin(&s_key, key);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        CrossOut r;
+        r.cmin = s_count ? s_cmin : -1;
+        r.count = s_count;
+        r.key = s_key;
+        r.exit_col = -1;
+        r.exit_state = 0;
+        r.exit_val = 0;
+        r.pad_[0] = r.pad_[1] = 0;
+        if (s_count == 1) {
+            const int64_t j = s_key >> 1;
+            if (s_key & 1) {
+                // vertical edge: the walk leaves F(r+1, j) upwards and closes the
+                // gap at G(r, j) when that is optimal, else extends into F(r, j)
+                const Border fw = d.fwd[j - d.L];
+                const bool close = fw.h - o == fw.f;
+                r.exit_col = (int32_t)j;
+                r.exit_state = close ? 0 : 1;
+                r.exit_val = close ? fw.h : fw.f + e;
+            } else {
+                r.exit_col = (int32_t)(j - 1);
+                r.exit_state = 0;
+                r.exit_val = d.fwd[j - 1 - d.L].h;
+            }
+        }
+        outs[blockIdx.x] = r;
+    }
+}
+
+// One wave per leaf.  Rows are processed 64 at a time, lane = row, with a
+// one-column skew per lane; H and the F handed down pass between lanes by a
+// DPP shift, and between row groups through a row buffer in LDS.  Each cell
+// stores its tie flags:
+//   bit 0  H == H(i-1,j-1) + s   bit 1  H == F
+//   bit 2  F == H(i-1,j) - o     bit 3  E == H(i,j-1) - o
+// Lane 0 then walks back from the end: at H prefer the diagonal, then F,
+// then E; inside a gap prefer closing it.
+__global__ void __launch_bounds__(64) leaf_kernel(const LeafDesc *descs, const int8_t *mat, int32_t asize, int32_t o,
+                                                  int32_t e, LeafOut *outs)
+{
+    extern __shared__ uint8_t lds[];
+    const LeafDesc d = descs[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int P = d.P, w = d.w;
+    int8_t *smat = reinterpret_cast<int8_t *>(lds);                 // 1024 bytes
+    Border *row = reinterpret_cast<Border *>(lds + 1024);           // w entries
+    uint8_t *fl = d.gflags ? d.gflags : lds + 1024 + (size_t)8 * w;
+
+    for (int k = lane; k < asize * asize; k += 64) smat[k] = mat[k];
+    for (int k = lane; k < w; k += 64) row[k] = d.front[k];
+    __syncthreads();
+
+    const int nstr = (P + 63) / 64;
+    for (int st = 0; st < nstr; ++st) {
+        const int i = st * 64 + lane + 1;          // 1-based leaf row
+        const bool real = i <= P;
+        const int qcode = real ? d.arows[i - 1] : 0;
+        int hprev = kNeg, E = kNeg, hup_prev = kNeg, hbot = kNeg, fbot = kNeg;
+        for (int t = 0; t < w + 63; ++t) {
+            const int c = t - lane;
+            const Border in = t < w ? row[t] : Border{kNeg, kNeg};
+            const int hup = shr1(in.h, hbot);
+            const int fin = shr1(in.f, fbot);
+            const bool valid = real && c >= 0 && c < w;
+            int h = kNeg, fdown = kNeg, En = kNeg;
+            if (valid) {
+                const int code = d.bcols[c];
+                const int s = code >= asize ? kNeg : (int)smat[qcode * asize + code];
+                const int dg = c == 0 ? kNeg : hup_prev;
+                const int t1 = dg + s;
+                h = max(t1, max(E, fin));
+                const int flag = (h == t1 ? 1 : 0) | (h == fin ? 2 : 0) | (fin == hup - o ? 4 : 0) |
+                                 (E == hprev - o ? 8 : 0);
+                fl[(int64_t)(i - 1) * w + c] = (uint8_t)flag;
+                fdown = max(fin - e, h - o);
+                En = max(E - e, h - o);
+            }
+            hbot = h;
+            fbot = fdown;
+            hprev = h;
+            E = En;
+            hup_prev = hup;
+            if (lane == 63 && valid) row[c] = Border{h, fdown};
+        }
+        __syncthreads();
+    }
+
+    if (lane == 0) {
+        int i = P, c = w - 1, state = d.end_state, n = 0, err = 0;
+        while (i > 0) {
+            if (c < 0 || n >= d.ops_cap) { err = 1; break; }
+            const int f = fl[(int64_t)(i - 1) * w + c];
+            if (state == 0) {
+                if (f & 1) { d.ops[n++] = 'M'; --i; --c; }
+                else state = (f & 2) ? 1 : 2;
+            } else if (state == 1) {
+                d.ops[n++] = 'I';
+                if (f & 4) state = 0;
+                --i;
+            } else {
+                d.ops[n++] = 'D';
+                if (f & 8) state = 0;
+                --c;
+            }
+        }
+        if (c < 0 || state == 2) err = err ? err : 2;
+        LeafOut r;
+        r.nops = n;
+        r.exit_col = c;
+        r.exit_state = state;
+        r.exit_val = (!err && c >= 0) ? (state == 0 ? d.front[c].h : d.front[c].f + e) : 0;
+        r.err = err;
+        r.pad_[0] = r.pad_[1] = r.pad_[2] = 0;
+        outs[blockIdx.x] = r;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_gather(const GatherDesc *d, int32_t nd, uint8_t pad, hipStream_t st)
+{
+    if (nd <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_kernel, dim3(nd), dim3(256), 0, st, d, pad);
+    return hipGetLastError();
+}
+
+hipError_t launch_border_init(const BorderInit *d, int32_t nd, int32_t o, int32_t e, hipStream_t st)
+{
+    if (nd <= 0) return hipSuccess;
+    hipLaunchKernelGGL(border_init_kernel, dim3(nd), dim3(256), 0, st, d, o, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_root_front(Border *dst, int64_t q, int32_t o, int32_t e, hipStream_t st)
+{
+    int64_t g = (q + 1 + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(root_front_kernel, dim3((unsigned)g), dim3(256), 0, st, dst, q, o, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_cross(const CrossDesc *d, int32_t nd, const int8_t *mat, int32_t asize, int32_t o, int32_t e,
+                        CrossOut *out, hipStream_t st)
+{
+    if (nd <= 0) return hipSuccess;
+    hipLaunchKernelGGL(cross_kernel, dim3(nd), dim3(256), 0, st, d, mat, asize, o, e, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_leaf(const LeafDesc *d, int32_t nd, const int8_t *mat, int32_t asize, int32_t o, int32_t e,
+                       size_t lds_bytes, LeafOut *out, hipStream_t st)
+{
+    if (nd <= 0) return hipSuccess;
+    hipLaunchKernelGGL(leaf_kernel, dim3(nd), dim3(64), lds_bytes, st, d, mat, asize, o, e, out);
+    return hipGetLastError();
+}
+
+}  // namespace swh

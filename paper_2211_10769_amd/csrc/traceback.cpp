@@ -1,12 +1,438 @@
-// traceback.cpp -- placeholder until the linear-space traceback lands.
+// traceback.cpp -- the reconstruction phase: canonical CIGAR of the aligned
+// rectangle in linear space.
+//
+// Definition reproduced (the full-matrix greedy walk): global Gotoh DP over
+// A[1..p] x B[1..q] (G = H without zero clamp), walked back from (p, q) in
+// state H preferring the diagonal, then F ('I'), then E ('D'), and inside a
+// gap preferring to close it.  That walk only ever compares forward values
+// of a node and its predecessors.
+//
+// Frontier-seeded divide and conquer, bottom half first.  A subproblem is
+// rows (r_top, r_bot], columns [L, J], the true forward values on row r_top
+// (H and the F it hands down) for those columns, and an end node (r_bot, J)
+// in state H or F with its forward value V.  A split at mid row r:
+//   * forward pass from the frontier to row r (strip kernel, global mode);
+//   * backward pass from the end node up to row r+1 (the same kernel on the
+//     reversed rows and columns; its values are the backward values);
+//   * crossing scan: edges from row r into row r+1 with fwd + edge + bwd = V;
+//     cmin = the leftmost frontier column such an edge uses.
+// Bottom child: rows (r, r_bot], columns [cmin, J], frontier = the forward
+// pass output there, same end.  Every node on an optimal path has a best
+// path that crosses inside the crossing set, so the restricted DP gives the
+// true forward value at every node the walk can visit, and non-optimal
+// predecessors stay non-optimal: the walk is identical to the full-matrix
+// one.  Top child: rows (r_top, r], columns [L, j*], the parent's frontier,
+// ending at the node (r, j*) where the bottom child's walk leaves row r+1.
+// When the crossing edge is unique that node is known at once and both
+// halves are ready together; otherwise the top half waits for the walk.
+//
+// Subproblems are processed level by level: all ready splits in one batch of
+// launches, all ready leaves in another, so the many small subproblems of
+// the deep levels run side by side across the GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "context.h"
+#include "strips.h"
+#include "tb_kernels.h"
 #include "traceback.h"
 
 namespace swh {
 
-swh_status traceback(swh_ctx *ctx, const uint8_t *, int64_t, const uint8_t *, int64_t, const Scoring &, int32_t,
-                     hipStream_t, std::string &, TracebackStats &)
+namespace {
+
+// Leaf budget inside the 64 KB of LDS one workgroup may take: 1 KB matrix,
+// an 8-byte row buffer entry per column, one byte of tie flags per cell.
+constexpr int64_t kLeafCells = 28672;
+constexpr int64_t kLeafMaxWidth = 4096;
+constexpr size_t kArenaChunk = (size_t)256 << 20;
+
+// Device memory that never moves once handed out (pointers into it are kept
+// across levels).
+struct Arena {
+    std::vector<void *> chunks;
+    std::vector<size_t> caps;
+    size_t used = 0;   // in the last chunk
+    ~Arena()
+    {
+        for (void *p : chunks) hipFree(p);
+    }
+    void *get(size_t bytes)
+    {
+        bytes = (bytes + 255) & ~(size_t)255;
+        if (chunks.empty() || used + bytes > caps.back()) {
+            size_t cap = std::max(kArenaChunk, bytes);
+            void *p = nullptr;
+            if (hipMalloc(&p, cap) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+            chunks.push_back(p);
+            caps.push_back(cap);
+            used = 0;
+        }
+        void *r = (char *)chunks.back() + used;
+        used += bytes;
+        return r;
+    }
+};
+
+struct Node {
+    int64_t r_top, r_bot, L, J;
+    const Border *front;      // front[k] <-> column front_L + k, covers [L, J]
+    int64_t front_L;
+    int end_state;            // 0 = H, 1 = F
+    int32_t V;
+    int bottom = -1, top = -1, parent = -1;
+    bool is_top_child = false;
+    bool ready = false, leaf = false;
+    bool exit_known = false;
+    int64_t exit_col = -1;
+    int exit_state = 0;
+    int32_t exit_val = 0;
+    int64_t ops_off = 0, nops = 0;   // leaf ops (backward) in the host op buffer
+};
+
+template <typename T>
+swh_status upload(swh_ctx *ctx, DevBuf &buf, const std::vector<T> &v, hipStream_t st, const char *what)
 {
-    return fail(ctx, SWH_E_INVAL, "CIGAR mode is not available yet");
+    swh_status s = ensure(ctx, buf, v.size() * sizeof(T) + 16, what);
+    if (s != SWH_OK) return s;
+    hipError_t e = hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, what);
+    return SWH_OK;
+}
+
+}  // namespace
+
+swh_status traceback(swh_ctx *ctx, const uint8_t *A, int64_t p, const uint8_t *B, int64_t q, const Scoring &sc,
+                     int32_t S, hipStream_t st, std::string &cigar, TracebackStats &ts)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const uint8_t pad = (uint8_t)sc.asize;
+    Arena arena;
+    hipError_t e;
+    swh_status s;
+
+    // B with the pad code in front: bpad[j] = code of B_j, bpad[0] = pad
+    uint8_t *bpad = (uint8_t *)arena.get((size_t)q + 2);
+    Border *root_front = (Border *)arena.get(sizeof(Border) * (size_t)(q + 1));
+    if (!bpad || !root_front) return fail(ctx, SWH_E_NOMEM, "traceback arena");
+    if ((e = hipMemsetAsync(bpad, pad, 1, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(bpad + 1, B, (size_t)q, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+        (e = launch_root_front(root_front, q, sc.o, sc.e, st)) != hipSuccess)
+        return hip_fail(ctx, e, "traceback setup");
+
+    std::vector<Node> nodes;
+    {
+        Node root;
+        root.r_top = 0;
+        root.r_bot = p;
+        root.L = 0;
+        root.J = q;
+        root.front = root_front;
+        root.front_L = 0;
+        root.end_state = 0;
+        root.V = S;
+        root.ready = true;
+        nodes.push_back(root);
+    }
+    std::vector<char> ops_host;
+    std::vector<int> ready{0};
+    // SWH_TB_LEAF lowers the leaf size (tests use it to force deep recursion on small inputs)
+    const int64_t leaf_cells = std::max<int64_t>(1, std::min<int64_t>(kLeafCells, env_int("SWH_TB_LEAF", (int)kLeafCells)));
+
+    // exit of node k is known: tell its parent chain and release a waiting top sibling
+    auto propagate = [&](int k) {
+        while (k >= 0) {
+            Node &n = nodes[k];
+            const int par = n.parent;
+            if (par < 0) break;
+            Node &pn = nodes[par];
+            if (!n.is_top_child) {
+                Node &tp = nodes[pn.top];
+                if (!tp.ready && !tp.exit_known && tp.J < 0) {
+                    tp.J = n.exit_col;
+                    tp.end_state = n.exit_state;
+                    tp.V = n.exit_val;
+                    tp.ready = true;
+                    ready.push_back(pn.top);
+                }
+                break;
+            }
+            // top child: its exit is its parent's exit
+            pn.exit_known = true;
+            pn.exit_col = n.exit_col;
+            pn.exit_state = n.exit_state;
+            pn.exit_val = n.exit_val;
+            k = par;
+        }
+    };
+
+    while (!ready.empty()) {
+        std::vector<int> cur;
+        cur.swap(ready);
+        std::vector<int> leaves, splits;
+        for (int k : cur) {
+            const Node &n = nodes[k];
+            const int64_t rows = n.r_bot - n.r_top, w = n.J - n.L + 1;
+            if (rows <= 1 || (rows * w <= leaf_cells && w <= kLeafMaxWidth))
+                leaves.push_back(k);
+            else
+                splits.push_back(k);
+        }
+
+        // ---------------------------------------------------------------- splits
+        if (!splits.empty()) {
+            const int ns = (int)splits.size();
+            int64_t maxrows = 1;
+            for (int k : splits) maxrows = std::max(maxrows, nodes[k].r_bot - nodes[k].r_top);
+            const int R = pick_rows_per_lane(maxrows / 2);
+            std::vector<GatherDesc> gd;
+            std::vector<BorderInit> bi;
+            std::vector<StripProblem> fwdp, bwdp;
+            std::vector<Border *> fwd_out(ns), bwd_out(ns);
+            std::vector<int64_t> mid(ns);
+            // sizes: codes scratch (temporary) and borders
+            int64_t codes_bytes = 0, bwd_entries = 0;
+            for (int i = 0; i < ns; ++i) {
+                const Node &n = nodes[splits[i]];
+                const int64_t w = n.J - n.L + 1;
+                mid[i] = (n.r_top + n.r_bot) / 2;
+                const int64_t P = mid[i] - n.r_top, Pb = n.r_bot - mid[i] - 1;
+                codes_bytes += rows_padded(P, R) + rows_padded(std::max<int64_t>(Pb, 1), R) + 2 * cols_padded(w);
+                bwd_entries += cols_padded(w);
+            }
+            if ((s = ensure(ctx, ctx->tb_codes_q, (size_t)codes_bytes + 256, "traceback codes")) != SWH_OK) return s;
+            if ((s = ensure(ctx, ctx->tb_bwd, (size_t)bwd_entries * sizeof(Border) + 256, "backward borders")) !=
+                SWH_OK)
+                return s;
+            uint8_t *cp = (uint8_t *)ctx->tb_codes_q.p;
+            Border *bp = (Border *)ctx->tb_bwd.p;
+            for (int i = 0; i < ns; ++i) {
+                const Node &n = nodes[splits[i]];
+                const int64_t w = n.J - n.L + 1, r = mid[i];
+                const int64_t P = r - n.r_top, Pb = n.r_bot - r - 1;
+                // forward pass rows A_{r_top+1}..A_r, columns L..J
+                uint8_t *fq = cp; cp += rows_padded(P, R);
+                uint8_t *ft = cp; cp += cols_padded(w);
+                uint8_t *bq = cp; cp += rows_padded(std::max<int64_t>(Pb, 1), R);
+                uint8_t *bt = cp; cp += cols_padded(w);
+                gd.push_back(GatherDesc{A, fq, n.r_top, P, rows_padded(P, R), 1, 0});
+                gd.push_back(GatherDesc{bpad, ft, n.L, w, cols_padded(w), 1, 0});
+                // backward pass rows A_{r_bot}..A_{r+2}, columns J..L reversed, pad first
+                gd.push_back(GatherDesc{A, bq, n.r_bot - 1, Pb, rows_padded(std::max<int64_t>(Pb, 1), R), -1, 0});
+                gd.push_back(GatherDesc{bpad, bt, n.J, w - 1, cols_padded(w), -1, 1});
+                Border *fo = (Border *)arena.get(sizeof(Border) * (size_t)cols_padded(w));
+                if (!fo) return fail(ctx, SWH_E_NOMEM, "traceback frontier arena");
+                fwd_out[i] = fo;
+                bwd_out[i] = bp;
+                bi.push_back(BorderInit{fo, n.front + (n.L - n.front_L), w, cols_padded(w), 0, 0});
+                bi.push_back(BorderInit{bp, nullptr, w, cols_padded(w), n.end_state == 0 ? 1 : 2, 0});
+                bp += cols_padded(w);
+                fwdp.push_back(StripProblem{fq, P, ft, w, fo});
+                if (Pb > 0) bwdp.push_back(StripProblem{bq, Pb, bt, w, bwd_out[i]});
+                ts.cells += (double)(P + std::max<int64_t>(Pb, 0)) * (double)w;
+            }
+            if ((s = upload(ctx, ctx->tb_misc, gd, st, "gather table")) != SWH_OK) return s;
+            if ((e = launch_gather((const GatherDesc *)ctx->tb_misc.p, (int32_t)gd.size(), pad, st)) != hipSuccess)
+                return hip_fail(ctx, e, "gather launch");
+            if ((s = upload(ctx, ctx->tb_leaf, bi, st, "border table")) != SWH_OK) return s;
+            if ((e = launch_border_init((const BorderInit *)ctx->tb_leaf.p, (int32_t)bi.size(), sc.o, sc.e, st)) !=
+                hipSuccess)
+                return hip_fail(ctx, e, "border init launch");
+            if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(ctx, e, "traceback setup");
+            if ((s = run_strips(ctx, fwdp, sc, R, false, st, nullptr, nullptr)) != SWH_OK) return s;
+            if (!bwdp.empty() && (s = run_strips(ctx, bwdp, sc, R, false, st, nullptr, nullptr)) != SWH_OK) return s;
+
+            std::vector<CrossDesc> cd(ns);
+            std::vector<uint8_t> arow(ns);
+            for (int i = 0; i < ns; ++i) {
+                const Node &n = nodes[splits[i]];
+                cd[i] = CrossDesc{fwd_out[i], bwd_out[i], bpad, n.L, n.J, 0, n.V};
+            }
+            // A_{r+1} codes: read back the few bytes we need
+            for (int i = 0; i < ns; ++i)
+                if ((e = hipMemcpyAsync(&arow[i], A + mid[i], 1, hipMemcpyDeviceToHost, st)) != hipSuccess)
+                    return hip_fail(ctx, e, "row code");
+            if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(ctx, e, "row code");
+            for (int i = 0; i < ns; ++i) cd[i].arow = arow[i];
+            if ((s = upload(ctx, ctx->tb_misc, cd, st, "cross table")) != SWH_OK) return s;
+            if ((s = ensure(ctx, ctx->tb_front, sizeof(CrossOut) * (size_t)ns, "cross results")) != SWH_OK) return s;
+            if ((e = launch_cross((const CrossDesc *)ctx->tb_misc.p, ns, (const int8_t *)ctx->mat.p, sc.asize, sc.o,
+                                  sc.e, (CrossOut *)ctx->tb_front.p, st)) != hipSuccess)
+                return hip_fail(ctx, e, "cross launch");
+            std::vector<CrossOut> co(ns);
+            if ((e = hipMemcpyAsync(co.data(), ctx->tb_front.p, sizeof(CrossOut) * ns, hipMemcpyDeviceToHost, st)) !=
+                    hipSuccess ||
+                (e = hipStreamSynchronize(st)) != hipSuccess)
+                return hip_fail(ctx, e, "cross results");
+
+            for (int i = 0; i < ns; ++i) {
+                const int k = splits[i];
+                if (co[i].count <= 0 || co[i].cmin < nodes[k].L)
+                    return fail(ctx, SWH_E_DEVICE, "traceback: no optimal crossing found (internal error)");
+                Node bot;
+                bot.r_top = mid[i];
+                bot.r_bot = nodes[k].r_bot;
+                bot.L = co[i].cmin;
+                bot.J = nodes[k].J;
+                bot.front = fwd_out[i];
+                bot.front_L = nodes[k].L;
+                bot.end_state = nodes[k].end_state;
+                bot.V = nodes[k].V;
+                bot.parent = k;
+                bot.is_top_child = false;
+                bot.ready = true;
+                Node top;
+                top.r_top = nodes[k].r_top;
+                top.r_bot = mid[i];
+                top.L = nodes[k].L;
+                top.J = -1;
+                top.front = nodes[k].front;
+                top.front_L = nodes[k].front_L;
+                top.parent = k;
+                top.is_top_child = true;
+                if (co[i].count == 1) {
+                    top.J = co[i].exit_col;
+                    top.end_state = co[i].exit_state;
+                    top.V = co[i].exit_val;
+                    top.ready = true;
+                }
+                nodes.push_back(bot);
+                nodes[k].bottom = (int)nodes.size() - 1;
+                ready.push_back(nodes[k].bottom);
+                nodes.push_back(top);
+                nodes[k].top = (int)nodes.size() - 1;
+                if (nodes.back().ready) ready.push_back(nodes[k].top);
+                ++ts.splits;
+            }
+        }
+
+        // ---------------------------------------------------------------- leaves
+        if (!leaves.empty()) {
+            const int nl = (int)leaves.size();
+            std::vector<LeafDesc> ld(nl);
+            int64_t ops_total = 0, gflag_bytes = 0;
+            size_t lds = 1024;
+            for (int i = 0; i < nl; ++i) {
+                const Node &n = nodes[leaves[i]];
+                const int64_t P = n.r_bot - n.r_top, w = n.J - n.L + 1;
+                if (w > kLeafMaxWidth)
+                    return fail(ctx, SWH_E_RANGE, "traceback: gap wider than " + std::to_string(kLeafMaxWidth) +
+                                                      " columns in a subproblem of one row");
+                ops_total += P + w + 1;
+                const bool in_lds = P * w <= kLeafCells;
+                if (!in_lds) gflag_bytes += P * w + 256;
+                lds = std::max(lds, (size_t)(1024 + 8 * w + (in_lds ? P * w : 0)));
+            }
+            if ((s = ensure(ctx, ctx->tb_fwd, (size_t)ops_total + 256, "traceback ops")) != SWH_OK) return s;
+            uint8_t *gfl = nullptr;
+            if (gflag_bytes && !(gfl = (uint8_t *)arena.get((size_t)gflag_bytes)))
+                return fail(ctx, SWH_E_NOMEM, "traceback flag scratch");
+            char *op = (char *)ctx->tb_fwd.p;
+            std::vector<int64_t> op_off(nl);
+            int64_t off = 0;
+            for (int i = 0; i < nl; ++i) {
+                const Node &n = nodes[leaves[i]];
+                const int64_t P = n.r_bot - n.r_top, w = n.J - n.L + 1;
+                LeafDesc d;
+                d.arows = A + n.r_top;
+                d.bcols = bpad + n.L;
+                d.front = n.front + (n.L - n.front_L);
+                d.gflags = nullptr;
+                if (P * w > kLeafCells) {
+                    d.gflags = gfl;
+                    gfl += ((P * w + 255) / 256) * 256;
+                }
+                d.ops = op + off;
+                d.P = (int32_t)P;
+                d.w = (int32_t)w;
+                d.end_state = n.end_state;
+                d.ops_cap = (int32_t)(P + w + 1);
+                op_off[i] = off;
+                off += P + w + 1;
+                ld[i] = d;
+                ts.cells += (double)P * (double)w;
+            }
+            if ((s = upload(ctx, ctx->tb_misc, ld, st, "leaf table")) != SWH_OK) return s;
+            if ((s = ensure(ctx, ctx->tb_front, sizeof(LeafOut) * (size_t)nl, "leaf results")) != SWH_OK) return s;
+            if ((e = launch_leaf((const LeafDesc *)ctx->tb_misc.p, nl, (const int8_t *)ctx->mat.p, sc.asize, sc.o,
+                                 sc.e, lds, (LeafOut *)ctx->tb_front.p, st)) != hipSuccess)
+                return hip_fail(ctx, e, "leaf launch");
+            std::vector<LeafOut> lo(nl);
+            const size_t base = ops_host.size();
+            ops_host.resize(base + (size_t)ops_total);
+            if ((e = hipMemcpyAsync(lo.data(), ctx->tb_front.p, sizeof(LeafOut) * nl, hipMemcpyDeviceToHost, st)) !=
+                    hipSuccess ||
+                (e = hipMemcpyAsync(ops_host.data() + base, op, (size_t)ops_total, hipMemcpyDeviceToHost, st)) !=
+                    hipSuccess ||
+                (e = hipStreamSynchronize(st)) != hipSuccess)
+                return hip_fail(ctx, e, "leaf results");
+            for (int i = 0; i < nl; ++i) {
+                Node &n = nodes[leaves[i]];
+                if (lo[i].err) return fail(ctx, SWH_E_DEVICE, "traceback walk left its subproblem (internal error)");
+                n.leaf = true;
+                n.ops_off = (int64_t)base + op_off[i];
+                n.nops = lo[i].nops;
+                n.exit_known = true;
+                n.exit_col = n.L + lo[i].exit_col;
+                n.exit_state = lo[i].exit_state;
+                n.exit_val = lo[i].exit_val;
+                ++ts.leaves;
+            }
+            for (int i = 0; i < nl; ++i) propagate(leaves[i]);
+        }
+    }
+
+    // every node must be resolved; assemble the ops, walking back from the end
+    for (const Node &n : nodes)
+        if (!n.leaf && (n.bottom < 0 || n.top < 0 || !nodes[n.top].ready))
+            return fail(ctx, SWH_E_DEVICE, "traceback left a subproblem unresolved (internal error)");
+    std::string back;
+    back.reserve((size_t)(p + q));
+    std::vector<int> stack{0};
+    while (!stack.empty()) {
+        const int k = stack.back();
+        stack.pop_back();
+        const Node &n = nodes[k];
+        if (n.leaf) {
+            back.append(ops_host.data() + n.ops_off, (size_t)n.nops);
+        } else {
+            stack.push_back(n.top);      // processed after the bottom half
+            stack.push_back(n.bottom);
+        }
+    }
+    const Node &root = nodes[0];
+    int64_t rexit = root.leaf ? root.exit_col : -1;
+    if (!root.leaf) {
+        int k = 0;
+        while (!nodes[k].leaf) k = nodes[k].top;
+        rexit = nodes[k].exit_col;
+    }
+    if (rexit < 0) return fail(ctx, SWH_E_DEVICE, "traceback: no exit on row 0 (internal error)");
+    back.append((size_t)rexit, 'D');     // leading target residues against a gap, back to (0, 0)
+
+    // run-length encode in forward order
+    cigar.clear();
+    int64_t k = (int64_t)back.size() - 1;
+    while (k >= 0) {
+        const char opc = back[(size_t)k];
+        int64_t run = 0;
+        while (k >= 0 && back[(size_t)k] == opc) {
+            ++run;
+            --k;
+        }
+        cigar += std::to_string(run);
+        cigar += opc;
+    }
+    ts.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return SWH_OK;
 }
 
 }  // namespace swh

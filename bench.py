@@ -42,10 +42,13 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--n", type=int, default=5_000_000, help="query length of the long pair")
     p.add_argument("--flank", type=int, default=50_000)
-    p.add_argument("--mode", default="coords", choices=["score", "coords", "cigar"])
+    p.add_argument("--mode", default="cigar", choices=["score", "coords", "cigar"])
     p.add_argument("--cpu-rows", type=int, default=500,
                    help="rows of the query used for the timed CPU-oracle sample")
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--copy-calib-mb", type=int, default=0,
+                   help="before the workload, copy a buffer of this many MiB once (a plain copy kernel of "
+                        "known size, used to scale the HBM byte counters of a profile)")
     return p.parse_args()
 
 
@@ -85,6 +88,12 @@ def main():
     torch.cuda.synchronize()
     eng = swh.Engine(0)
     stream = torch.cuda.current_stream().cuda_stream
+    if args.copy_calib_mb:
+        src = torch.empty(args.copy_calib_mb << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         eng.align_dev(qd, td, sc, mode=args.mode, stream=stream)

@@ -124,6 +124,56 @@ swh_status swh_align_dev(swh_ctx *ctx, const char *q_dev, int64_t qlen, const ch
                          swh_alignment *out, char *cigar, int64_t cigar_cap,
                          int64_t *cigar_len, swh_stats *stats);
 
+/* ------------------------------------------------------------------------
+ * Database search (paper, Background: database similarity search, many
+ * independent matrices; Experimental Work: 20 protein queries against
+ * Swiss-Prot / Env. NR with BLOSUM62, gap open 10, extend 2).
+ * ------------------------------------------------------------------------ */
+
+typedef struct swh_db swh_db;   /* encoded, length-sorted database in device memory */
+
+typedef struct {
+    int64_t db_index;   /* -1 when fewer than k sequences exist */
+    int32_t score;      /* -1 for an empty slot */
+    int32_t reserved;
+} swh_hit;
+
+typedef struct {
+    uint32_t struct_size;        /* sizeof(swh_search_stats) */
+    uint32_t reserved;
+    double   cells;              /* sum over queries of query length x database residues */
+    double   ms_inter;           /* device time of the 16-bit inter-task kernel */
+    double   ms_intra;           /* device time of the 32-bit single-pair kernel (long / saturated) */
+    double   ms_topk;            /* device time of the top-k selection */
+    int64_t  saturated;          /* pairs recomputed in 32 bits after a 16-bit saturation */
+    int64_t  intra_pairs;        /* pairs scored by the single-pair kernel */
+} swh_search_stats;
+
+/*
+ * Encode and lay out a database of ndb sequences (ASCII, concatenated in
+ * db_cat, sequence i = db_cat[db_off[i] .. db_off[i+1]), db_off has ndb+1
+ * non-decreasing entries).  The scoring is fixed for the handle.  The handle
+ * owns its device memory until swh_db_destroy.  Sequences longer than 2,048
+ * residues are scored by the single-pair kernel at search time.
+ */
+swh_status swh_db_create(swh_ctx *ctx, int64_t ndb, const char *db_cat, const int64_t *db_off,
+                         const swh_scoring *scoring, swh_db **out);
+void       swh_db_destroy(swh_db *db);
+
+/*
+ * Exhaustive local-alignment scores of nq queries (q_cat / q_off as for the
+ * database) against every database sequence, then the k best hits per query
+ * (score descending, database index ascending), hits[q * k + r].  Scores
+ * are exact 32-bit optima: pairs whose packed 16-bit values may have
+ * saturated are recomputed.  1 <= k <= 32.  stats may be NULL.
+ */
+swh_status swh_db_search(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat,
+                         const int64_t *q_off, int32_t k, swh_hit *hits, swh_search_stats *stats);
+
+/* All scores, scores[q * ndb + i] (host buffer of nq * ndb int32). */
+swh_status swh_db_scores(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat,
+                         const int64_t *q_off, int32_t *scores, swh_search_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -123,6 +123,74 @@ class Engine:
         return self._result(out, buf.value.decode() if buf is not None else None, st_obj)
 
 
+def _concat(seqs):
+    """list of sequences (or (concatenated bytes, offsets)) -> (uint8 array, int64 offsets)."""
+    if isinstance(seqs, tuple):
+        cat, off = seqs
+        cat = np.frombuffer(_bytes(cat), dtype=np.uint8) if not isinstance(cat, np.ndarray) else cat
+        return np.ascontiguousarray(cat, dtype=np.uint8), np.ascontiguousarray(off, dtype=np.int64)
+    bs = [_bytes(x) for x in seqs]
+    off = np.zeros(len(bs) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(b) for b in bs])
+    cat = np.frombuffer(b"".join(bs), dtype=np.uint8) if bs else np.zeros(0, np.uint8)
+    return np.ascontiguousarray(cat), off
+
+
+class Database:
+    """An encoded database on the device (swh_db); scoring fixed at creation."""
+
+    def __init__(self, engine: Engine, seqs, scoring):
+        self.eng = engine
+        self.sc = Scoring.of(scoring)
+        cat, off = _concat(seqs)
+        self.ndb = len(off) - 1
+        h = ctypes.c_void_p()
+        catp = cat.ctypes.data if len(cat) else None
+        st = engine.L.swh_db_create(engine.h, self.ndb, catp, off.ctypes.data, ctypes.byref(self.sc.c),
+                                    ctypes.byref(h))
+        engine._check(st)
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.eng.L.swh_db_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _stats(st):
+        return {k: getattr(st, k) for k, _ in st._fields_[2:]}
+
+    def search(self, queries, k: int = 10):
+        """Top-k hits per query: (indices int64 [nq, k], scores int32 [nq, k], stats dict)."""
+        cat, off = _concat(queries)
+        nq = len(off) - 1
+        hits = (_lib.swh_hit * max(1, nq * k))()
+        st = _lib.swh_search_stats(ctypes.sizeof(_lib.swh_search_stats))
+        rc = self.eng.L.swh_db_search(self.eng.h, self.h, nq, cat.ctypes.data if len(cat) else None,
+                                      off.ctypes.data, k, hits, ctypes.byref(st))
+        self.eng._check(rc)
+        idx = np.array([hits[i].db_index for i in range(nq * k)], dtype=np.int64).reshape(nq, k)
+        sco = np.array([hits[i].score for i in range(nq * k)], dtype=np.int32).reshape(nq, k)
+        return idx, sco, self._stats(st)
+
+    def scores(self, queries):
+        """All scores: int32 array [nq, ndb] and stats dict."""
+        cat, off = _concat(queries)
+        nq = len(off) - 1
+        out = np.zeros((nq, self.ndb), dtype=np.int32)
+        st = _lib.swh_search_stats(ctypes.sizeof(_lib.swh_search_stats))
+        rc = self.eng.L.swh_db_scores(self.eng.h, self.h, nq, cat.ctypes.data if len(cat) else None,
+                                      off.ctypes.data, out.ctypes.data, ctypes.byref(st))
+        self.eng._check(rc)
+        return out, self._stats(st)
+
+
 def dna_scoring(match: int = 1, mismatch: int = -3, gap_open: int = 5, gap_extend: int = 2) -> Scoring:
     mat = np.full((4, 4), mismatch, dtype=np.int8)
     np.fill_diagonal(mat, match)

@@ -36,6 +36,16 @@ class swh_stats(ctypes.Structure):
                 ("cells_traceback", ctypes.c_double)]
 
 
+class swh_hit(ctypes.Structure):
+    _fields_ = [("db_index", ctypes.c_int64), ("score", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class swh_search_stats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("cells", ctypes.c_double), ("ms_inter", ctypes.c_double), ("ms_intra", ctypes.c_double),
+                ("ms_topk", ctypes.c_double), ("saturated", ctypes.c_int64), ("intra_pairs", ctypes.c_int64)]
+
+
 # name -> (restype, argtypes); the C-ABI surface declared in include/swh.h
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -50,6 +60,11 @@ SIGNATURES = {
     "swh_align_dev": (ctypes.c_int, [_P, _P, _I64, _P, _I64, ctypes.POINTER(swh_scoring), ctypes.c_int,
                                      _P, ctypes.POINTER(swh_alignment), ctypes.c_char_p, _I64, _I64P,
                                      ctypes.POINTER(swh_stats)]),
+    "swh_db_create": (ctypes.c_int, [_P, _I64, _P, _P, ctypes.POINTER(swh_scoring), ctypes.POINTER(_P)]),
+    "swh_db_destroy": (None, [_P]),
+    "swh_db_search": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P,
+                                     ctypes.POINTER(swh_search_stats)]),
+    "swh_db_scores": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, ctypes.POINTER(swh_search_stats)]),
 }
 
 _lib = None

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "context.h"
+#include "db.h"
 
 namespace swh {
 
@@ -185,6 +186,63 @@ swh_status swh_align_dev(swh_ctx *ctx, const char *q_dev, int64_t qlen, const ch
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SWH_E_DEVICE, "hipSetDevice failed");
     return align_device(ctx, q_dev, qlen, t_dev, tlen, sc, mode, (hipStream_t)stream, out, cigar, cigar_cap,
                         cigar_len, stats);
+}
+
+swh_status swh_db_create(swh_ctx *ctx, int64_t ndb, const char *db_cat, const int64_t *db_off,
+                         const swh_scoring *scoring, swh_db **out)
+{
+    if (!ctx) return SWH_E_INVAL;
+    ctx->err.clear();
+    if (!out) return fail(ctx, SWH_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (ndb > 0 && (!db_cat || !db_off)) return fail(ctx, SWH_E_INVAL, "database pointers are NULL");
+    Scoring sc;
+    swh_status s = make_scoring(ctx, scoring, sc);
+    if (s != SWH_OK) return s;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SWH_E_DEVICE, "hipSetDevice failed");
+    return db_create(ctx, ndb, db_cat, db_off, sc, out);
+}
+
+void swh_db_destroy(swh_db *db) { db_destroy(db); }
+
+static swh_status search_common(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off,
+                                int32_t k, swh_hit *hits, int32_t *scores, swh_search_stats *stats)
+{
+    if (!ctx) return SWH_E_INVAL;
+    ctx->err.clear();
+    if (!db) return fail(ctx, SWH_E_INVAL, "database is NULL");
+    if (db->device != ctx->device) return fail(ctx, SWH_E_INVAL, "database lives on another device");
+    if (nq < 0 || (nq > 0 && (!q_off || (!q_cat && q_off[nq] > q_off[0]))))
+        return fail(ctx, SWH_E_INVAL, "bad query arguments");
+    if (hits && (k < 1 || k > 32)) return fail(ctx, SWH_E_INVAL, "k must be in 1..32");
+    if (stats && stats->struct_size < sizeof(swh_search_stats))
+        return fail(ctx, SWH_E_INVAL, "stats->struct_size too small");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SWH_E_DEVICE, "hipSetDevice failed");
+    DbStats ds;
+    swh_status s = db_search(ctx, db, nq, q_cat, q_off, k, hits, scores, ds);
+    if (s == SWH_OK && stats) {
+        stats->cells = ds.cells;
+        stats->ms_inter = ds.ms_inter;
+        stats->ms_intra = ds.ms_intra;
+        stats->ms_topk = ds.ms_topk;
+        stats->saturated = ds.redo;
+        stats->intra_pairs = ds.intra_pairs;
+    }
+    return s;
+}
+
+swh_status swh_db_search(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off,
+                         int32_t k, swh_hit *hits, swh_search_stats *stats)
+{
+    if (ctx && !hits) return fail(ctx, SWH_E_INVAL, "hits is NULL");
+    return search_common(ctx, db, nq, q_cat, q_off, k, hits, nullptr, stats);
+}
+
+swh_status swh_db_scores(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off,
+                         int32_t *scores, swh_search_stats *stats)
+{
+    if (ctx && !scores) return fail(ctx, SWH_E_INVAL, "scores is NULL");
+    return search_common(ctx, db, nq, q_cat, q_off, 0, nullptr, scores, stats);
 }
 
 }  // extern "C"

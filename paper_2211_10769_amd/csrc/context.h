@@ -45,11 +45,14 @@ struct swh_ctx {
     swh::DevBuf probs, strip_prob, prob_best, sync;
     std::vector<swh::Problem> h_probs;
     std::vector<int32_t> h_strip_prob;
+    // database search buffers
+    swh::DevBuf qoff, db_work, db_border, db_redo, db_scatter, db_scores, db_topk;
     // traceback buffers
     swh::DevBuf tb_fwd, tb_bwd, tb_front, tb_codes_q, tb_codes_t, tb_leaf, tb_misc;
     std::vector<swh::DevBuf *> all() {
         return {&qraw, &traw, &qc, &tc, &qr, &tr, &border, &flags, &misc, &strip_best, &mat, &lut,
                 &probs, &strip_prob, &prob_best, &sync,
+                &qoff, &db_work, &db_border, &db_redo, &db_scatter, &db_scores, &db_topk,
                 &tb_fwd, &tb_bwd, &tb_front, &tb_codes_q, &tb_codes_t, &tb_leaf, &tb_misc};
     }
 };

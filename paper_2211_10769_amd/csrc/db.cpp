@@ -1,0 +1,394 @@
+// db.cpp -- exhaustive query-vs-database search: database layout, the
+// inter-task kernel for sequences up to kInterMax residues, the single-pair
+// strip kernel for longer ones (the length-dependent choice between
+// inter-task and intra-task parallelism of SW#, paper, Background) and for
+// pairs whose 16-bit scores may have saturated, then the top-k.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "context.h"
+#include "db.h"
+#include "db_kernels.h"
+#include "strips.h"
+#include "tb_kernels.h"
+
+namespace swh {
+
+namespace {
+
+constexpr int64_t kInterMax = 2048;   // longest database sequence of the inter-task kernel
+
+void free_buf(DevBuf &b)
+{
+    if (b.p) hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+// Encode ASCII host sequences into device codes (original order); reports the
+// first bad byte of the concatenation.
+swh_status encode_host(swh_ctx *ctx, const Scoring &sc, const char *cat, int64_t total, DevBuf &raw, DevBuf &codes,
+                       hipStream_t st, const char *what)
+{
+    swh_status s;
+    if ((s = ensure(ctx, raw, (size_t)total + 1, what)) != SWH_OK) return s;
+    if ((s = ensure(ctx, codes, (size_t)total + 1, what)) != SWH_OK) return s;
+    if ((s = ensure(ctx, ctx->lut, 256, "symbol table")) != SWH_OK) return s;
+    if ((s = ensure(ctx, ctx->misc, 64, "scratch words")) != SWH_OK) return s;
+    hipError_t e;
+    const int32_t init = INT32_MAX;
+    if ((total && (e = hipMemcpyAsync(raw.p, cat, (size_t)total, hipMemcpyHostToDevice, st)) != hipSuccess) ||
+        (e = hipMemcpyAsync(ctx->lut.p, sc.lut, 256, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(ctx->misc.p, &init, 4, hipMemcpyHostToDevice, st)) != hipSuccess)
+        return hip_fail(ctx, e, "upload");
+    if ((e = launch_encode((const char *)raw.p, total, (uint8_t *)codes.p, total, (const uint8_t *)ctx->lut.p,
+                           (uint8_t)sc.asize, (int32_t *)ctx->misc.p, st)) != hipSuccess)
+        return hip_fail(ctx, e, "encode launch");
+    int32_t bad = 0;
+    if ((e = hipMemcpyAsync(&bad, ctx->misc.p, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(ctx, e, "encode");
+    if (bad != INT32_MAX)
+        return fail(ctx, SWH_E_ALPHABET, std::string(what) + ": byte at position " + std::to_string(bad) +
+                                             " of the concatenation is not in the alphabet");
+    return SWH_OK;
+}
+
+swh_status check_offsets(swh_ctx *ctx, int64_t n, const int64_t *off, const char *what)
+{
+    if (n < 0 || (n > 0 && !off)) return fail(ctx, SWH_E_INVAL, std::string(what) + ": bad count or offsets");
+    for (int64_t i = 0; i < n; ++i)
+        if (off[i + 1] < off[i]) return fail(ctx, SWH_E_INVAL, std::string(what) + ": offsets must not decrease");
+    return SWH_OK;
+}
+
+}  // namespace
+
+swh_status gather_lite(swh_ctx *ctx, const std::vector<GatherLite> &g, uint8_t pad, hipStream_t st)
+{
+    if (g.empty()) return SWH_OK;
+    std::vector<GatherDesc> d;
+    d.reserve(g.size());
+    for (const GatherLite &x : g) d.push_back(GatherDesc{x.src, x.dst, 0, x.count, x.padded, 1, 0});
+    swh_status s = ensure(ctx, ctx->tb_misc, sizeof(GatherDesc) * d.size() + 16, "gather table");
+    if (s != SWH_OK) return s;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(ctx->tb_misc.p, d.data(), sizeof(GatherDesc) * d.size(), hipMemcpyHostToDevice, st)) !=
+            hipSuccess ||
+        (e = launch_gather((const GatherDesc *)ctx->tb_misc.p, (int32_t)d.size(), pad, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(ctx, e, "gather");
+    return SWH_OK;
+}
+
+swh_status db_create(swh_ctx *ctx, int64_t ndb, const char *cat, const int64_t *off, const Scoring &sc,
+                     swh_db **out)
+{
+    swh_status s;
+    if ((s = check_offsets(ctx, ndb, off, "database")) != SWH_OK) return s;
+    if (ndb >= INT32_MAX) return fail(ctx, SWH_E_RANGE, "database larger than 2^31 - 1 sequences");
+    hipStream_t st = ctx->own_stream;
+    swh_db *db = new (std::nothrow) swh_db();
+    if (!db) return fail(ctx, SWH_E_NOMEM, "database handle");
+    db->device = ctx->device;
+    db->sc = sc;
+    db->ndb = ndb;
+    const int64_t base = ndb ? off[0] : 0, total = ndb ? off[ndb] - base : 0;
+    db->h_off.resize((size_t)ndb + 1);
+    for (int64_t i = 0; i <= ndb; ++i) db->h_off[i] = ndb ? off[i] - base : 0;
+    DevBuf raw;
+    s = encode_host(ctx, sc, cat ? cat + base : nullptr, total, raw, db->codes, st, "database");
+    free_buf(raw);
+    if (s != SWH_OK) {
+        db_destroy(db);
+        return s;
+    }
+    hipError_t e;
+    if ((s = ensure(ctx, db->offs, sizeof(int64_t) * (size_t)(ndb + 1), "database offsets")) != SWH_OK ||
+        (e = hipMemcpyAsync(db->offs.p, db->h_off.data(), sizeof(int64_t) * (size_t)(ndb + 1),
+                            hipMemcpyHostToDevice, st)) != hipSuccess) {
+        db_destroy(db);
+        return s != SWH_OK ? s : hip_fail(ctx, e, "offsets");
+    }
+
+    // sort by length; long sequences go to the single-pair kernel
+    std::vector<int32_t> order;
+    order.reserve((size_t)ndb);
+    for (int64_t i = 0; i < ndb; ++i) {
+        const int64_t L = db->h_off[i + 1] - db->h_off[i];
+        if (L > kInterMax)
+            db->long_idx.push_back((int32_t)i);
+        else
+            order.push_back((int32_t)i);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return db->h_off[a + 1] - db->h_off[a] < db->h_off[b + 1] - db->h_off[b];
+    });
+    const int64_t ngroups = ((int64_t)order.size() + 127) / 128;
+    db->h_perm.assign((size_t)ngroups * 128, -1);
+    std::copy(order.begin(), order.end(), db->h_perm.begin());
+    db->h_groups.resize((size_t)ngroups);
+    int64_t res_bytes = 0;
+    for (int64_t g = 0; g < ngroups; ++g) {
+        int32_t maxlen = 0;
+        for (int s2 = 0; s2 < 128; ++s2) {
+            const int32_t idx = db->h_perm[g * 128 + s2];
+            if (idx >= 0) maxlen = std::max<int32_t>(maxlen, (int32_t)(db->h_off[idx + 1] - db->h_off[idx]));
+        }
+        db->h_groups[g] = DbGroup{res_bytes, maxlen, (int32_t)(g * 128)};
+        res_bytes += (int64_t)maxlen * 128;
+    }
+    if ((s = ensure(ctx, db->res, (size_t)res_bytes + 256, "database layout")) != SWH_OK ||
+        (s = ensure(ctx, db->groups, sizeof(DbGroup) * (size_t)ngroups + 16, "database groups")) != SWH_OK ||
+        (s = ensure(ctx, db->perm, sizeof(int32_t) * (size_t)ngroups * 128 + 16, "database order")) != SWH_OK) {
+        db_destroy(db);
+        return s;
+    }
+    if ((ngroups && ((e = hipMemcpyAsync(db->groups.p, db->h_groups.data(), sizeof(DbGroup) * ngroups,
+                                         hipMemcpyHostToDevice, st)) != hipSuccess ||
+                     (e = hipMemcpyAsync(db->perm.p, db->h_perm.data(), sizeof(int32_t) * ngroups * 128,
+                                         hipMemcpyHostToDevice, st)) != hipSuccess)) ||
+        (e = launch_db_pack((const uint8_t *)db->codes.p, (const int64_t *)db->offs.p, (const int32_t *)db->perm.p,
+                            (const DbGroup *)db->groups.p, (int32_t)ngroups, (uint8_t)sc.asize,
+                            (uint8_t *)db->res.p, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+        db_destroy(db);
+        return hip_fail(ctx, e, "database layout");
+    }
+    db->total_residues = total;
+    *out = db;
+    return SWH_OK;
+}
+
+void db_destroy(swh_db *db)
+{
+    if (!db) return;
+    hipSetDevice(db->device);
+    hipDeviceSynchronize();
+    free_buf(db->codes);
+    free_buf(db->offs);
+    free_buf(db->res);
+    free_buf(db->groups);
+    free_buf(db->perm);
+    delete db;
+}
+
+swh_status db_scores_device(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off,
+                            int32_t *scores_dev, DbStats &stats)
+{
+    swh_status s;
+    if ((s = check_offsets(ctx, nq, q_off, "queries")) != SWH_OK) return s;
+    hipStream_t st = ctx->own_stream;
+    const Scoring &sc = db->sc;
+    const int64_t qbase = nq ? q_off[0] : 0, qtotal = nq ? q_off[nq] - qbase : 0;
+    std::vector<int64_t> qo((size_t)nq + 1);
+    int64_t maxq = 1;
+    for (int32_t i = 0; i <= nq; ++i) qo[i] = nq ? q_off[i] - qbase : 0;
+    for (int32_t i = 0; i < nq; ++i) maxq = std::max(maxq, qo[i + 1] - qo[i]);
+    if (maxq * std::max(sc.smax, 1) >= ((int64_t)1 << 26))
+        return fail(ctx, SWH_E_RANGE, "query length * max|s| must stay below 2^26");
+    if ((s = encode_host(ctx, sc, q_cat ? q_cat + qbase : nullptr, qtotal, ctx->qraw, ctx->qc, st, "queries")) !=
+        SWH_OK)
+        return s;
+    hipError_t e;
+    if ((s = ensure(ctx, ctx->qoff, sizeof(int64_t) * (qo.size() + 1), "query offsets")) != SWH_OK) return s;
+    if ((s = ensure(ctx, ctx->mat, 32 * 32, "matrix")) != SWH_OK) return s;
+    if ((e = hipMemcpyAsync(ctx->qoff.p, qo.data(), sizeof(int64_t) * qo.size(), hipMemcpyHostToDevice, st)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(ctx->mat.p, sc.mat, (size_t)sc.asize * sc.asize, hipMemcpyHostToDevice, st)) !=
+            hipSuccess)
+        return hip_fail(ctx, e, "query upload");
+
+    // ---- inter-task: every (query, group) unit, most expensive first
+    const int64_t ngroups = (int64_t)db->h_groups.size();
+    std::vector<DbWork> work;
+    work.reserve((size_t)(nq * ngroups));
+    int32_t max_len = 1;
+    for (int32_t q = 0; q < nq; ++q)
+        for (int64_t g = 0; g < ngroups; ++g)
+            if (qo[q + 1] > qo[q]) work.push_back(DbWork{q, (int32_t)g});
+    for (const DbGroup &g : db->h_groups) max_len = std::max(max_len, g.maxlen);
+    std::stable_sort(work.begin(), work.end(), [&](const DbWork &a, const DbWork &b) {
+        return (qo[a.q + 1] - qo[a.q]) * (int64_t)db->h_groups[a.g].maxlen >
+               (qo[b.q + 1] - qo[b.q]) * (int64_t)db->h_groups[b.g].maxlen;
+    });
+    for (int32_t q = 0; q < nq; ++q) {
+        stats.cells += (double)(qo[q + 1] - qo[q]) * (double)db->total_residues;
+    }
+    const int limit = db_search_grid_limit(ctx->device);
+    const int grid = std::max(1, std::min<int>(limit, (int)std::max<size_t>(1, work.size())));
+    const int redo_cap = 1 << 20;
+    if ((s = ensure(ctx, ctx->db_work, sizeof(DbWork) * work.size() + 16, "work list")) != SWH_OK ||
+        (s = ensure(ctx, ctx->db_border, (size_t)grid * max_len * 64 * 8 + 64, "inter-task borders")) != SWH_OK ||
+        (s = ensure(ctx, ctx->db_redo, sizeof(int32_t) * 2 * (size_t)redo_cap + 64, "redo list")) != SWH_OK ||
+        (s = ensure(ctx, ctx->sync, 64, "ticket")) != SWH_OK)
+        return s;
+    if ((!work.empty() && (e = hipMemcpyAsync(ctx->db_work.p, work.data(), sizeof(DbWork) * work.size(),
+                                              hipMemcpyHostToDevice, st)) != hipSuccess) ||
+        (e = hipMemsetAsync(ctx->sync.p, 0, 64, st)) != hipSuccess)
+        return hip_fail(ctx, e, "work upload");
+    DbSearchArgs a;
+    a.res = (const uint8_t *)db->res.p;
+    a.groups = (const DbGroup *)db->groups.p;
+    a.perm = (const int32_t *)db->perm.p;
+    a.qcodes = (const uint8_t *)ctx->qc.p;
+    a.qoff = (const int64_t *)ctx->qoff.p;
+    a.work = (const DbWork *)ctx->db_work.p;
+    a.nwork = (int32_t)work.size();
+    a.asize = sc.asize;
+    a.mat = (const int8_t *)ctx->mat.p;
+    a.o = sc.o;
+    a.e = sc.e;
+    a.ndb = db->ndb;
+    a.scores = scores_dev;
+    a.redo = (int32_t *)ctx->db_redo.p;
+    a.nredo = (int32_t *)ctx->sync.p + 8;
+    a.redo_cap = redo_cap;
+    a.ticket = (int32_t *)ctx->sync.p;
+    a.border = (uint32_t *)ctx->db_border.p;
+    a.max_len = max_len;
+    hipEventRecord(ctx->ev[2], st);
+    if (!work.empty() && (e = launch_db_search(a, grid, st)) != hipSuccess) return hip_fail(ctx, e, "search launch");
+    hipEventRecord(ctx->ev[3], st);
+    int32_t nredo = 0;
+    if ((e = hipMemcpyAsync(&nredo, a.nredo, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(ctx, e, "search");
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]);
+    stats.ms_inter = ms;
+    if (nredo > redo_cap) return fail(ctx, SWH_E_RANGE, "more than 2^20 saturated pairs in one search");
+    std::vector<int32_t> redo((size_t)2 * nredo);
+    if (nredo && ((e = hipMemcpyAsync(redo.data(), a.redo, sizeof(int32_t) * 2 * nredo, hipMemcpyDeviceToHost, st)) !=
+                      hipSuccess ||
+                  (e = hipStreamSynchronize(st)) != hipSuccess))
+        return hip_fail(ctx, e, "redo list");
+    stats.redo = nredo;
+
+    // ---- intra-task in 32 bits: long database sequences and saturated pairs
+    std::vector<std::pair<int32_t, int32_t>> pairs;
+    for (int32_t q = 0; q < nq; ++q)
+        if (qo[q + 1] > qo[q])
+            for (int32_t d : db->long_idx) pairs.push_back({q, d});
+    for (int32_t i = 0; i < nredo; ++i) pairs.push_back({redo[2 * i], redo[2 * i + 1]});
+    if (!pairs.empty()) {
+        const int R = pick_rows_per_lane(maxq);
+        // padded copies: each query once, each database sequence once
+        std::vector<int64_t> qpad_off((size_t)nq + 1, 0);
+        for (int32_t q = 0; q < nq; ++q) qpad_off[q + 1] = qpad_off[q] + rows_padded(qo[q + 1] - qo[q], R);
+        std::vector<int32_t> dids;
+        for (auto &pq : pairs) dids.push_back(pq.second);
+        std::sort(dids.begin(), dids.end());
+        dids.erase(std::unique(dids.begin(), dids.end()), dids.end());
+        std::vector<int64_t> dpad_off(dids.size() + 1, 0);
+        for (size_t i = 0; i < dids.size(); ++i)
+            dpad_off[i + 1] = dpad_off[i] + cols_padded(db->h_off[dids[i] + 1] - db->h_off[dids[i]]);
+        int64_t border_entries = 0;
+        for (auto &pq : pairs)
+            border_entries += cols_padded(db->h_off[pq.second + 1] - db->h_off[pq.second]);
+        const size_t code_bytes = (size_t)(qpad_off[nq] + dpad_off.back()) + 256;
+        if ((s = ensure(ctx, ctx->tb_codes_q, code_bytes, "intra-task codes")) != SWH_OK ||
+            (s = ensure(ctx, ctx->tb_bwd, sizeof(Border) * (size_t)border_entries + 256, "intra-task borders")) !=
+                SWH_OK)
+            return s;
+        std::vector<GatherLite> gl;
+        uint8_t *qbuf = (uint8_t *)ctx->tb_codes_q.p, *dbuf = qbuf + qpad_off[nq];
+        for (int32_t q = 0; q < nq; ++q)
+            gl.push_back(GatherLite{(const uint8_t *)ctx->qc.p + qo[q], qbuf + qpad_off[q], qo[q + 1] - qo[q],
+                                    qpad_off[q + 1] - qpad_off[q]});
+        for (size_t i = 0; i < dids.size(); ++i)
+            gl.push_back(GatherLite{(const uint8_t *)db->codes.p + db->h_off[dids[i]], dbuf + dpad_off[i],
+                                    db->h_off[dids[i] + 1] - db->h_off[dids[i]], dpad_off[i + 1] - dpad_off[i]});
+        if ((s = gather_lite(ctx, gl, (uint8_t)sc.asize, st)) != SWH_OK) return s;
+        if ((e = hipMemsetAsync(ctx->tb_bwd.p, 0, sizeof(Border) * (size_t)border_entries, st)) != hipSuccess)
+            return hip_fail(ctx, e, "intra-task borders");
+        std::vector<StripProblem> probs;
+        Border *bp = (Border *)ctx->tb_bwd.p;
+        for (auto &pq : pairs) {
+            const size_t di = (size_t)(std::lower_bound(dids.begin(), dids.end(), pq.second) - dids.begin());
+            const int64_t L = db->h_off[pq.second + 1] - db->h_off[pq.second];
+            probs.push_back(StripProblem{qbuf + qpad_off[pq.first], qo[pq.first + 1] - qo[pq.first],
+                                         dbuf + dpad_off[di], L, bp});
+            bp += cols_padded(L);
+        }
+        std::vector<BestCell> best;
+        float ms2 = 0.f;
+        if ((s = run_strips(ctx, probs, sc, R, true, st, &best, &ms2)) != SWH_OK) return s;
+        stats.ms_intra = ms2;
+        stats.intra_pairs = (int64_t)pairs.size();
+        std::vector<int64_t> pos(pairs.size());
+        std::vector<int32_t> val(pairs.size());
+        for (size_t i = 0; i < pairs.size(); ++i) {
+            pos[i] = (int64_t)pairs[i].first * db->ndb + pairs[i].second;
+            val[i] = best[i].score;
+        }
+        if ((s = ensure(ctx, ctx->db_scatter, (sizeof(int64_t) + sizeof(int32_t)) * pos.size() + 64, "scatter")) !=
+            SWH_OK)
+            return s;
+        int64_t *dpos = (int64_t *)ctx->db_scatter.p;
+        int32_t *dval = (int32_t *)(dpos + pos.size());
+        if ((e = hipMemcpyAsync(dpos, pos.data(), sizeof(int64_t) * pos.size(), hipMemcpyHostToDevice, st)) !=
+                hipSuccess ||
+            (e = hipMemcpyAsync(dval, val.data(), sizeof(int32_t) * val.size(), hipMemcpyHostToDevice, st)) !=
+                hipSuccess ||
+            (e = launch_scatter(dpos, dval, (int64_t)pos.size(), scores_dev, st)) != hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess)
+            return hip_fail(ctx, e, "scatter");
+    }
+    return SWH_OK;
+}
+
+swh_status db_search(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off, int32_t k,
+                     swh_hit *hits, int32_t *scores_host, DbStats &stats)
+{
+    swh_status s;
+    hipError_t e;
+    hipStream_t st = ctx->own_stream;
+    if ((s = ensure(ctx, ctx->db_scores, sizeof(int32_t) * (size_t)std::max<int64_t>(1, (int64_t)nq * db->ndb) + 64,
+                    "score matrix")) != SWH_OK)
+        return s;
+    int32_t *scores = (int32_t *)ctx->db_scores.p;
+    if ((s = db_scores_device(ctx, db, nq, q_cat, q_off, scores, stats)) != SWH_OK) return s;
+    if (scores_host && nq && db->ndb &&
+        ((e = hipMemcpyAsync(scores_host, scores, sizeof(int32_t) * (size_t)nq * db->ndb, hipMemcpyDeviceToHost,
+                             st)) != hipSuccess ||
+         (e = hipStreamSynchronize(st)) != hipSuccess))
+        return hip_fail(ctx, e, "scores download");
+    if (hits && k > 0 && nq > 0) {
+        const size_t cand = topk_scratch_entries(nq, db->ndb, k);
+        if ((s = ensure(ctx, ctx->db_topk, cand * 8 + (size_t)nq * k * 12 + 256, "top-k scratch")) != SWH_OK)
+            return s;
+        int32_t *cidx = (int32_t *)ctx->db_topk.p;
+        int32_t *cscore = cidx + cand;
+        int64_t *oidx = (int64_t *)(((uintptr_t)(cscore + cand) + 15) & ~(uintptr_t)15);
+        int32_t *oscore = (int32_t *)(oidx + (size_t)nq * k);
+        hipEventRecord(ctx->ev[2], st);
+        if ((e = launch_topk(scores, nq, db->ndb, k, cidx, cscore, oidx, oscore, st)) != hipSuccess)
+            return hip_fail(ctx, e, "top-k launch");
+        hipEventRecord(ctx->ev[3], st);
+        std::vector<int64_t> hi((size_t)nq * k);
+        std::vector<int32_t> hs((size_t)nq * k);
+        if ((e = hipMemcpyAsync(hi.data(), oidx, sizeof(int64_t) * hi.size(), hipMemcpyDeviceToHost, st)) !=
+                hipSuccess ||
+            (e = hipMemcpyAsync(hs.data(), oscore, sizeof(int32_t) * hs.size(), hipMemcpyDeviceToHost, st)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess)
+            return hip_fail(ctx, e, "top-k");
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]);
+        stats.ms_topk = ms;
+        for (size_t i = 0; i < hi.size(); ++i) {
+            hits[i].db_index = hi[i];
+            hits[i].score = hi[i] >= 0 ? hs[i] : -1;
+            hits[i].reserved = 0;
+        }
+    }
+    return SWH_OK;
+}
+
+}  // namespace swh

@@ -1,0 +1,49 @@
+// db.h -- the opaque database handle and the search entry points.
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "context.h"
+#include "db_kernels.h"
+
+struct swh_db {
+    int device = 0;
+    swh::Scoring sc;
+    int64_t ndb = 0;
+    int64_t total_residues = 0;
+    std::vector<int64_t> h_off;            // per database index, rebased to 0
+    std::vector<swh::DbGroup> h_groups;
+    std::vector<int32_t> h_perm;           // sorted position -> database index, -1 padding
+    std::vector<int32_t> long_idx;         // sequences handled by the single-pair kernel
+    swh::DevBuf codes, offs, res, groups, perm;
+};
+
+namespace swh {
+
+struct DbStats {
+    double cells = 0.0;
+    double ms_inter = 0.0, ms_intra = 0.0, ms_topk = 0.0;
+    int64_t redo = 0;
+    int64_t intra_pairs = 0;
+};
+
+// dst[i] = src[i] for i < count, pad code up to padded
+struct GatherLite {
+    const uint8_t *src;
+    uint8_t *dst;
+    int64_t count;
+    int64_t padded;
+};
+swh_status gather_lite(swh_ctx *ctx, const std::vector<GatherLite> &g, uint8_t pad, hipStream_t st);
+
+swh_status db_create(swh_ctx *ctx, int64_t ndb, const char *cat, const int64_t *off, const Scoring &sc,
+                     swh_db **out);
+void db_destroy(swh_db *db);
+swh_status db_scores_device(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off,
+                            int32_t *scores_dev, DbStats &stats);
+swh_status db_search(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off, int32_t k,
+                     swh_hit *hits, int32_t *scores_host, DbStats &stats);
+
+}  // namespace swh

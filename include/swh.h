@@ -124,6 +124,57 @@ swh_status swh_align_dev(swh_ctx *ctx, const char *q_dev, int64_t qlen, const ch
                          swh_alignment *out, char *cigar, int64_t cigar_cap,
                          int64_t *cigar_len, swh_stats *stats);
 
+/*
+ * Many independent local alignments in one call (paper, Background: SW# and
+ * CUDASW++ both run many independent matrices; the library batches them).
+ * Pair i is query q_cat[q_off[i] .. q_off[i+1]) against target
+ * t_cat[t_off[i] .. t_off[i+1]) (host pointers, offsets non-decreasing; the
+ * first offset need not be 0).  Every pair gets exactly the result swh_align
+ * gives it; all pairs share the launches of each phase (forward pass,
+ * reverse pass, traceback levels), most expensive pairs first.
+ *
+ * out: npairs results (caller-owned).  mode CIGAR: cigar_off (npairs + 1
+ * entries, caller-owned) receives offsets into cigar_cat, CIGAR i being the
+ * bytes cigar_cat[cigar_off[i] .. cigar_off[i+1]) without terminator; when
+ * cigar_cat is NULL or cigar_off[npairs] > cigar_cap the call returns
+ * SWH_E_RANGE with out and cigar_off filled (cigar_off[npairs] = bytes
+ * needed).  cigar arguments are ignored in the other modes.  Each pair must
+ * satisfy the limits of swh_align.  Errors: SWH_E_INVAL (NULL pointers,
+ * decreasing offsets, bad mode), SWH_E_ALPHABET (names the pair and the
+ * byte), SWH_E_RANGE, SWH_E_NOMEM, SWH_E_DEVICE, SWH_E_TIMEOUT.  stats
+ * (optional) sums the phases over all pairs.
+ */
+swh_status swh_align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const int64_t *q_off,
+                           const char *t_cat, const int64_t *t_off, const swh_scoring *scoring,
+                           int mode, swh_alignment *out, char *cigar_cat, int64_t cigar_cap,
+                           int64_t *cigar_off, swh_stats *stats);
+
+/*
+ * Strip shape of the intra-task kernel, per bucket of query rows: problems
+ * with n <= max_rows rows (first matching entry) use strips of
+ * 64 * rows_per_lane rows and a persistent grid of waves_per_simd waves per
+ * SIMD (0: the built-in choice for that height).  Shapes change speed only,
+ * never results.
+ */
+typedef struct {
+    int64_t max_rows;
+    int32_t rows_per_lane;      /* 4, 8, 16 or 32 */
+    int32_t waves_per_simd;     /* 0..8 */
+} swh_tune_entry;
+
+/* Measure every shape on synthetic problems for row buckets 1 Ki, 4 Ki, ...
+ * up to max_rows (about cells_per_trial DP cells per timed launch, scored
+ * with the given scoring) and install the fastest per bucket in ctx. */
+swh_status swh_autotune(swh_ctx *ctx, const swh_scoring *scoring, int64_t max_rows,
+                        double cells_per_trial);
+/* Copy ctx's table (at most cap entries) to out; *count = its length
+ * (0: built-in rule).  A caller may store it and install it with
+ * swh_tune_set in a later context. */
+swh_status swh_tune_get(const swh_ctx *ctx, swh_tune_entry *out, int32_t cap, int32_t *count);
+/* Install a table (count = 0 restores the built-in rule).  SWH_E_INVAL for
+ * an entry with an unsupported shape or max_rows not increasing. */
+swh_status swh_tune_set(swh_ctx *ctx, const swh_tune_entry *entries, int32_t count);
+
 /* ------------------------------------------------------------------------
  * Database search (paper, Background: database similarity search, many
  * independent matrices; Experimental Work: 20 protein queries against

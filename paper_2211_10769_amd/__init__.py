@@ -122,6 +122,60 @@ class Engine:
         self._check(st)
         return self._result(out, buf.value.decode() if buf is not None else None, st_obj)
 
+    def align_batch(self, queries, targets, scoring, mode: str = "cigar", stats: bool = False):
+        """Many pairs (query i vs target i) in one call; returns a list of result dicts
+        (and the summed stats dict when stats=True)."""
+        sc = Scoring.of(scoring)
+        qcat, qoff = _concat(queries)
+        tcat, toff = _concat(targets)
+        n = len(qoff) - 1
+        if len(toff) - 1 != n:
+            raise ValueError("queries and targets differ in count")
+        m = _MODES[mode]
+        out = (_lib.swh_alignment * max(1, n))()
+        st_obj = _lib.swh_stats(ctypes.sizeof(_lib.swh_stats)) if stats else None
+        coff = np.zeros(n + 1, dtype=np.int64)
+        cap = int(2 * (qoff[-1] - qoff[0] + toff[-1] - toff[0]) + 16) if m == MODE_CIGAR else 0
+        buf = ctypes.create_string_buffer(cap) if cap else None
+        args = [self.h, n, qcat.ctypes.data if len(qcat) else None, qoff.ctypes.data,
+                tcat.ctypes.data if len(tcat) else None, toff.ctypes.data, ctypes.byref(sc.c), m, out,
+                buf, cap, coff.ctypes.data if m == MODE_CIGAR else None,
+                ctypes.byref(st_obj) if st_obj is not None else None]
+        rc = self.L.swh_align_batch(*args)
+        if rc == -4 and m == MODE_CIGAR and coff[-1] > cap:      # grow to the reported size once
+            cap = int(coff[-1]) + 1
+            buf = ctypes.create_string_buffer(cap)
+            args[8], args[9] = buf, cap
+            rc = self.L.swh_align_batch(*args)
+        self._check(rc)
+        raw = buf.raw if buf is not None else b""
+        res = []
+        for i in range(n):
+            cg = raw[coff[i]:coff[i + 1]].decode() if m == MODE_CIGAR else None
+            res.append(self._result(out[i], cg, None))
+        if stats:
+            return res, {k: getattr(st_obj, k) for k, _ in st_obj._fields_[2:]}
+        return res
+
+    def autotune(self, scoring, max_rows: int = 1 << 20, cells_per_trial: float = 2e10):
+        """Measure and install the strip shapes; returns the table as a list of dicts."""
+        sc = Scoring.of(scoring)
+        self._check(self.L.swh_autotune(self.h, ctypes.byref(sc.c), int(max_rows), float(cells_per_trial)))
+        return self.tune_table()
+
+    def tune_table(self):
+        arr = (_lib.swh_tune_entry * 64)()
+        cnt = ctypes.c_int32()
+        self._check(self.L.swh_tune_get(self.h, arr, 64, ctypes.byref(cnt)))
+        return [dict(max_rows=arr[i].max_rows, rows_per_lane=arr[i].rows_per_lane,
+                     waves_per_simd=arr[i].waves_per_simd) for i in range(cnt.value)]
+
+    def set_tune_table(self, table):
+        arr = (_lib.swh_tune_entry * max(1, len(table)))()
+        for i, t in enumerate(table):
+            arr[i] = _lib.swh_tune_entry(int(t["max_rows"]), int(t["rows_per_lane"]), int(t["waves_per_simd"]))
+        self._check(self.L.swh_tune_set(self.h, arr, len(table)))
+
 
 def _concat(seqs):
     """list of sequences (or (concatenated bytes, offsets)) -> (uint8 array, int64 offsets)."""

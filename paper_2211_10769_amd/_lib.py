@@ -46,6 +46,10 @@ class swh_search_stats(ctypes.Structure):
                 ("ms_topk", ctypes.c_double), ("saturated", ctypes.c_int64), ("intra_pairs", ctypes.c_int64)]
 
 
+class swh_tune_entry(ctypes.Structure):
+    _fields_ = [("max_rows", ctypes.c_int64), ("rows_per_lane", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32)]
+
+
 # name -> (restype, argtypes); the C-ABI surface declared in include/swh.h
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -60,6 +64,11 @@ SIGNATURES = {
     "swh_align_dev": (ctypes.c_int, [_P, _P, _I64, _P, _I64, ctypes.POINTER(swh_scoring), ctypes.c_int,
                                      _P, ctypes.POINTER(swh_alignment), ctypes.c_char_p, _I64, _I64P,
                                      ctypes.POINTER(swh_stats)]),
+    "swh_align_batch": (ctypes.c_int, [_P, _I64, _P, _P, _P, _P, ctypes.POINTER(swh_scoring), ctypes.c_int,
+                                       _P, _P, _I64, _P, ctypes.POINTER(swh_stats)]),
+    "swh_autotune": (ctypes.c_int, [_P, ctypes.POINTER(swh_scoring), _I64, ctypes.c_double]),
+    "swh_tune_get": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "swh_tune_set": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "swh_db_create": (ctypes.c_int, [_P, _I64, _P, _P, ctypes.POINTER(swh_scoring), ctypes.POINTER(_P)]),
     "swh_db_destroy": (None, [_P]),
     "swh_db_search": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P,

@@ -1,0 +1,275 @@
+// batch.cpp -- many independent pairwise alignments in few launches.
+//
+// All pairs of a call share each phase: one forward local pass over every
+// pair (the strip kernel's problem table, strips of all pairs in one ticket
+// space, the most expensive pairs first), one reverse pass over the reversed
+// prefixes of every pair with a positive score, and one level-synchronous
+// traceback whose levels hold the subproblems of all pairs.  Pairs are cut
+// into chunks only to bound the device memory of one launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "batch.h"
+#include "context.h"
+#include "strips.h"
+#include "tb_kernels.h"
+#include "traceback.h"
+#include "tune.h"
+
+namespace swh {
+
+namespace {
+
+// device bytes of the per-pair copies and border rows of one launch
+constexpr int64_t kChunkBytes = (int64_t)3 << 30;
+// total rectangle columns of one traceback batch (arena: ~9 bytes per column)
+constexpr int64_t kTracebackCols = (int64_t)64 << 20;
+
+template <typename T>
+swh_status upload(swh_ctx *ctx, DevBuf &buf, const std::vector<T> &v, hipStream_t st, const char *what)
+{
+    swh_status s = ensure(ctx, buf, v.size() * sizeof(T) + 16, what);
+    if (s != SWH_OK) return s;
+    hipError_t e = hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, what);
+    return SWH_OK;
+}
+
+struct Pass {
+    const uint8_t *q;   // codes of the rows (device, unpadded)
+    int64_t n;
+    const uint8_t *t;   // codes of the columns
+    int64_t m;
+    int step;           // +1: rows/columns as stored; -1: reversed, q and t point at the last code
+};
+
+// One local pass over many (rows, columns) problems: padded copies, zeroed
+// borders, strip launches grouped by strip height and cut into chunks.
+swh_status local_passes(swh_ctx *ctx, const std::vector<Pass> &ps, const Scoring &sc, hipStream_t st,
+                        std::vector<BestCell> &best, double &ms_total)
+{
+    const size_t np = ps.size();
+    best.assign(np, BestCell{0, 0, 0, 0});
+    std::vector<StripShape> sh(np);
+    for (size_t i = 0; i < np; ++i) sh[i] = tuned_shape(ctx, ps[i].n);
+    auto same = [&](size_t a, size_t b) { return sh[a].R == sh[b].R && sh[a].waves == sh[b].waves; };
+    // by strip shape, then most expensive first
+    std::vector<size_t> order(np);
+    std::iota(order.begin(), order.end(), (size_t)0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+        if (sh[a].R != sh[b].R) return sh[a].R > sh[b].R;
+        if (sh[a].waves != sh[b].waves) return sh[a].waves > sh[b].waves;
+        return (double)ps[a].n * (double)ps[a].m > (double)ps[b].n * (double)ps[b].m;
+    });
+    const uint8_t pad = (uint8_t)sc.asize;
+    size_t k = 0;
+    while (k < np) {
+        while (k < np && (ps[order[k]].n == 0 || ps[order[k]].m == 0)) ++k;
+        if (k == np) break;
+        const size_t lead = order[k];
+        const int Rk = sh[lead].R;
+        // a chunk: one strip shape, bounded bytes
+        size_t end = k;
+        int64_t bytes = 0, nb = 0, nq = 0, nt = 0;
+        while (end < np && same(order[end], lead)) {
+            const Pass &p = ps[order[end]];
+            if (p.n == 0 || p.m == 0) {
+                ++end;
+                continue;
+            }
+            const int64_t b = rows_padded(p.n, Rk) + cols_padded(p.m) * (1 + (int64_t)sizeof(Border));
+            if (bytes && bytes + b > kChunkBytes) break;
+            bytes += b;
+            nq += rows_padded(p.n, Rk);
+            nt += cols_padded(p.m);
+            nb += cols_padded(p.m);
+            ++end;
+        }
+        swh_status s;
+        if ((s = ensure(ctx, ctx->bq, (size_t)nq + 256, "batch row codes")) != SWH_OK ||
+            (s = ensure(ctx, ctx->bt, (size_t)nt + 256, "batch column codes")) != SWH_OK ||
+            (s = ensure(ctx, ctx->bborder, sizeof(Border) * (size_t)nb + 256, "batch borders")) != SWH_OK)
+            return s;
+        std::vector<GatherDesc> gd;
+        std::vector<StripProblem> probs;
+        std::vector<size_t> idx;
+        uint8_t *qp = (uint8_t *)ctx->bq.p, *tp = (uint8_t *)ctx->bt.p;
+        Border *bp = (Border *)ctx->bborder.p;
+        for (size_t i = k; i < end; ++i) {
+            const Pass &p = ps[order[i]];
+            if (p.n == 0 || p.m == 0) continue;
+            const int64_t qpad = rows_padded(p.n, Rk), tpad = cols_padded(p.m);
+            gd.push_back(GatherDesc{p.q, qp, 0, p.n, qpad, p.step, 0});
+            gd.push_back(GatherDesc{p.t, tp, 0, p.m, tpad, p.step, 0});
+            probs.push_back(StripProblem{qp, p.n, tp, p.m, bp});
+            idx.push_back(order[i]);
+            qp += qpad;
+            tp += tpad;
+            bp += tpad;
+        }
+        hipError_t e;
+        if ((s = upload(ctx, ctx->tb_misc, gd, st, "gather table")) != SWH_OK) return s;
+        if ((e = launch_gather((const GatherDesc *)ctx->tb_misc.p, (int32_t)gd.size(), pad, st)) != hipSuccess ||
+            (e = hipMemsetAsync(ctx->bborder.p, 0, sizeof(Border) * (size_t)nb, st)) != hipSuccess)
+            return hip_fail(ctx, e, "batch setup");
+        std::vector<BestCell> b;
+        float ms = 0.f;
+        if ((s = run_strips(ctx, probs, sc, Rk, true, st, &b, &ms, sh[lead].waves)) != SWH_OK) return s;
+        ms_total += ms;
+        for (size_t i = 0; i < idx.size(); ++i) best[idx[i]] = b[i];
+        k = end;
+    }
+    return SWH_OK;
+}
+
+}  // namespace
+
+swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const int64_t *q_off, const char *t_cat,
+                       const int64_t *t_off, const Scoring &sc, int mode, swh_alignment *out, char *cigar_cat,
+                       int64_t cigar_cap, int64_t *cigar_off, swh_stats *stats)
+{
+    for (int64_t i = 0; i < npairs; ++i) {
+        out[i].score = 0;
+        out[i].flags = SWH_F_NONE;
+        out[i].q_begin = out[i].q_end = out[i].t_begin = out[i].t_end = -1;
+    }
+    if (mode == SWH_MODE_CIGAR && cigar_off)
+        for (int64_t i = 0; i <= npairs; ++i) cigar_off[i] = 0;
+    if (npairs == 0) return SWH_OK;
+    hipStream_t st = ctx->own_stream;
+    const int64_t qbase = q_off[0], tbase = t_off[0];
+    const int64_t qtot = q_off[npairs] - qbase, ttot = t_off[npairs] - tbase;
+    swh_status s;
+    hipError_t e;
+
+    // ---- encode both concatenations once
+    if ((s = ensure(ctx, ctx->qraw, (size_t)qtot + 1, "query copy")) != SWH_OK ||
+        (s = ensure(ctx, ctx->traw, (size_t)ttot + 1, "target copy")) != SWH_OK ||
+        (s = ensure(ctx, ctx->qc, (size_t)qtot + 1, "query codes")) != SWH_OK ||
+        (s = ensure(ctx, ctx->tc, (size_t)ttot + 1, "target codes")) != SWH_OK ||
+        (s = ensure(ctx, ctx->misc, 64, "scratch words")) != SWH_OK ||
+        (s = ensure(ctx, ctx->mat, 32 * 32, "matrix")) != SWH_OK ||
+        (s = ensure(ctx, ctx->lut, 256, "symbol table")) != SWH_OK)
+        return s;
+    static const int32_t init[2] = {INT32_MAX, INT32_MAX};
+    int32_t *misc = (int32_t *)ctx->misc.p;
+    const uint8_t pad = (uint8_t)sc.asize;
+    if ((qtot && (e = hipMemcpyAsync(ctx->qraw.p, q_cat + qbase, (size_t)qtot, hipMemcpyHostToDevice, st)) !=
+                     hipSuccess) ||
+        (ttot && (e = hipMemcpyAsync(ctx->traw.p, t_cat + tbase, (size_t)ttot, hipMemcpyHostToDevice, st)) !=
+                     hipSuccess) ||
+        (e = hipMemcpyAsync(misc, init, sizeof(init), hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(ctx->mat.p, sc.mat, (size_t)sc.asize * sc.asize, hipMemcpyHostToDevice, st)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(ctx->lut.p, sc.lut, 256, hipMemcpyHostToDevice, st)) != hipSuccess)
+        return hip_fail(ctx, e, "batch upload");
+    if ((e = launch_encode((const char *)ctx->qraw.p, qtot, (uint8_t *)ctx->qc.p, qtot, (const uint8_t *)ctx->lut.p,
+                           pad, misc, st)) != hipSuccess ||
+        (e = launch_encode((const char *)ctx->traw.p, ttot, (uint8_t *)ctx->tc.p, ttot, (const uint8_t *)ctx->lut.p,
+                           pad, misc + 1, st)) != hipSuccess)
+        return hip_fail(ctx, e, "encode kernel launch");
+    int32_t bad[2];
+    if ((e = hipMemcpyAsync(bad, misc, 8, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(ctx, e, "encode");
+    for (int side = 0; side < 2; ++side) {
+        if (bad[side] == INT32_MAX) continue;
+        const int64_t *off = side ? t_off : q_off;
+        const int64_t pos = bad[side] + (side ? tbase : qbase);
+        const int64_t pr = (int64_t)(std::upper_bound(off, off + npairs + 1, pos) - off) - 1;
+        return fail(ctx, SWH_E_ALPHABET, std::string(side ? "target" : "query") + " of pair " + std::to_string(pr) +
+                                             ": byte at position " + std::to_string(pos - off[pr]) +
+                                             " is not in the alphabet");
+    }
+    const uint8_t *qc = (const uint8_t *)ctx->qc.p, *tc = (const uint8_t *)ctx->tc.p;
+
+    // ---- resolution: forward local pass of every pair
+    std::vector<Pass> ps((size_t)npairs);
+    double cells = 0.0;
+    for (int64_t i = 0; i < npairs; ++i) {
+        ps[i] = Pass{qc + (q_off[i] - qbase), q_off[i + 1] - q_off[i], tc + (t_off[i] - tbase),
+                     t_off[i + 1] - t_off[i], 1};
+        cells += (double)ps[i].n * (double)ps[i].m;
+    }
+    std::vector<BestCell> fwd;
+    double ms_fwd = 0.0, ms_rev = 0.0;
+    if ((s = local_passes(ctx, ps, sc, st, fwd, ms_fwd)) != SWH_OK) return s;
+    if (stats) {
+        stats->cells_forward = cells;
+        stats->ms_forward = ms_fwd;
+    }
+    std::vector<int64_t> pos_pairs;
+    for (int64_t i = 0; i < npairs; ++i) {
+        out[i].score = fwd[i].score;
+        if (fwd[i].score > 0) {
+            out[i].q_end = fwd[i].row - 1;
+            out[i].t_end = fwd[i].col - 1;
+            pos_pairs.push_back(i);
+        }
+    }
+    if (mode == SWH_MODE_SCORE) return SWH_OK;
+
+    // ---- reverse pass over the reversed prefixes ending at each end cell
+    std::vector<Pass> rp;
+    rp.reserve(pos_pairs.size());
+    for (int64_t i : pos_pairs)
+        rp.push_back(Pass{ps[i].q + out[i].q_end, out[i].q_end + 1, ps[i].t + out[i].t_end, out[i].t_end + 1, -1});
+    std::vector<BestCell> rev;
+    if ((s = local_passes(ctx, rp, sc, st, rev, ms_rev)) != SWH_OK) return s;
+    if (stats) stats->ms_reverse = ms_rev;
+    for (size_t k = 0; k < pos_pairs.size(); ++k) {
+        const int64_t i = pos_pairs[k];
+        if (rev[k].score != fwd[i].score)
+            return fail(ctx, SWH_E_DEVICE, "pair " + std::to_string(i) + ": reverse pass maximum " +
+                                               std::to_string(rev[k].score) + " differs from the forward score " +
+                                               std::to_string(fwd[i].score));
+        out[i].q_begin = out[i].q_end - (rev[k].row - 1);
+        out[i].t_begin = out[i].t_end - (rev[k].col - 1);
+    }
+    if (mode == SWH_MODE_COORDS) return SWH_OK;
+
+    // ---- reconstruction: batched linear-space traceback
+    std::vector<std::string> cig((size_t)npairs);
+    TracebackStats ts;
+    size_t k = 0;
+    while (k < pos_pairs.size()) {
+        std::vector<TbInput> in;
+        std::vector<int64_t> ids;
+        int64_t cols = 0;
+        while (k < pos_pairs.size()) {
+            const int64_t i = pos_pairs[k];
+            const int64_t p = out[i].q_end - out[i].q_begin + 1, q = out[i].t_end - out[i].t_begin + 1;
+            if (!in.empty() && cols + q > kTracebackCols) break;
+            in.push_back(TbInput{ps[i].q + out[i].q_begin, p, ps[i].t + out[i].t_begin, q, out[i].score});
+            ids.push_back(i);
+            cols += q;
+            ++k;
+        }
+        std::vector<std::string> cg;
+        if ((s = traceback_batch(ctx, in, sc, st, cg, ts)) != SWH_OK) return s;
+        for (size_t j = 0; j < ids.size(); ++j) cig[ids[j]].swap(cg[j]);
+    }
+    if (stats) {
+        stats->ms_traceback = ts.ms;
+        stats->cells_traceback = ts.cells;
+    }
+    int64_t total = 0;
+    for (int64_t i = 0; i < npairs; ++i) {
+        cigar_off[i] = total;
+        total += (int64_t)cig[i].size();
+    }
+    cigar_off[npairs] = total;
+    if (!cigar_cat || total > cigar_cap)
+        return fail(ctx, SWH_E_RANGE, "CIGARs need " + std::to_string(total) + " bytes");
+    for (int64_t i = 0; i < npairs; ++i)
+        if (!cig[i].empty()) std::memcpy(cigar_cat + cigar_off[i], cig[i].data(), cig[i].size());
+    return SWH_OK;
+}
+
+}  // namespace swh

@@ -7,7 +7,9 @@
 #include <string>
 
 #include "context.h"
+#include "batch.h"
 #include "db.h"
+#include "tune.h"
 
 namespace swh {
 
@@ -186,6 +188,73 @@ swh_status swh_align_dev(swh_ctx *ctx, const char *q_dev, int64_t qlen, const ch
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SWH_E_DEVICE, "hipSetDevice failed");
     return align_device(ctx, q_dev, qlen, t_dev, tlen, sc, mode, (hipStream_t)stream, out, cigar, cigar_cap,
                         cigar_len, stats);
+}
+
+swh_status swh_align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const int64_t *q_off, const char *t_cat,
+                           const int64_t *t_off, const swh_scoring *scoring, int mode, swh_alignment *out,
+                           char *cigar_cat, int64_t cigar_cap, int64_t *cigar_off, swh_stats *stats)
+{
+    if (!ctx) return SWH_E_INVAL;
+    ctx->err.clear();
+    Scoring sc;
+    swh_status s = make_scoring(ctx, scoring, sc);
+    if (s != SWH_OK) return s;
+    if (npairs < 0) return fail(ctx, SWH_E_INVAL, "npairs is negative");
+    if (npairs > 0 && (!q_off || !t_off || !out)) return fail(ctx, SWH_E_INVAL, "offsets or out is NULL");
+    if (mode < SWH_MODE_SCORE || mode > SWH_MODE_CIGAR) return fail(ctx, SWH_E_INVAL, "unknown mode");
+    if (mode == SWH_MODE_CIGAR && !cigar_off) return fail(ctx, SWH_E_INVAL, "cigar_off is NULL");
+    if (stats && stats->struct_size < sizeof(swh_stats)) return fail(ctx, SWH_E_INVAL, "stats->struct_size too small");
+    if (npairs >= ((int64_t)1 << 31)) return fail(ctx, SWH_E_RANGE, "more than 2^31 - 1 pairs");
+    for (int64_t i = 0; i < npairs; ++i) {
+        const int64_t qlen = q_off[i + 1] - q_off[i], tlen = t_off[i + 1] - t_off[i];
+        if (qlen < 0 || tlen < 0) return fail(ctx, SWH_E_INVAL, "offsets decrease at pair " + std::to_string(i));
+        swh_alignment dummy;
+        if ((s = check_pair(ctx, qlen ? q_cat : nullptr, qlen, tlen ? t_cat : nullptr, tlen, sc, mode, &dummy)) !=
+            SWH_OK)
+            return fail(ctx, s, "pair " + std::to_string(i) + ": " + ctx->err);
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SWH_E_DEVICE, "hipSetDevice failed");
+    return align_batch(ctx, npairs, q_cat, q_off, t_cat, t_off, sc, mode, out, cigar_cat, cigar_cap, cigar_off,
+                       stats);
+}
+
+swh_status swh_autotune(swh_ctx *ctx, const swh_scoring *scoring, int64_t max_rows, double cells_per_trial)
+{
+    if (!ctx) return SWH_E_INVAL;
+    ctx->err.clear();
+    Scoring sc;
+    swh_status s = make_scoring(ctx, scoring, sc);
+    if (s != SWH_OK) return s;
+    if (max_rows < 1 || max_rows >= ((int64_t)1 << 31)) return fail(ctx, SWH_E_INVAL, "max_rows out of range");
+    if (!(cells_per_trial > 0.0) || cells_per_trial > 1e13)
+        return fail(ctx, SWH_E_INVAL, "cells_per_trial must be in (0, 1e13]");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SWH_E_DEVICE, "hipSetDevice failed");
+    return autotune(ctx, sc, max_rows, cells_per_trial);
+}
+
+swh_status swh_tune_get(const swh_ctx *ctx, swh_tune_entry *out, int32_t cap, int32_t *count)
+{
+    if (!ctx || !count || cap < 0 || (cap > 0 && !out)) return SWH_E_INVAL;
+    *count = (int32_t)ctx->tune.size();
+    for (int32_t i = 0; i < cap && i < *count; ++i) out[i] = ctx->tune[i];
+    return SWH_OK;
+}
+
+swh_status swh_tune_set(swh_ctx *ctx, const swh_tune_entry *entries, int32_t count)
+{
+    if (!ctx) return SWH_E_INVAL;
+    ctx->err.clear();
+    if (count < 0 || count > 64 || (count > 0 && !entries)) return fail(ctx, SWH_E_INVAL, "bad table size");
+    for (int32_t i = 0; i < count; ++i) {
+        const swh_tune_entry &t = entries[i];
+        const int R = t.rows_per_lane;
+        if (R != 4 && R != 8 && R != 16 && R != 32) return fail(ctx, SWH_E_INVAL, "rows_per_lane must be 4, 8, 16 or 32");
+        if (t.waves_per_simd < 0 || t.waves_per_simd > 8) return fail(ctx, SWH_E_INVAL, "waves_per_simd must be in 0..8");
+        if (t.max_rows < 1 || (i > 0 && t.max_rows <= entries[i - 1].max_rows))
+            return fail(ctx, SWH_E_INVAL, "max_rows must be positive and increasing");
+    }
+    ctx->tune.assign(entries, entries + count);
+    return SWH_OK;
 }
 
 swh_status swh_db_create(swh_ctx *ctx, int64_t ndb, const char *db_cat, const int64_t *db_off,

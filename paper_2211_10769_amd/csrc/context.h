@@ -47,12 +47,17 @@ struct swh_ctx {
     std::vector<int32_t> h_strip_prob;
     // database search buffers
     swh::DevBuf qoff, db_work, db_border, db_redo, db_scatter, db_scores, db_topk;
+    // batched pairs: padded per-pair copies and border rows of one launch
+    swh::DevBuf bq, bt, bborder;
+    // strip shapes measured by the autotuner (empty: built-in rule)
+    std::vector<swh_tune_entry> tune;
     // traceback buffers
     swh::DevBuf tb_fwd, tb_bwd, tb_front, tb_codes_q, tb_codes_t, tb_leaf, tb_misc;
     std::vector<swh::DevBuf *> all() {
         return {&qraw, &traw, &qc, &tc, &qr, &tr, &border, &flags, &misc, &strip_best, &mat, &lut,
                 &probs, &strip_prob, &prob_best, &sync,
                 &qoff, &db_work, &db_border, &db_redo, &db_scatter, &db_scores, &db_topk,
+                &bq, &bt, &bborder,
                 &tb_fwd, &tb_bwd, &tb_front, &tb_codes_q, &tb_codes_t, &tb_leaf, &tb_misc};
     }
 };

@@ -16,6 +16,7 @@
 #include "db_kernels.h"
 #include "strips.h"
 #include "tb_kernels.h"
+#include "tune.h"
 
 namespace swh {
 
@@ -277,7 +278,8 @@ swh_status db_scores_device(swh_ctx *ctx, const swh_db *db, int32_t nq, const ch
             for (int32_t d : db->long_idx) pairs.push_back({q, d});
     for (int32_t i = 0; i < nredo; ++i) pairs.push_back({redo[2 * i], redo[2 * i + 1]});
     if (!pairs.empty()) {
-        const int R = pick_rows_per_lane(maxq);
+        const StripShape shape = tuned_shape(ctx, maxq);
+        const int R = shape.R;
         // padded copies: each query once, each database sequence once
         std::vector<int64_t> qpad_off((size_t)nq + 1, 0);
         for (int32_t q = 0; q < nq; ++q) qpad_off[q + 1] = qpad_off[q] + rows_padded(qo[q + 1] - qo[q], R);
@@ -318,7 +320,7 @@ swh_status db_scores_device(swh_ctx *ctx, const swh_db *db, int32_t nq, const ch
         }
         std::vector<BestCell> best;
         float ms2 = 0.f;
-        if ((s = run_strips(ctx, probs, sc, R, true, st, &best, &ms2)) != SWH_OK) return s;
+        if ((s = run_strips(ctx, probs, sc, R, true, st, &best, &ms2, shape.waves)) != SWH_OK) return s;
         stats.ms_intra = ms2;
         stats.intra_pairs = (int64_t)pairs.size();
         std::vector<int64_t> pos(pairs.size());

@@ -12,6 +12,7 @@
 #include "engine.h"
 #include "strips.h"
 #include "traceback.h"
+#include "tune.h"
 
 namespace swh {
 
@@ -27,7 +28,7 @@ struct LocalPass {
 
 // One local score pass over encoded inputs already on the device.
 swh_status local_pass(swh_ctx *ctx, const uint8_t *qc, int64_t n, const uint8_t *tc, int64_t m,
-                      const Scoring &sc, int R, hipStream_t st, LocalPass &res)
+                      const Scoring &sc, StripShape shape, hipStream_t st, LocalPass &res)
 {
     const size_t bcount = (size_t)cols_padded(m);
     swh_status s;
@@ -37,7 +38,7 @@ swh_status local_pass(swh_ctx *ctx, const uint8_t *qc, int64_t n, const uint8_t 
         return hip_fail(ctx, e, "hipMemsetAsync(border)");
     std::vector<StripProblem> pr{{qc, n, tc, m, (Border *)ctx->border.p}};
     std::vector<BestCell> best;
-    if ((s = run_strips(ctx, pr, sc, R, true, st, &best, &res.ms)) != SWH_OK) return s;
+    if ((s = run_strips(ctx, pr, sc, shape.R, true, st, &best, &res.ms, shape.waves)) != SWH_OK) return s;
     res.best = best[0];
     return SWH_OK;
 }
@@ -55,8 +56,8 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
     if (cigar && cigar_cap > 0) cigar[0] = '\0';
     if (qlen == 0 || tlen == 0) return SWH_OK;
 
-    const int R = pick_rows_per_lane(qlen);
-    const int64_t qpad = rows_padded(qlen, R);
+    const StripShape shape = tuned_shape(ctx, qlen);
+    const int64_t qpad = rows_padded(qlen, shape.R);
     const int64_t tpad = cols_padded(tlen);
     swh_status s;
     if ((s = ensure(ctx, ctx->qc, (size_t)qpad, "query codes")) != SWH_OK) return s;
@@ -92,7 +93,7 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
 
     // ---- resolution: forward local pass
     LocalPass fwd;
-    if ((s = local_pass(ctx, (const uint8_t *)ctx->qc.p, qlen, (const uint8_t *)ctx->tc.p, tlen, sc, R, st, fwd)) !=
+    if ((s = local_pass(ctx, (const uint8_t *)ctx->qc.p, qlen, (const uint8_t *)ctx->tc.p, tlen, sc, shape, st, fwd)) !=
         SWH_OK)
         return s;
     if (stats) {
@@ -107,8 +108,8 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
 
     // ---- reverse local pass on the prefixes ending at the end cell
     const int64_t rn = out->q_end + 1, rm = out->t_end + 1;
-    const int Rr = pick_rows_per_lane(rn);
-    const int64_t rqpad = rows_padded(rn, Rr);
+    const StripShape rshape = tuned_shape(ctx, rn);
+    const int64_t rqpad = rows_padded(rn, rshape.R);
     const int64_t rtpad = cols_padded(rm);
     if ((s = ensure(ctx, ctx->qr, (size_t)rqpad, "reversed query")) != SWH_OK) return s;
     if ((s = ensure(ctx, ctx->tr, (size_t)rtpad, "reversed target")) != SWH_OK) return s;
@@ -116,7 +117,7 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
         (e = launch_reverse((const uint8_t *)ctx->tc.p, rm, (uint8_t *)ctx->tr.p, rtpad, pad, st)) != hipSuccess)
         return hip_fail(ctx, e, "reverse kernel launch");
     LocalPass rev;
-    if ((s = local_pass(ctx, (const uint8_t *)ctx->qr.p, rn, (const uint8_t *)ctx->tr.p, rm, sc, Rr, st, rev)) !=
+    if ((s = local_pass(ctx, (const uint8_t *)ctx->qr.p, rn, (const uint8_t *)ctx->tr.p, rm, sc, rshape, st, rev)) !=
         SWH_OK)
         return s;
     if (stats) stats->ms_reverse = rev.ms;

@@ -52,17 +52,17 @@ int pick_rows_per_lane(int64_t n)
 // loaded SIMD and an uneven spread of waves over SIMDs slows it down).  Waves
 // per SIMD by strip height, from sweeps on the long DNA pair: 8 for R=4, 4
 // for R=8, 2 for R=16 and R=32.
-int strip_grid(int64_t nstrips, int R, int limit, int num_cu)
+int strip_grid(int64_t nstrips, int R, int limit, int num_cu, int waves)
 {
     const int forced = env_int("SWH_GRID", 0);
     if (forced > 0) return (int)std::min<int64_t>(forced, nstrips);
-    const int per_simd = R <= 4 ? 8 : R <= 8 ? 4 : 2;
+    const int per_simd = waves > 0 ? waves : R <= 4 ? 8 : R <= 8 ? 4 : 2;
     const int want = std::min(limit, per_simd * 4 * std::max(num_cu, 1));
     return (int)std::max<int64_t>(1, std::min<int64_t>(nstrips, want));
 }
 
 swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, const Scoring &sc, int R, bool local,
-                      hipStream_t st, std::vector<BestCell> *best, float *ms)
+                      hipStream_t st, std::vector<BestCell> *best, float *ms, int waves)
 {
     const int np = (int)probs.size();
     if (np == 0) return SWH_OK;
@@ -124,7 +124,8 @@ swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, cons
     a.abort_flag = (int32_t *)ctx->sync.p + 1;
     a.strip_best = (BestCell *)ctx->strip_best.p;
     a.wait_ticks = wait_ticks(ctx->device);
-    const int grid = strip_grid(total_strips, R, strip_grid_limit(ctx->device, R, local, sc.asize), ctx->num_cu);
+    const int grid = strip_grid(total_strips, R, strip_grid_limit(ctx->device, R, local, sc.asize), ctx->num_cu,
+                                waves);
 
     hipEventRecord(ctx->ev[0], st);
     if ((e = launch_strip(a, R, local, grid, st)) != hipSuccess) return hip_fail(ctx, e, "strip kernel launch");

@@ -27,10 +27,11 @@ inline int64_t cols_padded(int64_t m) { return 64 * (sweep_blocks(m) + 3); }
 
 int env_int(const char *name, int dflt);
 int pick_rows_per_lane(int64_t n);
-int strip_grid(int64_t nstrips, int R, int limit, int num_cu);
+int strip_grid(int64_t nstrips, int R, int limit, int num_cu, int waves = 0);
 
 // One launch over all problems; local mode fills best (one entry per problem).
+// waves: waves per SIMD of the persistent grid, 0 = the rule for R.
 swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, const Scoring &sc, int R, bool local,
-                      hipStream_t st, std::vector<BestCell> *best, float *ms);
+                      hipStream_t st, std::vector<BestCell> *best, float *ms, int waves = 0);
 
 }  // namespace swh

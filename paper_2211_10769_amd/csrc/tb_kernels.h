@@ -40,9 +40,10 @@ struct CrossDesc {
     const Border *fwd;      // fwd[k]: G(r, L+k), D(L+k) = F(r+1, L+k)
     const Border *bwd;      // bwd[k]: G'(row r+1 of the reversed pass, col k), D'
     const uint8_t *bpad;    // bpad[j] = code of B_j, bpad[0] = pad
+    const uint8_t *arow;    // points at the code of A_{r+1}
     int64_t L, J;
-    int32_t arow;           // code of A_{r+1}
     int32_t V;              // forward value of the end node
+    int32_t pad_;
 };
 
 struct CrossOut {
@@ -77,9 +78,10 @@ struct LeafOut {
     int32_t pad_[3];
 };
 
+// Synthetic codes (timing runs of the autotuner): n codes in [0, asize), pad code up to padded.
+hipError_t launch_random_codes(uint8_t *dst, int64_t n, int64_t padded, int32_t asize, uint64_t seed, hipStream_t st);
 hipError_t launch_gather(const GatherDesc *d, int32_t nd, uint8_t pad, hipStream_t st);
 hipError_t launch_border_init(const BorderInit *d, int32_t nd, int32_t o, int32_t e, hipStream_t st);
-hipError_t launch_root_front(Border *dst, int64_t q, int32_t o, int32_t e, hipStream_t st);
 hipError_t launch_cross(const CrossDesc *d, int32_t nd, const int8_t *mat, int32_t asize, int32_t o, int32_t e,
                         CrossOut *out, hipStream_t st);
 hipError_t launch_leaf(const LeafDesc *d, int32_t nd, const int8_t *mat, int32_t asize, int32_t o, int32_t e,

@@ -9,6 +9,8 @@
 // cross at.  Leaves run the full DP with per-cell tie flags and walk back.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "tb_kernels.h"
 
 namespace swh {
@@ -33,6 +35,20 @@ __global__ void gather_kernel(const GatherDesc *descs, uint8_t pad)
     }
 }
 
+// Synthetic codes for timing runs: splitmix64 of (seed + position) mod asize;
+// the pad code asize beyond n.
+__global__ void random_codes_kernel(uint8_t *dst, int64_t n, int64_t padded, int32_t asize, uint64_t seed)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < padded; i += stride) {
+        uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        dst[i] = i < n ? (uint8_t)(z % (uint64_t)asize) : (uint8_t)asize;
+    }
+}
+
 __global__ void border_init_kernel(const BorderInit *descs, int32_t o, int32_t e)
 {
     const BorderInit d = descs[blockIdx.x];
@@ -52,15 +68,6 @@ __global__ void border_init_kernel(const BorderInit *descs, int32_t o, int32_t e
     }
 }
 
-__global__ void root_front_kernel(Border *dst, int64_t q, int32_t o, int32_t e)
-{
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j <= q; j += stride) {
-        const int32_t g = j == 0 ? 0 : (int32_t)(-(int64_t)o - (j - 1) * (int64_t)e);
-        dst[j] = Border{g, g - o};
-    }
-}
-
 // A path from the frontier to the end crosses from mid row r into row r+1
 // through exactly one edge: vertical into F(r+1, j) (forward value D(j),
 // backward value from F(r+1, j) = D'+o) or diagonal G(r, j-1) -> G(r+1, j).
@@ -77,6 +84,7 @@ __global__ void __launch_bounds__(256) cross_kernel(const CrossDesc *descs, cons
     }
     __syncthreads();
     const int64_t w = d.J - d.L + 1;
+    const int arow = *d.arow;
     int cmin = INT32_MAX, count = 0, key = INT32_MAX;
     for (int64_t k = threadIdx.x; k < w; k += blockDim.x) {
         const int64_t j = d.L + k;
@@ -88,7 +96,7 @@ __global__ void __launch_bounds__(256) cross_kernel(const CrossDesc *descs, cons
             key = min(key, (int)(j << 1) | 1);
         }
         if (k >= 1 && j >= 1) {
-            const int s = mat[d.arow * asize + d.bpad[j]];
+            const int s = mat[arow * asize + d.bpad[j]];
             if ((int64_t)d.fwd[k - 1].h + s + bw.h == d.V) {
                 cmin = min(cmin, (int)(j - 1));
                 ++count;
@@ -221,6 +229,14 @@ __global__ void __launch_bounds__(64) leaf_kernel(const LeafDesc *descs, const i
 
 }  // namespace
 
+hipError_t launch_random_codes(uint8_t *dst, int64_t n, int64_t padded, int32_t asize, uint64_t seed, hipStream_t st)
+{
+    if (padded <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((padded + 255) / 256, 65536);
+    hipLaunchKernelGGL(random_codes_kernel, dim3((unsigned)blocks), dim3(256), 0, st, dst, n, padded, asize, seed);
+    return hipGetLastError();
+}
+
 hipError_t launch_gather(const GatherDesc *d, int32_t nd, uint8_t pad, hipStream_t st)
 {
     if (nd <= 0) return hipSuccess;
@@ -235,13 +251,6 @@ hipError_t launch_border_init(const BorderInit *d, int32_t nd, int32_t o, int32_
     return hipGetLastError();
 }
 
-hipError_t launch_root_front(Border *dst, int64_t q, int32_t o, int32_t e, hipStream_t st)
-{
-    int64_t g = (q + 1 + 255) / 256;
-    if (g > 4096) g = 4096;
-    hipLaunchKernelGGL(root_front_kernel, dim3((unsigned)g), dim3(256), 0, st, dst, q, o, e);
-    return hipGetLastError();
-}
 
 hipError_t launch_cross(const CrossDesc *d, int32_t nd, const int8_t *mat, int32_t asize, int32_t o, int32_t e,
                         CrossOut *out, hipStream_t st)

@@ -41,6 +41,7 @@
 #include "strips.h"
 #include "tb_kernels.h"
 #include "traceback.h"
+#include "tune.h"
 
 namespace swh {
 
@@ -83,6 +84,9 @@ struct Arena {
 };
 
 struct Node {
+    int pair = 0;
+    const uint8_t *A = nullptr;      // codes of the pair's rectangle rows (device)
+    const uint8_t *bpad = nullptr;   // pad code, then the rectangle columns (device)
     int64_t r_top, r_bot, L, J;
     const Border *front;      // front[k] <-> column front_L + k, covers [L, J]
     int64_t front_L;
@@ -110,40 +114,58 @@ swh_status upload(swh_ctx *ctx, DevBuf &buf, const std::vector<T> &v, hipStream_
 
 }  // namespace
 
-swh_status traceback(swh_ctx *ctx, const uint8_t *A, int64_t p, const uint8_t *B, int64_t q, const Scoring &sc,
-                     int32_t S, hipStream_t st, std::string &cigar, TracebackStats &ts)
+swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const Scoring &sc, hipStream_t st,
+                           std::vector<std::string> &cigars, TracebackStats &ts)
 {
     const auto t0 = std::chrono::steady_clock::now();
     const uint8_t pad = (uint8_t)sc.asize;
+    const int npairs = (int)in.size();
+    cigars.assign((size_t)npairs, std::string());
+    if (npairs == 0) return SWH_OK;
     Arena arena;
     hipError_t e;
     swh_status s;
 
-    // B with the pad code in front: bpad[j] = code of B_j, bpad[0] = pad
-    uint8_t *bpad = (uint8_t *)arena.get((size_t)q + 2);
-    Border *root_front = (Border *)arena.get(sizeof(Border) * (size_t)(q + 1));
-    if (!bpad || !root_front) return fail(ctx, SWH_E_NOMEM, "traceback arena");
-    if ((e = hipMemsetAsync(bpad, pad, 1, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(bpad + 1, B, (size_t)q, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
-        (e = launch_root_front(root_front, q, sc.o, sc.e, st)) != hipSuccess)
-        return hip_fail(ctx, e, "traceback setup");
-
+    // per pair: B with the pad code in front (bpad[j] = code of B_j, bpad[0] =
+    // pad) and the root frontier G(0, j), F(1, j) = G(0, j) - o
     std::vector<Node> nodes;
-    {
+    nodes.reserve((size_t)npairs * 4);
+    std::vector<GatherDesc> gd0;
+    std::vector<BorderInit> bi0;
+    for (int k = 0; k < npairs; ++k) {
+        const TbInput &x = in[k];
+        uint8_t *bpad = (uint8_t *)arena.get((size_t)x.q + 2);
+        Border *root_front = (Border *)arena.get(sizeof(Border) * (size_t)(x.q + 1));
+        if (!bpad || !root_front) return fail(ctx, SWH_E_NOMEM, "traceback arena");
+        gd0.push_back(GatherDesc{x.B, bpad, 0, x.q, x.q + 1, 1, 1});
+        bi0.push_back(BorderInit{root_front, nullptr, x.q + 1, x.q + 1, 1, 0});
         Node root;
+        root.pair = k;
+        root.A = x.A;
+        root.bpad = bpad;
         root.r_top = 0;
-        root.r_bot = p;
+        root.r_bot = x.p;
         root.L = 0;
-        root.J = q;
+        root.J = x.q;
         root.front = root_front;
         root.front_L = 0;
         root.end_state = 0;
-        root.V = S;
+        root.V = x.S;
         root.ready = true;
         nodes.push_back(root);
     }
+    if ((s = upload(ctx, ctx->tb_misc, gd0, st, "gather table")) != SWH_OK) return s;
+    if ((e = launch_gather((const GatherDesc *)ctx->tb_misc.p, (int32_t)gd0.size(), pad, st)) != hipSuccess)
+        return hip_fail(ctx, e, "gather launch");
+    if ((s = upload(ctx, ctx->tb_leaf, bi0, st, "border table")) != SWH_OK) return s;
+    if ((e = launch_border_init((const BorderInit *)ctx->tb_leaf.p, (int32_t)bi0.size(), sc.o, sc.e, st)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(ctx, e, "traceback setup");
+
     std::vector<char> ops_host;
-    std::vector<int> ready{0};
+    std::vector<int> ready((size_t)npairs);
+    for (int k = 0; k < npairs; ++k) ready[k] = k;
     // SWH_TB_LEAF lowers the leaf size (tests use it to force deep recursion on small inputs)
     const int64_t leaf_cells = std::max<int64_t>(1, std::min<int64_t>(kLeafCells, env_int("SWH_TB_LEAF", (int)kLeafCells)));
 
@@ -192,7 +214,8 @@ swh_status traceback(swh_ctx *ctx, const uint8_t *A, int64_t p, const uint8_t *B
             const int ns = (int)splits.size();
             int64_t maxrows = 1;
             for (int k : splits) maxrows = std::max(maxrows, nodes[k].r_bot - nodes[k].r_top);
-            const int R = pick_rows_per_lane(maxrows / 2);
+            const StripShape shape = tuned_shape(ctx, maxrows / 2);
+            const int R = shape.R;
             std::vector<GatherDesc> gd;
             std::vector<BorderInit> bi;
             std::vector<StripProblem> fwdp, bwdp;
@@ -223,11 +246,11 @@ swh_status traceback(swh_ctx *ctx, const uint8_t *A, int64_t p, const uint8_t *B
                 uint8_t *ft = cp; cp += cols_padded(w);
                 uint8_t *bq = cp; cp += rows_padded(std::max<int64_t>(Pb, 1), R);
                 uint8_t *bt = cp; cp += cols_padded(w);
-                gd.push_back(GatherDesc{A, fq, n.r_top, P, rows_padded(P, R), 1, 0});
-                gd.push_back(GatherDesc{bpad, ft, n.L, w, cols_padded(w), 1, 0});
+                gd.push_back(GatherDesc{n.A, fq, n.r_top, P, rows_padded(P, R), 1, 0});
+                gd.push_back(GatherDesc{n.bpad, ft, n.L, w, cols_padded(w), 1, 0});
                 // backward pass rows A_{r_bot}..A_{r+2}, columns J..L reversed, pad first
-                gd.push_back(GatherDesc{A, bq, n.r_bot - 1, Pb, rows_padded(std::max<int64_t>(Pb, 1), R), -1, 0});
-                gd.push_back(GatherDesc{bpad, bt, n.J, w - 1, cols_padded(w), -1, 1});
+                gd.push_back(GatherDesc{n.A, bq, n.r_bot - 1, Pb, rows_padded(std::max<int64_t>(Pb, 1), R), -1, 0});
+                gd.push_back(GatherDesc{n.bpad, bt, n.J, w - 1, cols_padded(w), -1, 1});
                 Border *fo = (Border *)arena.get(sizeof(Border) * (size_t)cols_padded(w));
                 if (!fo) return fail(ctx, SWH_E_NOMEM, "traceback frontier arena");
                 fwd_out[i] = fo;
@@ -247,21 +270,16 @@ swh_status traceback(swh_ctx *ctx, const uint8_t *A, int64_t p, const uint8_t *B
                 hipSuccess)
                 return hip_fail(ctx, e, "border init launch");
             if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(ctx, e, "traceback setup");
-            if ((s = run_strips(ctx, fwdp, sc, R, false, st, nullptr, nullptr)) != SWH_OK) return s;
-            if (!bwdp.empty() && (s = run_strips(ctx, bwdp, sc, R, false, st, nullptr, nullptr)) != SWH_OK) return s;
+            if ((s = run_strips(ctx, fwdp, sc, R, false, st, nullptr, nullptr, shape.waves)) != SWH_OK) return s;
+            if (!bwdp.empty() &&
+                (s = run_strips(ctx, bwdp, sc, R, false, st, nullptr, nullptr, shape.waves)) != SWH_OK)
+                return s;
 
             std::vector<CrossDesc> cd(ns);
-            std::vector<uint8_t> arow(ns);
             for (int i = 0; i < ns; ++i) {
                 const Node &n = nodes[splits[i]];
-                cd[i] = CrossDesc{fwd_out[i], bwd_out[i], bpad, n.L, n.J, 0, n.V};
+                cd[i] = CrossDesc{fwd_out[i], bwd_out[i], n.bpad, n.A + mid[i], n.L, n.J, n.V, 0};
             }
-            // A_{r+1} codes: read back the few bytes we need
-            for (int i = 0; i < ns; ++i)
-                if ((e = hipMemcpyAsync(&arow[i], A + mid[i], 1, hipMemcpyDeviceToHost, st)) != hipSuccess)
-                    return hip_fail(ctx, e, "row code");
-            if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(ctx, e, "row code");
-            for (int i = 0; i < ns; ++i) cd[i].arow = arow[i];
             if ((s = upload(ctx, ctx->tb_misc, cd, st, "cross table")) != SWH_OK) return s;
             if ((s = ensure(ctx, ctx->tb_front, sizeof(CrossOut) * (size_t)ns, "cross results")) != SWH_OK) return s;
             if ((e = launch_cross((const CrossDesc *)ctx->tb_misc.p, ns, (const int8_t *)ctx->mat.p, sc.asize, sc.o,
@@ -278,6 +296,9 @@ swh_status traceback(swh_ctx *ctx, const uint8_t *A, int64_t p, const uint8_t *B
                 if (co[i].count <= 0 || co[i].cmin < nodes[k].L)
                     return fail(ctx, SWH_E_DEVICE, "traceback: no optimal crossing found (internal error)");
                 Node bot;
+                bot.pair = nodes[k].pair;
+                bot.A = nodes[k].A;
+                bot.bpad = nodes[k].bpad;
                 bot.r_top = mid[i];
                 bot.r_bot = nodes[k].r_bot;
                 bot.L = co[i].cmin;
@@ -290,6 +311,9 @@ swh_status traceback(swh_ctx *ctx, const uint8_t *A, int64_t p, const uint8_t *B
                 bot.is_top_child = false;
                 bot.ready = true;
                 Node top;
+                top.pair = nodes[k].pair;
+                top.A = nodes[k].A;
+                top.bpad = nodes[k].bpad;
                 top.r_top = nodes[k].r_top;
                 top.r_bot = mid[i];
                 top.L = nodes[k].L;
@@ -342,8 +366,8 @@ swh_status traceback(swh_ctx *ctx, const uint8_t *A, int64_t p, const uint8_t *B
                 const Node &n = nodes[leaves[i]];
                 const int64_t P = n.r_bot - n.r_top, w = n.J - n.L + 1;
                 LeafDesc d;
-                d.arows = A + n.r_top;
-                d.bcols = bpad + n.L;
+                d.arows = n.A + n.r_top;
+                d.bcols = n.bpad + n.L;
                 d.front = n.front + (n.L - n.front_L);
                 d.gflags = nullptr;
                 if (P * w > kLeafCells) {
@@ -395,44 +419,51 @@ swh_status traceback(swh_ctx *ctx, const uint8_t *A, int64_t p, const uint8_t *B
         if (!n.leaf && (n.bottom < 0 || n.top < 0 || !nodes[n.top].ready))
             return fail(ctx, SWH_E_DEVICE, "traceback left a subproblem unresolved (internal error)");
     std::string back;
-    back.reserve((size_t)(p + q));
-    std::vector<int> stack{0};
-    while (!stack.empty()) {
-        const int k = stack.back();
-        stack.pop_back();
-        const Node &n = nodes[k];
-        if (n.leaf) {
-            back.append(ops_host.data() + n.ops_off, (size_t)n.nops);
-        } else {
-            stack.push_back(n.top);      // processed after the bottom half
-            stack.push_back(n.bottom);
+    for (int pr = 0; pr < npairs; ++pr) {
+        back.clear();
+        std::vector<int> stack{pr};
+        while (!stack.empty()) {
+            const int k = stack.back();
+            stack.pop_back();
+            const Node &n = nodes[k];
+            if (n.leaf) {
+                back.append(ops_host.data() + n.ops_off, (size_t)n.nops);
+            } else {
+                stack.push_back(n.top);      // processed after the bottom half
+                stack.push_back(n.bottom);
+            }
         }
-    }
-    const Node &root = nodes[0];
-    int64_t rexit = root.leaf ? root.exit_col : -1;
-    if (!root.leaf) {
-        int k = 0;
+        int k = pr;
         while (!nodes[k].leaf) k = nodes[k].top;
-        rexit = nodes[k].exit_col;
-    }
-    if (rexit < 0) return fail(ctx, SWH_E_DEVICE, "traceback: no exit on row 0 (internal error)");
-    back.append((size_t)rexit, 'D');     // leading target residues against a gap, back to (0, 0)
+        const int64_t rexit = nodes[k].exit_col;
+        if (rexit < 0) return fail(ctx, SWH_E_DEVICE, "traceback: no exit on row 0 (internal error)");
+        back.append((size_t)rexit, 'D');     // leading target residues against a gap, back to (0, 0)
 
-    // run-length encode in forward order
-    cigar.clear();
-    int64_t k = (int64_t)back.size() - 1;
-    while (k >= 0) {
-        const char opc = back[(size_t)k];
-        int64_t run = 0;
-        while (k >= 0 && back[(size_t)k] == opc) {
-            ++run;
-            --k;
+        // run-length encode in forward order
+        std::string &cigar = cigars[pr];
+        int64_t q = (int64_t)back.size() - 1;
+        while (q >= 0) {
+            const char opc = back[(size_t)q];
+            int64_t run = 0;
+            while (q >= 0 && back[(size_t)q] == opc) {
+                ++run;
+                --q;
+            }
+            cigar += std::to_string(run);
+            cigar += opc;
         }
-        cigar += std::to_string(run);
-        cigar += opc;
     }
     ts.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return SWH_OK;
+}
+
+swh_status traceback(swh_ctx *ctx, const uint8_t *A, int64_t p, const uint8_t *B, int64_t q, const Scoring &sc,
+                     int32_t S, hipStream_t st, std::string &cigar, TracebackStats &ts)
+{
+    std::vector<std::string> out;
+    swh_status s = traceback_batch(ctx, {TbInput{A, p, B, q, S}}, sc, st, out, ts);
+    if (s == SWH_OK) cigar.swap(out[0]);
+    return s;
 }
 
 }  // namespace swh

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "context.h"
 
@@ -16,6 +17,19 @@ struct TracebackStats {
     int64_t leaves = 0;
     int64_t splits = 0;
 };
+
+struct TbInput {
+    const uint8_t *A;   // p codes on the device (rows of the aligned rectangle)
+    int64_t p;
+    const uint8_t *B;   // q codes on the device (columns)
+    int64_t q;
+    int32_t S;          // optimum of the rectangle (the local score)
+};
+
+// Canonical CIGARs of many rectangles; their subproblems share the launches
+// of each level.
+swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const Scoring &sc, hipStream_t st,
+                           std::vector<std::string> &cigars, TracebackStats &ts);
 
 // Canonical CIGAR of the global alignment of A (p codes, device) against
 // B (q codes, device) whose optimum is S (the local score of the rectangle).

@@ -1,0 +1,25 @@
+// tune.h -- strip shapes of the strip-wavefront kernel: built-in rule or a
+// table measured on the device by the autotuner.
+#pragma once
+
+#include <stdint.h>
+
+#include "context.h"
+
+namespace swh {
+
+struct StripShape {
+    int R;       // rows per lane (strip height 64 R)
+    int waves;   // waves per SIMD of the persistent grid (0: the rule for R)
+};
+
+// Shape for a problem of n rows: the context's tuned table when it has one,
+// else the built-in rule.  SWH_ROWS overrides R.
+StripShape tuned_shape(swh_ctx *ctx, int64_t n);
+inline int tuned_rows_per_lane(swh_ctx *ctx, int64_t n, int64_t) { return tuned_shape(ctx, n).R; }
+
+// Time every (R, waves) candidate on synthetic problems for row buckets
+// 1 Ki, 4 Ki, ... up to max_rows and install the fastest per bucket.
+swh_status autotune(swh_ctx *ctx, const Scoring &sc, int64_t max_rows, double cells_per_trial);
+
+}  // namespace swh

@@ -49,6 +49,10 @@ def parse():
     p.add_argument("--no-db", action="store_true", help="skip the protein database-search leg")
     p.add_argument("--db-size", type=int, default=500_000, help="database sequences of the search leg")
     p.add_argument("--db-steps", type=int, default=3)
+    p.add_argument("--no-pairs", action="store_true", help="skip the batched read-pairs leg")
+    p.add_argument("--pairs", type=int, default=20_000,
+                   help="read/reference pairs of the batched leg (the full configuration has 200,000)")
+    p.add_argument("--autotune", action="store_true", help="run the strip-shape autotuner before timing")
     p.add_argument("--copy-calib-mb", type=int, default=0,
                    help="before the workload, copy a buffer of this many MiB once (a plain copy kernel of "
                         "known size, used to scale the HBM byte counters of a profile)")
@@ -102,6 +106,33 @@ def bench_db(args, swh, eng):
             "saturated_pairs": int(stats[0]["saturated"]), "intra_pairs": int(stats[0]["intra_pairs"])}
 
 
+def bench_pairs(args, swh, eng):
+    """Batched uneven DNA pairs: reads log-uniform in 150-20,000 bp, each
+    reference the read mutated at 1-15% divergence inside a random window of
+    1.2x its length; +1/-3, open 5, extend 2.  One step = one swh_align_batch
+    call over all pairs: scores, coordinates and CIGARs."""
+    import seqgen
+
+    pairs = seqgen.workload4(n_pairs=args.pairs)
+    qs = [p[0] for p in pairs]
+    ts = [p[1] for p in pairs]
+    del pairs
+    sc = swh.Scoring(*seqgen.dna_scoring())
+    qcat, qoff = swh._concat(qs)
+    tcat, toff = swh._concat(ts)
+    del qs, ts
+    t0 = time.perf_counter()
+    _, st = eng.align_batch((qcat, qoff), (tcat, toff), sc, mode="cigar", stats=True)
+    dt = time.perf_counter() - t0
+    cells = st["cells_forward"]
+    return {"workload": f"{args.pairs} read/reference DNA pairs, reads log-uniform 150-20,000 bp, "
+                        f"1-15% divergence, 1.2x windows; scores, coordinates and CIGARs",
+            "pairs_per_s": round(args.pairs / dt, 1), "gcups_forward_cells": round(cells / dt / 1e9, 2),
+            "s_per_batch": round(dt, 3), "cells_forward": cells,
+            "forward_ms": round(st["ms_forward"], 2), "reverse_ms": round(st["ms_reverse"], 2),
+            "traceback_ms": round(st["ms_traceback"], 2), "cells_traceback": st["cells_traceback"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -130,6 +161,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.autotune:
+        eng.autotune(sc, max_rows=max(args.n, 1 << 20))
     for _ in range(args.warmup):
         eng.align_dev(qd, td, sc, mode=args.mode, stream=stream)
     torch.cuda.synchronize()
@@ -176,6 +209,8 @@ def main():
     }
     if not args.no_db:
         out["db_search"] = bench_db(args, swh, eng)
+    if not args.no_pairs:
+        out["batched_pairs"] = bench_pairs(args, swh, eng)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(q, t, args.cpu_rows)
     print(json.dumps(out))

@@ -453,7 +453,7 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
             cigar += opc;
         }
     }
-    ts.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    ts.ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return SWH_OK;
 }
 

@@ -216,29 +216,20 @@ def workload3(n_db: int = 2_000_000, n_queries: int = 20, per_query: int = 50):
     cat, off = protein_db(n_db, 3)
     prng, mrng = rng_for(3, 3), rng_for(3, 2)
     where = prng.choice(n_db, size=n_queries * per_query, replace=False)
-    seqs = {}
-    for k, idx in enumerate(where):
-        seqs[int(idx)] = homolog(mrng, qs[k // per_query])
-    # rebuild the db with the planted sequences in place
+    seqs = {int(idx): homolog(mrng, qs[k // per_query]) for k, idx in enumerate(where)}
+    # rebuild the concatenation with the planted sequences in place
     lens = np.diff(off).copy()
-    for idx, s in seqs.items():
-        lens[idx] = len(s)
+    for idx, h in seqs.items():
+        lens[idx] = len(h)
     noff = np.zeros(n_db + 1, dtype=np.int64)
     noff[1:] = np.cumsum(lens)
-    ncat = np.empty(int(noff[-1]), dtype=np.uint8)
-    # copy untouched runs in bulk
-    planted = np.zeros(n_db, dtype=bool)
-    planted[list(seqs.keys())] = True
-    src_idx = np.nonzero(~planted)[0]
-    # vectorised gather of unplanted sequences
-    starts, ends = off[src_idx], off[src_idx + 1]
-    dst = noff[src_idx]
-    L = ends - starts
-    rep = np.repeat(np.arange(len(src_idx)), L)
-    within = np.arange(int(L.sum())) - np.repeat(np.cumsum(L) - L, L)
-    ncat[dst[rep] + within] = cat[starts[rep] + within]
-    for idx, s in seqs.items():
-        ncat[noff[idx]:noff[idx + 1]] = s
+    pieces, prev = [], 0
+    for idx in sorted(seqs):
+        pieces.append(cat[off[prev]:off[idx]])
+        pieces.append(seqs[idx])
+        prev = idx + 1
+    pieces.append(cat[off[prev]:off[n_db]])
+    ncat = np.concatenate(pieces)
     pairs = [(k // per_query, int(idx)) for k, idx in enumerate(where)]
     return qs, (ncat, noff), pairs
 
@@ -257,6 +248,56 @@ def training_pairs(count: int, workload: int = 3):
         qs.append(q)
         ts.append(t)
     return qs, ts
+
+
+def _concat_pool(seqs):
+    off = np.zeros(len(seqs) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(x) for x in seqs])
+    return np.concatenate(seqs) if seqs else np.zeros(0, np.uint8), off
+
+
+def prefilter_training_set(n_pairs: int = 1_000_000, n_queries: int = 2_000, homologs: int = 25,
+                           n_background: int = 100_000, workload: int = 3):
+    """Labelled-pair inputs for the prefilter network: a sequence pool and
+    (row, column) index pairs into it, half unrelated and half related.
+
+    Pool: n_queries query-like sequences (log-uniform 100..5,000), for each
+    `homologs` mutated copies (identity U(0.30, 0.90), 5% of positions in
+    indels), and n_background database-like sequences (the db length law).
+    Unrelated pairs: a query-like row against a background column.  Related
+    pairs: two distinct members of one family (the query and its copies),
+    drawn without repetition while the families hold enough pairs.  Seed streams are disjoint from the evaluation
+    queries and database.
+    """
+    rng = rng_for(workload, 4)
+    qlen = query_lengths(rng, n_queries)
+    qres = random_protein(rng, int(qlen.sum()))
+    qoff = np.concatenate([[0], np.cumsum(qlen)])
+    qseqs = [qres[qoff[i]:qoff[i + 1]] for i in range(n_queries)]
+    hseqs = [homolog(rng, q) for q in qseqs for _ in range(homologs)]
+    blen = db_lengths(rng, n_background)
+    bres = random_protein(rng, int(blen.sum()))
+    boff = np.concatenate([[0], np.cumsum(blen)])
+    bseqs = [bres[boff[i]:boff[i + 1]] for i in range(n_background)]
+    cat, off = _concat_pool(qseqs + hseqs + bseqs)
+    h0, b0 = n_queries, n_queries + n_queries * homologs
+    n_unrel = n_pairs // 2
+    n_rel = n_pairs - n_unrel
+    ur = rng.integers(0, n_queries, size=n_unrel)
+    uc = b0 + rng.integers(0, n_background, size=n_unrel)
+    # family f: member 0 = query f, members 1..homologs = its copies
+    fam = homologs + 1
+    npf = fam * (fam - 1) // 2
+    pick = rng.choice(n_queries * npf, size=n_rel, replace=n_rel > n_queries * npf)
+    f, w = pick // npf, pick % npf
+    iu, ju = np.triu_indices(fam, k=1)
+    a, b = iu[w], ju[w]
+    member = lambda fi, k: np.where(k == 0, fi, h0 + fi * homologs + (k - 1))
+    rr, rc = member(f, a), member(f, b)
+    rows = np.concatenate([ur, rr]).astype(np.int32)
+    cols = np.concatenate([uc, rc]).astype(np.int32)
+    perm = rng.permutation(n_pairs)
+    return cat, off, rows[perm], cols[perm]
 
 
 def read_pair(rng, L: int) -> tuple[np.ndarray, np.ndarray]:

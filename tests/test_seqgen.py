@@ -69,3 +69,19 @@ def test_mutate_identity():
     t = seqgen.mutate(rng, q, 0.3, 0.0, protein=True)
     assert len(t) == len(q)
     assert abs((t != q).mean() - 0.3) < 0.02
+
+
+def test_prefilter_training_set_shape():
+    cat, off, rows, cols = seqgen.prefilter_training_set(n_pairs=4000, n_queries=40, homologs=5,
+                                                         n_background=300)
+    n_pool = 40 + 40 * 5 + 300
+    assert len(off) == n_pool + 1 and off[-1] == len(cat)
+    assert len(rows) == len(cols) == 4000
+    assert rows.min() >= 0 and cols.max() < n_pool
+    fam = lambda i: np.where(i < 40, i, np.where(i < 240, (i - 40) // 5, -1))
+    related = (fam(rows) == fam(cols)) & (fam(cols) >= 0)
+    unrelated = (rows < 40) & (cols >= 240)
+    assert related.sum() == 2000 and unrelated.sum() == 2000
+    assert np.all(rows != cols)
+    again = seqgen.prefilter_training_set(n_pairs=4000, n_queries=40, homologs=5, n_background=300)
+    assert np.array_equal(again[0], cat) and np.array_equal(again[2], rows)

@@ -225,6 +225,126 @@ swh_status swh_db_search(swh_ctx *ctx, const swh_db *db, int32_t nq, const char 
 swh_status swh_db_scores(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat,
                          const int64_t *q_off, int32_t *scores, swh_search_stats *stats);
 
+/* ------------------------------------------------------------------------
+ * Learned prefilter for the database search.  The paper runs the search
+ * exhaustively (Background: database similarity search); this growth ranks
+ * the database for each query with a small network that predicts the
+ * Smith-Waterman score, rescores the best-ranked fraction exactly with the
+ * search kernels above, and keeps the exhaustive search as its fallback, so
+ * every reported score is an exact one.
+ *
+ * Features of a (query, database sequence) pair: the 400 products
+ * f_q[k] f_t[k] of their dipeptide frequencies (over the first 20 alphabet
+ * symbols, the standard residues; f = counts / (L - 1)) and ln(min(L_q, L_t)),
+ * normalised with the training set's mean and standard deviation.  Network:
+ * 401 -> 256 (ReLU) -> 256 (ReLU) -> 1, predicting ln(1 + S); bfloat16
+ * products with float32 accumulation on the GPU, float32 master weights.
+ * Parameters are one float array of SWH_MODEL_PARAMS entries: W1 [256][401],
+ * b1 [256], W2 [256][256], b2 [256], w3 [256], b3.
+ * ------------------------------------------------------------------------ */
+
+#define SWH_MODEL_PARAMS 168961
+#define SWH_MODEL_INPUTS 401
+
+typedef struct swh_model swh_model;   /* weights (device), normalisation, Adam state */
+
+typedef struct {
+    uint32_t struct_size;
+    uint32_t reserved;
+    int32_t  epochs;       /* passes over the pairs (>= 1) */
+    int32_t  batch;        /* pairs per Adam step, a multiple of 64 (the last partial batch of an epoch is dropped) */
+    double   lr;           /* Adam step size (betas 0.9, 0.999, eps 1e-8) */
+    uint64_t seed;         /* batch order */
+} swh_train_cfg;
+
+typedef struct {
+    uint32_t struct_size;
+    uint32_t reserved;
+    double   first_epoch_loss;   /* mean squared error over the first epoch */
+    double   final_epoch_loss;
+    double   ms_label, ms_features, ms_train;
+    double   cells_label;        /* DP cells of the engine's labelling pass */
+    int64_t  steps;
+} swh_train_stats;
+
+typedef struct {
+    uint32_t struct_size;
+    uint32_t reserved;
+    int64_t  candidates;         /* pairs kept by the ranking, all queries */
+    int64_t  audited;            /* pairs rescored as audit sample */
+    int64_t  fallbacks;          /* queries that fell back to the exhaustive search */
+    double   cells_rescored;     /* DP cells of the exact rescoring (candidates + audit) */
+    double   cells_exhaustive;   /* DP cells an exhaustive search would take */
+    double   ms_features, ms_predict, ms_select, ms_rescore, ms_topk, ms_fallback;
+} swh_prefilter_stats;
+
+/* A model for `scoring` (alphabet of >= 20 symbols).  theta (SWH_MODEL_PARAMS
+ * floats), mu and sd (SWH_MODEL_INPUTS floats each) may be NULL: He-normal
+ * weights drawn from seed, zero biases, mu = 0, sd = 1.  Host pointers,
+ * copied. */
+swh_status swh_model_create(swh_ctx *ctx, const swh_scoring *scoring, const float *theta, const float *mu,
+                            const float *sd, uint64_t seed, swh_model **out);
+void       swh_model_destroy(swh_model *model);
+/* Copy out (NULL entries skipped) / replace (NULL: keep) the parameters and the
+ * normalisation; replacing resets the Adam state. */
+swh_status swh_model_get(swh_ctx *ctx, const swh_model *model, float *theta, float *mu, float *sd);
+swh_status swh_model_set(swh_ctx *ctx, swh_model *model, const float *theta, const float *mu, const float *sd);
+/* Binary model file: magic "SWHMLP01", alphabet size, parameter count,
+ * parameters, mu, sd (little-endian float32).  SWH_E_INVAL on I/O errors or a
+ * file of another kind. */
+swh_status swh_model_save(swh_ctx *ctx, const swh_model *model, const char *path);
+swh_status swh_model_load(swh_ctx *ctx, const char *path, swh_model **out);
+
+/*
+ * Train `model` on labelled pairs.  Sequences: a pool seq_cat[seq_off[i] ..
+ * seq_off[i+1]) of nseq entries; pair p is (pool[pair_row[p]],
+ * pool[pair_col[p]]).  Labels: scores (npairs exact local scores) or, when
+ * NULL, the engine's own score pass over every pair (the scoring of
+ * `scoring`); labels_out (optional, npairs) receives the labels used.  The
+ * feature normalisation is recomputed from these pairs, then cfg->epochs
+ * passes of Adam over shuffled batches run on the GPU.  Errors:
+ * SWH_E_INVAL (bad indices, cfg, alphabet), SWH_E_ALPHABET, SWH_E_RANGE,
+ * SWH_E_NOMEM, SWH_E_DEVICE.
+ */
+swh_status swh_prefilter_train(swh_ctx *ctx, swh_model *model, const swh_scoring *scoring, int64_t nseq,
+                               const char *seq_cat, const int64_t *seq_off, int64_t npairs,
+                               const int32_t *pair_row, const int32_t *pair_col, const int32_t *scores,
+                               const swh_train_cfg *cfg, int32_t *labels_out, swh_train_stats *stats);
+
+/*
+ * Top-k search through the prefilter: per query, the database sequences whose
+ * prediction is at or above the ceil(rescore_frac * ndb)-th largest (ties
+ * kept, at least k) are rescored exactly, plus an audit sample of the rest
+ * (pair (q, i) is audited when the high 32 bits of splitmix64(audit_seed +
+ * 0x9E3779B97F4A7C15 (q 2^32 + i + 1)) are below audit_frac 2^32).  A query
+ * whose top-k would contain an audited pair, or that has fewer than k
+ * candidates, is searched exhaustively instead.  hits as swh_db_search.
+ * 0 < rescore_frac <= 1, 0 <= audit_frac <= 1, 1 <= k <= 32; the database
+ * and the model must use alphabets of the same size.
+ */
+swh_status swh_prefilter_search(swh_ctx *ctx, const swh_model *model, swh_db *db, int32_t nq,
+                                const char *q_cat, const int64_t *q_off, int32_t k, double rescore_frac,
+                                double audit_frac, uint64_t audit_seed, swh_hit *hits,
+                                swh_prefilter_stats *stats);
+
+/* Predicted ln(1 + S) for every (query, database sequence): pred[q * ndb + i]. */
+swh_status swh_prefilter_predict(swh_ctx *ctx, const swh_model *model, swh_db *db, int32_t nq,
+                                 const char *q_cat, const int64_t *q_off, float *pred);
+
+/* Dipeptide counts of nseq sequences: counts[i * 400 + 20 a + b] (first 20
+ * alphabet symbols; pairs with any other symbol are not counted). */
+swh_status swh_dipeptide_counts(swh_ctx *ctx, const swh_scoring *scoring, int64_t nseq, const char *seq_cat,
+                                const int64_t *seq_off, int32_t *counts);
+
+/* One forward and backward pass of the model on B normalised inputs
+ * z [B][SWH_MODEL_INPUTS] with targets y [B]: *loss = mean squared error,
+ * grad = its gradient (SWH_MODEL_PARAMS floats).  B a multiple of 64. */
+swh_status swh_mlp_grad(swh_ctx *ctx, swh_model *model, int32_t B, const float *z, const float *y,
+                        double *loss, float *grad);
+/* `steps` Adam steps of size lr on one fixed batch (as swh_mlp_grad). */
+swh_status swh_mlp_train_steps(swh_ctx *ctx, swh_model *model, int32_t B, const float *z, const float *y,
+                               int32_t steps, double lr);
+
 #ifdef __cplusplus
 }
 #endif

@@ -184,6 +184,26 @@ def predict(P: dict, mu: np.ndarray, sd: np.ndarray, query, db_seqs, alphabet: s
     return forward(P, (X - mu) / sd)
 
 
+def predict_folded(P: dict, mu: np.ndarray, sd: np.ndarray, query, db_seqs, alphabet: str, rnd=None):
+    """The same predictions through the query-folded first layer:
+        W1 z = (W1 diag(f_q / sd)) f_t + (b1 - W1 (mu / sd)) + W1[:, 400] z_400
+    (exact algebra).  rnd, when given (for example bf16), rounds the operands
+    of the two matrix products: the folded weights, the database
+    frequencies, the hidden activations and W2."""
+    r = rnd if rnd is not None else (lambda a: np.asarray(a, dtype=np.float64))
+    fq = frequencies(query, alphabet)
+    Lq = len(bytes(query))
+    W1 = P["W1"]
+    A = r(W1[:, :NDIP] * (fq / sd[:NDIP])[None, :])
+    c = P["b1"] - W1[:, :NDIP] @ (mu[:NDIP] / sd[:NDIP])
+    w1x = W1[:, NDIP] / sd[NDIP]
+    F = r(np.stack([frequencies(d, alphabet) for d in db_seqs]))
+    z400 = np.array([(np.log(max(1, min(Lq, len(bytes(d))))) - mu[NDIP]) for d in db_seqs])
+    h1 = r(relu(F @ A.T + c + np.outer(z400, w1x)))
+    h2 = relu(h1 @ r(P["W2"]).T + P["b2"])
+    return h2 @ P["w3"] + P["b3"][0]
+
+
 def recall_at_k(found_idx, true_idx) -> float:
     """|found top-k  intersect  true top-k| / k, averaged over queries."""
     found_idx = np.asarray(found_idx)

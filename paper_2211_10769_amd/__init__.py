@@ -245,6 +245,140 @@ class Database:
         return out, self._stats(st)
 
 
+def _f32(x, n=None):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+class Model:
+    """The prefilter network (swh_model): weights on the device, feature normalisation, Adam state."""
+
+    def __init__(self, engine: Engine, scoring, theta=None, mu=None, sd=None, seed: int = 0, _handle=None):
+        self.eng = engine
+        self.sc = Scoring.of(scoring) if scoring is not None else None
+        if _handle is not None:
+            self.h = _handle
+            return
+        th = _f32(theta, _lib.MODEL_PARAMS) if theta is not None else None
+        m = _f32(mu, _lib.MODEL_INPUTS) if mu is not None else None
+        s = _f32(sd, _lib.MODEL_INPUTS) if sd is not None else None
+        h = ctypes.c_void_p()
+        rc = engine.L.swh_model_create(engine.h, ctypes.byref(self.sc.c),
+                                       th.ctypes.data if th is not None else None,
+                                       m.ctypes.data if m is not None else None,
+                                       s.ctypes.data if s is not None else None, int(seed), ctypes.byref(h))
+        engine._check(rc)
+        self.h = h
+
+    @classmethod
+    def load(cls, engine: Engine, path: str) -> "Model":
+        h = ctypes.c_void_p()
+        engine._check(engine.L.swh_model_load(engine.h, path.encode(), ctypes.byref(h)))
+        return cls(engine, None, _handle=h)
+
+    def save(self, path: str):
+        self.eng._check(self.eng.L.swh_model_save(self.eng.h, self.h, path.encode()))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.eng.L.swh_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get(self):
+        th = np.zeros(_lib.MODEL_PARAMS, np.float32)
+        mu = np.zeros(_lib.MODEL_INPUTS, np.float32)
+        sd = np.zeros(_lib.MODEL_INPUTS, np.float32)
+        self.eng._check(self.eng.L.swh_model_get(self.eng.h, self.h, th.ctypes.data, mu.ctypes.data, sd.ctypes.data))
+        return th, mu, sd
+
+    def set(self, theta=None, mu=None, sd=None):
+        th = _f32(theta, _lib.MODEL_PARAMS) if theta is not None else None
+        m = _f32(mu, _lib.MODEL_INPUTS) if mu is not None else None
+        s = _f32(sd, _lib.MODEL_INPUTS) if sd is not None else None
+        self.eng._check(self.eng.L.swh_model_set(self.eng.h, self.h, th.ctypes.data if th is not None else None,
+                                                 m.ctypes.data if m is not None else None,
+                                                 s.ctypes.data if s is not None else None))
+
+    def train(self, pool, rows, cols, scoring, scores=None, epochs: int = 4, batch: int = 4096, lr: float = 1e-3,
+              seed: int = 0, return_labels: bool = False):
+        """Train on labelled pairs (pool sequences, row/column indices); labels from the engine when scores is None."""
+        sc = Scoring.of(scoring)
+        cat, off = _concat(pool)
+        r = np.ascontiguousarray(rows, dtype=np.int32)
+        c = np.ascontiguousarray(cols, dtype=np.int32)
+        n = len(r)
+        sco = np.ascontiguousarray(scores, dtype=np.int32) if scores is not None else None
+        lab = np.zeros(n, np.int32) if return_labels else None
+        cfg = _lib.swh_train_cfg(ctypes.sizeof(_lib.swh_train_cfg), 0, int(epochs), int(batch), float(lr), int(seed))
+        st = _lib.swh_train_stats(ctypes.sizeof(_lib.swh_train_stats))
+        rc = self.eng.L.swh_prefilter_train(self.eng.h, self.h, ctypes.byref(sc.c), len(off) - 1,
+                                            cat.ctypes.data if len(cat) else None, off.ctypes.data, n,
+                                            r.ctypes.data, c.ctypes.data,
+                                            sco.ctypes.data if sco is not None else None, ctypes.byref(cfg),
+                                            lab.ctypes.data if lab is not None else None, ctypes.byref(st))
+        self.eng._check(rc)
+        stats = {k: getattr(st, k) for k, _ in st._fields_[2:]}
+        return (stats, lab) if return_labels else stats
+
+    def grad(self, z, y):
+        z = _f32(z)
+        y = _f32(y)
+        B = len(y)
+        g = np.zeros(_lib.MODEL_PARAMS, np.float32)
+        loss = ctypes.c_double()
+        self.eng._check(self.eng.L.swh_mlp_grad(self.eng.h, self.h, B, z.ctypes.data, y.ctypes.data,
+                                                ctypes.byref(loss), g.ctypes.data))
+        return loss.value, g
+
+    def train_steps(self, z, y, steps: int, lr: float = 1e-3):
+        z = _f32(z)
+        y = _f32(y)
+        self.eng._check(self.eng.L.swh_mlp_train_steps(self.eng.h, self.h, len(y), z.ctypes.data, y.ctypes.data,
+                                                       int(steps), float(lr)))
+
+    def predict(self, db: "Database", queries):
+        cat, off = _concat(queries)
+        nq = len(off) - 1
+        out = np.zeros((nq, db.ndb), np.float32)
+        self.eng._check(self.eng.L.swh_prefilter_predict(self.eng.h, self.h, db.h, nq,
+                                                         cat.ctypes.data if len(cat) else None, off.ctypes.data,
+                                                         out.ctypes.data))
+        return out
+
+    def search(self, db: "Database", queries, k: int = 10, rescore_frac: float = 0.05, audit_frac: float = 0.002,
+               audit_seed: int = 0x5EED):
+        """Top-k through the prefilter: (indices [nq, k], exact scores [nq, k], stats dict)."""
+        cat, off = _concat(queries)
+        nq = len(off) - 1
+        hits = (_lib.swh_hit * max(1, nq * k))()
+        st = _lib.swh_prefilter_stats(ctypes.sizeof(_lib.swh_prefilter_stats))
+        rc = self.eng.L.swh_prefilter_search(self.eng.h, self.h, db.h, nq, cat.ctypes.data if len(cat) else None,
+                                             off.ctypes.data, k, float(rescore_frac), float(audit_frac),
+                                             int(audit_seed), hits, ctypes.byref(st))
+        self.eng._check(rc)
+        idx = np.array([hits[i].db_index for i in range(nq * k)], dtype=np.int64).reshape(nq, k)
+        sco = np.array([hits[i].score for i in range(nq * k)], dtype=np.int32).reshape(nq, k)
+        return idx, sco, {k2: getattr(st, k2) for k2, _ in st._fields_[2:]}
+
+
+def dipeptide_counts(engine: Engine, seqs, scoring) -> np.ndarray:
+    sc = Scoring.of(scoring)
+    cat, off = _concat(seqs)
+    n = len(off) - 1
+    out = np.zeros((n, 400), np.int32)
+    engine._check(engine.L.swh_dipeptide_counts(engine.h, ctypes.byref(sc.c), n, cat.ctypes.data if len(cat) else None,
+                                                off.ctypes.data, out.ctypes.data))
+    return out
+
+
 def dna_scoring(match: int = 1, mismatch: int = -3, gap_open: int = 5, gap_extend: int = 2) -> Scoring:
     mat = np.full((4, 4), mismatch, dtype=np.int8)
     np.fill_diagonal(mat, match)

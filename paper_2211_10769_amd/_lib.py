@@ -50,6 +50,29 @@ class swh_tune_entry(ctypes.Structure):
     _fields_ = [("max_rows", ctypes.c_int64), ("rows_per_lane", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32)]
 
 
+class swh_train_cfg(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("epochs", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("lr", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class swh_train_stats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("first_epoch_loss", ctypes.c_double), ("final_epoch_loss", ctypes.c_double),
+                ("ms_label", ctypes.c_double), ("ms_features", ctypes.c_double), ("ms_train", ctypes.c_double),
+                ("cells_label", ctypes.c_double), ("steps", ctypes.c_int64)]
+
+
+class swh_prefilter_stats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("candidates", ctypes.c_int64), ("audited", ctypes.c_int64), ("fallbacks", ctypes.c_int64),
+                ("cells_rescored", ctypes.c_double), ("cells_exhaustive", ctypes.c_double),
+                ("ms_features", ctypes.c_double), ("ms_predict", ctypes.c_double), ("ms_select", ctypes.c_double),
+                ("ms_rescore", ctypes.c_double), ("ms_topk", ctypes.c_double), ("ms_fallback", ctypes.c_double)]
+
+
+MODEL_PARAMS = 168961
+MODEL_INPUTS = 401
+
 # name -> (restype, argtypes); the C-ABI surface declared in include/swh.h
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -69,6 +92,22 @@ SIGNATURES = {
     "swh_autotune": (ctypes.c_int, [_P, ctypes.POINTER(swh_scoring), _I64, ctypes.c_double]),
     "swh_tune_get": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "swh_tune_set": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
+    "swh_model_create": (ctypes.c_int, [_P, ctypes.POINTER(swh_scoring), _P, _P, _P, ctypes.c_uint64,
+                                        ctypes.POINTER(_P)]),
+    "swh_model_destroy": (None, [_P]),
+    "swh_model_get": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "swh_model_set": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "swh_model_save": (ctypes.c_int, [_P, _P, ctypes.c_char_p]),
+    "swh_model_load": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.POINTER(_P)]),
+    "swh_prefilter_train": (ctypes.c_int, [_P, _P, ctypes.POINTER(swh_scoring), _I64, _P, _P, _I64, _P, _P, _P,
+                                           ctypes.POINTER(swh_train_cfg), _P, ctypes.POINTER(swh_train_stats)]),
+    "swh_prefilter_search": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_uint64, _P,
+                                            ctypes.POINTER(swh_prefilter_stats)]),
+    "swh_prefilter_predict": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, _P, _P]),
+    "swh_dipeptide_counts": (ctypes.c_int, [_P, ctypes.POINTER(swh_scoring), _I64, _P, _P, _P]),
+    "swh_mlp_grad": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, ctypes.POINTER(ctypes.c_double), _P]),
+    "swh_mlp_train_steps": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.c_double]),
     "swh_db_create": (ctypes.c_int, [_P, _I64, _P, _P, ctypes.POINTER(swh_scoring), ctypes.POINTER(_P)]),
     "swh_db_destroy": (None, [_P]),
     "swh_db_search": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P,

@@ -41,17 +41,9 @@ swh_status upload(swh_ctx *ctx, DevBuf &buf, const std::vector<T> &v, hipStream_
     return SWH_OK;
 }
 
-struct Pass {
-    const uint8_t *q;   // codes of the rows (device, unpadded)
-    int64_t n;
-    const uint8_t *t;   // codes of the columns
-    int64_t m;
-    int step;           // +1: rows/columns as stored; -1: reversed, q and t point at the last code
-};
+}  // namespace
 
-// One local pass over many (rows, columns) problems: padded copies, zeroed
-// borders, strip launches grouped by strip height and cut into chunks.
-swh_status local_passes(swh_ctx *ctx, const std::vector<Pass> &ps, const Scoring &sc, hipStream_t st,
+swh_status score_passes(swh_ctx *ctx, const std::vector<PairPass> &ps, const Scoring &sc, hipStream_t st,
                         std::vector<BestCell> &best, double &ms_total)
 {
     const size_t np = ps.size();
@@ -78,7 +70,7 @@ swh_status local_passes(swh_ctx *ctx, const std::vector<Pass> &ps, const Scoring
         size_t end = k;
         int64_t bytes = 0, nb = 0, nq = 0, nt = 0;
         while (end < np && same(order[end], lead)) {
-            const Pass &p = ps[order[end]];
+            const PairPass &p = ps[order[end]];
             if (p.n == 0 || p.m == 0) {
                 ++end;
                 continue;
@@ -102,7 +94,7 @@ swh_status local_passes(swh_ctx *ctx, const std::vector<Pass> &ps, const Scoring
         uint8_t *qp = (uint8_t *)ctx->bq.p, *tp = (uint8_t *)ctx->bt.p;
         Border *bp = (Border *)ctx->bborder.p;
         for (size_t i = k; i < end; ++i) {
-            const Pass &p = ps[order[i]];
+            const PairPass &p = ps[order[i]];
             if (p.n == 0 || p.m == 0) continue;
             const int64_t qpad = rows_padded(p.n, Rk), tpad = cols_padded(p.m);
             gd.push_back(GatherDesc{p.q, qp, 0, p.n, qpad, p.step, 0});
@@ -127,8 +119,6 @@ swh_status local_passes(swh_ctx *ctx, const std::vector<Pass> &ps, const Scoring
     }
     return SWH_OK;
 }
-
-}  // namespace
 
 swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const int64_t *q_off, const char *t_cat,
                        const int64_t *t_off, const Scoring &sc, int mode, swh_alignment *out, char *cigar_cat,
@@ -190,16 +180,16 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
     const uint8_t *qc = (const uint8_t *)ctx->qc.p, *tc = (const uint8_t *)ctx->tc.p;
 
     // ---- resolution: forward local pass of every pair
-    std::vector<Pass> ps((size_t)npairs);
+    std::vector<PairPass> ps((size_t)npairs);
     double cells = 0.0;
     for (int64_t i = 0; i < npairs; ++i) {
-        ps[i] = Pass{qc + (q_off[i] - qbase), q_off[i + 1] - q_off[i], tc + (t_off[i] - tbase),
+        ps[i] = PairPass{qc + (q_off[i] - qbase), q_off[i + 1] - q_off[i], tc + (t_off[i] - tbase),
                      t_off[i + 1] - t_off[i], 1};
         cells += (double)ps[i].n * (double)ps[i].m;
     }
     std::vector<BestCell> fwd;
     double ms_fwd = 0.0, ms_rev = 0.0;
-    if ((s = local_passes(ctx, ps, sc, st, fwd, ms_fwd)) != SWH_OK) return s;
+    if ((s = score_passes(ctx, ps, sc, st, fwd, ms_fwd)) != SWH_OK) return s;
     if (stats) {
         stats->cells_forward = cells;
         stats->ms_forward = ms_fwd;
@@ -216,12 +206,12 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
     if (mode == SWH_MODE_SCORE) return SWH_OK;
 
     // ---- reverse pass over the reversed prefixes ending at each end cell
-    std::vector<Pass> rp;
+    std::vector<PairPass> rp;
     rp.reserve(pos_pairs.size());
     for (int64_t i : pos_pairs)
-        rp.push_back(Pass{ps[i].q + out[i].q_end, out[i].q_end + 1, ps[i].t + out[i].t_end, out[i].t_end + 1, -1});
+        rp.push_back(PairPass{ps[i].q + out[i].q_end, out[i].q_end + 1, ps[i].t + out[i].t_end, out[i].t_end + 1, -1});
     std::vector<BestCell> rev;
-    if ((s = local_passes(ctx, rp, sc, st, rev, ms_rev)) != SWH_OK) return s;
+    if ((s = score_passes(ctx, rp, sc, st, rev, ms_rev)) != SWH_OK) return s;
     if (stats) stats->ms_reverse = ms_rev;
     for (size_t k = 0; k < pos_pairs.size(); ++k) {
         const int64_t i = pos_pairs[k];

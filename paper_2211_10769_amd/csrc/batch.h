@@ -3,9 +3,25 @@
 
 #include <stdint.h>
 
+#include <vector>
+
 #include "context.h"
 
 namespace swh {
+
+// One local score pass: rows q[0..n) against columns t[0..m) (device codes);
+// step -1 walks both backwards from the given pointers (reversed prefixes).
+struct PairPass {
+    const uint8_t *q;
+    int64_t n;
+    const uint8_t *t;
+    int64_t m;
+    int step;
+};
+// Score, end row and end column of every pass (launches grouped by strip
+// shape, most expensive first, chunked to bound device memory).
+swh_status score_passes(swh_ctx *ctx, const std::vector<PairPass> &ps, const Scoring &sc, hipStream_t st,
+                        std::vector<BestCell> &best, double &ms_total);
 
 swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const int64_t *q_off, const char *t_cat,
                        const int64_t *t_off, const Scoring &sc, int mode, swh_alignment *out, char *cigar_cat,

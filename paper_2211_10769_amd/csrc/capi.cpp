@@ -9,6 +9,7 @@
 #include "context.h"
 #include "batch.h"
 #include "db.h"
+#include "prefilter.h"
 #include "tune.h"
 
 namespace swh {
@@ -312,6 +313,185 @@ swh_status swh_db_scores(swh_ctx *ctx, const swh_db *db, int32_t nq, const char 
 {
     if (ctx && !scores) return fail(ctx, SWH_E_INVAL, "scores is NULL");
     return search_common(ctx, db, nq, q_cat, q_off, 0, nullptr, scores, stats);
+}
+
+static swh_status model_ok(swh_ctx *ctx, const swh_model *m)
+{
+    if (!m) return fail(ctx, SWH_E_INVAL, "model is NULL");
+    if (m->device != ctx->device) return fail(ctx, SWH_E_INVAL, "model lives on another device");
+    return SWH_OK;
+}
+
+static swh_status enter(swh_ctx *ctx)
+{
+    ctx->err.clear();
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SWH_E_DEVICE, "hipSetDevice failed");
+    return SWH_OK;
+}
+
+swh_status swh_model_create(swh_ctx *ctx, const swh_scoring *scoring, const float *theta, const float *mu,
+                            const float *sd, uint64_t seed, swh_model **out)
+{
+    if (!ctx) return SWH_E_INVAL;
+    swh_status s = enter(ctx);
+    if (s != SWH_OK) return s;
+    if (!out) return fail(ctx, SWH_E_INVAL, "out is NULL");
+    *out = nullptr;
+    Scoring sc;
+    if ((s = make_scoring(ctx, scoring, sc)) != SWH_OK) return s;
+    return model_create(ctx, sc, theta, mu, sd, seed, out);
+}
+
+void swh_model_destroy(swh_model *model) { model_destroy(model); }
+
+swh_status swh_model_get(swh_ctx *ctx, const swh_model *model, float *theta, float *mu, float *sd)
+{
+    if (!ctx) return SWH_E_INVAL;
+    swh_status s = enter(ctx);
+    if (s == SWH_OK) s = model_ok(ctx, model);
+    return s != SWH_OK ? s : model_get(ctx, model, theta, mu, sd);
+}
+
+swh_status swh_model_set(swh_ctx *ctx, swh_model *model, const float *theta, const float *mu, const float *sd)
+{
+    if (!ctx) return SWH_E_INVAL;
+    swh_status s = enter(ctx);
+    if (s == SWH_OK) s = model_ok(ctx, model);
+    return s != SWH_OK ? s : model_set(ctx, model, theta, mu, sd);
+}
+
+swh_status swh_model_save(swh_ctx *ctx, const swh_model *model, const char *path)
+{
+    if (!ctx) return SWH_E_INVAL;
+    swh_status s = enter(ctx);
+    if (s == SWH_OK) s = model_ok(ctx, model);
+    if (s == SWH_OK && !path) s = fail(ctx, SWH_E_INVAL, "path is NULL");
+    return s != SWH_OK ? s : model_save(ctx, model, path);
+}
+
+swh_status swh_model_load(swh_ctx *ctx, const char *path, swh_model **out)
+{
+    if (!ctx) return SWH_E_INVAL;
+    swh_status s = enter(ctx);
+    if (s != SWH_OK) return s;
+    if (!path || !out) return fail(ctx, SWH_E_INVAL, "path or out is NULL");
+    *out = nullptr;
+    return model_load(ctx, path, out);
+}
+
+swh_status swh_prefilter_train(swh_ctx *ctx, swh_model *model, const swh_scoring *scoring, int64_t nseq,
+                               const char *seq_cat, const int64_t *seq_off, int64_t npairs, const int32_t *pair_row,
+                               const int32_t *pair_col, const int32_t *scores, const swh_train_cfg *cfg,
+                               int32_t *labels_out, swh_train_stats *stats)
+{
+    if (!ctx) return SWH_E_INVAL;
+    swh_status s = enter(ctx);
+    if (s == SWH_OK) s = model_ok(ctx, model);
+    if (s != SWH_OK) return s;
+    Scoring sc;
+    if ((s = make_scoring(ctx, scoring, sc)) != SWH_OK) return s;
+    if (sc.asize != model->asize) return fail(ctx, SWH_E_INVAL, "scoring alphabet differs from the model's");
+    if (!cfg || cfg->struct_size < sizeof(swh_train_cfg)) return fail(ctx, SWH_E_INVAL, "cfg missing or too small");
+    if (cfg->epochs < 1 || cfg->batch < 64 || cfg->batch % 64 != 0 || !(cfg->lr > 0.0))
+        return fail(ctx, SWH_E_INVAL, "cfg: epochs >= 1, batch a positive multiple of 64, lr > 0");
+    if (nseq < 0 || npairs < cfg->batch || (nseq > 0 && !seq_off) || !pair_row || !pair_col)
+        return fail(ctx, SWH_E_INVAL, "need a sequence pool and at least one batch of pairs");
+    if (stats && stats->struct_size < sizeof(swh_train_stats)) return fail(ctx, SWH_E_INVAL, "stats too small");
+    if (npairs >= ((int64_t)1 << 31)) return fail(ctx, SWH_E_RANGE, "more than 2^31 - 1 pairs");
+    TrainStats ts;
+    s = prefilter_train(ctx, sc, nseq, seq_cat, seq_off, npairs, pair_row, pair_col, scores, cfg->epochs, cfg->batch,
+                        cfg->lr, cfg->seed, model, labels_out, ts);
+    if (s == SWH_OK && stats) {
+        stats->first_epoch_loss = ts.first_loss;
+        stats->final_epoch_loss = ts.final_loss;
+        stats->ms_label = ts.ms_label;
+        stats->ms_features = ts.ms_features;
+        stats->ms_train = ts.ms_train;
+        stats->cells_label = ts.cells_label;
+        stats->steps = ts.steps;
+    }
+    return s;
+}
+
+swh_status swh_prefilter_search(swh_ctx *ctx, const swh_model *model, swh_db *db, int32_t nq, const char *q_cat,
+                                const int64_t *q_off, int32_t k, double rescore_frac, double audit_frac,
+                                uint64_t audit_seed, swh_hit *hits, swh_prefilter_stats *stats)
+{
+    if (!ctx) return SWH_E_INVAL;
+    swh_status s = enter(ctx);
+    if (s == SWH_OK) s = model_ok(ctx, model);
+    if (s != SWH_OK) return s;
+    if (!db || db->device != ctx->device) return fail(ctx, SWH_E_INVAL, "database missing or on another device");
+    if (db->sc.asize != model->asize) return fail(ctx, SWH_E_INVAL, "database alphabet differs from the model's");
+    if (nq < 0 || (nq > 0 && (!q_off || !hits))) return fail(ctx, SWH_E_INVAL, "bad query arguments");
+    if (k < 1 || k > 32) return fail(ctx, SWH_E_INVAL, "k must be in 1..32");
+    if (!(rescore_frac > 0.0 && rescore_frac <= 1.0) || !(audit_frac >= 0.0 && audit_frac <= 1.0))
+        return fail(ctx, SWH_E_INVAL, "rescore_frac must be in (0, 1], audit_frac in [0, 1]");
+    if (stats && stats->struct_size < sizeof(swh_prefilter_stats)) return fail(ctx, SWH_E_INVAL, "stats too small");
+    PrefilterStats ps;
+    s = prefilter_search(ctx, model, db, nq, q_cat, q_off, k, rescore_frac, audit_frac, audit_seed, hits, ps);
+    if (s == SWH_OK && stats) {
+        stats->candidates = ps.candidates;
+        stats->audited = ps.audited;
+        stats->fallbacks = ps.fallbacks;
+        stats->cells_rescored = ps.cells_rescored;
+        stats->cells_exhaustive = ps.cells_exhaustive;
+        stats->ms_features = ps.ms_features;
+        stats->ms_predict = ps.ms_predict;
+        stats->ms_select = ps.ms_select;
+        stats->ms_rescore = ps.ms_rescore;
+        stats->ms_topk = ps.ms_topk;
+        stats->ms_fallback = ps.ms_fallback;
+    }
+    return s;
+}
+
+swh_status swh_prefilter_predict(swh_ctx *ctx, const swh_model *model, swh_db *db, int32_t nq, const char *q_cat,
+                                 const int64_t *q_off, float *pred)
+{
+    if (!ctx) return SWH_E_INVAL;
+    swh_status s = enter(ctx);
+    if (s == SWH_OK) s = model_ok(ctx, model);
+    if (s != SWH_OK) return s;
+    if (!db || db->device != ctx->device) return fail(ctx, SWH_E_INVAL, "database missing or on another device");
+    if (db->sc.asize != model->asize) return fail(ctx, SWH_E_INVAL, "database alphabet differs from the model's");
+    if (nq < 0 || (nq > 0 && (!q_off || !pred))) return fail(ctx, SWH_E_INVAL, "bad query arguments");
+    return prefilter_predict(ctx, model, db, nq, q_cat, q_off, pred);
+}
+
+swh_status swh_dipeptide_counts(swh_ctx *ctx, const swh_scoring *scoring, int64_t nseq, const char *seq_cat,
+                                const int64_t *seq_off, int32_t *counts)
+{
+    if (!ctx) return SWH_E_INVAL;
+    swh_status s = enter(ctx);
+    if (s != SWH_OK) return s;
+    Scoring sc;
+    if ((s = make_scoring(ctx, scoring, sc)) != SWH_OK) return s;
+    if (nseq < 0 || (nseq > 0 && (!seq_off || !counts))) return fail(ctx, SWH_E_INVAL, "bad sequence arguments");
+    return dipeptide_counts(ctx, sc, nseq, seq_cat, seq_off, counts);
+}
+
+swh_status swh_mlp_grad(swh_ctx *ctx, swh_model *model, int32_t B, const float *z, const float *y, double *loss,
+                        float *grad)
+{
+    if (!ctx) return SWH_E_INVAL;
+    swh_status s = enter(ctx);
+    if (s == SWH_OK) s = model_ok(ctx, model);
+    if (s != SWH_OK) return s;
+    if (B < 64 || B % 64 != 0 || !z || !y || !grad) return fail(ctx, SWH_E_INVAL, "B a positive multiple of 64");
+    return mlp_grad(ctx, model, B, z, y, loss, grad);
+}
+
+swh_status swh_mlp_train_steps(swh_ctx *ctx, swh_model *model, int32_t B, const float *z, const float *y,
+                               int32_t steps, double lr)
+{
+    if (!ctx) return SWH_E_INVAL;
+    swh_status s = enter(ctx);
+    if (s == SWH_OK) s = model_ok(ctx, model);
+    if (s != SWH_OK) return s;
+    if (B < 64 || B % 64 != 0 || !z || !y || steps < 0 || !(lr > 0.0))
+        return fail(ctx, SWH_E_INVAL, "B a positive multiple of 64, steps >= 0, lr > 0");
+    return mlp_train_steps(ctx, model, B, z, y, steps, lr);
 }
 
 }  // extern "C"

@@ -51,6 +51,10 @@ struct swh_ctx {
     swh::DevBuf bq, bt, bborder;
     // strip shapes measured by the autotuner (empty: built-in rule)
     std::vector<swh_tune_entry> tune;
+    // prefilter: query features, folded queries, predictions, selection, candidate layout
+    swh::DevBuf pf_fq, pf_qlen, pf_Aq, pf_pred, pf_hist, pf_prefix, pf_marks, pf_chunk, pf_cand, pf_res, pf_groups,
+        pf_perm;
+    float pf_infer_ms = 0.f;
     // traceback buffers
     swh::DevBuf tb_fwd, tb_bwd, tb_front, tb_codes_q, tb_codes_t, tb_leaf, tb_misc;
     std::vector<swh::DevBuf *> all() {
@@ -58,6 +62,8 @@ struct swh_ctx {
                 &probs, &strip_prob, &prob_best, &sync,
                 &qoff, &db_work, &db_border, &db_redo, &db_scatter, &db_scores, &db_topk,
                 &bq, &bt, &bborder,
+                &pf_fq, &pf_qlen, &pf_Aq, &pf_pred, &pf_hist, &pf_prefix, &pf_marks, &pf_chunk, &pf_cand,
+                &pf_res, &pf_groups, &pf_perm,
                 &tb_fwd, &tb_bwd, &tb_front, &tb_codes_q, &tb_codes_t, &tb_leaf, &tb_misc};
     }
 };

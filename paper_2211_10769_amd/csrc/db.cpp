@@ -176,51 +176,57 @@ void db_destroy(swh_db *db)
     free_buf(db->res);
     free_buf(db->groups);
     free_buf(db->perm);
+    free_buf(db->pf_F);
+    free_buf(db->pf_row_len);
+    free_buf(db->pf_row_db);
     delete db;
 }
 
-swh_status db_scores_device(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off,
-                            int32_t *scores_dev, DbStats &stats)
+swh_status prepare_queries(swh_ctx *ctx, const Scoring &sc, int32_t nq, const char *q_cat, const int64_t *q_off,
+                           QuerySet &qs)
 {
     swh_status s;
     if ((s = check_offsets(ctx, nq, q_off, "queries")) != SWH_OK) return s;
     hipStream_t st = ctx->own_stream;
-    const Scoring &sc = db->sc;
     const int64_t qbase = nq ? q_off[0] : 0, qtotal = nq ? q_off[nq] - qbase : 0;
-    std::vector<int64_t> qo((size_t)nq + 1);
-    int64_t maxq = 1;
-    for (int32_t i = 0; i <= nq; ++i) qo[i] = nq ? q_off[i] - qbase : 0;
-    for (int32_t i = 0; i < nq; ++i) maxq = std::max(maxq, qo[i + 1] - qo[i]);
-    if (maxq * std::max(sc.smax, 1) >= ((int64_t)1 << 26))
+    qs.nq = nq;
+    qs.qo.assign((size_t)nq + 1, 0);
+    qs.maxq = 1;
+    for (int32_t i = 0; i <= nq; ++i) qs.qo[i] = nq ? q_off[i] - qbase : 0;
+    for (int32_t i = 0; i < nq; ++i) qs.maxq = std::max(qs.maxq, qs.qo[i + 1] - qs.qo[i]);
+    if (qs.maxq * std::max(sc.smax, 1) >= ((int64_t)1 << 26))
         return fail(ctx, SWH_E_RANGE, "query length * max|s| must stay below 2^26");
     if ((s = encode_host(ctx, sc, q_cat ? q_cat + qbase : nullptr, qtotal, ctx->qraw, ctx->qc, st, "queries")) !=
         SWH_OK)
         return s;
     hipError_t e;
-    if ((s = ensure(ctx, ctx->qoff, sizeof(int64_t) * (qo.size() + 1), "query offsets")) != SWH_OK) return s;
+    if ((s = ensure(ctx, ctx->qoff, sizeof(int64_t) * (qs.qo.size() + 1), "query offsets")) != SWH_OK) return s;
     if ((s = ensure(ctx, ctx->mat, 32 * 32, "matrix")) != SWH_OK) return s;
-    if ((e = hipMemcpyAsync(ctx->qoff.p, qo.data(), sizeof(int64_t) * qo.size(), hipMemcpyHostToDevice, st)) !=
+    if ((e = hipMemcpyAsync(ctx->qoff.p, qs.qo.data(), sizeof(int64_t) * qs.qo.size(), hipMemcpyHostToDevice, st)) !=
             hipSuccess ||
         (e = hipMemcpyAsync(ctx->mat.p, sc.mat, (size_t)sc.asize * sc.asize, hipMemcpyHostToDevice, st)) !=
             hipSuccess)
         return hip_fail(ctx, e, "query upload");
+    return SWH_OK;
+}
+
+swh_status score_units(swh_ctx *ctx, const swh_db *db, const QuerySet &qs, const GroupSet &gs,
+                       std::vector<DbWork> work, const std::vector<std::pair<int32_t, int32_t>> &long_pairs,
+                       int32_t *scores_dev, DbStats &stats)
+{
+    swh_status s;
+    hipError_t e;
+    hipStream_t st = ctx->own_stream;
+    const Scoring &sc = db->sc;
+    const std::vector<int64_t> &qo = qs.qo;
 
     // ---- inter-task: every (query, group) unit, most expensive first
-    const int64_t ngroups = (int64_t)db->h_groups.size();
-    std::vector<DbWork> work;
-    work.reserve((size_t)(nq * ngroups));
     int32_t max_len = 1;
-    for (int32_t q = 0; q < nq; ++q)
-        for (int64_t g = 0; g < ngroups; ++g)
-            if (qo[q + 1] > qo[q]) work.push_back(DbWork{q, (int32_t)g});
-    for (const DbGroup &g : db->h_groups) max_len = std::max(max_len, g.maxlen);
+    for (const DbWork &w : work) max_len = std::max(max_len, (*gs.h_groups)[w.g].maxlen);
     std::stable_sort(work.begin(), work.end(), [&](const DbWork &a, const DbWork &b) {
-        return (qo[a.q + 1] - qo[a.q]) * (int64_t)db->h_groups[a.g].maxlen >
-               (qo[b.q + 1] - qo[b.q]) * (int64_t)db->h_groups[b.g].maxlen;
+        return (qo[a.q + 1] - qo[a.q]) * (int64_t)(*gs.h_groups)[a.g].maxlen >
+               (qo[b.q + 1] - qo[b.q]) * (int64_t)(*gs.h_groups)[b.g].maxlen;
     });
-    for (int32_t q = 0; q < nq; ++q) {
-        stats.cells += (double)(qo[q + 1] - qo[q]) * (double)db->total_residues;
-    }
     const int limit = db_search_grid_limit(ctx->device);
     const int grid = std::max(1, std::min<int>(limit, (int)std::max<size_t>(1, work.size())));
     const int redo_cap = 1 << 20;
@@ -234,9 +240,9 @@ swh_status db_scores_device(swh_ctx *ctx, const swh_db *db, int32_t nq, const ch
         (e = hipMemsetAsync(ctx->sync.p, 0, 64, st)) != hipSuccess)
         return hip_fail(ctx, e, "work upload");
     DbSearchArgs a;
-    a.res = (const uint8_t *)db->res.p;
-    a.groups = (const DbGroup *)db->groups.p;
-    a.perm = (const int32_t *)db->perm.p;
+    a.res = gs.res;
+    a.groups = gs.groups;
+    a.perm = gs.perm;
     a.qcodes = (const uint8_t *)ctx->qc.p;
     a.qoff = (const int64_t *)ctx->qoff.p;
     a.work = (const DbWork *)ctx->db_work.p;
@@ -262,23 +268,21 @@ swh_status db_scores_device(swh_ctx *ctx, const swh_db *db, int32_t nq, const ch
         return hip_fail(ctx, e, "search");
     float ms = 0.f;
     hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]);
-    stats.ms_inter = ms;
+    stats.ms_inter += ms;
     if (nredo > redo_cap) return fail(ctx, SWH_E_RANGE, "more than 2^20 saturated pairs in one search");
     std::vector<int32_t> redo((size_t)2 * nredo);
     if (nredo && ((e = hipMemcpyAsync(redo.data(), a.redo, sizeof(int32_t) * 2 * nredo, hipMemcpyDeviceToHost, st)) !=
                       hipSuccess ||
                   (e = hipStreamSynchronize(st)) != hipSuccess))
         return hip_fail(ctx, e, "redo list");
-    stats.redo = nredo;
+    stats.redo += nredo;
 
     // ---- intra-task in 32 bits: long database sequences and saturated pairs
-    std::vector<std::pair<int32_t, int32_t>> pairs;
-    for (int32_t q = 0; q < nq; ++q)
-        if (qo[q + 1] > qo[q])
-            for (int32_t d : db->long_idx) pairs.push_back({q, d});
+    std::vector<std::pair<int32_t, int32_t>> pairs(long_pairs);
     for (int32_t i = 0; i < nredo; ++i) pairs.push_back({redo[2 * i], redo[2 * i + 1]});
     if (!pairs.empty()) {
-        const StripShape shape = tuned_shape(ctx, maxq);
+        const int32_t nq = qs.nq;
+        const StripShape shape = tuned_shape(ctx, qs.maxq);
         const int R = shape.R;
         // padded copies: each query once, each database sequence once
         std::vector<int64_t> qpad_off((size_t)nq + 1, 0);
@@ -321,8 +325,8 @@ swh_status db_scores_device(swh_ctx *ctx, const swh_db *db, int32_t nq, const ch
         std::vector<BestCell> best;
         float ms2 = 0.f;
         if ((s = run_strips(ctx, probs, sc, R, true, st, &best, &ms2, shape.waves)) != SWH_OK) return s;
-        stats.ms_intra = ms2;
-        stats.intra_pairs = (int64_t)pairs.size();
+        stats.ms_intra += ms2;
+        stats.intra_pairs += (int64_t)pairs.size();
         std::vector<int64_t> pos(pairs.size());
         std::vector<int32_t> val(pairs.size());
         for (size_t i = 0; i < pairs.size(); ++i) {
@@ -343,6 +347,27 @@ swh_status db_scores_device(swh_ctx *ctx, const swh_db *db, int32_t nq, const ch
             return hip_fail(ctx, e, "scatter");
     }
     return SWH_OK;
+}
+
+swh_status db_scores_device(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off,
+                            int32_t *scores_dev, DbStats &stats)
+{
+    QuerySet qs;
+    swh_status s = prepare_queries(ctx, db->sc, nq, q_cat, q_off, qs);
+    if (s != SWH_OK) return s;
+    const int64_t ngroups = (int64_t)db->h_groups.size();
+    std::vector<DbWork> work;
+    work.reserve((size_t)(nq * ngroups));
+    std::vector<std::pair<int32_t, int32_t>> long_pairs;
+    for (int32_t q = 0; q < nq; ++q) {
+        if (qs.qo[q + 1] == qs.qo[q]) continue;
+        for (int64_t g = 0; g < ngroups; ++g) work.push_back(DbWork{q, (int32_t)g});
+        for (int32_t d : db->long_idx) long_pairs.push_back({q, d});
+        stats.cells += (double)(qs.qo[q + 1] - qs.qo[q]) * (double)db->total_residues;
+    }
+    GroupSet gs{(const uint8_t *)db->res.p, (const DbGroup *)db->groups.p, (const int32_t *)db->perm.p,
+                &db->h_groups};
+    return score_units(ctx, db, qs, gs, std::move(work), long_pairs, scores_dev, stats);
 }
 
 swh_status db_search(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off, int32_t k,

@@ -3,6 +3,7 @@
 
 #include <stdint.h>
 
+#include <utility>
 #include <vector>
 
 #include "context.h"
@@ -18,6 +19,11 @@ struct swh_db {
     std::vector<int32_t> h_perm;           // sorted position -> database index, -1 padding
     std::vector<int32_t> long_idx;         // sequences handled by the single-pair kernel
     swh::DevBuf codes, offs, res, groups, perm;
+    // prefilter feature rows (built on first use): inter-task slots, then long sequences
+    bool pf_ready = false;
+    int64_t pf_nrows = 0, pf_nslots = 0;
+    std::vector<int32_t> h_row_db, h_row_len;
+    swh::DevBuf pf_F, pf_row_len, pf_row_db;
 };
 
 namespace swh {
@@ -37,6 +43,30 @@ struct GatherLite {
     int64_t padded;
 };
 swh_status gather_lite(swh_ctx *ctx, const std::vector<GatherLite> &g, uint8_t pad, hipStream_t st);
+
+// Encoded queries in ctx->qc with host offsets (rebased to 0) in qo and
+// device offsets in ctx->qoff; the matrix in ctx->mat.
+struct QuerySet {
+    int32_t nq = 0;
+    std::vector<int64_t> qo;
+    int64_t maxq = 1;
+};
+swh_status prepare_queries(swh_ctx *ctx, const Scoring &sc, int32_t nq, const char *q_cat, const int64_t *q_off,
+                           QuerySet &qs);
+
+// A set of interleaved 128-sequence groups (device) with the host copy of the
+// group table.
+struct GroupSet {
+    const uint8_t *res;
+    const DbGroup *groups;
+    const int32_t *perm;
+    const std::vector<DbGroup> *h_groups;
+};
+// Scores of the given (query, group) units and (query, database index) pairs
+// into scores_dev[q * ndb + index]; 16-bit saturation is redone in 32 bits.
+swh_status score_units(swh_ctx *ctx, const swh_db *db, const QuerySet &qs, const GroupSet &gs,
+                       std::vector<DbWork> work, const std::vector<std::pair<int32_t, int32_t>> &long_pairs,
+                       int32_t *scores_dev, DbStats &stats);
 
 swh_status db_create(swh_ctx *ctx, int64_t ndb, const char *cat, const int64_t *off, const Scoring &sc,
                      swh_db **out);

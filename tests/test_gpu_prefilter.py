@@ -1,0 +1,255 @@
+"""GPU parity of the learned prefilter: dipeptide counts (exact), the network's
+loss and gradients against the float64 oracle and its bfloat16-operand
+emulation, Adam steps, folded inference against the plain network, and the
+search itself (exact scores, recall against the exhaustive search, and what
+training gains over an untrained network)."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+import seqgen
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+ALPHA = seqgen.PROTEIN_ALPHABET
+
+
+@pytest.fixture(scope="module")
+def swh():
+    import paper_2211_10769_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def eng(swh):
+    return swh.Engine(0)
+
+
+def _params(rng, scale=1.0):
+    P = {}
+    for n, s in mlp.SHAPES:
+        fan = s[1] if len(s) == 2 else mlp.NH
+        P[n] = rng.normal(scale=scale * np.sqrt(2.0 / fan), size=s)
+    P["b1"] = rng.normal(scale=0.1, size=mlp.NH)
+    P["b2"] = rng.normal(scale=0.1, size=mlp.NH)
+    P["b3"] = np.array([2.0])
+    theta = mlp.flatten(P).astype(np.float32)
+    return theta, mlp.unflatten(theta.astype(np.float64))
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - np.asarray(b, np.float64)) / np.linalg.norm(b))
+
+
+def test_dipeptide_counts_exact(eng, swh):
+    rng = np.random.default_rng(4)
+    seqs = [b"", b"A", b"AR", b"ARNDCQ", b"AXAB*AZAA", b"wywyw"]
+    seqs += [bytes(seqgen.random_protein(rng, L)) for L in (2, 63, 64, 65, 500, 3000)]
+    got = swh.dipeptide_counts(eng, seqs, seqgen.protein_scoring())
+    want = np.stack([mlp.dipeptide_counts(s, ALPHA) for s in seqs])
+    assert np.array_equal(got, want)
+
+
+def test_loss_and_gradients(eng, swh):
+    rng = np.random.default_rng(8)
+    theta, P = _params(rng)
+    model = swh.Model(eng, seqgen.protein_scoring(), theta=theta)
+    B = 256
+    z = rng.normal(size=(B, 401)).astype(np.float32)
+    y = (3.0 + rng.normal(size=B)).astype(np.float32)
+    loss, g = model.grad(z, y)
+    Z = z.astype(np.float64)
+    Y = y.astype(np.float64)
+    l64, G64 = mlp.loss_and_grads(P, Z, Y)
+    lbf, Gbf = mlp.loss_and_grads_bf16(P, Z, Y)
+    gr = mlp.unflatten(g.astype(np.float64))
+    # against float64: bfloat16 operands (8 significant bits) move some
+    # pre-activations across zero, and each such ReLU flip changes a whole
+    # gradient entry; on these random inputs the float64 oracle's own bf16
+    # emulation is 3.4% (relative L2) away from float64, so the bound is 6%
+    assert abs(loss - l64) / l64 < 1e-2
+    assert _rel(g, mlp.flatten(G64)) < 6e-2
+    # against the bf16-operand emulation: only float32 summation order differs
+    assert abs(loss - lbf) / lbf < 1e-5, (loss, lbf)
+    for name, _ in mlp.SHAPES:
+        assert _rel(gr[name], Gbf[name]) < 2e-3, (name, _rel(gr[name], Gbf[name]))
+    assert _rel(g, mlp.flatten(Gbf)) < 1e-3
+
+
+def test_adam_steps(eng, swh):
+    rng = np.random.default_rng(9)
+    theta, P = _params(rng)
+    model = swh.Model(eng, seqgen.protein_scoring(), theta=theta)
+    B, lr = 128, 1e-3
+    z = rng.normal(size=(B, 401)).astype(np.float32)
+    y = (3.0 + rng.normal(size=B)).astype(np.float32)
+    model.train_steps(z, y, steps=3, lr=lr)
+    got, _, _ = model.get()
+    th = mlp.flatten(P)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    for t in range(1, 4):
+        _, G = mlp.loss_and_grads_bf16(mlp.unflatten(th), z.astype(np.float64), y.astype(np.float64))
+        th, m, v = mlp.adam_step(th, mlp.flatten(G), m, v, t, lr=lr)
+    d = np.abs(got - th)
+    # each step moves a parameter by about lr; a sign flip of a near-zero
+    # gradient can move it the other way (at most 2 lr per step)
+    assert d.max() <= 6 * lr + 1e-6
+    assert np.mean(d > 0.05 * lr) < 2e-3
+    assert _rel(got - theta, th - mlp.flatten(P)) < 5e-2
+
+
+def _small_db(n, seed):
+    rng = seqgen.rng_for(3, 100 + seed)
+    lens = seqgen.db_lengths(rng, n)
+    return [seqgen.random_protein(rng, int(L)) for L in lens]
+
+
+def test_folded_inference_matches_network(eng, swh):
+    rng = np.random.default_rng(10)
+    theta, P = _params(rng, scale=0.7)
+    qs = seqgen.queries(3, 3)
+    db = _small_db(400, 1) + [seqgen.random_protein(rng, 2500), seqgen.random_protein(rng, 4100)]
+    db.append(seqgen.homolog(rng, qs[0]))
+    # normalisation from the pair features of these sequences
+    X = np.stack([mlp.pair_features(mlp.frequencies(bytes(q), ALPHA), len(q), mlp.frequencies(bytes(d), ALPHA),
+                                    len(d)) for q in qs for d in db])
+    mu, sd = mlp.norm_stats(X)
+    model = swh.Model(eng, seqgen.protein_scoring(), theta=theta, mu=mu, sd=sd)
+    sdb = swh.Database(eng, [bytes(d) for d in db], seqgen.protein_scoring())
+    got = model.predict(sdb, [bytes(q) for q in qs])
+    mu32, sd32 = mu.astype(np.float32).astype(np.float64), sd.astype(np.float32).astype(np.float64)
+    rank = lambda a: np.argsort(np.argsort(a))
+    for qi, q in enumerate(qs):
+        dbb = [bytes(d) for d in db]
+        plain = mlp.predict(P, mu32, sd32, bytes(q), dbb, ALPHA)
+        emul = mlp.predict_folded(P, mu32, sd32, bytes(q), dbb, ALPHA, rnd=mlp.bf16)
+        # same operand rounding, float32 accumulation: summation order only
+        # (and the odd hidden activation rounded the other way)
+        assert np.max(np.abs(got[qi] - emul)) < 5e-3, (qi, np.max(np.abs(got[qi] - emul)))
+        # against the plain float64 network: bfloat16 rounding of the folded
+        # weights, frequencies, activations and W2, amplified where a large
+        # mean cancels in the folded bias
+        err = np.abs(got[qi] - plain)
+        assert np.percentile(err, 99) < 0.06 and np.median(err) < 0.02, (qi, np.percentile(err, 99))
+        assert np.corrcoef(rank(got[qi]), rank(plain))[0, 1] > 0.99
+
+
+def test_save_load_roundtrip(eng, swh):
+    rng = np.random.default_rng(12)
+    theta, _ = _params(rng)
+    mu = rng.normal(size=401).astype(np.float32)
+    sd = (1.0 + rng.random(401)).astype(np.float32)
+    model = swh.Model(eng, seqgen.protein_scoring(), theta=theta, mu=mu, sd=sd)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "m.bin")
+        model.save(path)
+        back = swh.Model.load(eng, path)
+        t2, m2, s2 = back.get()
+        assert np.array_equal(t2, theta) and np.array_equal(m2, mu) and np.array_equal(s2, sd)
+        with open(path, "r+b") as f:
+            f.write(b"XXXX")
+        with pytest.raises(swh.SwhError):
+            swh.Model.load(eng, path)
+
+
+def test_training_labels_are_exact(eng, swh):
+    cat, off, rows, cols = seqgen.prefilter_training_set(n_pairs=256, n_queries=20, homologs=4, n_background=200)
+    pool = [bytes(cat[off[i]:off[i + 1]]) for i in range(len(off) - 1)]
+    model = swh.Model(eng, seqgen.protein_scoring(), seed=1)
+    stats, labels = model.train((cat, off), rows, cols, seqgen.protein_scoring(), epochs=1, batch=64,
+                                return_labels=True)
+    sc = seqgen.protein_scoring()
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(8) as ex:
+        want = list(ex.map(lambda rc: oracle.sw_align(pool[rc[0]], pool[rc[1]], sc, want_cigar=False)["score"],
+                           zip(rows, cols)))
+    assert np.array_equal(labels, np.array(want))
+    assert stats["steps"] == 4
+
+
+@pytest.fixture(scope="module")
+def planted(swh, eng):
+    """10 queries, a 20,000-sequence database with 30 planted homologs per query."""
+    qs = [q[:1500] for q in seqgen.queries(10, 2)]
+    rng = seqgen.rng_for(3, 200)
+    db = _small_db(20_000, 2)
+    where = rng.choice(len(db), size=300, replace=False)
+    for k, idx in enumerate(where):
+        db[idx] = seqgen.homolog(rng, qs[k // 30])
+    sdb = swh.Database(eng, [bytes(d) for d in db], seqgen.protein_scoring())
+    exact_idx, exact_sc, _ = sdb.search([bytes(q) for q in qs], k=10)
+    return qs, db, sdb, exact_idx, exact_sc
+
+
+@pytest.fixture(scope="module")
+def trained(swh, eng):
+    cat, off, rows, cols = seqgen.prefilter_training_set(n_pairs=131072, n_queries=600, homologs=12,
+                                                         n_background=8000)
+    model = swh.Model(eng, seqgen.protein_scoring(), seed=3)
+    stats = model.train((cat, off), rows, cols, seqgen.protein_scoring(), epochs=6, batch=1024, lr=1e-3)
+    return model, stats
+
+
+def test_search_is_exact_and_recalls(swh, eng, planted, trained):
+    qs, db, sdb, exact_idx, exact_sc = planted
+    model, stats = trained
+    assert stats["final_epoch_loss"] < stats["first_epoch_loss"]
+    idx, sco, st = model.search(sdb, [bytes(q) for q in qs], k=10, rescore_frac=0.05, audit_frac=0.01)
+    assert mlp.recall_at_k(idx, exact_idx) >= 0.99
+    # every reported score is the exact score of that pair
+    sc = seqgen.protein_scoring()
+    for qi in range(len(qs)):
+        for j in range(10):
+            if idx[qi, j] >= 0:
+                w = oracle.sw_align(bytes(qs[qi]), bytes(db[idx[qi, j]]), sc, want_cigar=False)["score"]
+                assert sco[qi, j] == w
+    n = len(db)
+    assert st["candidates"] >= len(qs) * int(np.ceil(0.05 * n))
+    assert st["cells_rescored"] < 0.2 * st["cells_exhaustive"]
+
+
+def test_training_gains_over_untrained(swh, eng, planted, trained):
+    qs, db, sdb, exact_idx, _ = planted
+    model, _ = trained
+    untrained = swh.Model(eng, seqgen.protein_scoring(), seed=3)
+    _, mu, sd = model.get()
+    untrained.set(mu=mu, sd=sd)
+    q = [bytes(x) for x in qs]
+    # no audit: the ranking alone decides the candidates
+    r_tr = mlp.recall_at_k(model.search(sdb, q, k=10, rescore_frac=0.02, audit_frac=0.0)[0], exact_idx)
+    r_un = mlp.recall_at_k(untrained.search(sdb, q, k=10, rescore_frac=0.02, audit_frac=0.0)[0], exact_idx)
+    assert r_tr >= 0.97 and r_tr > r_un + 0.2, (r_tr, r_un)
+
+
+def test_audit_fallback_restores_exact_top(swh, eng, planted):
+    qs, db, sdb, exact_idx, exact_sc = planted
+    # an untrained network ranks poorly; a dense audit sends the queries to the
+    # exhaustive search, whose answer is exact
+    model = swh.Model(eng, seqgen.protein_scoring(), seed=5)
+    idx, sco, st = model.search(sdb, [bytes(q) for q in qs], k=10, rescore_frac=0.01, audit_frac=0.5)
+    assert st["fallbacks"] >= 1
+    assert mlp.recall_at_k(idx, exact_idx) == 1.0
+    assert np.array_equal(sco, exact_sc)
+
+
+def test_audit_sample_matches_its_definition(swh, eng, planted):
+    qs, db, sdb, _, _ = planted
+    model = swh.Model(eng, seqgen.protein_scoring(), seed=5)
+    frac, seed = 0.003, 0xABCDEF
+    _, _, st = model.search(sdb, [bytes(q) for q in qs], k=10, rescore_frac=0.05, audit_frac=frac, audit_seed=seed)
+    # splitmix64 of seed + golden * (q 2^32 + i + 1); audited when the high half < frac 2^32,
+    # among the non-candidates: count the draws over all pairs, bound by the candidates
+    q = np.arange(len(qs), dtype=np.uint64)[:, None]
+    i = np.arange(len(db), dtype=np.uint64)[None, :]
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + np.uint64(0x9E3779B97F4A7C15) * ((q << np.uint64(32)) + i + np.uint64(1))
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z ^= z >> np.uint64(31)
+    drawn = int(((z >> np.uint64(32)) < np.uint64(int(frac * 2 ** 32))).sum())
+    assert drawn - st["candidates"] <= st["audited"] <= drawn

@@ -167,3 +167,20 @@ def test_norm_stats_standardise():
 def test_recall():
     assert mlp.recall_at_k([[1, 2, 3]], [[3, 2, 1]]) == 1.0
     assert mlp.recall_at_k([[1, 2, 9], [4, 5, 6]], [[1, 2, 3], [7, 8, 9]]) == pytest.approx((2 / 3) / 2)
+
+
+def test_folded_prediction_equals_plain_network():
+    rng = np.random.default_rng(21)
+    P = _random_params(rng)
+    P["b1"] = rng.normal(scale=0.1, size=256)
+    q = seqgen.random_protein(rng, 300)
+    db = [seqgen.random_protein(rng, L) for L in (2, 30, 300, 1000)] + [q]
+    X = np.stack([mlp.pair_features(mlp.frequencies(bytes(q), ALPHA), 300, mlp.frequencies(bytes(d), ALPHA), len(d))
+                  for d in db])
+    mu, sd = mlp.norm_stats(X)
+    sd = sd + 0.5
+    a = mlp.predict(P, mu, sd, bytes(q), [bytes(d) for d in db], ALPHA)
+    b = mlp.predict_folded(P, mu, sd, bytes(q), [bytes(d) for d in db], ALPHA)
+    assert np.allclose(a, b, rtol=0, atol=1e-9)
+    c = mlp.predict_folded(P, mu, sd, bytes(q), [bytes(d) for d in db], ALPHA, rnd=mlp.bf16)
+    assert np.max(np.abs(c - a)) < 0.1

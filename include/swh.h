@@ -158,7 +158,7 @@ swh_status swh_align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, cons
  */
 typedef struct {
     int64_t max_rows;
-    int32_t rows_per_lane;      /* 4, 8, 16 or 32 */
+    int32_t rows_per_lane;      /* 4, 8, 16, 20, 24 or 32 */
     int32_t waves_per_simd;     /* 0..8 */
 } swh_tune_entry;
 

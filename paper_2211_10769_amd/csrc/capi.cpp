@@ -249,7 +249,8 @@ swh_status swh_tune_set(swh_ctx *ctx, const swh_tune_entry *entries, int32_t cou
     for (int32_t i = 0; i < count; ++i) {
         const swh_tune_entry &t = entries[i];
         const int R = t.rows_per_lane;
-        if (R != 4 && R != 8 && R != 16 && R != 32) return fail(ctx, SWH_E_INVAL, "rows_per_lane must be 4, 8, 16 or 32");
+        if (R != 4 && R != 8 && R != 16 && R != 20 && R != 24 && R != 32)
+            return fail(ctx, SWH_E_INVAL, "rows_per_lane must be 4, 8, 16, 20, 24 or 32");
         if (t.waves_per_simd < 0 || t.waves_per_simd > 8) return fail(ctx, SWH_E_INVAL, "waves_per_simd must be in 0..8");
         if (t.max_rows < 1 || (i > 0 && t.max_rows <= entries[i - 1].max_rows))
             return fail(ctx, SWH_E_INVAL, "max_rows must be positive and increasing");

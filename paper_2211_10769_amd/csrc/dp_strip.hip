@@ -24,8 +24,9 @@
 //
 // Substitution scores come from a per-strip query profile in LDS: for each
 // symbol code, the lane's R int8 scores in R/4 consecutive words,
-// prof[code][lane][R/4].  One step reads them with a single ds_read_b128
-// (R=16), conflict-free whatever code each lane holds, and each byte enters
+// prof[code][lane][R/4] (above 16 rows in two planes, see prof_index).  One
+// step reads them with a single ds_read_b128 (R=16), conflict-free whatever
+// code each lane holds, and each byte enters
 // the add through an SDWA sign-extended byte select at no extra cost.  The
 // pad code scores -128: in a virtual column left of the sweep the diagonal
 // is the boundary value, so the pad can never raise H there; everything to
@@ -101,16 +102,38 @@ __device__ __forceinline__ bool wait_chunk(const StripArgs &a, const int32_t *fl
 
 template <int R>
 struct Prof {
-    static constexpr int W = R / 4;   // profile words per (code, lane)
+    static constexpr int W = R / 4;                      // profile words per (code, lane)
+    static constexpr int LOGR = R > 16 ? 5 : R == 16 ? 4 : R == 8 ? 3 : 2;   // bits of a row index
 };
 
+// Word w of (code, lane): with W <= 4 words at prof[(code*64 + lane)*W + w];
+// with W > 4 in two planes so that every read is a conflict-free
+// lane-contiguous ds_read: words 0..3 at prof[(code*64 + lane)*4 + w], words
+// 4..W-1 at prof[A1*256 + (code*64 + lane)*(W-4) + w-4].
 template <int W>
-__device__ __forceinline__ void load_prof(const int *prof, int code, int lane, int (&w)[W])
+__device__ __forceinline__ int prof_index(int a1, int code, int lane, int w)
 {
-    const int *p = prof + (code * 64 + lane) * W;
-    if constexpr (W == 8) {
-        const int4 x = reinterpret_cast<const int4 *>(p)[0], y = reinterpret_cast<const int4 *>(p)[1];
-        w[0] = x.x; w[1] = x.y; w[2] = x.z; w[3] = x.w; w[4] = y.x; w[5] = y.y; w[6] = y.z; w[7] = y.w;
+    if constexpr (W <= 4) return (code * 64 + lane) * W + w;
+    return w < 4 ? (code * 64 + lane) * 4 + w : a1 * 256 + (code * 64 + lane) * (W - 4) + (w - 4);
+}
+
+template <int W>
+__device__ __forceinline__ void load_prof(const int *prof, int a1, int code, int lane, int (&w)[W])
+{
+    const int *p = prof + (code * 64 + lane) * (W > 4 ? 4 : W);
+    if constexpr (W > 4) {
+        const int4 x = reinterpret_cast<const int4 *>(p)[0];
+        w[0] = x.x; w[1] = x.y; w[2] = x.z; w[3] = x.w;
+        const int *q = prof + a1 * 256 + (code * 64 + lane) * (W - 4);
+        if constexpr (W == 8) {
+            const int4 y = reinterpret_cast<const int4 *>(q)[0];
+            w[4] = y.x; w[5] = y.y; w[6] = y.z; w[7] = y.w;
+        } else if constexpr (W == 6) {
+            const int2 y = reinterpret_cast<const int2 *>(q)[0];
+            w[4] = y.x; w[5] = y.y;
+        } else {
+            w[4] = q[0];
+        }
     } else if constexpr (W == 4) {
         const int4 x = reinterpret_cast<const int4 *>(p)[0];
         w[0] = x.x; w[1] = x.y; w[2] = x.z; w[3] = x.w;
@@ -191,7 +214,7 @@ __global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
                     const int v = (q >= a.asize || c >= a.asize) ? -128 : (int)a.mat[q * a.asize + c];
                     word |= (unsigned)(v & 0xFF) << (8 * b4);
                 }
-                prof[(c * 64 + lane) * W + w] = (int)word;
+                prof[prof_index<W>(A1, c, lane, w)] = (int)word;
             }
         }
         int nreal = (int)min<int64_t>(max<int64_t>(P.n - row0, 0), R);
@@ -222,7 +245,7 @@ __global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
         if (ok) load_border(P.border + lane, fh, ff);
 
         int sc[W];
-        load_prof<W>(prof, code, lane, sc);
+        load_prof<W>(prof, A1, code, lane, sc);
 
         for (int b = 0; b < P.nblocks && ok; ++b) {
             // prefetch the next block's target codes and border chunk
@@ -240,7 +263,7 @@ __global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
                 const int code_n = shr1(tfeed, code);
                 tfeed = shl1(tfeed, tfeed);
                 int sc_n[W];
-                load_prof<W>(prof, code_n, lane, sc_n);
+                load_prof<W>(prof, A1, code_n, lane, sc_n);
                 // keep the profile read for the next column ahead of this column's
                 // arithmetic, so its LDS latency overlaps one whole step
                 __builtin_amdgcn_sched_barrier(0);
@@ -261,7 +284,7 @@ __global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
                 of = shl1(fbot, of);
 
                 if (LOCAL) {
-                    constexpr int LOGR = R == 32 ? 5 : R == 16 ? 4 : R == 8 ? 3 : 2;
+                    constexpr int LOGR = Prof<R>::LOGR;
                     int mx = (hp[0] << LOGR) | (R - 1);
 #pragma unroll
                     for (int k = 1; k < R; ++k) mx = max(mx, (hp[k] << LOGR) | (R - 1 - k));
@@ -297,9 +320,9 @@ __global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
         }
 
         if (LOCAL) {
-            constexpr int LOGR = R == 32 ? 5 : R == 16 ? 4 : R == 8 ? 3 : 2;
+            constexpr int LOGR = Prof<R>::LOGR;
             int bv = bkey >> LOGR;
-            int br = bv > 0 ? (int)(row0 + (R - 1 - (bkey & (R - 1))) + 1) : 0;
+            int br = bv > 0 ? (int)(row0 + (R - 1 - (bkey & ((1 << LOGR) - 1))) + 1) : 0;
             int bc = bv > 0 ? bstep - lane + 1 : 0;
             // wave reduction: score desc, row asc, col asc
 #pragma unroll
@@ -478,6 +501,8 @@ hipError_t launch_reduce_best_multi(const BestCell *strip_best, const Problem *p
 hipError_t launch_strip(const StripArgs &a, int R, bool local, int grid, hipStream_t st)
 {
     if (R == 32) return local ? launch_strip_t<32, true>(a, grid, st) : launch_strip_t<32, false>(a, grid, st);
+    if (R == 24) return local ? launch_strip_t<24, true>(a, grid, st) : launch_strip_t<24, false>(a, grid, st);
+    if (R == 20) return local ? launch_strip_t<20, true>(a, grid, st) : launch_strip_t<20, false>(a, grid, st);
     if (R == 16) return local ? launch_strip_t<16, true>(a, grid, st) : launch_strip_t<16, false>(a, grid, st);
     if (R == 8) return local ? launch_strip_t<8, true>(a, grid, st) : launch_strip_t<8, false>(a, grid, st);
     if (R == 4) return local ? launch_strip_t<4, true>(a, grid, st) : launch_strip_t<4, false>(a, grid, st);
@@ -487,6 +512,8 @@ hipError_t launch_strip(const StripArgs &a, int R, bool local, int grid, hipStre
 int strip_grid_limit(int device, int R, bool local, int asize)
 {
     if (R == 32) return local ? grid_limit_t<32, true>(device, asize) : grid_limit_t<32, false>(device, asize);
+    if (R == 24) return local ? grid_limit_t<24, true>(device, asize) : grid_limit_t<24, false>(device, asize);
+    if (R == 20) return local ? grid_limit_t<20, true>(device, asize) : grid_limit_t<20, false>(device, asize);
     if (R == 16) return local ? grid_limit_t<16, true>(device, asize) : grid_limit_t<16, false>(device, asize);
     if (R == 8) return local ? grid_limit_t<8, true>(device, asize) : grid_limit_t<8, false>(device, asize);
     return local ? grid_limit_t<4, true>(device, asize) : grid_limit_t<4, false>(device, asize);

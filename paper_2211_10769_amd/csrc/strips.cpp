@@ -41,7 +41,7 @@ int env_int(const char *name, int dflt)
 int pick_rows_per_lane(int64_t n)
 {
     const int forced = env_int("SWH_ROWS", 0);
-    if (forced == 4 || forced == 8 || forced == 16 || forced == 32) return forced;
+    if (forced == 4 || forced == 8 || forced == 16 || forced == 20 || forced == 24 || forced == 32) return forced;
     if (n >= 200000) return 16;
     if (n >= 20000) return 8;
     return 4;

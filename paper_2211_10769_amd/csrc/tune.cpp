@@ -18,7 +18,8 @@ namespace swh {
 StripShape tuned_shape(swh_ctx *ctx, int64_t n)
 {
     const int forced = env_int("SWH_ROWS", 0);
-    if (forced == 4 || forced == 8 || forced == 16 || forced == 32) return StripShape{forced, 0};
+    if (forced == 4 || forced == 8 || forced == 16 || forced == 20 || forced == 24 || forced == 32)
+        return StripShape{forced, 0};
     for (const swh_tune_entry &t : ctx->tune)
         if (n <= t.max_rows) return StripShape{t.rows_per_lane, t.waves_per_simd};
     if (!ctx->tune.empty()) return StripShape{ctx->tune.back().rows_per_lane, ctx->tune.back().waves_per_simd};
@@ -58,7 +59,7 @@ swh_status autotune(swh_ctx *ctx, const Scoring &sc, int64_t max_rows, double ce
                                          (Border *)ctx->bborder.p + k * tpad});
         swh_tune_entry best{edge >= max_rows ? INT64_MAX : edge, 4, 0};
         float best_ms = 1e30f;
-        for (int R : {4, 8, 16, 32}) {
+        for (int R : {4, 8, 16, 20, 24, 32}) {
             if (64 * R > 4 * n && R > 4) continue;   // strips far taller than the problem
             for (int waves : {1, 2, 4, 8}) {
                 if (waves * 4 * ctx->num_cu > strip_grid_limit(ctx->device, R, true, sc.asize)) continue;

@@ -94,7 +94,8 @@ def test_bad_symbol(eng):
     assert "position 3" in str(ei.value)
 
 
-@pytest.mark.parametrize("rows,grid", [(4, 0), (8, 0), (16, 0), (32, 0), (16, 1), (8, 3), (32, 2)])
+@pytest.mark.parametrize("rows,grid", [(4, 0), (8, 0), (16, 0), (20, 0), (24, 0), (32, 0), (16, 1), (8, 3), (20, 3),
+                                       (24, 2), (32, 2)])
 def test_forced_strip_shapes(eng, rows, grid, monkeypatch):
     # every strip height and tiny persistent grids (one wave doing every strip in turn)
     monkeypatch.setenv("SWH_ROWS", str(rows))
@@ -106,3 +107,5 @@ def test_forced_strip_shapes(eng, rows, grid, monkeypatch):
                         seqgen.random_dna(rng, 333)])
     _cmp(eng, bytes(a), bytes(b), sc)
     _cmp(eng, bytes(seqgen.random_dna(rng, 2100)), bytes(seqgen.random_dna(rng, 1900)), sc)
+    q = seqgen.random_protein(rng, 1700)
+    _cmp(eng, bytes(q), bytes(seqgen.homolog(rng, q)), seqgen.protein_scoring())

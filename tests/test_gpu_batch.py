@@ -128,9 +128,9 @@ def test_tuned_shapes_keep_results(eng):
     try:
         table = eng.autotune(sc, max_rows=8192, cells_per_trial=2e9)
         assert table and table[-1]["max_rows"] == 2 ** 63 - 1
-        assert all(t["rows_per_lane"] in (4, 8, 16, 32) and 1 <= t["waves_per_simd"] <= 8 for t in table)
+        assert all(t["rows_per_lane"] in (4, 8, 16, 20, 24, 32) and 1 <= t["waves_per_simd"] <= 8 for t in table)
         _check(eng.align_batch(qs, ts, sc, mode="cigar"), base)
-        for R, w in ((8, 1), (16, 2), (32, 4)):
+        for R, w in ((8, 1), (16, 2), (20, 2), (24, 3), (32, 4)):
             eng.set_tune_table([{"max_rows": 2 ** 40, "rows_per_lane": R, "waves_per_simd": w}])
             _check(eng.align_batch(qs, ts, sc, mode="cigar"), base)
         with pytest.raises(swh.SwhError):

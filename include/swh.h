@@ -265,6 +265,8 @@ typedef struct {
     double   ms_label, ms_features, ms_train;
     double   cells_label;        /* DP cells of the engine's labelling pass */
     int64_t  steps;
+    int32_t  graph;              /* 1: each step ran as a replay of one captured HIP graph */
+    int32_t  reserved2;
 } swh_train_stats;
 
 typedef struct {

@@ -59,7 +59,8 @@ class swh_train_stats(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("first_epoch_loss", ctypes.c_double), ("final_epoch_loss", ctypes.c_double),
                 ("ms_label", ctypes.c_double), ("ms_features", ctypes.c_double), ("ms_train", ctypes.c_double),
-                ("cells_label", ctypes.c_double), ("steps", ctypes.c_int64)]
+                ("cells_label", ctypes.c_double), ("steps", ctypes.c_int64), ("graph", ctypes.c_int32),
+                ("reserved2", ctypes.c_int32)]
 
 
 class swh_prefilter_stats(ctypes.Structure):

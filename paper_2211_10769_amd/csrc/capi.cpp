@@ -410,6 +410,7 @@ swh_status swh_prefilter_train(swh_ctx *ctx, swh_model *model, const swh_scoring
         stats->ms_train = ts.ms_train;
         stats->cells_label = ts.cells_label;
         stats->steps = ts.steps;
+        stats->graph = ts.graph ? 1 : 0;
     }
     return s;
 }

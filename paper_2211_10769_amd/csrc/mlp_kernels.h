@@ -40,9 +40,9 @@ hipError_t launch_pair_z(const float *freq32, const int32_t *lens, const int32_t
 hipError_t launch_labels(const int32_t *scores, int64_t n, float *y, hipStream_t st);
 // float rows [B][401] -> bfloat16 [B][416]
 hipError_t launch_z_to_bf16(const float *z, int64_t B, uint16_t *Z, hipStream_t st);
-// Xb[i] = Z[idx[i]], yb[i] = y[idx[i]] for i < B
-hipError_t launch_gather_rows(const uint16_t *Z, const float *y, const int32_t *idx, int B, uint16_t *Xb, float *yb,
-                              hipStream_t st);
+// Xb[i] = Z[j], yb[i] = y[j] with j = idx[b B + i] for i < B, b = ctr ? ctr[0] : 0
+hipError_t launch_gather_rows(const uint16_t *Z, const float *y, const int32_t *idx, const int32_t *ctr, int B,
+                              uint16_t *Xb, float *yb, hipStream_t st);
 
 // C = A B (bfloat16 operands, float32 accumulation).  A(m,k) = at ? A[k lda + m]
 // : A[m lda + k]; B(k,n) = bt ? B[n ldb + k] : B[k ldb + n].  K % 32 == 0;
@@ -64,6 +64,10 @@ struct GemmArgs {
     int64_t ldc;
     const float *bias;
     const uint16_t *mask;   // bfloat16, leading dimension ldc
+    // split-K (kEpiF32 only): splits > 1 sums K in `splits` slices into
+    // partial [splits][M][N] and then into out32
+    int splits;
+    float *partial;
 };
 hipError_t launch_gemm(const GemmArgs &g, bool at, bool bt, hipStream_t st);
 
@@ -74,9 +78,12 @@ hipError_t launch_head(const float *H2, const float *y, const float *theta, int 
 // out[n] = sum_r X[r][n] * (scale ? scale[r] : 1) for n < cols (deterministic, two stages)
 hipError_t launch_colsum(const float *X, int64_t ldx, int rows, int cols, const float *scale, float *partial,
                          float *out, hipStream_t st);
-// Adam on the flat parameters; bc1 = 1 - b1^t, bc2 = 1 - b2^t
+// Adam on the flat parameters; bc1 = 1 - b1^t, bc2 = 1 - b2^t, or with ctr
+// t = ctr[1] + 1 read on the device (a captured step replays unchanged)
 hipError_t launch_adam(float *theta, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2,
-                       float eps, float bc1, float bc2, hipStream_t st);
+                       float eps, float bc1, float bc2, const int32_t *ctr, hipStream_t st);
+// ctr[0] (batch within the epoch) and ctr[1] (Adam step) advance by one
+hipError_t launch_step_end(int32_t *ctr, hipStream_t st);
 // bfloat16 copies of W1 ([256][416], zero padding) and W2 ([256][256])
 hipError_t launch_pack_weights(const float *theta, uint16_t *W1bf, uint16_t *W2bf, hipStream_t st);
 

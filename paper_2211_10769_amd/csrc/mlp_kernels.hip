@@ -142,10 +142,10 @@ __global__ void __launch_bounds__(448) z_to_bf16_kernel(const float *z, uint16_t
 }
 
 __global__ void __launch_bounds__(64) gather_rows_kernel(const uint16_t *Z, const float *y, const int32_t *idx,
-                                                         uint16_t *Xb, float *yb)
+                                                         const int32_t *ctr, uint16_t *Xb, float *yb)
 {
     const int i = blockIdx.x;
-    const int64_t src = idx[i];
+    const int64_t src = idx[(ctr ? (int64_t)ctr[0] * gridDim.x : 0) + i];
     const u32x4 *s = (const u32x4 *)(Z + src * kKPad);
     u32x4 *d = (u32x4 *)(Xb + (int64_t)i * kKPad);
     for (int t = threadIdx.x; t < kKPad / 8; t += 64) d[t] = s[t];
@@ -168,7 +168,9 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const u32x4 zero = {0u, 0u, 0u, 0u};
-    for (int k0 = 0; k0 < g.K; k0 += 32) {
+    const int kslice = g.K / gridDim.z;   // a multiple of 32 (checked by the launcher)
+    const int kbeg = blockIdx.z * kslice, kend = kbeg + kslice;
+    for (int k0 = kbeg; k0 < kend; k0 += 32) {
         if (!AT) {
             const int m = tid >> 2, kk = (tid & 3) * 8;
             u32x4 v = zero;
@@ -209,7 +211,9 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
                 if (m >= g.M || n >= g.N) continue;
                 const float c = acc[i][j][r];
                 const int64_t o = (int64_t)m * g.ldc + n;
-                if (g.epi == kEpiF32) {
+                if (gridDim.z > 1) {
+                    g.partial[((int64_t)blockIdx.z * g.M + m) * g.N + n] = c;
+                } else if (g.epi == kEpiF32) {
                     g.out32[o] = c;
                 } else if (g.epi == kEpiBiasReluBf) {
                     g.outbf[o] = f2bf(fmaxf(c + g.bias[n], 0.0f));
@@ -221,6 +225,15 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
                     g.outbf[o] = f2bf(v);
                 }
             }
+}
+
+__global__ void splitk_reduce_kernel(const float *partial, int splits, int M, int N, float *out, int64_t ldc)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)M * N) return;
+    float acc = 0.0f;
+    for (int s = 0; s < splits; ++s) acc += partial[(int64_t)s * M * N + i];
+    out[(i / N) * ldc + i % N] = acc;
 }
 
 // ------------------------------------------------------------------ training reductions
@@ -275,10 +288,15 @@ __global__ void colsum_final_kernel(const float *partial, int cols, float *out)
 }
 
 __global__ void adam_kernel(float *theta, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2,
-                            float eps, float bc1, float bc2)
+                            float eps, float bc1, float bc2, const int32_t *ctr)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (ctr) {   // step number from the device counter (graph replays)
+        const float t = (float)(ctr[1] + 1);
+        bc1 = 1.0f - powf(b1, t);
+        bc2 = 1.0f - powf(b2, t);
+    }
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
     const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
@@ -487,6 +505,14 @@ __global__ void __launch_bounds__(256) compact_kernel(const uint8_t *marks, int6
     }
 }
 
+__global__ void step_end_kernel(int32_t *ctr)
+{
+    if (threadIdx.x == 0) {
+        ctr[0] += 1;
+        ctr[1] += 1;
+    }
+}
+
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)std::max<int64_t>(1, (n + per - 1) / per); }
 
 }  // namespace
@@ -535,21 +561,26 @@ hipError_t launch_z_to_bf16(const float *z, int64_t B, uint16_t *Z, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_gather_rows(const uint16_t *Z, const float *y, const int32_t *idx, int B, uint16_t *Xb, float *yb,
-                              hipStream_t st)
+hipError_t launch_gather_rows(const uint16_t *Z, const float *y, const int32_t *idx, const int32_t *ctr, int B,
+                              uint16_t *Xb, float *yb, hipStream_t st)
 {
     if (B <= 0) return hipSuccess;
-    hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)B), dim3(64), 0, st, Z, y, idx, Xb, yb);
+    hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)B), dim3(64), 0, st, Z, y, idx, ctr, Xb, yb);
     return hipGetLastError();
 }
 
 hipError_t launch_gemm(const GemmArgs &g, bool at, bool bt, hipStream_t st)
 {
-    const dim3 grid(blocks_for(g.N, 64), blocks_for(g.M, 64));
+    const int splits = g.splits > 1 ? g.splits : 1;
+    if (g.K % (32 * splits) != 0 || (splits > 1 && (g.epi != kEpiF32 || !g.partial))) return hipErrorInvalidValue;
+    const dim3 grid(blocks_for(g.N, 64), blocks_for(g.M, 64), (unsigned)splits);
     if (!at && !bt) gemm_kernel<false, false><<<grid, dim3(256), 0, st>>>(g);
     if (!at && bt) gemm_kernel<false, true><<<grid, dim3(256), 0, st>>>(g);
     if (at && !bt) gemm_kernel<true, false><<<grid, dim3(256), 0, st>>>(g);
     if (at && bt) gemm_kernel<true, true><<<grid, dim3(256), 0, st>>>(g);
+    if (splits > 1)
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3(blocks_for((int64_t)g.M * g.N, 256)), dim3(256), 0, st,
+                           g.partial, splits, g.M, g.N, g.out32, g.ldc);
     return hipGetLastError();
 }
 
@@ -570,10 +601,16 @@ hipError_t launch_colsum(const float *X, int64_t ldx, int rows, int cols, const 
 }
 
 hipError_t launch_adam(float *theta, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2,
-                       float eps, float bc1, float bc2, hipStream_t st)
+                       float eps, float bc1, float bc2, const int32_t *ctr, hipStream_t st)
 {
     hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, theta, m, v, g, n, lr, b1, b2, eps,
-                       bc1, bc2);
+                       bc1, bc2, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_end(int32_t *ctr, hipStream_t st)
+{
+    hipLaunchKernelGGL(step_end_kernel, dim3(1), dim3(64), 0, st, ctr);
     return hipGetLastError();
 }
 

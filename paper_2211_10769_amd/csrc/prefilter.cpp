@@ -31,6 +31,7 @@
 #include "db_kernels.h"
 #include "mlp_kernels.h"
 #include "prefilter.h"
+#include "strips.h"
 
 namespace swh {
 
@@ -65,13 +66,18 @@ swh_status upload(swh_ctx *ctx, DevBuf &buf, const T *v, size_t n, hipStream_t s
     return SWH_OK;
 }
 
+// Weight gradients reduce over the batch (K = B, M x N = 256 x 256 or 401):
+// split K so that the grid holds enough workgroups.
+constexpr int kSplitMax = 16;
+
 // Device buffers of one training call (or one gradient evaluation).
 struct TrainWs {
-    DevBuf Xb, yb, H1bf, H2, d, dz2, dz2bf, dz1, dz1bf, grad, colpart;
+    DevBuf Xb, yb, H1bf, H2, d, dz2, dz2bf, dz1, dz1bf, grad, colpart, splitk;
     double *loss = nullptr;   // one double, device
     ~TrainWs()
     {
-        for (DevBuf *b : {&Xb, &yb, &H1bf, &H2, &d, &dz2, &dz2bf, &dz1, &dz1bf, &grad, &colpart}) free_buf(*b);
+        for (DevBuf *b : {&Xb, &yb, &H1bf, &H2, &d, &dz2, &dz2bf, &dz1, &dz1bf, &grad, &colpart, &splitk})
+            free_buf(*b);
         if (loss) hipFree(loss);
     }
 };
@@ -89,10 +95,18 @@ swh_status ws_alloc(swh_ctx *ctx, TrainWs &w, int B)
         (s = ensure(ctx, w.dz1, hb * 4, "gradient 1")) != SWH_OK ||
         (s = ensure(ctx, w.dz1bf, hb * 2, "gradient 1 (bf16)")) != SWH_OK ||
         (s = ensure(ctx, w.grad, (size_t)kNParams * 4, "parameter gradient")) != SWH_OK ||
-        (s = ensure(ctx, w.colpart, (size_t)32 * kNH * 4, "column sums")) != SWH_OK)
+        (s = ensure(ctx, w.colpart, (size_t)32 * kNH * 4, "column sums")) != SWH_OK ||
+        (s = ensure(ctx, w.splitk, (size_t)kSplitMax * kNH * kKPad * 4, "split-K partial sums")) != SWH_OK)
         return s;
     if (!w.loss && hipMalloc((void **)&w.loss, 8) != hipSuccess) return fail(ctx, SWH_E_NOMEM, "loss accumulator");
     return SWH_OK;
+}
+
+int splits_for(int B)
+{
+    int s = kSplitMax;
+    while (s > 1 && (B % (32 * s) != 0 || B / s < 128)) s /= 2;
+    return s;
 }
 
 GemmArgs gemm(const uint16_t *A, int64_t lda, const uint16_t *B, int64_t ldb, int M, int N, int K, int mload,
@@ -137,6 +151,8 @@ hipError_t forward_backward(swh_model *m, TrainWs &w, int B, hipStream_t st)
     // dW2 = dz2^T h1
     g = gemm((const uint16_t *)w.dz2bf.p, kNH, H1, kNH, kNH, kNH, B, kNH, kNH, kEpiF32, kNH);
     g.out32 = grad + kOffW2;
+    g.splits = splits_for(B);
+    g.partial = (float *)w.splitk.p;
     if ((e = launch_gemm(g, true, false, st)) != hipSuccess) return e;
     // dz1 = (dz2 W2) * (h1 > 0)
     g = gemm((const uint16_t *)w.dz2bf.p, kNH, (const uint16_t *)m->W2bf.p, kNH, B, kNH, kNH, B, kNH, kEpiMask, kNH);
@@ -147,6 +163,8 @@ hipError_t forward_backward(swh_model *m, TrainWs &w, int B, hipStream_t st)
     // dW1 = dz1^T x
     g = gemm((const uint16_t *)w.dz1bf.p, kNH, Xb, kKPad, kNH, kNIn, B, kNH, kKPad, kEpiF32, kNIn);
     g.out32 = grad + kOffW1;
+    g.splits = splits_for(B);
+    g.partial = (float *)w.splitk.p;
     if ((e = launch_gemm(g, true, false, st)) != hipSuccess) return e;
     float *cp = (float *)w.colpart.p;
     if ((e = launch_colsum((const float *)w.dz1.p, kNH, B, kNH, nullptr, cp, grad + kOffB1, st)) != hipSuccess ||
@@ -157,15 +175,16 @@ hipError_t forward_backward(swh_model *m, TrainWs &w, int B, hipStream_t st)
     return hipSuccess;
 }
 
-hipError_t adam_update(swh_model *m, TrainWs &w, double lr, hipStream_t st)
+// Adam step; with ctr the step number is read on the device (graph replays).
+hipError_t adam_update(swh_model *m, TrainWs &w, double lr, hipStream_t st, const int32_t *ctr = nullptr)
 {
     const double b1 = 0.9, b2 = 0.999;
-    m->steps += 1;
+    if (!ctr) m->steps += 1;
     const float bc1 = (float)(1.0 - std::pow(b1, (double)m->steps));
     const float bc2 = (float)(1.0 - std::pow(b2, (double)m->steps));
     hipError_t e;
     if ((e = launch_adam((float *)m->theta.p, (float *)m->adam_m.p, (float *)m->adam_v.p, (const float *)w.grad.p,
-                         kNParams, (float)lr, (float)b1, (float)b2, 1e-8f, bc1, bc2, st)) != hipSuccess)
+                         kNParams, (float)lr, (float)b1, (float)b2, 1e-8f, bc1, bc2, ctr, st)) != hipSuccess)
         return e;
     return launch_pack_weights((const float *)m->theta.p, (uint16_t *)m->W1bf.p, (uint16_t *)m->W2bf.p, st);
 }
@@ -651,19 +670,61 @@ swh_status prefilter_train(swh_ctx *ctx, const Scoring &sc, int64_t nseq, const 
     const int64_t nb = npairs / batch;
     std::vector<int32_t> order((size_t)npairs);
     uint64_t rs = seed ^ 0x5eedf00dull;
+    // One step = gather, forward, backward, Adam, bf16 copies, counter bump.
+    // It is captured once in a HIP graph and replayed: the batch index and
+    // the Adam step live in device counters, so every replay is identical.
+    DevBuf ctrbuf;
+    guard.v.push_back(&ctrbuf);
+    if ((s = ensure(ctx, ctrbuf, 64, "step counters")) != SWH_OK) return s;
+    int32_t *ctr = (int32_t *)ctrbuf.p;
+    const int32_t ctr0[2] = {0, (int32_t)model->steps};
+    if ((e = hipMemcpyAsync(ctr, ctr0, 8, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(ctx, e, "step counters");
+    auto step = [&](hipStream_t s2) -> hipError_t {
+        hipError_t e2;
+        if ((e2 = launch_gather_rows((const uint16_t *)Z.p, (const float *)y.p, (const int32_t *)perm.p, ctr, batch,
+                                     (uint16_t *)w.Xb.p, (float *)w.yb.p, s2)) != hipSuccess ||
+            (e2 = forward_backward(model, w, batch, s2)) != hipSuccess ||
+            (e2 = adam_update(model, w, lr, s2, ctr)) != hipSuccess)
+            return e2;
+        return launch_step_end(ctr, s2);
+    };
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (nb > 0 && env_int("SWH_NO_GRAPH", 0) == 0) {
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            const hipError_t ce = step(st);
+            const hipError_t ee = hipStreamEndCapture(st, &graph);
+            if (ce != hipSuccess || ee != hipSuccess || !graph ||
+                hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+                if (graph) hipGraphDestroy(graph);
+                graph = nullptr;
+                exec = nullptr;
+            }
+        }
+        (void)hipGetLastError();
+    }
+    struct GraphGuard {
+        hipGraph_t &g;
+        hipGraphExec_t &x;
+        ~GraphGuard()
+        {
+            if (x) hipGraphExecDestroy(x);
+            if (g) hipGraphDestroy(g);
+        }
+    } gguard{graph, exec};
+    ts.graph = exec != nullptr;
     for (int32_t ep = 0; ep < epochs; ++ep) {
         std::iota(order.begin(), order.end(), 0);
         for (int64_t i = npairs - 1; i > 0; --i) std::swap(order[i], order[splitmix(rs) % (uint64_t)(i + 1)]);
         if ((e = hipMemcpyAsync(perm.p, order.data(), (size_t)npairs * 4, hipMemcpyHostToDevice, st)) != hipSuccess ||
-            (e = hipMemsetAsync(w.loss, 0, 8, st)) != hipSuccess)
+            (e = hipMemsetAsync(w.loss, 0, 8, st)) != hipSuccess || (e = hipMemsetAsync(ctr, 0, 4, st)) != hipSuccess)
             return hip_fail(ctx, e, "epoch setup");
         for (int64_t b = 0; b < nb; ++b) {
-            if ((e = launch_gather_rows((const uint16_t *)Z.p, (const float *)y.p, (const int32_t *)perm.p + b * batch,
-                                        batch, (uint16_t *)w.Xb.p, (float *)w.yb.p, st)) != hipSuccess ||
-                (e = forward_backward(model, w, batch, st)) != hipSuccess ||
-                (e = adam_update(model, w, lr, st)) != hipSuccess)
-                return hip_fail(ctx, e, "training step");
+            if ((e = exec ? hipGraphLaunch(exec, st) : step(st)) != hipSuccess) return hip_fail(ctx, e, "training step");
             ++ts.steps;
+            ++model->steps;
         }
         double lsum = 0.0;
         if ((e = hipMemcpyAsync(&lsum, w.loss, 8, hipMemcpyDeviceToHost, st)) != hipSuccess ||

@@ -32,6 +32,7 @@ struct TrainStats {
     double ms_label = 0.0, ms_features = 0.0, ms_train = 0.0;
     double cells_label = 0.0;
     int64_t steps = 0;
+    bool graph = false;   // the step ran as a replayed HIP graph
 };
 swh_status prefilter_train(swh_ctx *ctx, const Scoring &sc, int64_t nseq, const char *cat, const int64_t *off,
                            int64_t npairs, const int32_t *rows, const int32_t *cols, const int32_t *scores,

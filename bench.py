@@ -35,6 +35,11 @@ VALU_LANE_OPS = 256 * 64 * 2.4e9
 OPS_PER_CELL = 7
 
 
+def log(msg: str):
+    """Progress on stderr (stdout carries only the result line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -89,13 +94,15 @@ def bench_db(args, swh, eng):
     qs, (cat, off) = seqgen.workload2(n_db=args.db_size)
     sc = swh.Scoring(*seqgen.protein_scoring())
     db = swh.Database(eng, (cat, off), sc)
+    log(f"database search: {args.db_size} proteins encoded")
     qcat, qoff = swh._concat(qs)
     db.search((qcat, qoff), k=10)   # warm-up: buffers grow once
     t0 = time.perf_counter()
     stats = []
-    for _ in range(args.db_steps):
+    for i in range(args.db_steps):
         _, _, st = db.search((qcat, qoff), k=10)
         stats.append(st)
+        log(f"database search {i + 1}/{args.db_steps} done")
     dt = (time.perf_counter() - t0) / args.db_steps
     cells = stats[0]["cells"]
     inter = sum(x["ms_inter"] for x in stats) / len(stats)
@@ -118,6 +125,7 @@ def bench_pairs(args, swh, eng):
     import seqgen
 
     pairs = seqgen.workload4(n_pairs=args.pairs)
+    log(f"batched pairs: {args.pairs} pairs generated")
     qs = [p[0] for p in pairs]
     ts = [p[1] for p in pairs]
     del pairs
@@ -128,6 +136,7 @@ def bench_pairs(args, swh, eng):
     t0 = time.perf_counter()
     _, st = eng.align_batch((qcat, qoff), (tcat, toff), sc, mode="cigar", stats=True)
     dt = time.perf_counter() - t0
+    log(f"batched pairs done ({dt:.1f} s)")
     cells = st["cells_forward"]
     return {"workload": f"{args.pairs} read/reference DNA pairs, reads log-uniform 150-20,000 bp, "
                         f"1-15% divergence, 1.2x windows; scores, coordinates and CIGARs",
@@ -152,23 +161,28 @@ def bench_prefilter(args, swh, eng):
     t0 = time.perf_counter()
     cat, off, rows, cols = seqgen.prefilter_training_set(n_pairs=args.pf_train_pairs)
     gen_train = time.perf_counter() - t0
+    log("prefilter: training pairs generated")
     model = swh.Model(eng, sc, seed=7)
     t0 = time.perf_counter()
     tst = model.train((cat, off), rows, cols, sc, epochs=args.pf_epochs, batch=4096, lr=1e-3, seed=11)
     train_s = time.perf_counter() - t0
+    log(f"prefilter: network trained ({train_s:.1f} s)")
     del cat, off, rows, cols
     qs, (dcat, doff), planted = seqgen.workload3(n_db=args.pf_db)
     db = swh.Database(eng, (dcat, doff), sc)
+    log(f"prefilter: database of {args.pf_db} proteins encoded")
     qcat, qoff = swh._concat(qs)
     del dcat
     db.search((qcat, qoff), k=10)                                  # warm-up
     t0 = time.perf_counter()
     ex_idx, ex_sco, ex_st = db.search((qcat, qoff), k=10)
     t_ex = time.perf_counter() - t0
+    log(f"prefilter: exhaustive search {t_ex:.2f} s")
     model.search(db, (qcat, qoff), k=10, rescore_frac=0.05, audit_frac=0.002)   # warm-up: database features
     t0 = time.perf_counter()
     pf_idx, pf_sco, pf_st = model.search(db, (qcat, qoff), k=10, rescore_frac=0.05, audit_frac=0.002)
     t_pf = time.perf_counter() - t0
+    log(f"prefilter: prefilter search {t_pf:.2f} s")
     recall = float(np.mean([len(set(a) & set(b)) / 10.0 for a, b in zip(pf_idx.tolist(), ex_idx.tolist())]))
     flops = 2.0 * len(qs) * args.pf_db * (416 * 256 + 256 * 256)
     pred_ms = pf_st["ms_predict"]
@@ -198,6 +212,7 @@ def main():
               "multi-GPU mode in this build", file=sys.stderr)
         sys.exit(2)
 
+    log("starting (imports)")
     import numpy as np
     import torch
 
@@ -205,6 +220,7 @@ def main():
     import seqgen
 
     q, t = seqgen.workload1(args.n, flank=args.flank)
+    log(f"long pair generated ({len(q)} x {len(t)})")
     sc = swh.Scoring(*seqgen.dna_scoring())
     dev = torch.device("cuda:0")
     qd = torch.from_numpy(np.ascontiguousarray(q)).to(dev)
@@ -221,15 +237,18 @@ def main():
 
     if args.autotune:
         eng.autotune(sc, max_rows=max(args.n, 1 << 20))
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
+        t1 = time.perf_counter()
         eng.align_dev(qd, td, sc, mode=args.mode, stream=stream)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        log(f"warm-up step {i + 1}/{args.warmup} done ({time.perf_counter() - t1:.1f} s)")
 
     fwd_ms, rev_ms, tb_ms = [], [], []
     t0 = time.perf_counter()
     res = None
-    for _ in range(args.steps):
+    for i in range(args.steps):
         res = eng.align_dev(qd, td, sc, mode=args.mode, stream=stream, stats=True)
+        log(f"timed step {i + 1}/{args.steps} done")
         fwd_ms.append(res["stats"]["ms_forward"])
         rev_ms.append(res["stats"]["ms_reverse"])
         tb_ms.append(res["stats"]["ms_traceback"])
@@ -273,6 +292,7 @@ def main():
         out["prefilter"] = bench_prefilter(args, swh, eng)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(q, t, args.cpu_rows)
+        log("CPU oracle sample done")
     print(json.dumps(out))
 
 

@@ -33,6 +33,8 @@
 // the right of the last column or below the last row is never read back.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "engine.h"
 
 namespace swh {
@@ -180,15 +182,23 @@ __device__ __forceinline__ void dp_step(int (&hp)[R], int (&E)[R], const int (&s
     }
 }
 
+// Waves per SIMD one workgroup may bring (its waves spread round-robin over
+// the CU's four SIMDs); it bounds the registers a wave may use.
+template <int R>
+constexpr int kWgPerSimd = R <= 8 ? 4 : 2;
+
+// Each wave of a workgroup runs strips on its own (no barrier anywhere); the
+// workgroup only places waves evenly over the SIMDs of a CU.
 template <int R, bool LOCAL>
-__global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
+__global__ void __launch_bounds__(256 * kWgPerSimd<R>) strip_kernel(StripArgs a)
 {
-    extern __shared__ int prof[];
+    extern __shared__ int prof_all[];
     constexpr int W = Prof<R>::W;
     constexpr int B = LOCAL ? 0 : kNeg;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const int pad = a.asize;
     const int A1 = a.asize + 1;
+    int *prof = prof_all + (threadIdx.x >> 6) * (A1 * 64 * W);   // this wave's profile
     const int o = a.o, e = a.e;
 
     for (;;) {
@@ -263,6 +273,10 @@ __global__ void __launch_bounds__(64) strip_kernel(StripArgs a)
                 const int code_n = shr1(tfeed, code);
                 tfeed = shl1(tfeed, tfeed);
                 int sc_n[W];
+                // retire the previous profile read (issued a whole step ago) before
+                // issuing this one, so that the wait for `sc` below never has to
+                // include the read just issued
+                __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0), vmcnt/expcnt untouched
                 load_prof<W>(prof, A1, code_n, lane, sc_n);
                 // keep the profile read for the next column ahead of this column's
                 // arithmetic, so its LDS latency overlaps one whole step
@@ -439,12 +453,32 @@ int grid_for(int64_t work, int threads)
 }
 
 template <int R, bool LOCAL>
-hipError_t launch_strip_t(const StripArgs &a, int grid, hipStream_t st)
+hipError_t launch_strip_t(const StripArgs &a, const StripLaunch &l, hipStream_t st)
 {
-    const size_t lds = strip_lds_bytes(R, a.asize);
-    hipLaunchKernelGGL((strip_kernel<R, LOCAL>), dim3(grid), dim3(64), lds, st, a);
+    hipLaunchKernelGGL((strip_kernel<R, LOCAL>), dim3(l.nwg), dim3(64 * l.waves), l.lds, st, a);
     return hipGetLastError();
 }
+
+template <int R, bool LOCAL>
+int blocks_per_cu_t(int threads, size_t lds)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&strip_kernel<R, LOCAL>),
+                                                     threads, lds) != hipSuccess)
+        return 0;
+    return n;
+}
+
+int blocks_per_cu(int R, bool local, int threads, size_t lds)
+{
+#define SWH_BPC(RR)                                                                                         \
+    if (R == RR) return local ? blocks_per_cu_t<RR, true>(threads, lds) : blocks_per_cu_t<RR, false>(threads, lds);
+    SWH_BPC(4) SWH_BPC(8) SWH_BPC(16) SWH_BPC(20) SWH_BPC(24) SWH_BPC(32)
+#undef SWH_BPC
+    return 0;
+}
+
+int wg_per_simd(int R) { return R <= 8 ? kWgPerSimd<4> : kWgPerSimd<16>; }
 
 template <int R, bool LOCAL>
 int grid_limit_t(int device, int asize)
@@ -498,7 +532,31 @@ hipError_t launch_reduce_best_multi(const BestCell *strip_best, const Problem *p
     return hipGetLastError();
 }
 
-hipError_t launch_strip(const StripArgs &a, int R, bool local, int grid, hipStream_t st)
+bool strip_balanced_launch(int device, int R, bool local, int asize, int per_simd, int num_cu, StripLaunch &out)
+{
+    int lds_cu = 0, lds_wg = 0;
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_wg, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess ||
+        lds_cu <= 0 || lds_wg <= 0 || num_cu <= 0 || per_simd < 1) {
+        (void)hipGetLastError();
+        return false;
+    }
+    const size_t wave_lds = strip_lds_bytes(R, asize);
+    // one workgroup per CU (needs a request above half the CU's LDS), else two
+    for (int wgs = 1; wgs <= 2; ++wgs) {
+        if (per_simd % wgs != 0) continue;
+        const int waves = 4 * per_simd / wgs;
+        if (waves > 4 * wg_per_simd(R)) continue;
+        const size_t lds = std::max(wave_lds * waves, (size_t)lds_cu / (wgs + 1) + 256);
+        if (lds > (size_t)lds_wg || lds * wgs > (size_t)lds_cu) continue;
+        if (blocks_per_cu(R, local, 64 * waves, lds) != wgs) continue;
+        out = StripLaunch{num_cu * wgs, waves, lds};
+        return true;
+    }
+    return false;
+}
+
+hipError_t launch_strip(const StripArgs &a, int R, bool local, const StripLaunch &grid, hipStream_t st)
 {
     if (R == 32) return local ? launch_strip_t<32, true>(a, grid, st) : launch_strip_t<32, false>(a, grid, st);
     if (R == 24) return local ? launch_strip_t<24, true>(a, grid, st) : launch_strip_t<24, false>(a, grid, st);

@@ -62,7 +62,18 @@ hipError_t launch_encode(const char *src, int64_t len, uint8_t *dst, int64_t pad
 hipError_t launch_reverse(const uint8_t *src, int64_t len, uint8_t *dst, int64_t padded_len,
                           uint8_t pad, hipStream_t st);
 hipError_t launch_fill_border(Border *b, int64_t count, Border v, hipStream_t st);
-hipError_t launch_strip(const StripArgs &a, int R, bool local, int grid, hipStream_t st);
+// A launch of the strip kernel: nwg workgroups of `waves` waves (every wave
+// runs strips on its own), lds bytes of LDS per workgroup.
+struct StripLaunch {
+    int nwg;
+    int waves;
+    size_t lds;
+};
+// Every SIMD gets exactly per_simd waves: one or two workgroups per CU whose
+// waves the CU spreads over its four SIMDs, held to that count per CU by
+// their LDS request.  False when that placement cannot be made.
+bool strip_balanced_launch(int device, int R, bool local, int asize, int per_simd, int num_cu, StripLaunch &out);
+hipError_t launch_strip(const StripArgs &a, int R, bool local, const StripLaunch &grid, hipStream_t st);
 hipError_t launch_reduce_best(const BestCell *in, int32_t count, BestCell *out, hipStream_t st);
 // Per problem: best cell over its strips (strip_best indexed by global strip).
 hipError_t launch_reduce_best_multi(const BestCell *strip_best, const Problem *probs, int32_t nprobs,

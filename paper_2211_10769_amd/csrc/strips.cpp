@@ -38,12 +38,17 @@ int env_int(const char *name, int dflt)
     return std::atoi(v);
 }
 
+// The tallest strips that still give the problem one strip per SIMD (1,024
+// on MI355X): taller strips spend fewer lane shifts and border transfers per
+// cell, and every strip of a problem waits on the one above it, so a problem
+// with fewer strips than SIMDs leaves SIMDs idle.  Sweeps on the 5 Mbp pair:
+// R = 32 3,070 GCUPS, R = 16 2,530, R = 8 2,060.
 int pick_rows_per_lane(int64_t n)
 {
     const int forced = env_int("SWH_ROWS", 0);
     if (forced == 4 || forced == 8 || forced == 16 || forced == 20 || forced == 24 || forced == 32) return forced;
-    if (n >= 200000) return 16;
-    if (n >= 20000) return 8;
+    for (int R : {32, 16, 8})
+        if ((n + 64 * R - 1) / (64 * R) >= 1024) return R;
     return 4;
 }
 
@@ -124,9 +129,19 @@ swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, cons
     a.abort_flag = (int32_t *)ctx->sync.p + 1;
     a.strip_best = (BestCell *)ctx->strip_best.p;
     a.wait_ticks = wait_ticks(ctx->device);
-    const int grid = strip_grid(total_strips, R, strip_grid_limit(ctx->device, R, local, sc.asize), ctx->num_cu,
-                                waves);
-
+    // Strips of one problem form a chain that moves at the pace of its slowest
+    // wave, so every SIMD must hold the same number of waves: a balanced
+    // placement when it can be made (with fewer waves per SIMD when there are
+    // few strips), else single-wave workgroups (SWH_GRID forces those).
+    StripLaunch grid{0, 1, strip_lds_bytes(R, sc.asize)};
+    const int forced = env_int("SWH_GRID", 0);
+    int per_simd = waves > 0 ? waves : (R <= 4 ? 8 : R <= 8 ? 4 : 2);
+    while (per_simd > 1 && (int64_t)per_simd / 2 * 4 * ctx->num_cu >= total_strips) per_simd /= 2;
+    if (forced > 0 || !strip_balanced_launch(ctx->device, R, local, sc.asize, per_simd, ctx->num_cu, grid)) {
+        grid = StripLaunch{strip_grid(total_strips, R, strip_grid_limit(ctx->device, R, local, sc.asize), ctx->num_cu,
+                                      waves),
+                           1, strip_lds_bytes(R, sc.asize)};
+    }
     hipEventRecord(ctx->ev[0], st);
     if ((e = launch_strip(a, R, local, grid, st)) != hipSuccess) return hip_fail(ctx, e, "strip kernel launch");
     hipEventRecord(ctx->ev[1], st);

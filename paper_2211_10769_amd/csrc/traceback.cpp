@@ -270,10 +270,10 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
                 hipSuccess)
                 return hip_fail(ctx, e, "border init launch");
             if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(ctx, e, "traceback setup");
+            // forward and backward passes are independent problems: one launch
+            // for both keeps the strip chains' ramp and tail to one per level
+            fwdp.insert(fwdp.end(), bwdp.begin(), bwdp.end());
             if ((s = run_strips(ctx, fwdp, sc, R, false, st, nullptr, nullptr, shape.waves)) != SWH_OK) return s;
-            if (!bwdp.empty() &&
-                (s = run_strips(ctx, bwdp, sc, R, false, st, nullptr, nullptr, shape.waves)) != SWH_OK)
-                return s;
 
             std::vector<CrossDesc> cd(ns);
             for (int i = 0; i < ns; ++i) {

@@ -290,6 +290,7 @@ def main():
         "reverse_ms_each": [round(x, 1) for x in rev_ms],
         "reverse_ms": round(sum(rev_ms) / len(rev_ms), 2),
         "traceback_ms": round(sum(tb_ms) / len(tb_ms), 2),
+        "traceback_cells": res["stats"]["cells_traceback"],
         "roofline": {"bound": "alu", "kernel": "strip_kernel (local; forward and reverse passes)",
                      "achieved": round(k_gcups, 2), "peak": round(peak_gcups, 1), "unit": "GCUPS",
                      "frac": round(k_gcups / peak_gcups, 4), "traffic": None},

@@ -139,6 +139,7 @@ void swh_destroy(swh_ctx *ctx)
     if (ctx->own_stream) hipStreamSynchronize(ctx->own_stream);
     for (DevBuf *b : ctx->all())
         if (b->p) hipFree(b->p);
+    ctx->tb_arena.free_all();
     for (auto &ev : ctx->ev)
         if (ev) hipEventDestroy(ev);
     if (ctx->own_stream) hipStreamDestroy(ctx->own_stream);

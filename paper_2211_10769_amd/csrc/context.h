@@ -27,6 +27,50 @@ struct Scoring {
     int smax = 0, smin = 0;    // extreme matrix entries
 };
 
+// Device memory handed out in pieces that never move during one use (the
+// traceback keeps pointers across levels); chunks are kept for the next use,
+// so a call allocates only when it needs more than any call before it.
+struct Arena {
+    static constexpr size_t kChunk = (size_t)256 << 20;
+    std::vector<void *> chunks;
+    std::vector<size_t> caps;
+    size_t cur = 0, used = 0;
+    void reset()
+    {
+        cur = 0;
+        used = 0;
+    }
+    void *get(size_t bytes)
+    {
+        bytes = (bytes + 255) & ~(size_t)255;
+        while (cur < chunks.size() && used + bytes > caps[cur]) {
+            ++cur;
+            used = 0;
+        }
+        if (cur == chunks.size()) {
+            const size_t cap = bytes > kChunk ? bytes : kChunk;
+            void *p = nullptr;
+            if (hipMalloc(&p, cap) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+            chunks.push_back(p);
+            caps.push_back(cap);
+            used = 0;
+        }
+        void *r = (char *)chunks[cur] + used;
+        used += bytes;
+        return r;
+    }
+    void free_all()
+    {
+        for (void *p : chunks) hipFree(p);
+        chunks.clear();
+        caps.clear();
+        reset();
+    }
+};
+
 }  // namespace swh
 
 struct swh_ctx {
@@ -56,6 +100,7 @@ struct swh_ctx {
         pf_perm;
     float pf_infer_ms = 0.f;
     // traceback buffers
+    swh::Arena tb_arena;
     swh::DevBuf tb_fwd, tb_bwd, tb_front, tb_codes_q, tb_codes_t, tb_leaf, tb_misc;
     std::vector<swh::DevBuf *> all() {
         return {&qraw, &traw, &qc, &tc, &qr, &tr, &border, &flags, &misc, &strip_best, &mat, &lut,

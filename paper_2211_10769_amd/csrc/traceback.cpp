@@ -51,37 +51,7 @@ namespace {
 // an 8-byte row buffer entry per column, one byte of tie flags per cell.
 constexpr int64_t kLeafCells = 28672;
 constexpr int64_t kLeafMaxWidth = 4096;
-constexpr size_t kArenaChunk = (size_t)256 << 20;
 
-// Device memory that never moves once handed out (pointers into it are kept
-// across levels).
-struct Arena {
-    std::vector<void *> chunks;
-    std::vector<size_t> caps;
-    size_t used = 0;   // in the last chunk
-    ~Arena()
-    {
-        for (void *p : chunks) hipFree(p);
-    }
-    void *get(size_t bytes)
-    {
-        bytes = (bytes + 255) & ~(size_t)255;
-        if (chunks.empty() || used + bytes > caps.back()) {
-            size_t cap = std::max(kArenaChunk, bytes);
-            void *p = nullptr;
-            if (hipMalloc(&p, cap) != hipSuccess) {
-                (void)hipGetLastError();
-                return nullptr;
-            }
-            chunks.push_back(p);
-            caps.push_back(cap);
-            used = 0;
-        }
-        void *r = (char *)chunks.back() + used;
-        used += bytes;
-        return r;
-    }
-};
 
 struct Node {
     int pair = 0;
@@ -122,7 +92,8 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
     const int npairs = (int)in.size();
     cigars.assign((size_t)npairs, std::string());
     if (npairs == 0) return SWH_OK;
-    Arena arena;
+    Arena &arena = ctx->tb_arena;   // kept across calls, handed out afresh each time
+    arena.reset();
     hipError_t e;
     swh_status s;
 

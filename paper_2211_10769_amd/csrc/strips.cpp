@@ -38,30 +38,33 @@ int env_int(const char *name, int dflt)
     return std::atoi(v);
 }
 
-// The tallest strips that still give the problem one strip per SIMD (1,024
-// on MI355X): taller strips spend fewer lane shifts and border transfers per
-// cell, and every strip of a problem waits on the one above it, so a problem
-// with fewer strips than SIMDs leaves SIMDs idle.  Sweeps on the 5 Mbp pair:
-// R = 32 3,070 GCUPS, R = 16 2,530, R = 8 2,060.
+// Strip height for a launch whose problems hold n rows in all.  The strips of
+// one problem form a chain that moves at the pace of its slowest wave, so a
+// long problem runs best with one wave per SIMD and enough strips for several
+// rounds over the 1,024 SIMDs (the last, partly empty round then costs
+// little); within that, taller strips spend fewer lane shifts and border
+// transfers per cell.  Same-box sweeps on the 5 Mbp pair: R = 16 with one
+// wave per SIMD 7.8 s, R = 32 8.1-8.3 s, R = 16 with two waves 9.6 s, R = 8
+// with two 10.1 s, R = 16 with four 18.0 s.
 int pick_rows_per_lane(int64_t n)
 {
     const int forced = env_int("SWH_ROWS", 0);
     if (forced == 4 || forced == 8 || forced == 16 || forced == 20 || forced == 24 || forced == 32) return forced;
     for (int R : {32, 16, 8})
-        if ((n + 64 * R - 1) / (64 * R) >= 1024) return R;
-    return 4;
+        if ((n + 64 * R - 1) / (64 * R) >= 4 * 1024) return R;
+    // shorter problems come in batches: 8 rows per lane costs fewer operations
+    // per cell than 4 (sweep on 20,000 read pairs: 1.78 s against 2.01 s)
+    return n >= 512 ? 8 : 4;
 }
 
-// Persistent grid: a whole number of waves per SIMD (every strip waits on the
-// previous one of its problem, so a wavefront runs at the pace of the most
-// loaded SIMD and an uneven spread of waves over SIMDs slows it down).  Waves
-// per SIMD by strip height, from sweeps on the long DNA pair: 8 for R=4, 4
-// for R=8, 2 for R=16 and R=32.
+// Grid of single-wave workgroups (used when the balanced placement cannot be
+// made, or SWH_GRID forces it): a whole number of waves per SIMD on average,
+// 8 for R=4, 4 for R=8 and 1 for taller strips.
 int strip_grid(int64_t nstrips, int R, int limit, int num_cu, int waves)
 {
     const int forced = env_int("SWH_GRID", 0);
     if (forced > 0) return (int)std::min<int64_t>(forced, nstrips);
-    const int per_simd = waves > 0 ? waves : R <= 4 ? 8 : R <= 8 ? 4 : 2;
+    const int per_simd = waves > 0 ? waves : R <= 4 ? 8 : R <= 8 ? 4 : 1;
     const int want = std::min(limit, per_simd * 4 * std::max(num_cu, 1));
     return (int)std::max<int64_t>(1, std::min<int64_t>(nstrips, want));
 }
@@ -135,7 +138,10 @@ swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, cons
     // few strips), else single-wave workgroups (SWH_GRID forces those).
     StripLaunch grid{0, 1, strip_lds_bytes(R, sc.asize)};
     const int forced = env_int("SWH_GRID", 0);
-    int per_simd = waves > 0 ? waves : (R <= 4 ? 8 : R <= 8 ? 4 : 2);
+    // long chains (a few big problems) want one wave per SIMD; many short
+    // ones want several to hide latency (read-pair batch: 4 for R = 8)
+    const bool long_chains = total_strips >= 16 * (int64_t)np;
+    int per_simd = waves > 0 ? waves : long_chains ? 1 : (R <= 4 ? 8 : 4);
     while (per_simd > 1 && (int64_t)per_simd / 2 * 4 * ctx->num_cu >= total_strips) per_simd /= 2;
     if (forced > 0 || !strip_balanced_launch(ctx->device, R, local, sc.asize, per_simd, ctx->num_cu, grid)) {
         grid = StripLaunch{strip_grid(total_strips, R, strip_grid_limit(ctx->device, R, local, sc.asize), ctx->num_cu,

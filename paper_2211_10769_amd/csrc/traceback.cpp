@@ -183,9 +183,15 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
         // ---------------------------------------------------------------- splits
         if (!splits.empty()) {
             const int ns = (int)splits.size();
-            int64_t maxrows = 1;
-            for (int k : splits) maxrows = std::max(maxrows, nodes[k].r_bot - nodes[k].r_top);
-            const StripShape shape = tuned_shape(ctx, maxrows / 2);
+            // strip height from the rows of every pass of this level (forward
+            // and backward halves together), but no taller than the mean pass
+            // so that many short passes are not padded to tall strips
+            int64_t allrows = 1;
+            for (int k : splits) allrows += nodes[k].r_bot - nodes[k].r_top;
+            StripShape shape = tuned_shape(ctx, allrows);
+            const int64_t mean_pass = allrows / (2 * (int64_t)splits.size()) + 1;
+            while (shape.R > 4 && 64 * shape.R > mean_pass && env_int("SWH_ROWS", 0) == 0)
+                shape.R = shape.R > 16 ? 16 : shape.R / 2;
             const int R = shape.R;
             std::vector<GatherDesc> gd;
             std::vector<BorderInit> bi;

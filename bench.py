@@ -33,6 +33,14 @@ VALU_LANE_OPS = 256 * 64 * 2.4e9
 # Algorithmic integer operations per DP cell of the local pass:
 # add (diag + s), max3 (H), sub (H - o), sub + max3 (E), sub + max3 (F).
 OPS_PER_CELL = 7
+# HBM bytes per DP cell of the local strip kernel on the long pair, from two
+# rocprofv3 counter passes over one forward launch (2.55e13 cells), each
+# scaled by the same counter on a 1 GiB plain copy (profiles/
+# strip_kernel_long_dna.md): FETCH_SIZE 118,000,542 KiB x 2.0 + WRITE_SIZE
+# 218,883,673 KiB x 1.0 = 465.8 GB.  Valid for the kernel those counters were
+# taken on; the roofline's traffic field is this figure times the cells of a
+# launch.
+HBM_BYTES_PER_CELL = (2.0 * 118_000_542.4375 + 1.0 * 218_883_673.15625) * 1024 / 25_500_765_000_000
 
 
 def log(msg: str):
@@ -267,6 +275,8 @@ def main():
     k_ms = sum(fwd_ms) + (sum(rev_ms) if args.mode != "score" else 0.0)
     k_gcups = k_cells / (k_ms / 1e3) / 1e9
     peak_gcups = VALU_LANE_OPS / OPS_PER_CELL / 1e9
+    launches = len(fwd_ms) + (len(rev_ms) if args.mode != "score" else 0)
+    traffic = HBM_BYTES_PER_CELL * k_cells / launches
     out = {
         "metric": "GCUPS (score-only SW, 1 MI355X) + prefilter search speedup at recall@10>=0.99",
         "value": round(value, 2),
@@ -293,7 +303,9 @@ def main():
         "traceback_cells": res["stats"]["cells_traceback"],
         "roofline": {"bound": "alu", "kernel": "strip_kernel (local; forward and reverse passes)",
                      "achieved": round(k_gcups, 2), "peak": round(peak_gcups, 1), "unit": "GCUPS",
-                     "frac": round(k_gcups / peak_gcups, 4), "traffic": None},
+                     "frac": round(k_gcups / peak_gcups, 4), "traffic": round(traffic),
+                     "traffic_unit": "bytes per launch (HBM, from counters)",
+                     "traffic_gbps": round(traffic / (k_ms / launches / 1e3) / 1e9, 1)},
     }
     if not args.no_db:
         out["db_search"] = bench_db(args, swh, eng)

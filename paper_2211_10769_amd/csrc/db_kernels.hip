@@ -4,19 +4,19 @@
 //
 // Each lane aligns one query against two database sequences at once: the
 // two DP values live in the two halves of a 32-bit register and every
-// recurrence step is one packed 16-bit instruction.  Values are unsigned
-// and the substitution score enters biased by +128, so
-//   max(H(i-1,j-1) + s, 0) = sat_sub(sat_add(diag, s + 128), 128)
-// costs two instructions with the zero clamp for free, and E, F are stored
-// clamped at zero exactly as in the single-pair kernel.  A lane result of
-// 65535 - 255 or more may have saturated; such pairs are recomputed in
-// 32-bit (flagged -1 here, redone by the host on the strip kernel).
+// recurrence step is one packed 16-bit instruction.  H, E and F are kept in
+// [0, 32767]: E and F clamped at zero by unsigned saturating subtraction (as
+// in the single-pair kernel), and the diagonal term diag + s by a signed
+// saturating add that may go below zero, where the signed max with E, F >= 0
+// supplies the zero of the local recurrence.  A lane result of 32767 - 127
+// or more may have saturated; such pairs are recomputed in 32-bit (flagged
+// -1 here, redone by the host on the strip kernel).
 //
 // The query is processed 32 rows at a time (rows in registers); the row
 // between two chunks (H and the F handed down, both packed) is kept per lane
 // in a per-wave border area laid out column-major over the 64 lanes so every
 // access is one coalesced 512-byte transaction.  The query profile of a
-// chunk (32 biased int8 scores per symbol) sits in LDS.
+// chunk (32 int16 scores per symbol) sits in LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,15 +28,25 @@ namespace swh {
 namespace {
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ u16x2 as16(unsigned x) { return __builtin_bit_cast(u16x2, x); }
 __device__ __forceinline__ unsigned as32(u16x2 x) { return __builtin_bit_cast(unsigned, x); }
-__device__ __forceinline__ u16x2 adds(u16x2 a, u16x2 b) { return __builtin_elementwise_add_sat(a, b); }
 __device__ __forceinline__ u16x2 subs(u16x2 a, u16x2 b) { return __builtin_elementwise_sub_sat(a, b); }
 __device__ __forceinline__ u16x2 vmax(u16x2 a, u16x2 b) { return __builtin_elementwise_max(a, b); }
+// signed halves: diag + s (may be negative) and the max that absorbs it
+__device__ __forceinline__ i16x2 sadds(u16x2 a, i16x2 b)
+{
+    return __builtin_elementwise_add_sat(__builtin_bit_cast(i16x2, a), b);
+}
+__device__ __forceinline__ u16x2 smax3(i16x2 t, u16x2 e, u16x2 f)
+{
+    return __builtin_bit_cast(u16x2, __builtin_elementwise_max(__builtin_elementwise_max(t, __builtin_bit_cast(i16x2, e)),
+                                                                __builtin_bit_cast(i16x2, f)));
+}
 
 constexpr int kChunk = 32;                 // query rows per register chunk
-constexpr unsigned kSatLimit = 65535 - 255;
+constexpr unsigned kSatLimit = 32767 - 127;
 
 __global__ void db_pack_kernel(const uint8_t *codes, const int64_t *offs, const int32_t *perm,
                                const DbGroup *groups, uint8_t pad, uint8_t *res)
@@ -58,11 +68,10 @@ __global__ void db_pack_kernel(const uint8_t *codes, const int64_t *offs, const 
 
 __global__ void __launch_bounds__(64) db_search_kernel(DbSearchArgs a)
 {
-    __shared__ __align__(16) int prof[33 * 8];   // (asize + 1) symbols x 32 biased int8 scores
+    __shared__ __align__(16) int prof[33 * 16];   // (asize + 1) symbols x 32 int16 scores
     const int lane = threadIdx.x;
     const int pad = a.asize;
     uint2 *border = reinterpret_cast<uint2 *>(a.border) + (size_t)blockIdx.x * a.max_len * 64;
-    const u16x2 bias = as16(0x00800080u);
     const u16x2 o2 = as16((unsigned)a.o | ((unsigned)a.o << 16));
     const u16x2 e2 = as16((unsigned)a.e | ((unsigned)a.e << 16));
 
@@ -85,16 +94,16 @@ __global__ void __launch_bounds__(64) db_search_kernel(DbSearchArgs a)
             __syncthreads();
             if (lane <= pad) {
 #pragma unroll
-                for (int w8 = 0; w8 < 8; ++w8) {
+                for (int w = 0; w < 16; ++w) {
                     unsigned word = 0;
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const int row = c * kChunk + 4 * w8 + b;
+                    for (int b = 0; b < 2; ++b) {
+                        const int row = c * kChunk + 2 * w + b;
                         const int qv = row < n ? (int)qc[row] : pad;
-                        const int s = (qv >= pad || lane >= pad) ? 0 : (int)a.mat[qv * a.asize + lane] + 128;
-                        word |= (unsigned)(s & 0xFF) << (8 * b);
+                        const int s = (qv >= pad || lane >= pad) ? -128 : (int)a.mat[qv * a.asize + lane];
+                        word |= (unsigned)(s & 0xFFFF) << (16 * b);
                     }
-                    prof[lane * 8 + w8] = (int)word;
+                    prof[lane * 16 + w] = (int)word;
                 }
             }
             __syncthreads();
@@ -109,6 +118,7 @@ __global__ void __launch_bounds__(64) db_search_kernel(DbSearchArgs a)
             const bool first = c == 0, last = c == nchunks - 1;
             unsigned cn = *reinterpret_cast<const unsigned short *>(res + 2 * lane);
             uint2 tn = first ? make_uint2(0u, 0u) : border[lane];
+#pragma unroll 2
             for (int j = 0; j < maxlen; ++j) {
                 const unsigned cab = cn;
                 const uint2 top = tn;
@@ -117,23 +127,24 @@ __global__ void __launch_bounds__(64) db_search_kernel(DbSearchArgs a)
                     if (!first) tn = border[(int64_t)(j + 1) * 64 + lane];
                 }
                 const int ca = (int)(cab & 0xFF), cb = (int)(cab >> 8);
-                const int4 a0 = reinterpret_cast<const int4 *>(prof + ca * 8)[0];
-                const int4 a1 = reinterpret_cast<const int4 *>(prof + ca * 8)[1];
-                const int4 b0 = reinterpret_cast<const int4 *>(prof + cb * 8)[0];
-                const int4 b1 = reinterpret_cast<const int4 *>(prof + cb * 8)[1];
-                const unsigned wa[8] = {(unsigned)a0.x, (unsigned)a0.y, (unsigned)a0.z, (unsigned)a0.w,
-                                        (unsigned)a1.x, (unsigned)a1.y, (unsigned)a1.z, (unsigned)a1.w};
-                const unsigned wb[8] = {(unsigned)b0.x, (unsigned)b0.y, (unsigned)b0.z, (unsigned)b0.w,
-                                        (unsigned)b1.x, (unsigned)b1.y, (unsigned)b1.z, (unsigned)b1.w};
+                unsigned wa[16], wb[16];
+#pragma unroll
+                for (int q4 = 0; q4 < 4; ++q4) {
+                    const int4 x = reinterpret_cast<const int4 *>(prof + ca * 16)[q4];
+                    const int4 y = reinterpret_cast<const int4 *>(prof + cb * 16)[q4];
+                    wa[4 * q4] = (unsigned)x.x; wa[4 * q4 + 1] = (unsigned)x.y;
+                    wa[4 * q4 + 2] = (unsigned)x.z; wa[4 * q4 + 3] = (unsigned)x.w;
+                    wb[4 * q4] = (unsigned)y.x; wb[4 * q4 + 1] = (unsigned)y.y;
+                    wb[4 * q4 + 2] = (unsigned)y.z; wb[4 * q4 + 3] = (unsigned)y.w;
+                }
                 u16x2 diag = diag0;
                 u16x2 f = as16(top.y);
 #pragma unroll
                 for (int k = 0; k < kChunk; ++k) {
-                    // byte k%4 of each sequence's profile word, zero-extended into the halves
-                    const unsigned sel = 0x0C000C00u | ((unsigned)(4 + (k & 3)) << 16) | (unsigned)(k & 3);
-                    const u16x2 s = as16(__builtin_amdgcn_perm(wb[k >> 2], wa[k >> 2], sel));
-                    const u16x2 t = subs(adds(diag, s), bias);
-                    const u16x2 h = vmax(vmax(t, E[k]), f);
+                    // row k's int16 score of each sequence into the two halves
+                    const unsigned sel = (k & 1) ? 0x07060302u : 0x05040100u;
+                    const i16x2 sk = __builtin_bit_cast(i16x2, __builtin_amdgcn_perm(wb[k >> 1], wa[k >> 1], sel));
+                    const u16x2 h = smax3(sadds(diag, sk), E[k], f);
                     const u16x2 hop = subs(h, o2);
                     f = vmax(subs(f, e2), hop);
                     E[k] = vmax(subs(E[k], e2), hop);

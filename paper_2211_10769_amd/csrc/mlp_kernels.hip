@@ -420,6 +420,104 @@ __global__ void __launch_bounds__(256) infer_kernel(InferArgs a)
     }
 }
 
+// 128 database rows x one query per workgroup with the rows' frequencies
+// staged once in LDS (108.5 KB, then reused for the layer-1 activations):
+// the four waves share the tile instead of each reading it from L2, and the
+// folded weights and W2 are read once per 128 rows instead of per 64.  Wave
+// w owns hidden units [64 w, 64 w + 64); its B fragments for the next K step
+// are loaded while the current one multiplies.
+constexpr int kInferRows = 128;
+constexpr int kFStride = kKPad + 8;   // bf16 per LDS row of the F tile (rows stay 16-byte aligned)
+constexpr int kHStride = kNH + 8;     // bf16 per LDS row of the activations
+
+__global__ void __launch_bounds__(256) infer128_kernel(InferArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) uint16_t sm[];
+    __shared__ float part[4][kInferRows];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int64_t row0 = (int64_t)blockIdx.x * kInferRows;
+    const int q = blockIdx.y;
+    const int li = lane & 15, lk = 8 * (lane >> 4);
+    for (int c = tid; c < kInferRows * (kKPad / 8); c += 256) {
+        const int r = c / (kKPad / 8), k8 = c - r * (kKPad / 8);
+        const int64_t row = min(row0 + r, a.nrows - 1);
+        *(u32x4 *)&sm[r * kFStride + 8 * k8] = *(const u32x4 *)(a.F + row * kKPad + 8 * k8);
+    }
+    __syncthreads();
+
+    const uint16_t *Aq = a.Aq + (int64_t)q * kNH * kKPad;
+    f32x4 acc[8][4];
+    for (int i = 0; i < 8; ++i)
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint16_t *brow[4];
+    for (int j = 0; j < 4; ++j) brow[j] = Aq + (int64_t)(64 * w + 16 * j + li) * kKPad + lk;
+    bf16x8 fb[4];
+    for (int j = 0; j < 4; ++j) fb[j] = as_bf(*(const u32x4 *)brow[j]);
+    for (int kk = 0; kk < kKPad; kk += 32) {
+        bf16x8 fn[4];
+        if (kk + 32 < kKPad)
+            for (int j = 0; j < 4; ++j) fn[j] = as_bf(*(const u32x4 *)(brow[j] + kk + 32));
+        for (int i = 0; i < 8; ++i) {
+            const bf16x8 fa = as_bf(*(const u32x4 *)&sm[(16 * i + li) * kFStride + kk + lk]);
+            for (int j = 0; j < 4; ++j) acc[i][j] = mfma(fa, fb[j], acc[i][j]);
+        }
+        if (kk + 32 < kKPad)
+            for (int j = 0; j < 4; ++j) fb[j] = fn[j];
+    }
+    __syncthreads();   // the F tile is dead: its LDS now holds the activations
+
+    const int32_t Lq = a.qlen[q];
+    for (int i = 0; i < 8; ++i)
+        for (int r = 0; r < 4; ++r) {
+            const int lr = 16 * i + 4 * (lane >> 4) + r;
+            const int64_t row = min(row0 + lr, a.nrows - 1);
+            const float x400 = log_len(Lq, a.row_len[row]) - a.mu400;   // w1x holds the 1 / sd
+            for (int j = 0; j < 4; ++j) {
+                const int n = 64 * w + 16 * j + li;
+                const float z = acc[i][j][r] + a.cvec[n] + a.w1x[n] * x400;
+                sm[lr * kHStride + n] = f2bf(fmaxf(z, 0.0f));
+            }
+        }
+    __syncthreads();
+
+    const float *b2 = a.theta + kOffB2;
+    const float *w3 = a.theta + kOffW3;
+    for (int i = 0; i < 8; ++i)
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint16_t *wrow[4];
+    for (int j = 0; j < 4; ++j) wrow[j] = a.W2bf + (int64_t)(64 * w + 16 * j + li) * kNH + lk;
+    for (int j = 0; j < 4; ++j) fb[j] = as_bf(*(const u32x4 *)wrow[j]);
+    for (int kk = 0; kk < kNH; kk += 32) {
+        bf16x8 fn[4];
+        if (kk + 32 < kNH)
+            for (int j = 0; j < 4; ++j) fn[j] = as_bf(*(const u32x4 *)(wrow[j] + kk + 32));
+        for (int i = 0; i < 8; ++i) {
+            const bf16x8 ha = as_bf(*(const u32x4 *)&sm[(16 * i + li) * kHStride + kk + lk]);
+            for (int j = 0; j < 4; ++j) acc[i][j] = mfma(ha, fb[j], acc[i][j]);
+        }
+        if (kk + 32 < kNH)
+            for (int j = 0; j < 4; ++j) fb[j] = fn[j];
+    }
+    for (int i = 0; i < 8; ++i)
+        for (int r = 0; r < 4; ++r) {
+            float sum = 0.0f;
+            for (int j = 0; j < 4; ++j) {
+                const int n = 64 * w + 16 * j + li;
+                sum += fmaxf(acc[i][j][r] + b2[n], 0.0f) * w3[n];
+            }
+            for (int o = 8; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
+            if (li == 0) part[w][16 * i + 4 * (lane >> 4) + r] = sum;
+        }
+    __syncthreads();
+    if (tid < kInferRows) {
+        const int64_t row = row0 + tid;
+        if (row < a.nrows) {
+            const float y = a.theta[kOffB3] + part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
+            a.pred[(int64_t)q * a.nrows + row] = a.row_db[row] >= 0 ? y : -INFINITY;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ selection
 
 constexpr int kHistRows = 16384;
@@ -638,6 +736,16 @@ hipError_t launch_fold_query(const float *theta, const float *fq, int nq, const 
 hipError_t launch_infer(const InferArgs &a, hipStream_t st)
 {
     if (a.nrows <= 0 || a.nq <= 0) return hipSuccess;
+    // the 128-row kernel needs 108.5 KB of LDS per workgroup; otherwise the 64-row one
+    const size_t lds = (size_t)kInferRows * std::max(kFStride, kHStride) * 2;
+    int dev = 0, lds_wg = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds_wg, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        (size_t)lds_wg >= lds + sizeof(float) * 4 * kInferRows) {
+        hipLaunchKernelGGL(infer128_kernel, dim3(blocks_for(a.nrows, kInferRows), a.nq), dim3(256), lds, st, a);
+        return hipGetLastError();
+    }
+    (void)hipGetLastError();
     hipLaunchKernelGGL(infer_kernel, dim3(blocks_for(a.nrows, 64), a.nq), dim3(256), 0, st, a);
     return hipGetLastError();
 }

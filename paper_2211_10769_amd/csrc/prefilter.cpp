@@ -23,7 +23,6 @@
 #include <cstring>
 #include <numeric>
 #include <string>
-#include <unordered_set>
 #include <vector>
 
 #include "batch.h"
@@ -824,42 +823,46 @@ swh_status prefilter_search(swh_ctx *ctx, const swh_model *m, swh_db *db, int32_
     //      (slots are length-sorted already) and its long candidates as pairs
     std::vector<DbGroup> groups;
     std::vector<int32_t> gperm;
+    gperm.reserve((size_t)tot + 128 * (size_t)nq);
     std::vector<DbWork> work;
     std::vector<std::pair<int32_t, int32_t>> long_pairs;
-    std::vector<std::unordered_set<int32_t>> audit_set((size_t)nq);
+    std::vector<std::vector<int32_t>> audit_idx((size_t)nq);   // sorted after the loop
     std::vector<int64_t> ncand((size_t)nq, 0);
     int64_t res_bytes = 0;
     for (int32_t q = 0; q < nq; ++q) {
         const int64_t Lq = qs.qo[q + 1] - qs.qo[q];
-        std::vector<int32_t> slots;
+        const size_t first_slot = gperm.size();
         for (int64_t i = qbase[q]; i < qbase[q + 1]; ++i) {
             const int32_t r = crow[i];
             const int32_t idx = db->h_row_db[r];
             if (ckind[i] == 1) {
                 ++ncand[q];
-                ++ps.candidates;
             } else {
-                audit_set[q].insert(idx);
-                ++ps.audited;
+                audit_idx[q].push_back(idx);
             }
             ps.cells_rescored += (double)Lq * (double)db->h_row_len[r];
             if (Lq == 0) continue;
-            if (r < db->pf_nslots)
-                slots.push_back(idx);
-            else
-                long_pairs.push_back({q, idx});
-        }
-        for (size_t i = 0; i < slots.size(); i += 128) {
-            DbGroup g{res_bytes, 0, (int32_t)gperm.size()};
-            for (size_t j = 0; j < 128; ++j) {
-                const int32_t idx = i + j < slots.size() ? slots[i + j] : -1;
+            if (r < db->pf_nslots) {
                 gperm.push_back(idx);
-                if (idx >= 0) g.maxlen = std::max<int32_t>(g.maxlen, (int32_t)(db->h_off[idx + 1] - db->h_off[idx]));
+            } else {
+                long_pairs.push_back({q, idx});
             }
-            res_bytes += (int64_t)g.maxlen * 128;
-            work.push_back(DbWork{q, (int32_t)groups.size()});
-            groups.push_back(g);
         }
+        ps.candidates += ncand[q];
+        ps.audited += (int64_t)audit_idx[q].size();
+        std::sort(audit_idx[q].begin(), audit_idx[q].end());
+        // groups of 128 slots; slots are in ascending length, so a group's
+        // longest member is its last one
+        const size_t nslot = gperm.size() - first_slot;
+        for (size_t i = 0; i < nslot; i += 128) {
+            const size_t last = std::min(nslot, i + 128) - 1;
+            const int32_t idx_last = gperm[first_slot + last];
+            const int32_t maxlen = (int32_t)(db->h_off[idx_last + 1] - db->h_off[idx_last]);
+            work.push_back(DbWork{q, (int32_t)groups.size()});
+            groups.push_back(DbGroup{res_bytes, maxlen, (int32_t)(first_slot + i)});
+            res_bytes += (int64_t)maxlen * 128;
+        }
+        gperm.resize(first_slot + (nslot + 127) / 128 * 128, -1);
         ps.cells_exhaustive += (double)Lq * (double)db->total_residues;
     }
     if ((s = ensure(ctx, ctx->pf_res, (size_t)res_bytes + 256, "candidate layout")) != SWH_OK ||
@@ -918,7 +921,7 @@ swh_status prefilter_search(swh_ctx *ctx, const swh_model *m, swh_db *db, int32_
         bool need = ncand[q] < std::min<int64_t>(k, ndb);
         for (int32_t j = 0; j < k && !need; ++j) {
             const int64_t idx = hi[(size_t)q * k + j];
-            if (idx >= 0 && audit_set[q].count((int32_t)idx)) need = true;
+            if (idx >= 0 && std::binary_search(audit_idx[q].begin(), audit_idx[q].end(), (int32_t)idx)) need = true;
         }
         if (need) fb.push_back(q);
     }

@@ -301,6 +301,8 @@ def main():
         "reverse_ms": round(sum(rev_ms) / len(rev_ms), 2),
         "traceback_ms": round(sum(tb_ms) / len(tb_ms), 2),
         "traceback_cells": res["stats"]["cells_traceback"],
+        "traceback_bands": res["stats"]["traceback_bands"],
+        "traceback_retries": res["stats"]["traceback_retries"],
         "roofline": {"bound": "alu", "kernel": "strip_kernel (local; forward and reverse passes)",
                      "achieved": round(k_gcups, 2), "peak": round(peak_gcups, 1), "unit": "GCUPS",
                      "frac": round(k_gcups / peak_gcups, 4), "traffic": round(traffic),

@@ -86,6 +86,9 @@ typedef struct {
     double   ms_reverse;        /* device time of the reverse pass */
     double   ms_traceback;      /* wall time of the traceback */
     double   cells_traceback;   /* DP cells evaluated by the traceback */
+    int64_t  traceback_bands;   /* bands the traceback was cut into at rows kept by the
+                                   score passes (0: one divide and conquer over the rectangle) */
+    int64_t  traceback_retries; /* band traceback abandoned for the plain one (expected 0) */
 } swh_stats;
 
 /* Context on HIP device `device` (ordinal).  Allocates nothing large; device

@@ -33,7 +33,8 @@ class swh_stats(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("cells_forward", ctypes.c_double), ("ms_forward", ctypes.c_double),
                 ("ms_reverse", ctypes.c_double), ("ms_traceback", ctypes.c_double),
-                ("cells_traceback", ctypes.c_double)]
+                ("cells_traceback", ctypes.c_double), ("traceback_bands", ctypes.c_int64),
+                ("traceback_retries", ctypes.c_int64)]
 
 
 class swh_hit(ctypes.Structure):

@@ -124,6 +124,11 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
                        const int64_t *t_off, const Scoring &sc, int mode, swh_alignment *out, char *cigar_cat,
                        int64_t cigar_cap, int64_t *cigar_off, swh_stats *stats)
 {
+    if (stats) {
+        const uint32_t size = stats->struct_size;
+        *stats = swh_stats{};
+        stats->struct_size = size;
+    }
     for (int64_t i = 0; i < npairs; ++i) {
         out[i].score = 0;
         out[i].flags = SWH_F_NONE;

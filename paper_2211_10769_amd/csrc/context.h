@@ -102,6 +102,8 @@ struct swh_ctx {
     // traceback buffers
     swh::Arena tb_arena;
     swh::DevBuf tb_fwd, tb_bwd, tb_front, tb_codes_q, tb_codes_t, tb_leaf, tb_misc;
+    // band traceback: rows kept by the forward and reverse score passes, cut tables
+    swh::DevBuf keep_f, keep_r, cut_desc, cut_cnt, cut_out;
     std::vector<swh::DevBuf *> all() {
         return {&qraw, &traw, &qc, &tc, &qr, &tr, &border, &flags, &misc, &strip_best, &mat, &lut,
                 &probs, &strip_prob, &prob_best, &sync,
@@ -109,7 +111,8 @@ struct swh_ctx {
                 &bq, &bt, &bborder,
                 &pf_fq, &pf_qlen, &pf_Aq, &pf_pred, &pf_hist, &pf_prefix, &pf_marks, &pf_chunk, &pf_cand,
                 &pf_res, &pf_groups, &pf_perm,
-                &tb_fwd, &tb_bwd, &tb_front, &tb_codes_q, &tb_codes_t, &tb_leaf, &tb_misc};
+                &tb_fwd, &tb_bwd, &tb_front, &tb_codes_q, &tb_codes_t, &tb_leaf, &tb_misc,
+                &keep_f, &keep_r, &cut_desc, &cut_cnt, &cut_out};
     }
 };
 

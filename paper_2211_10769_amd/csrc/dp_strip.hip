@@ -227,6 +227,12 @@ __global__ void __launch_bounds__(256 * kWgPerSimd<R>) strip_kernel(StripArgs a)
                 prof[prof_index<W>(A1, c, lane, w)] = (int)word;
             }
         }
+        // kept copy of this strip's last row (wave-uniform), if any
+        Border *keep = nullptr;
+        if (P.save_every > 0) {
+            const int t = s + 1 + P.save_phase;
+            if (t % P.save_every == 0) keep = P.save + (int64_t)(t / P.save_every - 1) * P.save_stride;
+        }
         int nreal = (int)min<int64_t>(max<int64_t>(P.n - row0, 0), R);
         const bool ragged = !LOCAL && __builtin_amdgcn_readfirstlane(
                                           (int)((int64_t)(s + 1) * 64 * R > P.n));
@@ -313,7 +319,10 @@ __global__ void __launch_bounds__(256 * kWgPerSimd<R>) strip_kernel(StripArgs a)
 
             // lane l holds lane 63's output of step 64b+l: column 64b+l-62 (1-based)
             const int idx = 64 * b + lane - 63;
-            if (idx >= 0 && idx < P.m) store_border(P.border + idx, oh, of);
+            if (idx >= 0 && idx < P.m) {
+                store_border(P.border + idx, oh, of);
+                if (keep) keep[idx] = Border{oh, of};
+            }
             drain_stores();
             // chunk b-1 (columns 64(b-1)+1 .. 64b) is now complete
             if (lane == 0 && b >= 1)
@@ -372,11 +381,15 @@ __global__ void encode_kernel(const char *src, int64_t len, uint8_t *dst, int64_
     }
 }
 
-__global__ void reverse_kernel(const uint8_t *src, int64_t len, uint8_t *dst, int64_t padded_len, uint8_t pad)
+// dst = lead pad codes, then src reversed, then pad codes up to padded_len
+__global__ void reverse_kernel(const uint8_t *src, int64_t len, uint8_t *dst, int64_t padded_len, int64_t lead,
+                               uint8_t pad)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < padded_len; i += stride)
-        dst[i] = i < len ? src[len - 1 - i] : pad;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < padded_len; i += stride) {
+        const int64_t k = i - lead;
+        dst[i] = (k >= 0 && k < len) ? src[len - 1 - k] : pad;
+    }
 }
 
 __global__ void fill_border_kernel(Border *b, int64_t count, Border v)
@@ -505,10 +518,10 @@ hipError_t launch_encode(const char *src, int64_t len, uint8_t *dst, int64_t pad
 }
 
 hipError_t launch_reverse(const uint8_t *src, int64_t len, uint8_t *dst, int64_t padded_len, uint8_t pad,
-                          hipStream_t st)
+                          hipStream_t st, int64_t lead)
 {
     hipLaunchKernelGGL(reverse_kernel, dim3(grid_for(padded_len, 256)), dim3(256), 0, st, src, len, dst,
-                       padded_len, pad);
+                       padded_len, lead, pad);
     return hipGetLastError();
 }
 

@@ -39,6 +39,13 @@ struct Problem {
     int32_t nstrips;
     int32_t nblocks;         // sweep_blocks(m)
     int32_t strip0;          // global index of this problem's first strip
+    int32_t save_every;      // > 0: keep the bottom rows of some strips (below)
+    // Strip s with (s + 1 + save_phase) % save_every == 0 also writes its last
+    // row (the same records as the border) to save + slot * save_stride, slot =
+    // (s + 1 + save_phase) / save_every - 1, columns 0 .. m-1.
+    Border *save;
+    int64_t save_stride;
+    int32_t save_phase;
     int32_t pad_;
 };
 
@@ -59,8 +66,9 @@ struct StripArgs {
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_encode(const char *src, int64_t len, uint8_t *dst, int64_t padded_len,
                          const uint8_t *lut, uint8_t pad, int32_t *bad_pos, hipStream_t st);
+// dst = lead pad codes, then src[len-1] .. src[0], then pad codes up to padded_len
 hipError_t launch_reverse(const uint8_t *src, int64_t len, uint8_t *dst, int64_t padded_len,
-                          uint8_t pad, hipStream_t st);
+                          uint8_t pad, hipStream_t st, int64_t lead = 0);
 hipError_t launch_fill_border(Border *b, int64_t count, Border v, hipStream_t st);
 // A launch of the strip kernel: nwg workgroups of `waves` waves (every wave
 // runs strips on its own), lds bytes of LDS per workgroup.

@@ -91,6 +91,10 @@ swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, cons
         P.nblocks = (int32_t)sweep_blocks(q.m);
         P.strip0 = (int32_t)total_strips;
         P.flags = (int32_t *)(intptr_t)total_flags;   // offset, fixed up below
+        P.save = q.save;
+        P.save_every = q.save ? q.save_every : 0;
+        P.save_stride = q.save_stride;
+        P.save_phase = q.save_phase;
         P.pad_ = 0;
         total_strips += P.nstrips;
         total_flags += P.nblocks + 3;

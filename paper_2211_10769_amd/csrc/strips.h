@@ -20,6 +20,11 @@ struct StripProblem {
     const uint8_t *tc;
     int64_t m;
     Border *border;
+    // optional: keep the last rows of every save_every-th strip (Problem)
+    Border *save = nullptr;
+    int64_t save_stride = 0;
+    int32_t save_every = 0;
+    int32_t save_phase = 0;
 };
 
 inline int64_t rows_padded(int64_t n, int R) { return ((n + 64 * R - 1) / (64 * R)) * 64 * R; }

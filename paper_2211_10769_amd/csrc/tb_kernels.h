@@ -25,13 +25,16 @@ struct GatherDesc {
 // kind 1: backward pass whose end is an H cell: G'(c) = c ? -o-(c-1)e : 0,
 //         D'(c) = G'(c) - o;
 // kind 2: backward pass whose end is an F cell: G' = -inf, D'(0) = -o,
-//         D'(c>0) = -inf.  Entries from count to padded are (-inf, -inf).
+//         D'(c>0) = -inf;
+// kind 3: a single frontier node: entry 0 = (seed_h, seed_f), the rest -inf.
+// Entries from count to padded are (-inf, -inf).
 struct BorderInit {
     Border *dst;
     const Border *src;
     int64_t count;
     int64_t padded;
     int32_t kind;
+    int32_t seed_h, seed_f;
     int32_t pad_;
 };
 
@@ -56,6 +59,37 @@ struct CrossOut {
     int32_t pad_[2];
 };
 
+// Crossing scan of one kept row of the two local score passes (the first
+// split of the band traceback, traceback.cpp).  For the cut between rows x
+// and x+1 of the full matrix:
+//   fwd[j] = (H(x, j), F(x+1, j))            forward local pass, j = 0..te
+//   rev[c] = (H'(x+2, te-c), F'(x+1, te-c))  reverse local pass (reversed
+//            columns; H' and F' are local values of the reversed DP)
+// An edge lies on an optimal local alignment iff forward + edge + reverse = S:
+//   vertical into F(x+1, j):   F(x+1, j) + F'(x+1, j) + o        = S
+//   diagonal into (x+1, j):    H(x, j-1) + s(A_{x+1}, B_j) + H'(x+2, j+1) = S
+// (H(x, -1) = 0 and H'(x+2, te+1) = 0 are the matrix borders).
+struct CutDesc {
+    const Border *fwd;
+    const Border *rev;
+    const uint8_t *arow;    // points at the code of A_{x+1}
+};
+
+// Resolved cut: clean = exactly one edge, and at a vertical edge the gap
+// cannot close at row x (H(x, j) - o != F(x+1, j)), so that the node where
+// the path meets row x is fixed.  That node is (x, col) in state H
+// (diagonal edge, value H(x, col)) or F (vertical edge, value F(x+1, col) +
+// e); the band below starts from it (seed record at column col).
+struct CutOut {
+    int32_t count;
+    int32_t key;            // smallest (j << 1) | vertical
+    int32_t clean;
+    int32_t col;
+    int32_t state;          // 0 = H, 1 = F
+    int32_t val;
+    int32_t seed_h, seed_f;
+};
+
 // One leaf: full DP with tie flags, then the greedy walk back to row 0 of
 // the leaf (its frontier row).
 struct LeafDesc {
@@ -67,6 +101,8 @@ struct LeafDesc {
     int32_t P, w;
     int32_t end_state;      // 0 = H, 1 = F; the end is (P, w-1)
     int32_t ops_cap;
+    int32_t V;              // forward value the end must have
+    int32_t pad_;
 };
 
 struct LeafOut {
@@ -74,7 +110,7 @@ struct LeafOut {
     int32_t exit_col;       // leaf column of the node reached in row 0
     int32_t exit_state;     // 0 = H, 1 = F
     int32_t exit_val;       // its forward value
-    int32_t err;            // nonzero: walk left the leaf (internal error)
+    int32_t err;            // nonzero: the walk left the leaf, or the end value is not V
     int32_t pad_[3];
 };
 
@@ -84,6 +120,12 @@ hipError_t launch_gather(const GatherDesc *d, int32_t nd, uint8_t pad, hipStream
 hipError_t launch_border_init(const BorderInit *d, int32_t nd, int32_t o, int32_t e, hipStream_t st);
 hipError_t launch_cross(const CrossDesc *d, int32_t nd, const int8_t *mat, int32_t asize, int32_t o, int32_t e,
                         CrossOut *out, hipStream_t st);
+// counts[k] += edges of cut k, keys[k] = min key (counts zero, keys INT32_MAX
+// or above on entry); one launch over all cuts, columns 0..te
+hipError_t launch_cut_scan(const CutDesc *d, int32_t nd, const uint8_t *tc, int64_t te, const int8_t *mat,
+                           int32_t asize, int32_t o, int32_t S, int32_t *counts, int32_t *keys, hipStream_t st);
+hipError_t launch_cut_resolve(const CutDesc *d, int32_t nd, const int32_t *counts, const int32_t *keys, int32_t o,
+                              int32_t e, CutOut *out, hipStream_t st);
 hipError_t launch_leaf(const LeafDesc *d, int32_t nd, const int8_t *mat, int32_t asize, int32_t o, int32_t e,
                        size_t lds_bytes, LeafOut *out, hipStream_t st);
 

@@ -60,8 +60,10 @@ __global__ void border_init_kernel(const BorderInit *descs, int32_t o, int32_t e
             } else if (d.kind == 1) {
                 const int32_t g = c == 0 ? 0 : (int32_t)(-(int64_t)o - (c - 1) * (int64_t)e);
                 v = Border{g, g - o};
-            } else {
+            } else if (d.kind == 2) {
                 v = Border{kNeg, c == 0 ? -o : kNeg};
+            } else if (c == 0) {
+                v = Border{d.seed_h, d.seed_f};
             }
         }
         d.dst[c] = v;
@@ -139,6 +141,82 @@ __global__ void __launch_bounds__(256) cross_kernel(const CrossDesc *descs, cons
     }
 }
 
+__global__ void __launch_bounds__(256) cut_scan_kernel(const CutDesc *descs, const uint8_t *tc, int64_t te,
+                                                       const int8_t *mat, int32_t asize, int32_t o, int32_t S,
+                                                       int32_t *counts, int32_t *keys)
+{
+    __shared__ int32_t s_count, s_key;
+    const CutDesc d = descs[blockIdx.y];
+    if (threadIdx.x == 0) {
+        s_count = 0;
+        s_key = INT32_MAX;
+    }
+    __syncthreads();
+    const int8_t *mrow = mat + (int)*d.arow * asize;
+    int count = 0, key = INT32_MAX;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j <= te; j += stride) {
+        const Border fw = d.fwd[j];
+        const Border rv = d.rev[te - j];
+        if ((int64_t)fw.f + rv.f + o == S) {
+            ++count;
+            key = min(key, (int)(j << 1) | 1);
+        }
+        const int64_t hd = j >= 1 ? d.fwd[j - 1].h : 0;
+        const int64_t hr = j < te ? d.rev[te - j - 1].h : 0;
+        if (hd + mrow[tc[j]] + hr == S) {
+            ++count;
+            key = min(key, (int)(j << 1));
+        }
+    }
+    if (count) {
+        atomicAdd(&s_count, count);
+        atomicMin(&s_key, key);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_count) {
+        atomicAdd(counts + blockIdx.y, s_count);
+        atomicMin(keys + blockIdx.y, s_key);
+    }
+}
+
+__global__ void cut_resolve_kernel(const CutDesc *descs, int32_t nd, const int32_t *counts, const int32_t *keys,
+                                   int32_t o, int32_t e, CutOut *outs)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nd) return;
+    const CutDesc d = descs[k];
+    CutOut r;
+    r.count = counts[k];
+    r.key = keys[k];
+    r.clean = 0;
+    r.col = -1;
+    r.state = 0;
+    r.val = 0;
+    r.seed_h = r.seed_f = kNeg;
+    if (r.count == 1) {
+        const int j = r.key >> 1;
+        if (r.key & 1) {
+            const Border fw = d.fwd[j];
+            if (fw.h - o != fw.f) {
+                r.clean = 1;
+                r.col = j;
+                r.state = 1;
+                r.val = fw.f + e;
+                r.seed_f = fw.f;
+            }
+        } else if (j >= 1) {
+            const Border fw = d.fwd[j - 1];
+            r.clean = 1;
+            r.col = j - 1;
+            r.state = 0;
+            r.val = fw.h;
+            r.seed_h = fw.h;
+        }
+    }
+    outs[k] = r;
+}
+
 // One wave per leaf.  Rows are processed 64 at a time, lane = row, with a
 // one-column skew per lane; H and the F handed down pass between lanes by a
 // DPP shift, and between row groups through a row buffer in LDS.  Each cell
@@ -158,8 +236,10 @@ __global__ void __launch_bounds__(64) leaf_kernel(const LeafDesc *descs, const i
     Border *row = reinterpret_cast<Border *>(lds + 1024);           // w entries
     uint8_t *fl = d.gflags ? d.gflags : lds + 1024 + (size_t)8 * w;
 
+    __shared__ int32_t s_endv;
     for (int k = lane; k < asize * asize; k += 64) smat[k] = mat[k];
     for (int k = lane; k < w; k += 64) row[k] = d.front[k];
+    if (lane == 0) s_endv = kNeg;
     __syncthreads();
 
     const int nstr = (P + 63) / 64;
@@ -186,6 +266,7 @@ __global__ void __launch_bounds__(64) leaf_kernel(const LeafDesc *descs, const i
                 fl[(int64_t)(i - 1) * w + c] = (uint8_t)flag;
                 fdown = max(fin - e, h - o);
                 En = max(E - e, h - o);
+                if (i == P && c == w - 1) s_endv = d.end_state ? fin : h;
             }
             hbot = h;
             fbot = fdown;
@@ -216,6 +297,7 @@ __global__ void __launch_bounds__(64) leaf_kernel(const LeafDesc *descs, const i
             }
         }
         if (c < 0 || state == 2) err = err ? err : 2;
+        if (s_endv != d.V) err = 3;
         LeafOut r;
         r.nops = n;
         r.exit_col = c;
@@ -257,6 +339,31 @@ hipError_t launch_cross(const CrossDesc *d, int32_t nd, const int8_t *mat, int32
 {
     if (nd <= 0) return hipSuccess;
     hipLaunchKernelGGL(cross_kernel, dim3(nd), dim3(256), 0, st, d, mat, asize, o, e, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cut_scan(const CutDesc *d, int32_t nd, const uint8_t *tc, int64_t te, const int8_t *mat,
+                           int32_t asize, int32_t o, int32_t S, int32_t *counts, int32_t *keys, hipStream_t st)
+{
+    if (nd <= 0 || te < 0) return hipSuccess;
+    // about 16 K columns per workgroup, enough workgroups per cut to fill the GPU
+    const int64_t chunks = std::max<int64_t>(1, std::min<int64_t>((te + 1 + 16383) / 16384, 1024));
+    for (int32_t k0 = 0; k0 < nd; k0 += 65535) {   // grid y is at most 65,535
+        const int32_t n = std::min<int32_t>(nd - k0, 65535);
+        hipLaunchKernelGGL(cut_scan_kernel, dim3((unsigned)chunks, (unsigned)n), dim3(256), 0, st, d + k0, tc, te, mat,
+                           asize, o, S, counts + k0, keys + k0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_cut_resolve(const CutDesc *d, int32_t nd, const int32_t *counts, const int32_t *keys, int32_t o,
+                              int32_t e, CutOut *out, hipStream_t st)
+{
+    if (nd <= 0) return hipSuccess;
+    hipLaunchKernelGGL(cut_resolve_kernel, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, st, d, nd, counts, keys,
+                       o, e, out);
     return hipGetLastError();
 }
 

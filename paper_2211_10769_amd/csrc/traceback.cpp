@@ -98,32 +98,47 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
     swh_status s;
 
     // per pair: B with the pad code in front (bpad[j] = code of B_j, bpad[0] =
-    // pad) and the root frontier G(0, j), F(1, j) = G(0, j) - o
+    // pad); per band the root of its subproblem tree: the top band starts from
+    // the rectangle's top border G(0, j), F(1, j) = G(0, j) - o, every other
+    // band from the single node where the path crosses into it
     std::vector<Node> nodes;
     nodes.reserve((size_t)npairs * 4);
+    std::vector<std::vector<int>> roots((size_t)npairs);   // top band first
     std::vector<GatherDesc> gd0;
     std::vector<BorderInit> bi0;
     for (int k = 0; k < npairs; ++k) {
         const TbInput &x = in[k];
         uint8_t *bpad = (uint8_t *)arena.get((size_t)x.q + 2);
-        Border *root_front = (Border *)arena.get(sizeof(Border) * (size_t)(x.q + 1));
-        if (!bpad || !root_front) return fail(ctx, SWH_E_NOMEM, "traceback arena");
+        if (!bpad) return fail(ctx, SWH_E_NOMEM, "traceback arena");
         gd0.push_back(GatherDesc{x.B, bpad, 0, x.q, x.q + 1, 1, 1});
-        bi0.push_back(BorderInit{root_front, nullptr, x.q + 1, x.q + 1, 1, 0});
-        Node root;
-        root.pair = k;
-        root.A = x.A;
-        root.bpad = bpad;
-        root.r_top = 0;
-        root.r_bot = x.p;
-        root.L = 0;
-        root.J = x.q;
-        root.front = root_front;
-        root.front_L = 0;
-        root.end_state = 0;
-        root.V = x.S;
-        root.ready = true;
-        nodes.push_back(root);
+        std::vector<TbBand> bands = x.bands;
+        if (bands.empty()) bands.push_back(TbBand{0, x.p, 0, x.q, false, 0, 0, 0, x.S});
+        for (const TbBand &b : bands) {
+            if (b.r_top < 0 || b.r_bot > x.p || b.r_top >= b.r_bot || b.L < 0 || b.J > x.q || b.L > b.J ||
+                (!b.seeded && (b.r_top != 0 || b.L != 0))) {
+                ts.inconsistent = true;
+                return fail(ctx, SWH_E_DEVICE, "traceback: malformed band (internal error)");
+            }
+            const int64_t cnt = b.seeded ? b.J - b.L + 1 : x.q + 1;
+            Border *front = (Border *)arena.get(sizeof(Border) * (size_t)cnt);
+            if (!front) return fail(ctx, SWH_E_NOMEM, "traceback arena");
+            bi0.push_back(BorderInit{front, nullptr, cnt, cnt, b.seeded ? 3 : 1, b.seed_h, b.seed_f, 0});
+            Node root;
+            root.pair = k;
+            root.A = x.A;
+            root.bpad = bpad;
+            root.r_top = b.r_top;
+            root.r_bot = b.r_bot;
+            root.L = b.L;
+            root.J = b.J;
+            root.front = front;
+            root.front_L = b.seeded ? b.L : 0;
+            root.end_state = b.end_state;
+            root.V = b.V;
+            root.ready = true;
+            roots[k].push_back((int)nodes.size());
+            nodes.push_back(root);
+        }
     }
     if ((s = upload(ctx, ctx->tb_misc, gd0, st, "gather table")) != SWH_OK) return s;
     if ((e = launch_gather((const GatherDesc *)ctx->tb_misc.p, (int32_t)gd0.size(), pad, st)) != hipSuccess)
@@ -135,8 +150,8 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
         return hip_fail(ctx, e, "traceback setup");
 
     std::vector<char> ops_host;
-    std::vector<int> ready((size_t)npairs);
-    for (int k = 0; k < npairs; ++k) ready[k] = k;
+    std::vector<int> ready((size_t)nodes.size());
+    for (size_t k = 0; k < nodes.size(); ++k) ready[k] = (int)k;
     // SWH_TB_LEAF lowers the leaf size (tests use it to force deep recursion on small inputs)
     const int64_t leaf_cells = std::max<int64_t>(1, std::min<int64_t>(kLeafCells, env_int("SWH_TB_LEAF", (int)kLeafCells)));
 
@@ -270,8 +285,10 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
 
             for (int i = 0; i < ns; ++i) {
                 const int k = splits[i];
-                if (co[i].count <= 0 || co[i].cmin < nodes[k].L)
+                if (co[i].count <= 0 || co[i].cmin < nodes[k].L) {
+                    ts.inconsistent = true;
                     return fail(ctx, SWH_E_DEVICE, "traceback: no optimal crossing found (internal error)");
+                }
                 Node bot;
                 bot.pair = nodes[k].pair;
                 bot.A = nodes[k].A;
@@ -356,6 +373,8 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
                 d.w = (int32_t)w;
                 d.end_state = n.end_state;
                 d.ops_cap = (int32_t)(P + w + 1);
+                d.V = n.V;
+                d.pad_ = 0;
                 op_off[i] = off;
                 off += P + w + 1;
                 ld[i] = d;
@@ -377,7 +396,10 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
                 return hip_fail(ctx, e, "leaf results");
             for (int i = 0; i < nl; ++i) {
                 Node &n = nodes[leaves[i]];
-                if (lo[i].err) return fail(ctx, SWH_E_DEVICE, "traceback walk left its subproblem (internal error)");
+                if (lo[i].err) {
+                    ts.inconsistent = true;
+                    return fail(ctx, SWH_E_DEVICE, "traceback walk left its subproblem (internal error)");
+                }
                 n.leaf = true;
                 n.ops_off = (int64_t)base + op_off[i];
                 n.nops = lo[i].nops;
@@ -393,27 +415,49 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
 
     // every node must be resolved; assemble the ops, walking back from the end
     for (const Node &n : nodes)
-        if (!n.leaf && (n.bottom < 0 || n.top < 0 || !nodes[n.top].ready))
+        if (!n.leaf && (n.bottom < 0 || n.top < 0 || !nodes[n.top].ready)) {
+            ts.inconsistent = true;
             return fail(ctx, SWH_E_DEVICE, "traceback left a subproblem unresolved (internal error)");
+        }
+    // the node where a band's walk leaves its top row
+    auto band_exit = [&](int k) -> const Node & {
+        while (!nodes[k].leaf) k = nodes[k].top;
+        return nodes[k];
+    };
     std::string back;
     for (int pr = 0; pr < npairs; ++pr) {
         back.clear();
-        std::vector<int> stack{pr};
-        while (!stack.empty()) {
-            const int k = stack.back();
-            stack.pop_back();
-            const Node &n = nodes[k];
-            if (n.leaf) {
-                back.append(ops_host.data() + n.ops_off, (size_t)n.nops);
-            } else {
-                stack.push_back(n.top);      // processed after the bottom half
-                stack.push_back(n.bottom);
+        const std::vector<int> &rt = roots[(size_t)pr];
+        for (size_t b = rt.size(); b-- > 0;) {   // bottom band first
+            const Node &root = nodes[rt[b]];
+            if (b > 0) {
+                // a seeded band must leave through its seed node (column L,
+                // state H for a diagonal entry, F for a vertical one)
+                const Node &x = band_exit(rt[b]);
+                const bool seed_f = in[pr].bands[b].seed_h == kNeg;
+                if (x.exit_col != root.L || x.exit_state != (seed_f ? 1 : 0)) {
+                    ts.inconsistent = true;
+                    return fail(ctx, SWH_E_DEVICE, "traceback: band left through another node (internal error)");
+                }
+            }
+            std::vector<int> stack{rt[b]};
+            while (!stack.empty()) {
+                const int k = stack.back();
+                stack.pop_back();
+                const Node &n = nodes[k];
+                if (n.leaf) {
+                    back.append(ops_host.data() + n.ops_off, (size_t)n.nops);
+                } else {
+                    stack.push_back(n.top);      // processed after the bottom half
+                    stack.push_back(n.bottom);
+                }
             }
         }
-        int k = pr;
-        while (!nodes[k].leaf) k = nodes[k].top;
-        const int64_t rexit = nodes[k].exit_col;
-        if (rexit < 0) return fail(ctx, SWH_E_DEVICE, "traceback: no exit on row 0 (internal error)");
+        const int64_t rexit = band_exit(rt[0]).exit_col;
+        if (rexit < 0) {
+            ts.inconsistent = true;
+            return fail(ctx, SWH_E_DEVICE, "traceback: no exit on row 0 (internal error)");
+        }
         back.append((size_t)rexit, 'D');     // leading target residues against a gap, back to (0, 0)
 
         // run-length encode in forward order

@@ -246,11 +246,16 @@ __global__ void __launch_bounds__(256 * kWgPerSimd<R>) strip_kernel(StripArgs a)
         // best cell (local): key = (H << log2 R) | (R-1-k) orders cells of one
         // step by value, then smaller row; bkey keeps the largest key seen and
         // bstep the first step that reached it, so (value desc, row asc, column
-        // asc) -- the first cell in row-major order -- falls out without any
-        // branch.  Cells right of the last column or below the last row only
-        // hold values derived from real cells minus a gap penalty, so they can
-        // never reach the optimum and need no mask.
-        int bkey = 0, bstep = 0;
+        // asc) -- the first cell in row-major order -- falls out of a max.
+        // The keys of a step are only formed when some lane holds a cell of at
+        // least bthr = max(best value, 1): otherwise no key can exceed bkey
+        // (cells of value 0 never decide the result), and after a lane's first
+        // few hundred columns such steps are rare, so the tracker costs one
+        // max tree per step instead of a key per cell.  Cells right of the last
+        // column or below the last row only hold values derived from real cells
+        // minus a gap penalty, so they can never reach the optimum and need no
+        // mask.
+        int bkey = 0, bstep = 0, bthr = 1;
 
         // block 0 inputs
         int code = lane == 0 ? (int)P.tc[0] : pad;       // current column's code
@@ -305,12 +310,18 @@ __global__ void __launch_bounds__(256 * kWgPerSimd<R>) strip_kernel(StripArgs a)
 
                 if (LOCAL) {
                     constexpr int LOGR = Prof<R>::LOGR;
-                    int mx = (hp[0] << LOGR) | (R - 1);
+                    int hm = hp[0];
 #pragma unroll
-                    for (int k = 1; k < R; ++k) mx = max(mx, (hp[k] << LOGR) | (R - 1 - k));
-                    const bool gt = mx > bkey;
-                    bkey = gt ? mx : bkey;
-                    bstep = gt ? tbase + u : bstep;
+                    for (int k = 1; k < R; ++k) hm = max(hm, hp[k]);
+                    if (__builtin_amdgcn_ballot_w64(hm >= bthr)) {   // wave-uniform
+                        int mx = (hp[0] << LOGR) | (R - 1);
+#pragma unroll
+                        for (int k = 1; k < R; ++k) mx = max(mx, (hp[k] << LOGR) | (R - 1 - k));
+                        const bool gt = mx > bkey;
+                        bkey = gt ? mx : bkey;
+                        bstep = gt ? tbase + u : bstep;
+                        bthr = max(bkey >> LOGR, 1);
+                    }
                 }
 #pragma unroll
                 for (int w = 0; w < W; ++w) sc[w] = sc_n[w];

@@ -40,18 +40,33 @@ int env_int(const char *name, int dflt)
 
 // Strip height for a launch whose problems hold n rows in all.  The strips of
 // one problem form a chain that moves at the pace of its slowest wave, so a
-// long problem runs best with one wave per SIMD and enough strips for several
-// rounds over the 1,024 SIMDs (the last, partly empty round then costs
-// little); within that, taller strips spend fewer lane shifts and border
-// transfers per cell.  Same-box sweeps on the 5 Mbp pair: R = 16 with one
-// wave per SIMD 7.8 s, R = 32 8.1-8.3 s, R = 16 with two waves 9.6 s, R = 8
-// with two 10.1 s, R = 16 with four 18.0 s.
-int pick_rows_per_lane(int64_t n)
+// long problem runs with one wave per SIMD; each SIMD then runs
+// ceil(strips / SIMDs) strips one after the other, and a step of a strip costs
+// about 7.5 R + 24 instructions (7 per cell, half a max per cell for the
+// end-cell tracker, and lane shifts and profile reads per step).  Long
+// problems take the R in {8, 16, 20, 24, 32} that minimises
+// ceil(strips / SIMDs) (7.5 R + 24).  Same-box measurements on the 5 Mbp pair
+// (4,883 strips of 1,024 rows, 3,907 of 1,280, ...): R = 20 7.21 s, R = 16
+// 7.45 s, R = 24 8.13 s; earlier R = 32 about 5% slower than R = 16, and two
+// waves per SIMD 23% slower.
+int pick_rows_per_lane(int64_t n, int simds)
 {
     const int forced = env_int("SWH_ROWS", 0);
     if (forced == 4 || forced == 8 || forced == 16 || forced == 20 || forced == 24 || forced == 32) return forced;
-    for (int R : {32, 16, 8})
-        if ((n + 64 * R - 1) / (64 * R) >= 4 * 1024) return R;
+    simds = std::max(simds, 1);
+    auto strips = [&](int R) { return (n + 64 * R - 1) / (64 * R); };
+    if (strips(8) >= 4 * (int64_t)simds) {
+        int best = 8;
+        int64_t best_cost = INT64_MAX;
+        for (int R : {8, 16, 20, 24, 32}) {
+            const int64_t cost = (strips(R) + simds - 1) / simds * (15 * (int64_t)R + 48);
+            if (cost < best_cost) {
+                best_cost = cost;
+                best = R;
+            }
+        }
+        return best;
+    }
     // shorter problems come in batches: 8 rows per lane costs fewer operations
     // per cell than 4 (sweep on 20,000 read pairs: 1.78 s against 2.01 s)
     return n >= 512 ? 8 : 4;

@@ -60,15 +60,19 @@ struct CrossOut {
 };
 
 // Crossing scan of one kept row of the two local score passes (the first
-// split of the band traceback, traceback.cpp).  For the cut between rows x
-// and x+1 of the full matrix:
+// split of the band traceback, engine.cpp).  For the cut between rows x and
+// x+1 of the full matrix:
 //   fwd[j] = (H(x, j), F(x+1, j))            forward local pass, j = 0..te
 //   rev[c] = (H'(x+2, te-c), F'(x+1, te-c))  reverse local pass (reversed
-//            columns; H' and F' are local values of the reversed DP)
-// An edge lies on an optimal local alignment iff forward + edge + reverse = S:
-//   vertical into F(x+1, j):   F(x+1, j) + F'(x+1, j) + o        = S
+//            columns; H'(i, j) and F'(i, j) are local values of the reversed
+//            DP: the best alignment of A_i.., B_j.. that starts at row i)
+// After a node in column j the path goes on with columns j+1 onwards, so an
+// edge lies on an optimal local alignment iff forward + edge + reverse = S:
+//   vertical into F(x+1, j):   F(x+1, j) + F'(x+1, j+1) + o               = S
 //   diagonal into (x+1, j):    H(x, j-1) + s(A_{x+1}, B_j) + H'(x+2, j+1) = S
-// (H(x, -1) = 0 and H'(x+2, te+1) = 0 are the matrix borders).
+// (the open penalty of a gap through the cut is counted by both passes;
+// H(x, -1) = 0 and H'(x+2, te+1) = 0 are the matrix borders, and no vertical
+// edge in the last column can continue to the end cell).
 struct CutDesc {
     const Border *fwd;
     const Border *rev;

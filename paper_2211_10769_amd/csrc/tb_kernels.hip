@@ -156,15 +156,15 @@ __global__ void __launch_bounds__(256) cut_scan_kernel(const CutDesc *descs, con
     int count = 0, key = INT32_MAX;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j <= te; j += stride) {
-        const Border fw = d.fwd[j];
-        const Border rv = d.rev[te - j];
-        if ((int64_t)fw.f + rv.f + o == S) {
+        // the rest of the path after a node in column j uses columns j+1 ..:
+        // reverse record of column j+1 (none after the last column)
+        const Border rv = j < te ? d.rev[te - j - 1] : Border{0, kNeg};
+        if ((int64_t)d.fwd[j].f + rv.f + o == S) {
             ++count;
             key = min(key, (int)(j << 1) | 1);
         }
         const int64_t hd = j >= 1 ? d.fwd[j - 1].h : 0;
-        const int64_t hr = j < te ? d.rev[te - j - 1].h : 0;
-        if (hd + mrow[tc[j]] + hr == S) {
+        if (hd + mrow[tc[j]] + rv.h == S) {
             ++count;
             key = min(key, (int)(j << 1));
         }

@@ -23,7 +23,7 @@ StripShape tuned_shape(swh_ctx *ctx, int64_t n)
     for (const swh_tune_entry &t : ctx->tune)
         if (n <= t.max_rows) return StripShape{t.rows_per_lane, t.waves_per_simd};
     if (!ctx->tune.empty()) return StripShape{ctx->tune.back().rows_per_lane, ctx->tune.back().waves_per_simd};
-    return StripShape{pick_rows_per_lane(n), 0};
+    return StripShape{pick_rows_per_lane(n, 4 * ctx->num_cu), 0};
 }
 
 swh_status autotune(swh_ctx *ctx, const Scoring &sc, int64_t max_rows, double cells_per_trial)

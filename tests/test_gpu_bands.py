@@ -53,7 +53,7 @@ def test_flanks_move_the_cuts(eng, bands, flank):
     _cmp(eng, bytes(q), bytes(t), sc, min_bands=10)
 
 
-@pytest.mark.parametrize("rows,R", [(512, 8), (1024, 16), (2048, 8)])
+@pytest.mark.parametrize("rows,R", [(512, 8), (1024, 16), (2048, 8), (1280, 20), (1536, 24), (2048, 32)])
 def test_strip_heights(eng, bands, rows, R):
     bands(rows, R=R)
     rng = np.random.default_rng(rows + R)
@@ -74,7 +74,8 @@ def test_long_gaps_cross_kept_rows(eng, bands):
     dele = seqgen.random_dna(rng, 700)
     q = np.concatenate([x, ins, y, z])
     t = np.concatenate([seqgen.mutate(rng, x, 0.01, 0.0), y, dele, seqgen.mutate(rng, z, 0.01, 0.0)])
-    st = _cmp(eng, bytes(q), bytes(t), sc, min_bands=2)
+    # nearly every kept row must be a clean cut, those inside the gaps included
+    st = _cmp(eng, bytes(q), bytes(t), sc, min_bands=int(0.8 * len(q) / 256))
     assert st["cells_traceback"] < 0.5 * len(q) * len(t)
 
 

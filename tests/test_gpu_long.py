@@ -55,7 +55,7 @@ def test_full_size_pair(eng):
     res = eng.align(q, t, sc, mode="cigar", stats=True)
     st = res["stats"]
     assert res["score"] > 0.8 * len(q)
-    assert st["traceback_bands"] > 100 and st["traceback_retries"] == 0
+    assert st["traceback_bands"] > 100 and st["traceback_retries"] == 0, st
     assert st["cells_traceback"] < 0.05 * len(q) * len(t)
     assert _rescore(q, t, res, sc) == res["score"]
 

@@ -34,13 +34,15 @@ VALU_LANE_OPS = 256 * 64 * 2.4e9
 # add (diag + s), max3 (H), sub (H - o), sub + max3 (E), sub + max3 (F).
 OPS_PER_CELL = 7
 # HBM bytes per DP cell of the local strip kernel on the long pair, from two
-# rocprofv3 counter passes over one forward launch (2.55e13 cells), each
+# rocprofv3 counter passes over one CIGAR step (forward launch 2.55e13 cells,
+# reverse launch 2.53e13, both keeping rows for the band traceback), each
 # scaled by the same counter on a 1 GiB plain copy (profiles/
-# strip_kernel_long_dna.md): FETCH_SIZE 118,000,542 KiB x 2.0 + WRITE_SIZE
-# 218,883,673 KiB x 1.0 = 465.8 GB.  Valid for the kernel those counters were
-# taken on; the roofline's traffic field is this figure times the cells of a
-# launch.
-HBM_BYTES_PER_CELL = (2.0 * 118_000_542.4375 + 1.0 * 218_883_673.15625) * 1024 / 25_500_765_000_000
+# strip_kernel_long_dna.md): FETCH_SIZE (95,722,018 + 95,321,930) KiB x 2.0 +
+# WRITE_SIZE (190,673,379 + 188,888,006) KiB x 1.0 = 779.9 GB over both.
+# Valid for the kernel those counters were taken on; the roofline's traffic
+# field is this figure times the cells of a launch.
+HBM_BYTES_PER_CELL = ((95_722_017.75 + 95_321_930.125) * 2.0 + 190_673_379.0625 + 188_888_006.0625) * 1024 / (
+    25_500_765_000_000 + 5_000_000 * 5_050_153)
 
 
 def log(msg: str):

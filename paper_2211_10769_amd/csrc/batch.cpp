@@ -15,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "bands.h"
 #include "batch.h"
 #include "context.h"
 #include "strips.h"
@@ -30,6 +31,10 @@ namespace {
 constexpr int64_t kChunkBytes = (int64_t)3 << 30;
 // total rectangle columns of one traceback batch (arena: ~9 bytes per column)
 constexpr int64_t kTracebackCols = (int64_t)64 << 20;
+// band traceback of a batch: rows between kept rows, and the device bytes the
+// kept rows of one group of pairs may take (both passes)
+constexpr int64_t kBatchBandRows = 1024;
+constexpr int64_t kBatchKeepBytes = (int64_t)16 << 30;
 
 template <typename T>
 swh_status upload(swh_ctx *ctx, DevBuf &buf, const std::vector<T> &v, hipStream_t st, const char *what)
@@ -49,7 +54,7 @@ swh_status score_passes(swh_ctx *ctx, const std::vector<PairPass> &ps, const Sco
     const size_t np = ps.size();
     best.assign(np, BestCell{0, 0, 0, 0});
     std::vector<StripShape> sh(np);
-    for (size_t i = 0; i < np; ++i) sh[i] = tuned_shape(ctx, ps[i].n);
+    for (size_t i = 0; i < np; ++i) sh[i] = ps[i].R ? StripShape{ps[i].R, ps[i].waves} : tuned_shape(ctx, ps[i].n);
     auto same = [&](size_t a, size_t b) { return sh[a].R == sh[b].R && sh[a].waves == sh[b].waves; };
     // by strip shape, then most expensive first
     std::vector<size_t> order(np);
@@ -75,10 +80,10 @@ swh_status score_passes(swh_ctx *ctx, const std::vector<PairPass> &ps, const Sco
                 ++end;
                 continue;
             }
-            const int64_t b = rows_padded(p.n, Rk) + cols_padded(p.m) * (1 + (int64_t)sizeof(Border));
+            const int64_t b = rows_padded(p.n + p.lead, Rk) + cols_padded(p.m) * (1 + (int64_t)sizeof(Border));
             if (bytes && bytes + b > kChunkBytes) break;
             bytes += b;
-            nq += rows_padded(p.n, Rk);
+            nq += rows_padded(p.n + p.lead, Rk);
             nt += cols_padded(p.m);
             nb += cols_padded(p.m);
             ++end;
@@ -96,10 +101,17 @@ swh_status score_passes(swh_ctx *ctx, const std::vector<PairPass> &ps, const Sco
         for (size_t i = k; i < end; ++i) {
             const PairPass &p = ps[order[i]];
             if (p.n == 0 || p.m == 0) continue;
-            const int64_t qpad = rows_padded(p.n, Rk), tpad = cols_padded(p.m);
-            gd.push_back(GatherDesc{p.q, qp, 0, p.n, qpad, p.step, 0});
+            const int64_t qpad = rows_padded(p.n + p.lead, Rk), tpad = cols_padded(p.m);
+            gd.push_back(GatherDesc{p.q, qp, 0, p.n, qpad, p.step, (int32_t)p.lead});
             gd.push_back(GatherDesc{p.t, tp, 0, p.m, tpad, p.step, 0});
-            probs.push_back(StripProblem{qp, p.n, tp, p.m, bp});
+            StripProblem sp{qp, p.n + p.lead, tp, p.m, bp};
+            if (p.keep) {
+                sp.save = p.keep;
+                sp.save_stride = tpad;
+                sp.save_every = p.every;
+                sp.save_phase = p.phase;
+            }
+            probs.push_back(sp);
             idx.push_back(order[i]);
             qp += qpad;
             tp += tpad;
@@ -184,76 +196,209 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
     }
     const uint8_t *qc = (const uint8_t *)ctx->qc.p, *tc = (const uint8_t *)ctx->tc.p;
 
-    // ---- resolution: forward local pass of every pair
+    // ---- the pairs' passes, in groups: in CIGAR mode both score passes keep
+    // rows for the band traceback (bands.cpp), and a group is sized so that
+    // its kept rows fit the budget; otherwise one group holds every pair
     std::vector<PairPass> ps((size_t)npairs);
     double cells = 0.0;
     for (int64_t i = 0; i < npairs; ++i) {
         ps[i] = PairPass{qc + (q_off[i] - qbase), q_off[i + 1] - q_off[i], tc + (t_off[i] - tbase),
-                     t_off[i + 1] - t_off[i], 1};
+                         t_off[i + 1] - t_off[i], 1};
         cells += (double)ps[i].n * (double)ps[i].m;
     }
-    std::vector<BestCell> fwd;
-    double ms_fwd = 0.0, ms_rev = 0.0;
-    if ((s = score_passes(ctx, ps, sc, st, fwd, ms_fwd)) != SWH_OK) return s;
-    if (stats) {
-        stats->cells_forward = cells;
-        stats->ms_forward = ms_fwd;
-    }
-    std::vector<int64_t> pos_pairs;
-    for (int64_t i = 0; i < npairs; ++i) {
-        out[i].score = fwd[i].score;
-        if (fwd[i].score > 0) {
-            out[i].q_end = fwd[i].row - 1;
-            out[i].t_end = fwd[i].col - 1;
-            pos_pairs.push_back(i);
+    if (stats) stats->cells_forward = cells;
+    const int forced = env_int("SWH_BAND_ROWS", 0);
+    const bool banded = mode == SWH_MODE_CIGAR && forced >= 0;
+    std::vector<BandKeep> bk((size_t)npairs);
+    std::vector<int64_t> frecs((size_t)npairs, 0);
+    if (banded)
+        for (int64_t i = 0; i < npairs; ++i) {
+            const StripShape sh = tuned_shape(ctx, ps[i].n);
+            const int64_t H = 64 * (int64_t)sh.R;
+            const int64_t want = forced > 0 ? forced : kBatchBandRows;
+            const int every = (int)std::max<int64_t>(1, (want + H - 1) / H);
+            frecs[i] = band_forward_layout(sh.R, every, ps[i].n, ps[i].m, bk[i]);
+            ps[i].R = sh.R;
+            ps[i].waves = sh.waves;
         }
+    int64_t budget = kBatchKeepBytes / (int64_t)sizeof(Border);
+    {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+            budget = std::min<int64_t>(budget, (int64_t)(free_b / 8 / sizeof(Border)));
+        else
+            (void)hipGetLastError();
     }
-    if (mode == SWH_MODE_SCORE) return SWH_OK;
-
-    // ---- reverse pass over the reversed prefixes ending at each end cell
-    std::vector<PairPass> rp;
-    rp.reserve(pos_pairs.size());
-    for (int64_t i : pos_pairs)
-        rp.push_back(PairPass{ps[i].q + out[i].q_end, out[i].q_end + 1, ps[i].t + out[i].t_end, out[i].t_end + 1, -1});
-    std::vector<BestCell> rev;
-    if ((s = score_passes(ctx, rp, sc, st, rev, ms_rev)) != SWH_OK) return s;
-    if (stats) stats->ms_reverse = ms_rev;
-    for (size_t k = 0; k < pos_pairs.size(); ++k) {
-        const int64_t i = pos_pairs[k];
-        if (rev[k].score != fwd[i].score)
-            return fail(ctx, SWH_E_DEVICE, "pair " + std::to_string(i) + ": reverse pass maximum " +
-                                               std::to_string(rev[k].score) + " differs from the forward score " +
-                                               std::to_string(fwd[i].score));
-        out[i].q_begin = out[i].q_end - (rev[k].row - 1);
-        out[i].t_begin = out[i].t_end - (rev[k].col - 1);
-    }
-    if (mode == SWH_MODE_COORDS) return SWH_OK;
-
-    // ---- reconstruction: batched linear-space traceback
     std::vector<std::string> cig((size_t)npairs);
     TracebackStats ts;
-    size_t k = 0;
-    while (k < pos_pairs.size()) {
-        std::vector<TbInput> in;
-        std::vector<int64_t> ids;
-        int64_t cols = 0;
-        while (k < pos_pairs.size()) {
-            const int64_t i = pos_pairs[k];
-            const int64_t p = out[i].q_end - out[i].q_begin + 1, q = out[i].t_end - out[i].t_begin + 1;
-            if (!in.empty() && cols + q > kTracebackCols) break;
-            in.push_back(TbInput{ps[i].q + out[i].q_begin, p, ps[i].t + out[i].t_begin, q, out[i].score});
-            ids.push_back(i);
-            cols += q;
-            ++k;
+    double ms_fwd = 0.0, ms_rev = 0.0;
+    int64_t nbands = 0, retries = 0;
+    int64_t g0 = 0;
+    while (g0 < npairs) {
+        // a group: kept rows of both passes within the budget (a pair whose
+        // rows do not fit alone runs without them)
+        int64_t g1 = g0, recs = 0;
+        while (g1 < npairs) {
+            const int64_t r = 2 * frecs[(size_t)g1];
+            if (g1 > g0 && recs + r > budget) break;
+            recs += r;
+            ++g1;
         }
-        std::vector<std::string> cg;
-        if ((s = traceback_batch(ctx, in, sc, st, cg, ts)) != SWH_OK) return s;
-        for (size_t j = 0; j < ids.size(); ++j) cig[ids[j]].swap(cg[j]);
+        std::vector<PairPass> gps(ps.begin() + g0, ps.begin() + g1);
+        if (banded) {
+            int64_t off = 0;
+            const bool fits = recs <= budget && ensure(ctx, ctx->keep_f, (size_t)std::max<int64_t>(recs / 2, 1) *
+                                                                             sizeof(Border), "kept rows") == SWH_OK;
+            if (!fits) ctx->err.clear();
+            for (int64_t i = g0; i < g1; ++i) {
+                BandKeep &k = bk[(size_t)i];
+                if (!fits || k.every == 0) {
+                    k.every = 0;
+                    continue;
+                }
+                k.keep_f = (const Border *)ctx->keep_f.p + off;
+                PairPass &p = gps[(size_t)(i - g0)];
+                p.keep = (Border *)ctx->keep_f.p + off;
+                p.every = k.every;
+                p.phase = 0;
+                off += frecs[(size_t)i];
+            }
+        }
+
+        // ---- resolution: forward local pass of every pair of the group
+        std::vector<BestCell> fwd;
+        if ((s = score_passes(ctx, gps, sc, st, fwd, ms_fwd)) != SWH_OK) return s;
+        std::vector<int64_t> pos_pairs;
+        for (int64_t i = g0; i < g1; ++i) {
+            const BestCell &f = fwd[(size_t)(i - g0)];
+            out[i].score = f.score;
+            if (f.score > 0) {
+                out[i].q_end = f.row - 1;
+                out[i].t_end = f.col - 1;
+                pos_pairs.push_back(i);
+            }
+        }
+        if (mode == SWH_MODE_SCORE) {
+            g0 = g1;
+            continue;
+        }
+
+        // ---- reverse pass over the reversed prefixes ending at each end cell
+        // (with kept rows: the forward strip height and the lead rows that put
+        // its strip boundaries on the forward cuts)
+        std::vector<PairPass> rp;
+        rp.reserve(pos_pairs.size());
+        int64_t rrecs = 0;
+        for (int64_t i : pos_pairs) {
+            PairPass p{ps[i].q + out[i].q_end, out[i].q_end + 1, ps[i].t + out[i].t_end, out[i].t_end + 1, -1};
+            BandKeep &k = bk[(size_t)i];
+            if (k.every > 0) {
+                rrecs += band_reverse_layout(out[i].q_end, out[i].t_end, k);
+                p.R = k.R;
+                p.waves = ps[i].waves;
+                p.lead = k.lead;
+            }
+            rp.push_back(p);
+        }
+        if (rrecs > 0) {
+            if (ensure(ctx, ctx->keep_r, (size_t)rrecs * sizeof(Border), "kept rows") != SWH_OK) {
+                ctx->err.clear();
+                for (int64_t i : pos_pairs) bk[(size_t)i].every = 0;   // lead rows stay; they change nothing
+            } else {
+                int64_t off = 0;
+                for (size_t j = 0; j < pos_pairs.size(); ++j) {
+                    BandKeep &k = bk[(size_t)pos_pairs[j]];
+                    if (k.every <= 0) continue;
+                    k.keep_r = (const Border *)ctx->keep_r.p + off;
+                    rp[j].keep = (Border *)ctx->keep_r.p + off;
+                    rp[j].every = k.every;
+                    rp[j].phase = k.phase;
+                    off += k.kr * k.rstride;
+                }
+            }
+        }
+        std::vector<BestCell> rev;
+        if ((s = score_passes(ctx, rp, sc, st, rev, ms_rev)) != SWH_OK) return s;
+        for (size_t j = 0; j < pos_pairs.size(); ++j) {
+            const int64_t i = pos_pairs[j];
+            if (rev[j].score != out[i].score)
+                return fail(ctx, SWH_E_DEVICE, "pair " + std::to_string(i) + ": reverse pass maximum " +
+                                                   std::to_string(rev[j].score) + " differs from the forward score " +
+                                                   std::to_string(out[i].score));
+            out[i].q_begin = out[i].q_end - (rev[j].row - rp[j].lead - 1);
+            out[i].t_begin = out[i].t_end - (rev[j].col - 1);
+        }
+        if (mode == SWH_MODE_COORDS) {
+            g0 = g1;
+            continue;
+        }
+
+        // ---- band cuts of every pair of the group: one scan over all of them
+        std::vector<std::vector<TbBand>> bands(pos_pairs.size());
+        if (banded) {
+            std::vector<CutDesc> cd;
+            std::vector<int64_t> rows;
+            std::vector<size_t> first(pos_pairs.size() + 1, 0);
+            for (size_t j = 0; j < pos_pairs.size(); ++j) {
+                const int64_t i = pos_pairs[j];
+                first[j] = cd.size();
+                band_cuts(bk[(size_t)i], out[i], out[i].score, ps[i].q, ps[i].t, cd, rows);
+            }
+            first[pos_pairs.size()] = cd.size();
+            std::vector<CutOut> co;
+            if ((s = resolve_cuts(ctx, sc, st, cd, co)) != SWH_OK) return s;
+            for (size_t j = 0; j < pos_pairs.size(); ++j)
+                if (first[j + 1] > first[j])
+                    bands_from_cuts(co.data() + first[j], rows.data() + first[j], (int)(first[j + 1] - first[j]),
+                                    out[pos_pairs[j]], out[pos_pairs[j]].score, bands[j]);
+        }
+
+        // ---- reconstruction: batched linear-space traceback
+        size_t k = 0;
+        while (k < pos_pairs.size()) {
+            std::vector<TbInput> in;
+            std::vector<int64_t> ids;
+            int64_t cols = 0;
+            while (k < pos_pairs.size()) {
+                const int64_t i = pos_pairs[k];
+                const int64_t p = out[i].q_end - out[i].q_begin + 1, q = out[i].t_end - out[i].t_begin + 1;
+                if (!in.empty() && cols + q > kTracebackCols) break;
+                in.push_back(TbInput{ps[i].q + out[i].q_begin, p, ps[i].t + out[i].t_begin, q, out[i].score});
+                in.back().bands.swap(bands[k]);
+                ids.push_back(i);
+                cols += q;
+                ++k;
+            }
+            std::vector<std::string> cg;
+            TracebackStats t1;
+            s = traceback_batch(ctx, in, sc, st, cg, t1);
+            bool with_bands = false;
+            for (const TbInput &x : in) with_bands = with_bands || !x.bands.empty();
+            if (s != SWH_OK && t1.inconsistent && with_bands) {
+                // a band did not check out: this chunk again with the plain traceback
+                ++retries;
+                ctx->err.clear();
+                for (TbInput &x : in) x.bands.clear();
+                t1 = TracebackStats{};
+                s = traceback_batch(ctx, in, sc, st, cg, t1);
+            }
+            if (s != SWH_OK) return s;
+            for (const TbInput &x : in) nbands += (int64_t)x.bands.size();
+            ts.ms += t1.ms;
+            ts.cells += t1.cells;
+            for (size_t j = 0; j < ids.size(); ++j) cig[ids[j]].swap(cg[j]);
+        }
+        g0 = g1;
     }
     if (stats) {
+        stats->ms_forward = ms_fwd;
+        stats->ms_reverse = ms_rev;
         stats->ms_traceback = ts.ms;
         stats->cells_traceback = ts.cells;
+        stats->traceback_bands = nbands;
+        stats->traceback_retries = retries;
     }
+    if (mode != SWH_MODE_CIGAR) return SWH_OK;
     int64_t total = 0;
     for (int64_t i = 0; i < npairs; ++i) {
         cigar_off[i] = total;

@@ -17,6 +17,10 @@ struct PairPass {
     const uint8_t *t;
     int64_t m;
     int step;
+    int R = 0, waves = 0;      // strip shape (R = 0: the shape rule for n rows)
+    int64_t lead = 0;          // all-zero pad rows above row 0 (best rows count them)
+    Border *keep = nullptr;    // kept rows (strips.h StripProblem), or NULL
+    int32_t every = 0, phase = 0;
 };
 // Score, end row and end column of every pass (launches grouped by strip
 // shape, most expensive first, chunked to bound device memory).

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <string>
 
+#include "bands.h"
 #include "context.h"
 #include "engine.h"
 #include "strips.h"
@@ -59,27 +60,9 @@ swh_status local_pass(swh_ctx *ctx, const uint8_t *qc, int64_t n, const uint8_t 
     return SWH_OK;
 }
 
-// ---------------------------------------------------------------- band traceback
-//
-// The divide and conquer of the reconstruction needs, for a row x of the
-// aligned rectangle, where the optimal path crosses from row x into row x+1.
-// Both score passes already sweep the whole rectangle (the forward pass from
-// the top, the reverse pass from the end cell), so each keeps its last row
-// of every few strips; for the same rows x the forward record (H(x, j),
-// F(x+1, j)) and the reverse record (H'(x+2, j), F'(x+1, j)) give every edge
-// of an optimal local alignment as forward + edge + reverse = S (see
-// CutDesc).  Local values are at least the rectangle's global values and
-// equal them on every optimal path that ends at the end cell (a higher
-// prefix or suffix would beat S), so an edge set with one member holds the
-// path's crossing, with its true forward value.  Where a kept row has one
-// such edge (and, for a vertical edge, the gap cannot close on row x), the
-// path is cut there; the bands between cuts are independent subproblems of
-// the ordinary divide and conquer, each seeded with the single node it is
-// entered through (rows with several edges join the bands on both sides).
-// A band's restricted DP holds the true value at every node the canonical
-// walk can visit, as in the ordinary split, so the CIGAR is the same; the
-// work drops from about twice the rectangle to about twice the bands.
-
+// Band traceback (bands.cpp): in CIGAR mode both score passes keep rows for
+// the traceback's first split; budget per pass, and the smallest number of
+// kept rows worth keeping.
 constexpr int64_t kKeepBudget = (int64_t)16 << 30;   // bytes of kept rows per pass
 constexpr int64_t kKeepMinRows = 8;                  // fewer kept rows: not worth it
 
@@ -102,85 +85,6 @@ int band_stride(swh_ctx *ctx, int64_t n, int64_t m, int R)
     const int64_t max_rows = budget / row_bytes;
     if (max_rows < kKeepMinRows) return 0;
     return (int)std::max<int64_t>(1, (nstrips + max_rows - 1) / max_rows);
-}
-
-struct BandOutcome {
-    std::vector<TbBand> bands;   // empty: no usable cut (plain traceback)
-};
-
-// Cuts of the rectangle [qb, qe] x [tb, te] at the kept rows, resolved on the
-// device, turned into bands.  keep_f: forward rows (slot k-1 <-> row k*C - 1);
-// keep_r: reverse rows (slot (T + phase_r) / every - 1 - k <-> the same cut).
-swh_status plan_bands(swh_ctx *ctx, const Scoring &sc, hipStream_t st, int64_t C, int every, int64_t kf,
-                      int64_t T, int phase_r, int64_t kr, int64_t m, int64_t rm, const swh_alignment &al,
-                      int32_t S, BandOutcome &bo)
-{
-    bo.bands.clear();
-    const int64_t qb = al.q_begin, qe = al.q_end, tb = al.t_begin, te = al.t_end;
-    const int64_t k_lo = std::max<int64_t>(1, (qb + 1 + C - 1) / C), k_hi = qe / C;
-    std::vector<CutDesc> cd;
-    std::vector<int64_t> rows;   // cut row x per entry
-    const Border *kfp = (const Border *)ctx->keep_f.p, *krp = (const Border *)ctx->keep_r.p;
-    for (int64_t k = k_lo; k <= k_hi; ++k) {
-        const int64_t x = k * C - 1;
-        const int64_t slot_r = (T + phase_r) / every - 1 - k;
-        if (x < qb || x + 1 > qe || k - 1 >= kf || slot_r < 0 || slot_r >= kr || k * every > T - 1) continue;
-        cd.push_back(CutDesc{kfp + (k - 1) * cols_padded(m), krp + slot_r * cols_padded(rm),
-                             (const uint8_t *)ctx->qc.p + x + 1});
-        rows.push_back(x);
-    }
-    const int nc = (int)cd.size();
-    if (nc == 0) return SWH_OK;
-    swh_status s;
-    if ((s = ensure(ctx, ctx->cut_desc, sizeof(CutDesc) * (size_t)nc, "cut table")) != SWH_OK ||
-        (s = ensure(ctx, ctx->cut_cnt, 8 * (size_t)nc, "cut counters")) != SWH_OK ||
-        (s = ensure(ctx, ctx->cut_out, sizeof(CutOut) * (size_t)nc, "cut results")) != SWH_OK)
-        return s;
-    int32_t *cnt = (int32_t *)ctx->cut_cnt.p, *keys = cnt + nc;
-    hipError_t e;
-    if ((e = hipMemcpyAsync(ctx->cut_desc.p, cd.data(), sizeof(CutDesc) * (size_t)nc, hipMemcpyHostToDevice, st)) !=
-            hipSuccess ||
-        (e = hipMemsetAsync(cnt, 0, 4 * (size_t)nc, st)) != hipSuccess ||
-        (e = hipMemsetAsync(keys, 0x7F, 4 * (size_t)nc, st)) != hipSuccess)
-        return hip_fail(ctx, e, "cut tables");
-    if ((e = launch_cut_scan((const CutDesc *)ctx->cut_desc.p, nc, (const uint8_t *)ctx->tc.p, te,
-                             (const int8_t *)ctx->mat.p, sc.asize, sc.o, S, cnt, keys, st)) != hipSuccess ||
-        (e = launch_cut_resolve((const CutDesc *)ctx->cut_desc.p, nc, cnt, keys, sc.o, sc.e,
-                                (CutOut *)ctx->cut_out.p, st)) != hipSuccess)
-        return hip_fail(ctx, e, "cut scan launch");
-    std::vector<CutOut> co((size_t)nc);
-    if ((e = hipMemcpyAsync(co.data(), ctx->cut_out.p, sizeof(CutOut) * (size_t)nc, hipMemcpyDeviceToHost, st)) !=
-            hipSuccess ||
-        (e = hipStreamSynchronize(st)) != hipSuccess)
-        return hip_fail(ctx, e, "cut results");
-
-    // boundaries in rectangle coordinates: the top border, the clean cuts, the end
-    struct Bound {
-        int64_t row, col;
-        int state;
-        int32_t val, seed_h, seed_f;
-    };
-    std::vector<Bound> bd;
-    bd.push_back(Bound{0, 0, 0, 0, 0, 0});
-    for (int i = 0; i < nc; ++i) {
-        const CutOut &c = co[(size_t)i];
-        if (c.count <= 0) return SWH_OK;   // cannot happen for a true optimum: leave it to the plain traceback
-        if (!c.clean) continue;
-        const int64_t col = c.col - tb + 1, row = rows[(size_t)i] - qb + 1;
-        if (col < 1 || col > te - tb + 1) return SWH_OK;
-        bd.push_back(Bound{row, col, c.state, c.val, c.seed_h, c.seed_f});
-    }
-    if (bd.size() < 2) return SWH_OK;
-    bd.push_back(Bound{qe - qb + 1, te - tb + 1, 0, S, 0, 0});
-    for (size_t i = 0; i + 1 < bd.size(); ++i) {
-        const Bound &u = bd[i], &d = bd[i + 1];
-        if (u.col > d.col || u.row >= d.row) {
-            bo.bands.clear();
-            return SWH_OK;
-        }
-        bo.bands.push_back(TbBand{u.row, d.row, u.col, d.col, i > 0, u.seed_h, u.seed_f, d.state, d.val});
-    }
-    return SWH_OK;
 }
 
 }  // namespace
@@ -237,18 +141,19 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
                                              " is not in the alphabet");
 
     // ---- resolution: forward local pass (keeping rows for the band traceback in CIGAR mode)
-    const int64_t H = 64 * (int64_t)shape.R;
-    int every = mode == SWH_MODE_CIGAR ? band_stride(ctx, qlen, tlen, shape.R) : 0;
-    int64_t kf = 0;
+    BandKeep bk;
     KeepRows kfwd;
-    if (every > 0) {
-        kf = ((qlen + H - 1) / H) / every;
-        if (kf < 1 || ensure(ctx, ctx->keep_f, (size_t)(kf * cols_padded(tlen)) * sizeof(Border), "kept rows") !=
-                          SWH_OK) {
-            every = 0;
-            ctx->err.clear();
-        } else {
-            kfwd = KeepRows{(Border *)ctx->keep_f.p, every, 0};
+    {
+        const int every = mode == SWH_MODE_CIGAR ? band_stride(ctx, qlen, tlen, shape.R) : 0;
+        const int64_t recs = band_forward_layout(shape.R, every, qlen, tlen, bk);
+        if (bk.every > 0) {
+            if (ensure(ctx, ctx->keep_f, (size_t)recs * sizeof(Border), "kept rows") != SWH_OK) {
+                bk.every = 0;
+                ctx->err.clear();
+            } else {
+                bk.keep_f = (const Border *)ctx->keep_f.p;
+                kfwd = KeepRows{(Border *)ctx->keep_f.p, bk.every, 0};
+            }
         }
     }
     LocalPass fwd;
@@ -272,8 +177,9 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
     // q_end - (s'+1) H + 1 + lead, which is x + 2 for the forward cut row x = k C - 1
     // when (s'+1) = T - k every, T = (q_end + lead) / H.
     const int64_t rn = out->q_end + 1, rm = out->t_end + 1;
-    const StripShape rshape = every > 0 ? shape : tuned_shape(ctx, rn);
-    const int64_t lead = every > 0 ? (H - out->q_end % H) % H : 0;
+    const int64_t rrecs = band_reverse_layout(out->q_end, out->t_end, bk);
+    const StripShape rshape = bk.every > 0 ? shape : tuned_shape(ctx, rn);
+    const int64_t lead = bk.every > 0 ? bk.lead : 0;
     const int64_t rqpad = rows_padded(rn + lead, rshape.R);
     const int64_t rtpad = cols_padded(rm);
     if ((s = ensure(ctx, ctx->qr, (size_t)rqpad, "reversed query")) != SWH_OK) return s;
@@ -282,17 +188,14 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
             hipSuccess ||
         (e = launch_reverse((const uint8_t *)ctx->tc.p, rm, (uint8_t *)ctx->tr.p, rtpad, pad, st)) != hipSuccess)
         return hip_fail(ctx, e, "reverse kernel launch");
-    const int64_t T = every > 0 ? (out->q_end + lead) / H : 0;
-    const int phase_r = every > 0 ? (int)((every - T % every) % every) : 0;
-    int64_t kr = 0;
     KeepRows krev;
-    if (every > 0) {
-        kr = ((rn + lead + H - 1) / H + phase_r) / every;
-        if (kr < 1 || ensure(ctx, ctx->keep_r, (size_t)(kr * rtpad) * sizeof(Border), "kept rows") != SWH_OK) {
-            every = 0;
+    if (bk.every > 0) {
+        if (bk.kr < 1 || ensure(ctx, ctx->keep_r, (size_t)rrecs * sizeof(Border), "kept rows") != SWH_OK) {
+            bk.every = 0;
             ctx->err.clear();
         } else {
-            krev = KeepRows{(Border *)ctx->keep_r.p, every, phase_r};
+            bk.keep_r = (const Border *)ctx->keep_r.p;
+            krev = KeepRows{(Border *)ctx->keep_r.p, bk.every, bk.phase};
         }
     }
     LocalPass rev;
@@ -315,12 +218,13 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
                 (const uint8_t *)ctx->tc.p + out->t_begin, out->t_end - out->t_begin + 1, fwd.best.score};
     int64_t retries = 0;
     const auto t_cut = std::chrono::steady_clock::now();
-    if (every > 0) {
-        BandOutcome bo;
-        if ((s = plan_bands(ctx, sc, st, H * every, every, kf, T, phase_r, kr, tlen, rm, *out, fwd.best.score, bo)) !=
-            SWH_OK)
-            return s;
-        tin.bands = bo.bands;
+    if (bk.every > 0) {
+        std::vector<CutDesc> cd;
+        std::vector<int64_t> rows;
+        std::vector<CutOut> co;
+        band_cuts(bk, *out, fwd.best.score, (const uint8_t *)ctx->qc.p, (const uint8_t *)ctx->tc.p, cd, rows);
+        if ((s = resolve_cuts(ctx, sc, st, cd, co)) != SWH_OK) return s;
+        bands_from_cuts(co.data(), rows.data(), (int)co.size(), *out, fwd.best.score, tin.bands);
     }
     const double cut_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_cut).count();
     std::vector<std::string> cgs;

@@ -9,8 +9,8 @@
 
 namespace swh {
 
-// dst[i] = first_pad && i == 0 ? pad : src[start + step * (i - first_pad)]
-// for i < count; pad up to padded.
+// dst[i] = i < first_pad ? pad : src[start + step * (i - first_pad)] for
+// i - first_pad < count; pad up to padded.
 struct GatherDesc {
     const uint8_t *src;
     uint8_t *dst;
@@ -18,7 +18,7 @@ struct GatherDesc {
     int64_t count;
     int64_t padded;
     int32_t step;        // +1 or -1
-    int32_t first_pad;   // 1: dst[0] is the pad code and the copy starts at dst[1]
+    int32_t first_pad;   // pad codes before the copy (the copy starts at dst[first_pad])
 };
 
 // Top row of one DP pass.  kind 0: copy count entries from src;
@@ -77,6 +77,10 @@ struct CutDesc {
     const Border *fwd;
     const Border *rev;
     const uint8_t *arow;    // points at the code of A_{x+1}
+    const uint8_t *tc;      // target codes, columns 0..te
+    int64_t te;             // last column of the pair's rectangle
+    int32_t S;              // the pair's optimum
+    int32_t pad_;
 };
 
 // Resolved cut: clean = exactly one edge, and at a vertical edge the gap
@@ -125,9 +129,10 @@ hipError_t launch_border_init(const BorderInit *d, int32_t nd, int32_t o, int32_
 hipError_t launch_cross(const CrossDesc *d, int32_t nd, const int8_t *mat, int32_t asize, int32_t o, int32_t e,
                         CrossOut *out, hipStream_t st);
 // counts[k] += edges of cut k, keys[k] = min key (counts zero, keys INT32_MAX
-// or above on entry); one launch over all cuts, columns 0..te
-hipError_t launch_cut_scan(const CutDesc *d, int32_t nd, const uint8_t *tc, int64_t te, const int8_t *mat,
-                           int32_t asize, int32_t o, int32_t S, int32_t *counts, int32_t *keys, hipStream_t st);
+// or above on entry); one launch over all cuts (of any pairs); max_te = the
+// largest te among them
+hipError_t launch_cut_scan(const CutDesc *d, int32_t nd, int64_t max_te, const int8_t *mat, int32_t asize,
+                           int32_t o, int32_t *counts, int32_t *keys, hipStream_t st);
 hipError_t launch_cut_resolve(const CutDesc *d, int32_t nd, const int32_t *counts, const int32_t *keys, int32_t o,
                               int32_t e, CutOut *out, hipStream_t st);
 hipError_t launch_leaf(const LeafDesc *d, int32_t nd, const int8_t *mat, int32_t asize, int32_t o, int32_t e,

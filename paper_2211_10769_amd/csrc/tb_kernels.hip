@@ -141,9 +141,8 @@ __global__ void __launch_bounds__(256) cross_kernel(const CrossDesc *descs, cons
     }
 }
 
-__global__ void __launch_bounds__(256) cut_scan_kernel(const CutDesc *descs, const uint8_t *tc, int64_t te,
-                                                       const int8_t *mat, int32_t asize, int32_t o, int32_t S,
-                                                       int32_t *counts, int32_t *keys)
+__global__ void __launch_bounds__(256) cut_scan_kernel(const CutDesc *descs, const int8_t *mat, int32_t asize,
+                                                       int32_t o, int32_t *counts, int32_t *keys)
 {
     __shared__ int32_t s_count, s_key;
     const CutDesc d = descs[blockIdx.y];
@@ -153,6 +152,9 @@ __global__ void __launch_bounds__(256) cut_scan_kernel(const CutDesc *descs, con
     }
     __syncthreads();
     const int8_t *mrow = mat + (int)*d.arow * asize;
+    const uint8_t *tc = d.tc;
+    const int64_t te = d.te;
+    const int32_t S = d.S;
     int count = 0, key = INT32_MAX;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j <= te; j += stride) {
@@ -342,16 +344,16 @@ hipError_t launch_cross(const CrossDesc *d, int32_t nd, const int8_t *mat, int32
     return hipGetLastError();
 }
 
-hipError_t launch_cut_scan(const CutDesc *d, int32_t nd, const uint8_t *tc, int64_t te, const int8_t *mat,
-                           int32_t asize, int32_t o, int32_t S, int32_t *counts, int32_t *keys, hipStream_t st)
+hipError_t launch_cut_scan(const CutDesc *d, int32_t nd, int64_t max_te, const int8_t *mat, int32_t asize,
+                           int32_t o, int32_t *counts, int32_t *keys, hipStream_t st)
 {
-    if (nd <= 0 || te < 0) return hipSuccess;
+    if (nd <= 0 || max_te < 0) return hipSuccess;
     // about 16 K columns per workgroup, enough workgroups per cut to fill the GPU
-    const int64_t chunks = std::max<int64_t>(1, std::min<int64_t>((te + 1 + 16383) / 16384, 1024));
+    const int64_t chunks = std::max<int64_t>(1, std::min<int64_t>((max_te + 1 + 16383) / 16384, 1024));
     for (int32_t k0 = 0; k0 < nd; k0 += 65535) {   // grid y is at most 65,535
         const int32_t n = std::min<int32_t>(nd - k0, 65535);
-        hipLaunchKernelGGL(cut_scan_kernel, dim3((unsigned)chunks, (unsigned)n), dim3(256), 0, st, d + k0, tc, te, mat,
-                           asize, o, S, counts + k0, keys + k0);
+        hipLaunchKernelGGL(cut_scan_kernel, dim3((unsigned)chunks, (unsigned)n), dim3(256), 0, st, d + k0, mat, asize,
+                           o, counts + k0, keys + k0);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -141,3 +141,35 @@ def test_tuned_shapes_keep_results(eng):
     finally:
         eng.set_tune_table([])
     assert eng.tune_table() == []
+
+
+@pytest.mark.parametrize("rows", [256, 1024])
+def test_band_traceback_in_batches(eng, monkeypatch, rows):
+    # kept rows every few strips in both passes of every pair; CIGARs unchanged
+    monkeypatch.setenv("SWH_BAND_ROWS", str(rows))
+    qs, ts = _read_pairs(120, 6000, seed_stream=12)
+    sc = seqgen.dna_scoring()
+    got, st = eng.align_batch(qs, ts, sc, mode="cigar", stats=True)
+    _check(got, _oracle_all(qs, ts, sc))
+    assert st["traceback_retries"] == 0
+    assert st["traceback_bands"] > len(qs)
+    monkeypatch.setenv("SWH_BAND_ROWS", "-1")
+    got2, st2 = eng.align_batch(qs, ts, sc, mode="cigar", stats=True)
+    assert st2["traceback_bands"] == 0 and st2["cells_traceback"] > 2 * st["cells_traceback"]
+    _check(got2, got)
+
+
+def test_band_traceback_tie_heavy_batch(eng, monkeypatch):
+    monkeypatch.setenv("SWH_BAND_ROWS", "256")
+    monkeypatch.setenv("SWH_ROWS", "4")
+    tie = ("AC", np.array([[1, -1], [-1, 1]], dtype=np.int8), 1, 1)
+    rng = np.random.default_rng(13)
+    qs, ts = [], []
+    for n in (300, 900, 1500, 2500):
+        a = rng.choice(np.frombuffer(b"AC", np.uint8), n)
+        flip = rng.random(n) < 0.1
+        qs.append(bytes(a))
+        ts.append(bytes(np.where(flip, np.where(a == ord("A"), ord("C"), ord("A")), a).astype(np.uint8)))
+    got, st = eng.align_batch(qs, ts, tie, mode="cigar", stats=True)
+    _check(got, _oracle_all(qs, ts, tie))
+    assert st["traceback_retries"] == 0

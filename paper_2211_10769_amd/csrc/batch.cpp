@@ -33,7 +33,7 @@ constexpr int64_t kChunkBytes = (int64_t)3 << 30;
 constexpr int64_t kTracebackCols = (int64_t)64 << 20;
 // band traceback of a batch: rows between kept rows, and the device bytes the
 // kept rows of one group of pairs may take (both passes)
-constexpr int64_t kBatchBandRows = 1024;
+constexpr int64_t kBatchBandRows = 512;
 constexpr int64_t kBatchKeepBytes = (int64_t)16 << 30;
 
 template <typename T>

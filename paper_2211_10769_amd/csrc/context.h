@@ -101,7 +101,7 @@ struct swh_ctx {
     float pf_infer_ms = 0.f;
     // traceback buffers
     swh::Arena tb_arena;
-    swh::DevBuf tb_fwd, tb_bwd, tb_front, tb_codes_q, tb_codes_t, tb_leaf, tb_misc;
+    swh::DevBuf tb_fwd, tb_bwd, tb_front, tb_codes_q, tb_flags, tb_leaf, tb_misc;
     // band traceback: rows kept by the forward and reverse score passes, cut tables
     swh::DevBuf keep_f, keep_r, cut_desc, cut_cnt, cut_out;
     std::vector<swh::DevBuf *> all() {
@@ -111,7 +111,7 @@ struct swh_ctx {
                 &bq, &bt, &bborder,
                 &pf_fq, &pf_qlen, &pf_Aq, &pf_pred, &pf_hist, &pf_prefix, &pf_marks, &pf_chunk, &pf_cand,
                 &pf_res, &pf_groups, &pf_perm,
-                &tb_fwd, &tb_bwd, &tb_front, &tb_codes_q, &tb_codes_t, &tb_leaf, &tb_misc,
+                &tb_fwd, &tb_bwd, &tb_front, &tb_codes_q, &tb_flags, &tb_leaf, &tb_misc,
                 &keep_f, &keep_r, &cut_desc, &cut_cnt, &cut_out};
     }
 };

@@ -104,7 +104,7 @@ struct LeafDesc {
     const uint8_t *arows;   // codes of the leaf rows (P)
     const uint8_t *bcols;   // codes of the leaf columns (w); pad for DP column 0
     const Border *front;    // front[k]: frontier row value at leaf column k
-    uint8_t *gflags;        // P*w bytes in global memory, or NULL to use LDS
+    uint8_t *gflags;        // large leaves: leaf_flag_bytes(P, w) bytes of global memory (else unused)
     char *ops;              // ops out, backward order
     int32_t P, w;
     int32_t end_state;      // 0 = H, 1 = F; the end is (P, w-1)
@@ -112,6 +112,16 @@ struct LeafDesc {
     int32_t V;              // forward value the end must have
     int32_t pad_;
 };
+
+// Large leaves (leaf_big_kernel): kLeafR rows per lane; tie flags in global
+// memory, a nibble per cell, ceil(P / (64 kLeafR)) * (w + 63) * 64 dwords;
+// LDS: matrix, per-lane profile, row buffer and column codes.
+constexpr int kLeafR = 8;
+inline int64_t leaf_flag_bytes(int64_t P, int64_t w) { return (P + 64 * kLeafR - 1) / (64 * kLeafR) * (w + 63) * 256; }
+inline size_t leaf_big_lds(int asize, int64_t max_w)
+{
+    return (size_t)(1024 + (asize + 1) * 64 * (kLeafR / 4) * 4 + 9 * max_w + 16);
+}
 
 struct LeafOut {
     int32_t nops;
@@ -137,5 +147,8 @@ hipError_t launch_cut_resolve(const CutDesc *d, int32_t nd, const int32_t *count
                               int32_t e, CutOut *out, hipStream_t st);
 hipError_t launch_leaf(const LeafDesc *d, int32_t nd, const int8_t *mat, int32_t asize, int32_t o, int32_t e,
                        size_t lds_bytes, LeafOut *out, hipStream_t st);
+// large leaves; max_w = the widest leaf of the launch
+hipError_t launch_leaf_big(const LeafDesc *d, int32_t nd, const int8_t *mat, int32_t asize, int32_t o, int32_t e,
+                           int32_t max_w, LeafOut *out, hipStream_t st);
 
 }  // namespace swh

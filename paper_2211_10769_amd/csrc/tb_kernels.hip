@@ -219,10 +219,10 @@ __global__ void cut_resolve_kernel(const CutDesc *descs, int32_t nd, const int32
     outs[k] = r;
 }
 
-// One wave per leaf.  Rows are processed 64 at a time, lane = row, with a
-// one-column skew per lane; H and the F handed down pass between lanes by a
-// DPP shift, and between row groups through a row buffer in LDS.  Each cell
-// stores its tie flags:
+// Small leaves (flags in LDS): one wave per leaf.  Rows are processed 64 at a
+// time, lane = row, with a one-column skew per lane; H and the F handed down
+// pass between lanes by a DPP shift, and between row groups through a row
+// buffer in LDS.  Each cell stores its tie flags:
 //   bit 0  H == H(i-1,j-1) + s   bit 1  H == F
 //   bit 2  F == H(i-1,j) - o     bit 3  E == H(i,j-1) - o
 // Lane 0 then walks back from the end: at H prefer the diagonal, then F,
@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(64) leaf_kernel(const LeafDesc *descs, const i
     const int P = d.P, w = d.w;
     int8_t *smat = reinterpret_cast<int8_t *>(lds);                 // 1024 bytes
     Border *row = reinterpret_cast<Border *>(lds + 1024);           // w entries
-    uint8_t *fl = d.gflags ? d.gflags : lds + 1024 + (size_t)8 * w;
+    uint8_t *fl = lds + 1024 + (size_t)8 * w;                      // P*w tie flags
 
     __shared__ int32_t s_endv;
     for (int k = lane; k < asize * asize; k += 64) smat[k] = mat[k];
@@ -265,7 +265,7 @@ __global__ void __launch_bounds__(64) leaf_kernel(const LeafDesc *descs, const i
                 h = max(t1, max(E, fin));
                 const int flag = (h == t1 ? 1 : 0) | (h == fin ? 2 : 0) | (fin == hup - o ? 4 : 0) |
                                  (E == hprev - o ? 8 : 0);
-                fl[(int64_t)(i - 1) * w + c] = (uint8_t)flag;
+                fl[(i - 1) * w + c] = (uint8_t)flag;
                 fdown = max(fin - e, h - o);
                 En = max(E - e, h - o);
                 if (i == P && c == w - 1) s_endv = d.end_state ? fin : h;
@@ -284,7 +284,157 @@ __global__ void __launch_bounds__(64) leaf_kernel(const LeafDesc *descs, const i
         int i = P, c = w - 1, state = d.end_state, n = 0, err = 0;
         while (i > 0) {
             if (c < 0 || n >= d.ops_cap) { err = 1; break; }
-            const int f = fl[(int64_t)(i - 1) * w + c];
+            const int f = fl[(i - 1) * w + c];
+            if (state == 0) {
+                if (f & 1) { d.ops[n++] = 'M'; --i; --c; }
+                else state = (f & 2) ? 1 : 2;
+            } else if (state == 1) {
+                d.ops[n++] = 'I';
+                if (f & 4) state = 0;
+                --i;
+            } else {
+                d.ops[n++] = 'D';
+                if (f & 8) state = 0;
+                --c;
+            }
+        }
+        if (c < 0 || state == 2) err = err ? err : 2;
+        if (s_endv != d.V) err = 3;
+        LeafOut r;
+        r.nops = n;
+        r.exit_col = c;
+        r.exit_state = state;
+        r.exit_val = (!err && c >= 0) ? (state == 0 ? d.front[c].h : d.front[c].f + e) : 0;
+        r.err = err;
+        r.pad_[0] = r.pad_[1] = r.pad_[2] = 0;
+        outs[blockIdx.x] = r;
+    }
+}
+
+// Large leaves (flags in global memory): one wave per leaf, kLeafR rows per
+// lane (64 kLeafR rows per group), the strip kernel's layout: the lane's rows
+// in registers, a one-column skew per lane, the row above handed over by a
+// DPP shift, a per-lane int8 score profile of its rows in LDS.  The four tie
+// flags of each cell (as in leaf_kernel) take a nibble; the lane's kLeafR
+// cells of one step make one dword, and the 64 dwords of a step one
+// coalesced store at flags[(group * (w + 63) + step) * 64 + lane].  Lane 0
+// then walks back as in leaf_kernel.
+__device__ __forceinline__ uint32_t big_flag(const uint32_t *fl, int w, int64_t r, int64_t c)
+{
+    constexpr int64_t G = 64 * kLeafR;
+    const int64_t g = r / G, lr = r - g * G, ln = lr / kLeafR, k = lr - ln * kLeafR;
+    return (fl[(g * (w + 63) + c + ln) * 64 + ln] >> (4 * k)) & 15u;
+}
+
+template <bool CAPTURE>
+__device__ __forceinline__ void big_step(int (&hp)[kLeafR], int (&E)[kLeafR], const int (&sc)[kLeafR / 4], int dg,
+                                         int hup, int &f, int o, int e, uint32_t &flags, int kstar, int end_state,
+                                         int32_t *endv)
+{
+    int habove = hup;
+    flags = 0;
+#pragma unroll
+    for (int k = 0; k < kLeafR; ++k) {
+        const int t1 = dg + (int)(signed char)(sc[k >> 2] >> (8 * (k & 3)));
+        const int h = max(max(t1, E[k]), f);
+        const uint32_t fb = (h == t1 ? 1u : 0u) | (h == f ? 2u : 0u) | (f == habove - o ? 4u : 0u) |
+                            (E[k] == hp[k] - o ? 8u : 0u);
+        flags |= fb << (4 * k);
+        if (CAPTURE && k == kstar) *endv = end_state ? f : h;
+        const int hop = h - o;
+        const int fn = max(f - e, hop);
+        E[k] = max(E[k] - e, hop);
+        dg = hp[k];
+        hp[k] = h;
+        habove = h;
+        f = fn;
+    }
+}
+
+__global__ void __launch_bounds__(64) leaf_big_kernel(const LeafDesc *descs, const int8_t *mat, int32_t asize,
+                                                      int32_t o, int32_t e, LeafOut *outs)
+{
+    extern __shared__ uint8_t lds[];
+    constexpr int R = kLeafR, W = kLeafR / 4;
+    const LeafDesc d = descs[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int P = d.P, w = d.w;
+    const int A1 = asize + 1;
+    int8_t *smat = reinterpret_cast<int8_t *>(lds);                                  // 1024 bytes
+    int *prof = reinterpret_cast<int *>(lds + 1024);                                  // A1 * 64 * W words
+    Border *row = reinterpret_cast<Border *>(lds + 1024 + (size_t)A1 * 64 * W * 4);   // w entries
+    uint8_t *bc = reinterpret_cast<uint8_t *>(row + w);                               // w column codes
+    uint32_t *fl = reinterpret_cast<uint32_t *>(d.gflags);
+    __shared__ int32_t s_endv;
+    for (int k = lane; k < asize * asize; k += 64) smat[k] = mat[k];
+    for (int k = lane; k < w; k += 64) {
+        row[k] = d.front[k];
+        bc[k] = d.bcols[k];
+    }
+    if (lane == 0) s_endv = kNeg;
+    __syncthreads();
+
+    const int ngroups = (P + 64 * R - 1) / (64 * R);
+    // the lane and row (within the lane) of the end cell (P, w-1)
+    const int gend = (P - 1) / (64 * R), lend = ((P - 1) - gend * 64 * R) / R, kend = (P - 1) - gend * 64 * R - lend * R;
+    for (int g = 0; g < ngroups; ++g) {
+        const int r0 = g * 64 * R + lane * R;   // the lane's first row (from 0)
+        for (int cd = 0; cd < A1; ++cd)
+#pragma unroll
+            for (int wd = 0; wd < W; ++wd) {
+                uint32_t word = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int r = r0 + 4 * wd + b;
+                    const int q = r < P ? (int)d.arows[r] : asize;
+                    const int v = (q >= asize || cd >= asize) ? -128 : (int)smat[q * asize + cd];
+                    word |= (uint32_t)(v & 0xFF) << (8 * b);
+                }
+                prof[(cd * 64 + lane) * W + wd] = (int)word;
+            }
+        int hp[R], E[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            hp[k] = kNeg;
+            E[k] = kNeg;
+        }
+        int hup_prev = kNeg, hbot = kNeg, fbot = kNeg;
+        uint32_t *flg = fl + (size_t)g * (w + 63) * 64 + lane;
+        const bool rows_real = r0 < P;
+        const int tcap = g == gend ? w - 1 + lend : -1;   // the step that holds the end cell
+        for (int t = 0; t < w + 63; ++t) {
+            const int c = t - lane;
+            const Border in = t < w ? row[t] : Border{kNeg, kNeg};
+            const int hup = shr1(in.h, hbot);
+            int f = shr1(in.f, fbot);
+            if (rows_real && c >= 0 && c < w) {
+                const int code = bc[c];
+                int sc[W];
+                const int *pp = prof + (code * 64 + lane) * W;
+#pragma unroll
+                for (int wd = 0; wd < W; ++wd) sc[wd] = pp[wd];
+                const int dg = c == 0 ? kNeg : hup_prev;
+                uint32_t flags;
+                if (t == tcap)
+                    big_step<true>(hp, E, sc, dg, hup, f, o, e, flags, lane == lend ? kend : -1, d.end_state,
+                                   &s_endv);
+                else
+                    big_step<false>(hp, E, sc, dg, hup, f, o, e, flags, -1, 0, nullptr);
+                flg[(size_t)t * 64] = flags;
+                hbot = hp[R - 1];
+                fbot = f;
+                if (lane == 63) row[c] = Border{hbot, fbot};
+            }
+            hup_prev = hup;
+        }
+        __syncthreads();
+    }
+
+    if (lane == 0) {
+        int i = P, c = w - 1, state = d.end_state, n = 0, err = 0;
+        while (i > 0) {
+            if (c < 0 || n >= d.ops_cap) { err = 1; break; }
+            const uint32_t f = big_flag(fl, w, i - 1, c);
             if (state == 0) {
                 if (f & 1) { d.ops[n++] = 'M'; --i; --c; }
                 else state = (f & 2) ? 1 : 2;
@@ -374,6 +524,14 @@ hipError_t launch_leaf(const LeafDesc *d, int32_t nd, const int8_t *mat, int32_t
 {
     if (nd <= 0) return hipSuccess;
     hipLaunchKernelGGL(leaf_kernel, dim3(nd), dim3(64), lds_bytes, st, d, mat, asize, o, e, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_leaf_big(const LeafDesc *d, int32_t nd, const int8_t *mat, int32_t asize, int32_t o, int32_t e,
+                           int32_t max_w, LeafOut *out, hipStream_t st)
+{
+    if (nd <= 0) return hipSuccess;
+    hipLaunchKernelGGL(leaf_big_kernel, dim3(nd), dim3(64), leaf_big_lds(asize, max_w), st, d, mat, asize, o, e, out);
     return hipGetLastError();
 }
 

@@ -32,9 +32,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <charconv>
 #include <chrono>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "context.h"
@@ -51,6 +54,13 @@ namespace {
 // an 8-byte row buffer entry per column, one byte of tie flags per cell.
 constexpr int64_t kLeafCells = 28672;
 constexpr int64_t kLeafMaxWidth = 4096;
+// Larger leaves keep their tie flags in global memory (one byte per cell):
+// a subproblem of up to this many cells is solved by one wave at once rather
+// than split further, which saves levels (each a host round trip) when many
+// small subproblems are in flight; leaf launches are cut so that one launch's
+// flags stay within kLeafFlagBytes.
+constexpr int64_t kLeafCellsMax = (int64_t)1 << 19;
+constexpr int64_t kLeafFlagBytes = (int64_t)8 << 30;
 
 
 struct Node {
@@ -153,7 +163,8 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
     std::vector<int> ready((size_t)nodes.size());
     for (size_t k = 0; k < nodes.size(); ++k) ready[k] = (int)k;
     // SWH_TB_LEAF lowers the leaf size (tests use it to force deep recursion on small inputs)
-    const int64_t leaf_cells = std::max<int64_t>(1, std::min<int64_t>(kLeafCells, env_int("SWH_TB_LEAF", (int)kLeafCells)));
+    const int64_t leaf_cells =
+        std::max<int64_t>(1, std::min<int64_t>(kLeafCellsMax, env_int("SWH_TB_LEAF", (int)kLeafCellsMax)));
 
     // exit of node k is known: tell its parent chain and release a waiting top sibling
     auto propagate = [&](int k) {
@@ -333,31 +344,43 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
         }
 
         // ---------------------------------------------------------------- leaves
-        if (!leaves.empty()) {
-            const int nl = (int)leaves.size();
-            std::vector<LeafDesc> ld(nl);
+        for (size_t c0 = 0; c0 < leaves.size();) {
+            // one launch: leaves whose global tie flags fit kLeafFlagBytes
+            size_t c1 = c0;
             int64_t ops_total = 0, gflag_bytes = 0;
             size_t lds = 1024;
-            for (int i = 0; i < nl; ++i) {
-                const Node &n = nodes[leaves[i]];
+            while (c1 < leaves.size()) {
+                const Node &n = nodes[leaves[c1]];
                 const int64_t P = n.r_bot - n.r_top, w = n.J - n.L + 1;
                 if (w > kLeafMaxWidth)
                     return fail(ctx, SWH_E_RANGE, "traceback: gap wider than " + std::to_string(kLeafMaxWidth) +
                                                       " columns in a subproblem of one row");
-                ops_total += P + w + 1;
                 const bool in_lds = P * w <= kLeafCells;
-                if (!in_lds) gflag_bytes += P * w + 256;
-                lds = std::max(lds, (size_t)(1024 + 8 * w + (in_lds ? P * w : 0)));
+                const int64_t gb = in_lds ? 0 : (leaf_flag_bytes(P, w) + 255) / 256 * 256;
+                if (c1 > c0 && gflag_bytes + gb > kLeafFlagBytes) break;
+                gflag_bytes += gb;
+                ops_total += P + w + 1;
+                if (in_lds) lds = std::max(lds, (size_t)(1024 + 8 * w + P * w));
+                ++c1;
             }
+            // small leaves (flags in LDS) first, then the large ones
+            std::stable_partition(leaves.begin() + c0, leaves.begin() + c1, [&](int k) {
+                const Node &n = nodes[k];
+                return (n.r_bot - n.r_top) * (n.J - n.L + 1) <= kLeafCells;
+            });
+            const int nl = (int)(c1 - c0);
+            int nsmall = 0;
+            int32_t max_w = 1;
+            std::vector<LeafDesc> ld(nl);
             if ((s = ensure(ctx, ctx->tb_fwd, (size_t)ops_total + 256, "traceback ops")) != SWH_OK) return s;
-            uint8_t *gfl = nullptr;
-            if (gflag_bytes && !(gfl = (uint8_t *)arena.get((size_t)gflag_bytes)))
-                return fail(ctx, SWH_E_NOMEM, "traceback flag scratch");
+            if (gflag_bytes && (s = ensure(ctx, ctx->tb_flags, (size_t)gflag_bytes, "traceback flags")) != SWH_OK)
+                return s;
+            uint8_t *gfl = (uint8_t *)ctx->tb_flags.p;
             char *op = (char *)ctx->tb_fwd.p;
             std::vector<int64_t> op_off(nl);
             int64_t off = 0;
             for (int i = 0; i < nl; ++i) {
-                const Node &n = nodes[leaves[i]];
+                const Node &n = nodes[leaves[c0 + i]];
                 const int64_t P = n.r_bot - n.r_top, w = n.J - n.L + 1;
                 LeafDesc d;
                 d.arows = n.A + n.r_top;
@@ -366,7 +389,10 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
                 d.gflags = nullptr;
                 if (P * w > kLeafCells) {
                     d.gflags = gfl;
-                    gfl += ((P * w + 255) / 256) * 256;
+                    gfl += (leaf_flag_bytes(P, w) + 255) / 256 * 256;
+                    max_w = std::max<int32_t>(max_w, (int32_t)w);
+                } else {
+                    ++nsmall;
                 }
                 d.ops = op + off;
                 d.P = (int32_t)P;
@@ -382,8 +408,12 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
             }
             if ((s = upload(ctx, ctx->tb_misc, ld, st, "leaf table")) != SWH_OK) return s;
             if ((s = ensure(ctx, ctx->tb_front, sizeof(LeafOut) * (size_t)nl, "leaf results")) != SWH_OK) return s;
-            if ((e = launch_leaf((const LeafDesc *)ctx->tb_misc.p, nl, (const int8_t *)ctx->mat.p, sc.asize, sc.o,
-                                 sc.e, lds, (LeafOut *)ctx->tb_front.p, st)) != hipSuccess)
+            const LeafDesc *ldd = (const LeafDesc *)ctx->tb_misc.p;
+            LeafOut *lod = (LeafOut *)ctx->tb_front.p;
+            if ((e = launch_leaf(ldd, nsmall, (const int8_t *)ctx->mat.p, sc.asize, sc.o, sc.e, lds, lod, st)) !=
+                    hipSuccess ||
+                (e = launch_leaf_big(ldd + nsmall, nl - nsmall, (const int8_t *)ctx->mat.p, sc.asize, sc.o, sc.e,
+                                     max_w, lod + nsmall, st)) != hipSuccess)
                 return hip_fail(ctx, e, "leaf launch");
             std::vector<LeafOut> lo(nl);
             const size_t base = ops_host.size();
@@ -395,7 +425,7 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
                 (e = hipStreamSynchronize(st)) != hipSuccess)
                 return hip_fail(ctx, e, "leaf results");
             for (int i = 0; i < nl; ++i) {
-                Node &n = nodes[leaves[i]];
+                Node &n = nodes[leaves[c0 + i]];
                 if (lo[i].err) {
                     ts.inconsistent = true;
                     return fail(ctx, SWH_E_DEVICE, "traceback walk left its subproblem (internal error)");
@@ -409,7 +439,8 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
                 n.exit_val = lo[i].exit_val;
                 ++ts.leaves;
             }
-            for (int i = 0; i < nl; ++i) propagate(leaves[i]);
+            for (int i = 0; i < nl; ++i) propagate(leaves[c0 + i]);
+            c0 = c1;
         }
     }
 
@@ -424,22 +455,31 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
         while (!nodes[k].leaf) k = nodes[k].top;
         return nodes[k];
     };
-    std::string back;
+    // checks first (serial, cheap): every seeded band leaves through its seed
+    // node (column L, state H for a diagonal entry, F for a vertical one), and
+    // the top band reaches row 0
     for (int pr = 0; pr < npairs; ++pr) {
-        back.clear();
         const std::vector<int> &rt = roots[(size_t)pr];
-        for (size_t b = rt.size(); b-- > 0;) {   // bottom band first
-            const Node &root = nodes[rt[b]];
-            if (b > 0) {
-                // a seeded band must leave through its seed node (column L,
-                // state H for a diagonal entry, F for a vertical one)
-                const Node &x = band_exit(rt[b]);
-                const bool seed_f = in[pr].bands[b].seed_h == kNeg;
-                if (x.exit_col != root.L || x.exit_state != (seed_f ? 1 : 0)) {
-                    ts.inconsistent = true;
-                    return fail(ctx, SWH_E_DEVICE, "traceback: band left through another node (internal error)");
-                }
+        for (size_t b = 1; b < rt.size(); ++b) {
+            const Node &x = band_exit(rt[b]);
+            const bool seed_f = in[pr].bands[b].seed_h == kNeg;
+            if (x.exit_col != nodes[rt[b]].L || x.exit_state != (seed_f ? 1 : 0)) {
+                ts.inconsistent = true;
+                return fail(ctx, SWH_E_DEVICE, "traceback: band left through another node (internal error)");
             }
+        }
+        if (band_exit(rt[0]).exit_col < 0) {
+            ts.inconsistent = true;
+            return fail(ctx, SWH_E_DEVICE, "traceback: no exit on row 0 (internal error)");
+        }
+    }
+    // then the CIGARs, pairs spread over host threads: the leaves' ops
+    // (backward order) bottom band first, each subproblem's bottom half before
+    // its top half, then run-length encoded in forward order
+    auto assemble = [&](int pr) {
+        std::string back;
+        const std::vector<int> &rt = roots[(size_t)pr];
+        for (size_t b = rt.size(); b-- > 0;) {
             std::vector<int> stack{rt[b]};
             while (!stack.empty()) {
                 const int k = stack.back();
@@ -448,31 +488,36 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
                 if (n.leaf) {
                     back.append(ops_host.data() + n.ops_off, (size_t)n.nops);
                 } else {
-                    stack.push_back(n.top);      // processed after the bottom half
+                    stack.push_back(n.top);
                     stack.push_back(n.bottom);
                 }
             }
         }
-        const int64_t rexit = band_exit(rt[0]).exit_col;
-        if (rexit < 0) {
-            ts.inconsistent = true;
-            return fail(ctx, SWH_E_DEVICE, "traceback: no exit on row 0 (internal error)");
-        }
-        back.append((size_t)rexit, 'D');     // leading target residues against a gap, back to (0, 0)
-
-        // run-length encode in forward order
-        std::string &cigar = cigars[pr];
+        back.append((size_t)band_exit(rt[0]).exit_col, 'D');   // leading target residues against a gap
+        std::string &cigar = cigars[(size_t)pr];
+        char num[24];
         int64_t q = (int64_t)back.size() - 1;
         while (q >= 0) {
             const char opc = back[(size_t)q];
-            int64_t run = 0;
-            while (q >= 0 && back[(size_t)q] == opc) {
-                ++run;
-                --q;
-            }
-            cigar += std::to_string(run);
+            const int64_t q0 = q;
+            while (q >= 0 && back[(size_t)q] == opc) --q;
+            const auto r = std::to_chars(num, num + sizeof(num), q0 - q);
+            cigar.append(num, r.ptr);
             cigar += opc;
         }
+    };
+    const int nthreads = (int)std::min<int64_t>(npairs / 64 + 1, std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+    if (nthreads <= 1) {
+        for (int pr = 0; pr < npairs; ++pr) assemble(pr);
+    } else {
+        std::atomic<int> next{0};
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nthreads; ++t)
+            pool.emplace_back([&] {
+                for (int pr; (pr = next.fetch_add(16)) < npairs;)
+                    for (int k = pr; k < std::min(pr + 16, npairs); ++k) assemble(k);
+            });
+        for (std::thread &t : pool) t.join();
     }
     ts.ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return SWH_OK;

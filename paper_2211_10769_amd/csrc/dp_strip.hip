@@ -102,6 +102,17 @@ __device__ __forceinline__ bool wait_chunk(const StripArgs &a, const int32_t *fl
     }
 }
 
+// Chunk counter, read without waiting for it (the value is checked a whole
+// block of steps later, when the load has long returned).
+__device__ __forceinline__ int peek_chunk(const int32_t *flags, int chunk)
+{
+    return __hip_atomic_load(flags + chunk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A lane-identity DPP move: its result is a plain register value, so the
+// loads that produced v are waited for here, outside the step loop.
+__device__ __forceinline__ int settled(int v) { return __builtin_amdgcn_update_dpp(0, v, 0xE4, 0xF, 0xF, false); }
+
 template <int R>
 struct Prof {
     static constexpr int W = R / 4;                      // profile words per (code, lane)
@@ -257,24 +268,38 @@ __global__ void __launch_bounds__(256 * kWgPerSimd<R>) strip_kernel(StripArgs a)
         // mask.
         int bkey = 0, bstep = 0, bthr = 1;
 
-        // block 0 inputs
+        // block 0 inputs, settled before the step loop so that no load is in
+        // flight into a register the loop reads (the loop then carries no wait
+        // for the next block's prefetches)
         int code = lane == 0 ? (int)P.tc[0] : pad;       // current column's code
         int tfeed = P.tc[1 + lane];                       // lane 0 = code of column t+2
         int fh = B, ff = B;
         bool ok = true;
         if (ok && !wait_chunk(a, P.flags, 0, s)) ok = false;
         if (ok) load_border(P.border + lane, fh, ff);
+        // chunk 1's counter, read ahead: checked at the top of block 0
+        int fl_next = 64 < P.m ? peek_chunk(P.flags, 1) : s;
+        code = settled(code);
+        tfeed = settled(tfeed);
+        fh = settled(fh);
+        ff = settled(ff);
 
         int sc[W];
         load_prof<W>(prof, A1, code, lane, sc);
 
         for (int b = 0; b < P.nblocks && ok; ++b) {
-            // prefetch the next block's target codes and border chunk
+            // prefetch the next block's target codes and border chunk; its
+            // counter was read a block ago, so the wait is only taken when the
+            // strip above had not yet published the chunk then
             const int tfeed_n = P.tc[64 * (b + 1) + 1 + lane];
             int fh_n = B, ff_n = B;
             if (64 * (b + 1) < P.m) {
-                if (!wait_chunk(a, P.flags, b + 1, s)) { ok = false; break; }
+                if (__builtin_amdgcn_readfirstlane(fl_next) < s && !wait_chunk(a, P.flags, b + 1, s)) {
+                    ok = false;
+                    break;
+                }
                 load_border(P.border + 64 * (b + 1) + lane, fh_n, ff_n);
+                fl_next = 64 * (b + 2) < P.m ? peek_chunk(P.flags, b + 2) : s;
             }
 
             const int tbase = 64 * b;

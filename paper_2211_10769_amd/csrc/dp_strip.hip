@@ -353,24 +353,30 @@ __global__ void __launch_bounds__(256 * kWgPerSimd<R>) strip_kernel(StripArgs a)
                 code = code_n;
             }
 
+            // The previous block's border records (chunk b-2, columns
+            // 64(b-2)+1 .. 64(b-1)) were stored a whole block ago: the drain
+            // finds them (and this block's prefetches) done, and chunk b-2 is
+            // published.  This block's records stay in flight across the next
+            // block, so no wave ever stalls on its own stores.
+            drain_stores();
+            if (lane == 0 && b >= 2)
+                __hip_atomic_store(P.flags + (b - 2), s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            tfeed = settled(tfeed_n);
+            fh = settled(fh_n);
+            ff = settled(ff_n);
             // lane l holds lane 63's output of step 64b+l: column 64b+l-62 (1-based)
             const int idx = 64 * b + lane - 63;
             if (idx >= 0 && idx < P.m) {
                 store_border(P.border + idx, oh, of);
                 if (keep) keep[idx] = Border{oh, of};
             }
-            drain_stores();
-            // chunk b-1 (columns 64(b-1)+1 .. 64b) is now complete
-            if (lane == 0 && b >= 1)
-                __hip_atomic_store(P.flags + (b - 1), s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            tfeed = tfeed_n;
-            fh = fh_n;
-            ff = ff_n;
         }
-        // publish the remaining chunks (also on abort, so that no waiter is left behind)
+        // publish the remaining chunks once the last records are done (also on
+        // abort, so that no waiter is left behind)
+        drain_stores();
         {
             const int nchunks = (P.m + 63) / 64;
-            const int first = ok ? max(P.nblocks - 1, 0) : 0;
+            const int first = ok ? max(P.nblocks - 2, 0) : 0;
             for (int c0 = first; c0 < nchunks; c0 += 64) {
                 const int c = c0 + lane;
                 if (c < nchunks)

@@ -37,11 +37,11 @@ OPS_PER_CELL = 7
 # rocprofv3 counter passes over one CIGAR step (forward launch 2.55e13 cells,
 # reverse launch 2.53e13, both keeping rows for the band traceback), each
 # scaled by the same counter on a 1 GiB plain copy (profiles/
-# strip_kernel_long_dna.md): FETCH_SIZE (95,722,018 + 95,321,930) KiB x 2.0 +
-# WRITE_SIZE (190,673,379 + 188,888,006) KiB x 1.0 = 779.9 GB over both.
+# strip_kernel_long_dna.md): FETCH_SIZE (96,075,669 + 95,050,279) KiB x 2.0 +
+# WRITE_SIZE (190,673,387 + 188,887,997) KiB x 1.0 = 780.1 GB over both.
 # Valid for the kernel those counters were taken on; the roofline's traffic
 # field is this figure times the cells of a launch.
-HBM_BYTES_PER_CELL = ((95_722_017.75 + 95_321_930.125) * 2.0 + 190_673_379.0625 + 188_888_006.0625) * 1024 / (
+HBM_BYTES_PER_CELL = ((96_075_668.625 + 95_050_279.25) * 2.0 + 190_673_386.78125 + 188_887_996.59375) * 1024 / (
     25_500_765_000_000 + 5_000_000 * 5_050_153)
 
 

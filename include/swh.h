@@ -77,6 +77,21 @@ enum { SWH_MODE_SCORE = 0,   /* score and end coordinates (forward pass only) */
        SWH_MODE_COORDS = 1,  /* + start coordinates (reverse pass) */
        SWH_MODE_CIGAR = 2 }; /* + CIGAR (linear-space traceback) */
 
+/*
+ * OR'd into mode (swh_align, swh_align_dev, swh_align_batch): the optimal
+ * GLOBAL alignment of the whole query against the whole target instead of
+ * the local one -- Needleman-Wunsch with the same affine gaps (paper,
+ * Background, "Needleman-Wunsch algorithm"; SW# offers it beside SW).  score
+ * = G(n, m) of the global DP (may be negative); the coordinates are always
+ * 0 .. n-1 and 0 .. m-1 (-1 for an empty sequence); the CIGAR is the greedy
+ * backward walk of the global DP from (n, m) to (0, 0) with the preferences
+ * of the local CIGAR (at H: diagonal, then I, then D; in a gap: close it), so
+ * it may begin or end with I or D runs.  An empty sequence against one of
+ * length k scores -(gap_open + (k-1) gap_extend).  Extra limit:
+ * (qlen + tlen) * (max(gap_extend, |min s|) + max s) + 2 gap_open < 2^27.
+ */
+#define SWH_GLOBAL 0x100
+
 /* Per-call statistics; set struct_size = sizeof(swh_stats) before the call. */
 typedef struct {
     uint32_t struct_size;

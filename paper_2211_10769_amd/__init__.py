@@ -18,6 +18,7 @@ from . import _lib
 from ._lib import MODE_CIGAR, MODE_COORDS, MODE_SCORE, STATUS_NAMES
 
 _MODES = {"score": MODE_SCORE, "coords": MODE_COORDS, "cigar": MODE_CIGAR}
+_ALIGNMENTS = {"local": 0, "global": _lib.GLOBAL}
 
 
 class SwhError(RuntimeError):
@@ -87,26 +88,30 @@ class Engine:
             r["stats"] = {k: getattr(stats, k) for k, _ in stats._fields_[2:]}
         return r
 
-    def align(self, query, target, scoring, mode: str = "cigar", stats: bool = False):
-        """Local alignment of host sequences; returns dict(score, q_begin, q_end, t_begin, t_end[, cigar])."""
+    def align(self, query, target, scoring, mode: str = "cigar", stats: bool = False, alignment: str = "local"):
+        """Local (or, alignment="global", Needleman-Wunsch) alignment of host sequences;
+        returns dict(score, q_begin, q_end, t_begin, t_end[, cigar])."""
         sc = Scoring.of(scoring)
         q, t = _bytes(query), _bytes(target)
         m = _MODES[mode]
+        g = _ALIGNMENTS[alignment]
         out = _lib.swh_alignment()
         st_obj = _lib.swh_stats(ctypes.sizeof(_lib.swh_stats)) if stats else None
         cap = 2 * (len(q) + len(t)) + 16 if m == MODE_CIGAR else 0
         buf = ctypes.create_string_buffer(cap) if cap else None
         clen = ctypes.c_int64()
-        st = self.L.swh_align(self.h, q, len(q), t, len(t), ctypes.byref(sc.c), m, ctypes.byref(out),
+        st = self.L.swh_align(self.h, q, len(q), t, len(t), ctypes.byref(sc.c), m | g, ctypes.byref(out),
                               buf, cap, ctypes.byref(clen),
                               ctypes.byref(st_obj) if st_obj is not None else None)
         self._check(st)
         return self._result(out, buf.value.decode() if buf is not None else None, st_obj)
 
-    def align_dev(self, q_tensor, t_tensor, scoring, mode: str = "score", stream=None, stats: bool = False):
-        """Local alignment of uint8 ASCII torch tensors already on the GPU."""
+    def align_dev(self, q_tensor, t_tensor, scoring, mode: str = "score", stream=None, stats: bool = False,
+                  alignment: str = "local"):
+        """Local (or global) alignment of uint8 ASCII torch tensors already on the GPU."""
         sc = Scoring.of(scoring)
         m = _MODES[mode]
+        g = _ALIGNMENTS[alignment]
         out = _lib.swh_alignment()
         st_obj = _lib.swh_stats(ctypes.sizeof(_lib.swh_stats)) if stats else None
         cap = 2 * (q_tensor.numel() + t_tensor.numel()) + 16 if m == MODE_CIGAR else 0
@@ -116,15 +121,16 @@ class Engine:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
         st = self.L.swh_align_dev(self.h, q_tensor.data_ptr(), q_tensor.numel(), t_tensor.data_ptr(),
-                                  t_tensor.numel(), ctypes.byref(sc.c), m, stream, ctypes.byref(out), buf,
+                                  t_tensor.numel(), ctypes.byref(sc.c), m | g, stream, ctypes.byref(out), buf,
                                   cap, ctypes.byref(clen),
                                   ctypes.byref(st_obj) if st_obj is not None else None)
         self._check(st)
         return self._result(out, buf.value.decode() if buf is not None else None, st_obj)
 
-    def align_batch(self, queries, targets, scoring, mode: str = "cigar", stats: bool = False):
+    def align_batch(self, queries, targets, scoring, mode: str = "cigar", stats: bool = False,
+                    alignment: str = "local"):
         """Many pairs (query i vs target i) in one call; returns a list of result dicts
-        (and the summed stats dict when stats=True)."""
+        (and the summed stats dict when stats=True).  alignment="global": Needleman-Wunsch."""
         sc = Scoring.of(scoring)
         qcat, qoff = _concat(queries)
         tcat, toff = _concat(targets)
@@ -132,13 +138,14 @@ class Engine:
         if len(toff) - 1 != n:
             raise ValueError("queries and targets differ in count")
         m = _MODES[mode]
+        g = _ALIGNMENTS[alignment]
         out = (_lib.swh_alignment * max(1, n))()
         st_obj = _lib.swh_stats(ctypes.sizeof(_lib.swh_stats)) if stats else None
         coff = np.zeros(n + 1, dtype=np.int64)
         cap = int(2 * (qoff[-1] - qoff[0] + toff[-1] - toff[0]) + 16) if m == MODE_CIGAR else 0
         buf = ctypes.create_string_buffer(cap) if cap else None
         args = [self.h, n, qcat.ctypes.data if len(qcat) else None, qoff.ctypes.data,
-                tcat.ctypes.data if len(tcat) else None, toff.ctypes.data, ctypes.byref(sc.c), m, out,
+                tcat.ctypes.data if len(tcat) else None, toff.ctypes.data, ctypes.byref(sc.c), m | g, out,
                 buf, cap, coff.ctypes.data if m == MODE_CIGAR else None,
                 ctypes.byref(st_obj) if st_obj is not None else None]
         rc = self.L.swh_align_batch(*args)

@@ -132,6 +132,90 @@ swh_status score_passes(swh_ctx *ctx, const std::vector<PairPass> &ps, const Sco
     return SWH_OK;
 }
 
+swh_status global_scores(swh_ctx *ctx, const std::vector<PairPass> &ps, const Scoring &sc, hipStream_t st,
+                         std::vector<int32_t> &scores, double &ms_total)
+{
+    const size_t np = ps.size();
+    scores.assign(np, 0);
+    std::vector<StripShape> sh(np);
+    for (size_t i = 0; i < np; ++i) sh[i] = tuned_shape(ctx, ps[i].n);
+    std::vector<size_t> order(np);
+    std::iota(order.begin(), order.end(), (size_t)0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+        if (sh[a].R != sh[b].R) return sh[a].R > sh[b].R;
+        if (sh[a].waves != sh[b].waves) return sh[a].waves > sh[b].waves;
+        return (double)ps[a].n * (double)ps[a].m > (double)ps[b].n * (double)ps[b].m;
+    });
+    const uint8_t pad = (uint8_t)sc.asize;
+    size_t k = 0;
+    while (k < np) {
+        const size_t lead = order[k];
+        const int Rk = sh[lead].R;
+        size_t end = k;
+        int64_t bytes = 0, nq = 0, nt = 0;
+        while (end < np && sh[order[end]].R == Rk && sh[order[end]].waves == sh[lead].waves) {
+            const PairPass &p = ps[order[end]];
+            const int64_t b = rows_padded(p.n, Rk) + cols_padded(p.m + 1) * (1 + (int64_t)sizeof(Border));
+            if (bytes && bytes + b > kChunkBytes) break;
+            bytes += b;
+            nq += rows_padded(p.n, Rk);
+            nt += cols_padded(p.m + 1);
+            ++end;
+        }
+        const size_t nc = end - k;
+        swh_status s;
+        if ((s = ensure(ctx, ctx->bq, (size_t)nq + 256, "batch row codes")) != SWH_OK ||
+            (s = ensure(ctx, ctx->bt, (size_t)nt + 256, "batch column codes")) != SWH_OK ||
+            (s = ensure(ctx, ctx->bborder, sizeof(Border) * (size_t)nt + 256, "batch borders")) != SWH_OK ||
+            (s = ensure(ctx, ctx->gscores, sizeof(Border) * nc + 256, "global scores")) != SWH_OK)
+            return s;
+        std::vector<GatherDesc> gd, ends;
+        std::vector<BorderInit> bi;
+        std::vector<StripProblem> probs;
+        uint8_t *qp = (uint8_t *)ctx->bq.p, *tp = (uint8_t *)ctx->bt.p;
+        Border *bp = (Border *)ctx->bborder.p;
+        for (size_t i = k; i < end; ++i) {
+            const PairPass &p = ps[order[i]];
+            const int64_t qpad = rows_padded(p.n, Rk), tpad = cols_padded(p.m + 1);
+            gd.push_back(GatherDesc{p.q, qp, 0, p.n, qpad, 1, 0});
+            gd.push_back(GatherDesc{p.t, tp, 0, p.m, tpad, 1, 1});   // pad code first: column 0 is the border
+            bi.push_back(BorderInit{bp, nullptr, p.m + 1, tpad, 1, 0, 0, 0});
+            probs.push_back(StripProblem{qp, p.n, tp, p.m + 1, bp});
+            // G(n, m) is the last row's record of column m
+            ends.push_back(GatherDesc{reinterpret_cast<const uint8_t *>(bp + p.m), (uint8_t *)ctx->gscores.p +
+                                          sizeof(Border) * (i - k), 0, (int64_t)sizeof(Border),
+                                      (int64_t)sizeof(Border), 1, 0});
+            qp += qpad;
+            tp += tpad;
+            bp += tpad;
+        }
+        hipError_t e;
+        if ((s = upload(ctx, ctx->tb_misc, gd, st, "gather table")) != SWH_OK) return s;
+        if ((e = launch_gather((const GatherDesc *)ctx->tb_misc.p, (int32_t)gd.size(), pad, st)) != hipSuccess)
+            return hip_fail(ctx, e, "gather launch");
+        if ((s = upload(ctx, ctx->tb_leaf, bi, st, "border table")) != SWH_OK) return s;
+        if ((e = launch_border_init((const BorderInit *)ctx->tb_leaf.p, (int32_t)bi.size(), sc.o, sc.e, st)) !=
+            hipSuccess)
+            return hip_fail(ctx, e, "border init launch");
+        // the tables above are read by launches already queued on st before
+        // the buffers are reused: synchronise before run_strips rewrites them
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(ctx, e, "global setup");
+        float ms = 0.f;
+        if ((s = run_strips(ctx, probs, sc, Rk, false, st, nullptr, &ms, sh[lead].waves)) != SWH_OK) return s;
+        ms_total += ms;
+        if ((s = upload(ctx, ctx->tb_misc, ends, st, "end table")) != SWH_OK) return s;
+        std::vector<Border> res(nc);
+        if ((e = launch_gather((const GatherDesc *)ctx->tb_misc.p, (int32_t)ends.size(), pad, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(res.data(), ctx->gscores.p, sizeof(Border) * nc, hipMemcpyDeviceToHost, st)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess)
+            return hip_fail(ctx, e, "global scores");
+        for (size_t i = k; i < end; ++i) scores[order[i]] = res[i - k].h;
+        k = end;
+    }
+    return SWH_OK;
+}
+
 swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const int64_t *q_off, const char *t_cat,
                        const int64_t *t_off, const Scoring &sc, int mode, swh_alignment *out, char *cigar_cat,
                        int64_t cigar_cap, int64_t *cigar_off, swh_stats *stats)
@@ -141,6 +225,8 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
         *stats = swh_stats{};
         stats->struct_size = size;
     }
+    const bool global = (mode & SWH_GLOBAL) != 0;
+    mode &= ~SWH_GLOBAL;
     for (int64_t i = 0; i < npairs; ++i) {
         out[i].score = 0;
         out[i].flags = SWH_F_NONE;
@@ -207,6 +293,55 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
         cells += (double)ps[i].n * (double)ps[i].m;
     }
     if (stats) stats->cells_forward = cells;
+    std::vector<std::string> cig((size_t)npairs);
+    if (global) {
+        // ---- global alignments: G(n, m) per pair, then the plain divide and
+        // conquer over each whole matrix (an empty side: a single gap)
+        std::vector<PairPass> gp;
+        std::vector<int64_t> gi;
+        for (int64_t i = 0; i < npairs; ++i) {
+            out[i].q_begin = ps[i].n ? 0 : -1;
+            out[i].q_end = ps[i].n - 1;
+            out[i].t_begin = ps[i].m ? 0 : -1;
+            out[i].t_end = ps[i].m - 1;
+            if (ps[i].n && ps[i].m) {
+                gp.push_back(ps[i]);
+                gi.push_back(i);
+                continue;
+            }
+            const int64_t len = ps[i].n + ps[i].m;
+            out[i].score = len ? -(int32_t)(sc.o + (len - 1) * (int64_t)sc.e) : 0;
+            if (len) cig[i] = std::to_string(len) + (ps[i].n ? "I" : "D");
+        }
+        std::vector<int32_t> gs;
+        double ms = 0.0;
+        if ((s = global_scores(ctx, gp, sc, st, gs, ms)) != SWH_OK) return s;
+        for (size_t j = 0; j < gi.size(); ++j) out[gi[j]].score = gs[j];
+        if (stats) stats->ms_forward = ms;
+        if (mode != SWH_MODE_CIGAR) return SWH_OK;
+        TracebackStats ts;
+        size_t k = 0;
+        while (k < gi.size()) {
+            std::vector<TbInput> in;
+            std::vector<int64_t> ids;
+            int64_t cols = 0;
+            while (k < gi.size()) {
+                const int64_t i = gi[k];
+                if (!in.empty() && cols + ps[i].m > kTracebackCols) break;
+                in.push_back(TbInput{ps[i].q, ps[i].n, ps[i].t, ps[i].m, out[i].score});
+                ids.push_back(i);
+                cols += ps[i].m;
+                ++k;
+            }
+            std::vector<std::string> cg;
+            if ((s = traceback_batch(ctx, in, sc, st, cg, ts)) != SWH_OK) return s;
+            for (size_t j = 0; j < ids.size(); ++j) cig[ids[j]].swap(cg[j]);
+        }
+        if (stats) {
+            stats->ms_traceback = ts.ms;
+            stats->cells_traceback = ts.cells;
+        }
+    } else {
     const int forced = env_int("SWH_BAND_ROWS", 0);
     const bool banded = mode == SWH_MODE_CIGAR && forced >= 0;
     std::vector<BandKeep> bk((size_t)npairs);
@@ -229,7 +364,6 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
         else
             (void)hipGetLastError();
     }
-    std::vector<std::string> cig((size_t)npairs);
     TracebackStats ts;
     double ms_fwd = 0.0, ms_rev = 0.0;
     int64_t nbands = 0, retries = 0;
@@ -397,6 +531,7 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
         stats->cells_traceback = ts.cells;
         stats->traceback_bands = nbands;
         stats->traceback_retries = retries;
+    }
     }
     if (mode != SWH_MODE_CIGAR) return SWH_OK;
     int64_t total = 0;

@@ -27,6 +27,12 @@ struct PairPass {
 swh_status score_passes(swh_ctx *ctx, const std::vector<PairPass> &ps, const Scoring &sc, hipStream_t st,
                         std::vector<BestCell> &best, double &ms_total);
 
+// Global alignment scores G(n, m) of every pass (n, m > 0; step must be 1):
+// the strip kernel in global mode over A against [pad] + B from the global
+// top border G(0, j) = -(o + (j-1) e), G(0, 0) = 0.
+swh_status global_scores(swh_ctx *ctx, const std::vector<PairPass> &ps, const Scoring &sc, hipStream_t st,
+                         std::vector<int32_t> &scores, double &ms_total);
+
 swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const int64_t *q_off, const char *t_cat,
                        const int64_t *t_off, const Scoring &sc, int mode, swh_alignment *out, char *cigar_cat,
                        int64_t cigar_cap, int64_t *cigar_off, swh_stats *stats);

@@ -83,6 +83,8 @@ swh_status check_pair(swh_ctx *ctx, const void *q, int64_t qlen, const void *t, 
     if (!out) return fail(ctx, SWH_E_INVAL, "out is NULL");
     if (qlen < 0 || tlen < 0) return fail(ctx, SWH_E_INVAL, "negative sequence length");
     if ((qlen && !q) || (tlen && !t)) return fail(ctx, SWH_E_INVAL, "sequence pointer is NULL");
+    const bool global = (mode & SWH_GLOBAL) != 0;
+    mode &= ~SWH_GLOBAL;
     if (mode < SWH_MODE_SCORE || mode > SWH_MODE_CIGAR) return fail(ctx, SWH_E_INVAL, "unknown mode");
     if (qlen >= (int64_t)1 << 31 || tlen >= (int64_t)1 << 31)
         return fail(ctx, SWH_E_RANGE, "sequence longer than 2^31 - 1");
@@ -92,6 +94,12 @@ swh_status check_pair(swh_ctx *ctx, const void *q, int64_t qlen, const void *t, 
         return fail(ctx, SWH_E_RANGE, "min(qlen, tlen) * max|s| must stay below 2^26");
     if (mode == SWH_MODE_CIGAR && (smax + sc.e) * (qlen + tlen) + sc.o >= ((int64_t)1 << 27))
         return fail(ctx, SWH_E_RANGE, "(max s + gap_extend) * (qlen + tlen) + gap_open must stay below 2^27");
+    if (global) {
+        const int64_t low = sc.e > -sc.smin ? sc.e : -sc.smin;
+        if ((qlen + tlen) * (low + smax) + 2 * (int64_t)sc.o >= ((int64_t)1 << 27))
+            return fail(ctx, SWH_E_RANGE,
+                        "global: (qlen + tlen) * (max(gap_extend, |min s|) + max s) + 2 gap_open must stay below 2^27");
+    }
     return SWH_OK;
 }
 
@@ -203,8 +211,9 @@ swh_status swh_align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, cons
     if (s != SWH_OK) return s;
     if (npairs < 0) return fail(ctx, SWH_E_INVAL, "npairs is negative");
     if (npairs > 0 && (!q_off || !t_off || !out)) return fail(ctx, SWH_E_INVAL, "offsets or out is NULL");
-    if (mode < SWH_MODE_SCORE || mode > SWH_MODE_CIGAR) return fail(ctx, SWH_E_INVAL, "unknown mode");
-    if (mode == SWH_MODE_CIGAR && !cigar_off) return fail(ctx, SWH_E_INVAL, "cigar_off is NULL");
+    if (((mode & ~SWH_GLOBAL) < SWH_MODE_SCORE || (mode & ~SWH_GLOBAL) > SWH_MODE_CIGAR))
+        return fail(ctx, SWH_E_INVAL, "unknown mode");
+    if ((mode & ~SWH_GLOBAL) == SWH_MODE_CIGAR && !cigar_off) return fail(ctx, SWH_E_INVAL, "cigar_off is NULL");
     if (stats && stats->struct_size < sizeof(swh_stats)) return fail(ctx, SWH_E_INVAL, "stats->struct_size too small");
     if (npairs >= ((int64_t)1 << 31)) return fail(ctx, SWH_E_RANGE, "more than 2^31 - 1 pairs");
     for (int64_t i = 0; i < npairs; ++i) {

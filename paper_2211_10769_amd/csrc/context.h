@@ -104,6 +104,8 @@ struct swh_ctx {
     swh::DevBuf tb_fwd, tb_bwd, tb_front, tb_codes_q, tb_flags, tb_leaf, tb_misc;
     // band traceback: rows kept by the forward and reverse score passes, cut tables
     swh::DevBuf keep_f, keep_r, cut_desc, cut_cnt, cut_out;
+    // global alignments: the end values G(n, m) of a launch's problems
+    swh::DevBuf gscores;
     std::vector<swh::DevBuf *> all() {
         return {&qraw, &traw, &qc, &tc, &qr, &tr, &border, &flags, &misc, &strip_best, &mat, &lut,
                 &probs, &strip_prob, &prob_best, &sync,
@@ -112,7 +114,7 @@ struct swh_ctx {
                 &pf_fq, &pf_qlen, &pf_Aq, &pf_pred, &pf_hist, &pf_prefix, &pf_marks, &pf_chunk, &pf_cand,
                 &pf_res, &pf_groups, &pf_perm,
                 &tb_fwd, &tb_bwd, &tb_front, &tb_codes_q, &tb_flags, &tb_leaf, &tb_misc,
-                &keep_f, &keep_r, &cut_desc, &cut_cnt, &cut_out};
+                &keep_f, &keep_r, &cut_desc, &cut_cnt, &cut_out, &gscores};
     }
 };
 

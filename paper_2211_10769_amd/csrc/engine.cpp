@@ -10,6 +10,7 @@
 #include <string>
 
 #include "bands.h"
+#include "batch.h"
 #include "context.h"
 #include "engine.h"
 #include "strips.h"
@@ -98,11 +99,31 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
         *stats = swh_stats{};
         stats->struct_size = size;
     }
+    const bool global = (mode & SWH_GLOBAL) != 0;
+    mode &= ~SWH_GLOBAL;
     out->score = 0;
     out->flags = SWH_F_NONE;
     out->q_begin = out->q_end = out->t_begin = out->t_end = -1;
     if (cigar_len) *cigar_len = 0;
     if (cigar && cigar_cap > 0) cigar[0] = '\0';
+    if (global) {
+        out->q_begin = qlen ? 0 : -1;
+        out->q_end = qlen - 1;
+        out->t_begin = tlen ? 0 : -1;
+        out->t_end = tlen - 1;
+        if (qlen == 0 || tlen == 0) {
+            // one sequence against nothing: a single gap (or the empty alignment)
+            const int64_t len = qlen + tlen;
+            out->score = len ? -(int32_t)(sc.o + (len - 1) * (int64_t)sc.e) : 0;
+            if (mode != SWH_MODE_CIGAR) return SWH_OK;
+            const std::string cg = len ? std::to_string(len) + (qlen ? "I" : "D") : std::string();
+            if (cigar_len) *cigar_len = (int64_t)cg.size();
+            if (!cigar || (int64_t)cg.size() + 1 > cigar_cap)
+                return fail(ctx, SWH_E_RANGE, "CIGAR needs " + std::to_string(cg.size() + 1) + " bytes");
+            std::memcpy(cigar, cg.c_str(), cg.size() + 1);
+            return SWH_OK;
+        }
+    }
     if (qlen == 0 || tlen == 0) return SWH_OK;
 
     const StripShape shape = tuned_shape(ctx, qlen);
@@ -139,6 +160,36 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
     if (bad[1] != INT32_MAX)
         return fail(ctx, SWH_E_ALPHABET, "target byte at position " + std::to_string(bad[1]) +
                                              " is not in the alphabet");
+
+    if (global) {
+        // ---- global alignment: the forward pass in global mode gives G(n, m),
+        // the reconstruction is the divide and conquer over the whole matrix
+        std::vector<int32_t> gs;
+        double ms = 0.0;
+        if ((s = global_scores(ctx, {PairPass{(const uint8_t *)ctx->qc.p, qlen, (const uint8_t *)ctx->tc.p, tlen, 1}},
+                               sc, st, gs, ms)) != SWH_OK)
+            return s;
+        out->score = gs[0];
+        if (stats) {
+            stats->cells_forward = (double)qlen * (double)tlen;
+            stats->ms_forward = ms;
+        }
+        if (mode != SWH_MODE_CIGAR) return SWH_OK;
+        std::string cg;
+        TracebackStats ts;
+        if ((s = traceback(ctx, (const uint8_t *)ctx->qc.p, qlen, (const uint8_t *)ctx->tc.p, tlen, sc, gs[0], st, cg,
+                           ts)) != SWH_OK)
+            return s;
+        if (stats) {
+            stats->ms_traceback = ts.ms;
+            stats->cells_traceback = ts.cells;
+        }
+        if (cigar_len) *cigar_len = (int64_t)cg.size();
+        if (!cigar || (int64_t)cg.size() + 1 > cigar_cap)
+            return fail(ctx, SWH_E_RANGE, "CIGAR needs " + std::to_string(cg.size() + 1) + " bytes");
+        std::memcpy(cigar, cg.c_str(), cg.size() + 1);
+        return SWH_OK;
+    }
 
     // ---- resolution: forward local pass (keeping rows for the band traceback in CIGAR mode)
     BandKeep bk;

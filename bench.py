@@ -71,6 +71,8 @@ def parse():
     p.add_argument("--pf-db", type=int, default=2_000_000, help="database sequences of the prefilter leg")
     p.add_argument("--pf-train-pairs", type=int, default=1_000_000)
     p.add_argument("--pf-epochs", type=int, default=4)
+    p.add_argument("--no-global", action="store_true", help="skip the global-alignment (Needleman-Wunsch) leg")
+    p.add_argument("--global-n", type=int, default=1_000_000, help="query length of the global-alignment pair")
     p.add_argument("--autotune", action="store_true", help="run the strip-shape autotuner before timing")
     p.add_argument("--copy-calib-mb", type=int, default=0,
                    help="before the workload, copy a buffer of this many MiB once (a plain copy kernel of "
@@ -153,6 +155,28 @@ def bench_pairs(args, swh, eng):
             "pairs_per_s": round(args.pairs / dt, 1), "gcups_forward_cells": round(cells / dt / 1e9, 2),
             "s_per_batch": round(dt, 3), "cells_forward": cells,
             "forward_ms": round(st["ms_forward"], 2), "reverse_ms": round(st["ms_reverse"], 2),
+            "traceback_ms": round(st["ms_traceback"], 2), "cells_traceback": st["cells_traceback"]}
+
+
+def bench_global(args, swh, eng):
+    """Global alignment (Needleman-Wunsch with affine gaps) of a long DNA pair:
+    a uniform query and its mutated copy (2% substitutions, 0.5% indel events,
+    no flanks); score and CIGAR of the whole pair.  One warm-up call, one timed."""
+    import seqgen
+
+    q, t = seqgen.workload1(args.global_n, flank=0)
+    q, t = bytes(q), bytes(t)
+    sc = swh.Scoring(*seqgen.dna_scoring())
+    eng.align(q, t, sc, mode="cigar", alignment="global")
+    t0 = time.perf_counter()
+    res = eng.align(q, t, sc, mode="cigar", stats=True, alignment="global")
+    dt = time.perf_counter() - t0
+    st = res["stats"]
+    log(f"global pair done ({dt:.2f} s)")
+    return {"workload": f"global alignment of a {len(q)} bp DNA query and its mutated copy ({len(t)} bp), "
+                        f"+1/-3, open 5, extend 2; score and CIGAR",
+            "gcups": round(len(q) * len(t) / dt / 1e9, 2), "s_per_pair": round(dt, 3), "score": res["score"],
+            "forward_ms": round(st["ms_forward"], 2), "forward_gcups": round(st["cells_forward"] / st["ms_forward"] / 1e6, 2),
             "traceback_ms": round(st["ms_traceback"], 2), "cells_traceback": st["cells_traceback"]}
 
 
@@ -315,6 +339,8 @@ def main():
         out["db_search"] = bench_db(args, swh, eng)
     if not args.no_pairs:
         out["batched_pairs"] = bench_pairs(args, swh, eng)
+    if not args.no_global:
+        out["global_pair"] = bench_global(args, swh, eng)
     if not args.no_prefilter:
         out["prefilter"] = bench_prefilter(args, swh, eng)
     if not args.no_cpu:

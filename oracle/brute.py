@@ -186,3 +186,30 @@ def local_with_cigar(a, b, scoring):
 def all_strings(alphabet: str, n: int):
     for t in product(alphabet, repeat=n):
         yield "".join(t)
+
+
+def hw_result(a, b, scoring):
+    """Semi-global result by enumeration: the whole query against every target
+    substring b[j1..j2] aligned end to end (or against no target residue at
+    all), the residues around it unpenalised.  End = smallest j2 among the
+    optima, start = largest j1 among those with that end; the CIGAR is the
+    canonical path of the chosen rectangle."""
+    alphabet, mat, o, e = scoring
+    A, B = _codes(a, alphabet), _codes(b, alphabet)
+    n, m = len(A), len(B)
+    if n == 0:
+        return dict(score=0, q_begin=-1, q_end=-1, t_begin=-1, t_end=-1, cigar="")
+    cands = [(-(o + (n - 1) * e), 0, 0)]               # every query residue against a gap
+    for j1 in range(1, m + 1):
+        for j2 in range(j1, m + 1):
+            sb = B[j1 - 1:j2]
+            best = max(score_ops(ops, A, sb, mat, o, e) for ops in op_strings(n, len(sb)))
+            cands.append((best, j1, j2))
+    S = max(c[0] for c in cands)
+    end = min(c[2] for c in cands if c[0] == S)
+    if end == 0:
+        return dict(score=S, q_begin=0, q_end=n - 1, t_begin=-1, t_end=-1, cigar=f"{n}I")
+    start = max(c[1] for c in cands if c[0] == S and c[2] == end)
+    g, cig = global_canonical(a, b[start - 1:end], scoring)
+    assert g == S
+    return dict(score=S, q_begin=0, q_end=n - 1, t_begin=start - 1, t_end=end - 1, cigar=cig)

@@ -368,6 +368,117 @@ int orc_global_cigar(const char *alphabet, int asize, const int8_t *matrix, int 
     return ORC_OK;
 }
 
+/*
+ * Semi-global alignment (paper, Background, "Semi-global algorithm (HW)").
+ * Reading: the whole query against a part of the target whose surrounding
+ * target residues are not penalised; gaps at the ends of the query are.
+ *   G(0,j) = 0 (free leading target), G(i,0) = -(o + (i-1) e), E and F as
+ *   for the local DP, no zero floor; S = max_j G(n, j) (free trailing
+ *   target), end = the smallest such j (the first cell in row-major order).
+ *   start: the same DP on the reversed query and reversed target prefix
+ *   b[1..je], entered at its corner (top border -(o + (j-1) e)): its last
+ *   row holds at column c the best alignment of the whole query against
+ *   b[je-c+1..je]; the smallest c with value S gives the largest start.
+ *   path: the greedy walk of the global DP over a x b[js..je].
+ * An alignment with no target residue (S = G(n, 0)) has t_begin = t_end = -1
+ * and the CIGAR "nI"; an empty query scores 0 with no alignment.
+ */
+static int64_t *hw_last_row(const scoring *sc, const uint8_t *A, int64_t n, const uint8_t *B, int64_t m,
+                            int free_top)
+{
+    int64_t *G = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 1));
+    int64_t *F = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 1));
+    if (!G || !F) { free(G); free(F); return NULL; }
+    G[0] = 0;
+    F[0] = NEG_INF;
+    for (int64_t j = 1; j <= m; ++j) {
+        G[j] = free_top ? 0 : -(sc->o + (j - 1) * sc->e);
+        F[j] = NEG_INF;
+    }
+    for (int64_t i = 1; i <= n; ++i) {
+        int64_t diag = G[0];
+        F[0] = max2(F[0] - sc->e, G[0] - sc->o);
+        G[0] = F[0];
+        int64_t E = NEG_INF;
+        for (int64_t j = 1; j <= m; ++j) {
+            int64_t Ej = max2(E - sc->e, G[j - 1] - sc->o);
+            int64_t Fj = max2(F[j] - sc->e, G[j] - sc->o);
+            int64_t g = max2(diag + subst(sc, A[i - 1], B[j - 1]), max2(Ej, Fj));
+            diag = G[j];
+            G[j] = g;
+            F[j] = Fj;
+            E = Ej;
+        }
+    }
+    free(F);
+    return G;
+}
+
+int orc_hw_align(const char *alphabet, int asize, const int8_t *matrix, int o, int e,
+                 const char *a, int64_t n, const char *b, int64_t m, int want_cigar,
+                 int64_t *score, int64_t *coords, char *cigar, int64_t cigar_cap, int64_t *cigar_len)
+{
+    scoring sc;
+    int rc = make_scoring(&sc, alphabet, asize, matrix, o, e);
+    if (rc) return rc;
+    if (n < 0 || m < 0 || (!a && n) || (!b && m) || !score || !coords) return ORC_E_INVAL;
+    coords[0] = coords[1] = coords[2] = coords[3] = -1;
+    *score = 0;
+    if (cigar_len) *cigar_len = 0;
+    if (cigar && cigar_cap > 0) cigar[0] = '\0';
+    if (n == 0) return ORC_OK;
+    uint8_t *ca = (uint8_t *)malloc((size_t)(n + 1));
+    uint8_t *cb = (uint8_t *)malloc((size_t)(m + 1));
+    if (!ca || !cb) { free(ca); free(cb); return ORC_E_NOMEM; }
+    int64_t bad;
+    if ((rc = encode(&sc, a, n, ca, &bad)) || (rc = encode(&sc, b, m, cb, &bad))) {
+        free(ca); free(cb); return rc;
+    }
+    int64_t *row = hw_last_row(&sc, ca, n, cb, m, 1);
+    if (!row) { free(ca); free(cb); return ORC_E_NOMEM; }
+    int64_t S = row[0], je = 0;
+    for (int64_t j = 1; j <= m; ++j)
+        if (row[j] > S) { S = row[j]; je = j; }
+    free(row);
+    *score = S;
+    coords[0] = 0;
+    coords[1] = n - 1;
+    int64_t js = 1;
+    if (je > 0) {
+        uint8_t *ra = (uint8_t *)malloc((size_t)n);
+        uint8_t *rb = (uint8_t *)malloc((size_t)je);
+        if (!ra || !rb) { free(ra); free(rb); free(ca); free(cb); return ORC_E_NOMEM; }
+        for (int64_t k = 0; k < n; ++k) ra[k] = ca[n - 1 - k];
+        for (int64_t k = 0; k < je; ++k) rb[k] = cb[je - 1 - k];
+        int64_t *rrow = hw_last_row(&sc, ra, n, rb, je, 0);
+        free(ra); free(rb);
+        if (!rrow) { free(ca); free(cb); return ORC_E_NOMEM; }
+        int64_t c = 1;
+        while (c <= je && rrow[c] != S) ++c;
+        free(rrow);
+        if (c > je) { free(ca); free(cb); return ORC_E_INVAL; }   /* cannot happen */
+        js = je - c + 1;
+        coords[2] = js - 1;
+        coords[3] = je - 1;
+    }
+    if (want_cigar) {
+        const int64_t q = je > 0 ? je - js + 1 : 0;
+        char *ops = (char *)malloc((size_t)(n + q + 1));
+        if (!ops) { free(ca); free(cb); return ORC_E_NOMEM; }
+        int64_t g;
+        int64_t nops = global_walk(&sc, ca, n, cb + (je > 0 ? js - 1 : 0), q, ops, &g);
+        if (nops < 0) { free(ops); free(ca); free(cb); return (int)nops; }
+        if (g != S) { free(ops); free(ca); free(cb); return ORC_E_INVAL; }
+        int64_t need = cigar_from_backward(ops, nops, cigar, cigar_cap);
+        free(ops);
+        if (cigar_len) *cigar_len = need;
+        if (!cigar || need + 1 > cigar_cap) { free(ca); free(cb); return ORC_E_RANGE; }
+    }
+    free(ca);
+    free(cb);
+    return ORC_OK;
+}
+
 /* ---- many independent pairs / database search (threads over units) ---- */
 
 typedef struct {

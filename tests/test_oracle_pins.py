@@ -73,6 +73,27 @@ def test_global_walk_matches_path_enumeration(scheme):
         assert oracle.global_cigar(a, b, sc) == brute.global_canonical(a, b, sc), (a, b)
 
 
+@pytest.mark.parametrize("scheme", range(len(SCHEMES)))
+def test_semiglobal_matches_enumeration(scheme):
+    alphabet, mat, o, e = SCHEMES[scheme]
+    sc = (alphabet, mat, o, e)
+    rng = random.Random(3000 + scheme)
+    for _ in range(20):
+        a = _rand(rng, alphabet, 0, 3)
+        b = _rand(rng, alphabet, 0, 5)
+        assert oracle.hw_align(a, b, sc) == brute.hw_result(a, b, sc), (a, b)
+
+
+def test_semiglobal_closed_forms():
+    sc = seqgen.dna_scoring()
+    # a query that occurs in the target: all matches, placed at its first occurrence's end
+    r = oracle.hw_align(b"ACGTA", b"TTACGTAGGACGTA", sc)
+    assert (r["score"], r["t_begin"], r["t_end"], r["cigar"]) == (5, 2, 6, "5M")
+    # empty target: one gap run; empty query: nothing
+    assert oracle.hw_align(b"ACG", b"", sc)["score"] == -(5 + 2 * 2)
+    assert oracle.hw_align(b"", b"ACG", sc)["score"] == 0
+
+
 def test_enumeration_counts_are_delannoy():
     # the op-string enumerator itself: Delannoy numbers D(p,q)
     assert len(brute.op_strings(2, 2)) == 13

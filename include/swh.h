@@ -92,6 +92,21 @@ enum { SWH_MODE_SCORE = 0,   /* score and end coordinates (forward pass only) */
  */
 #define SWH_GLOBAL 0x100
 
+/*
+ * OR'd into mode (swh_align, swh_align_dev; not swh_align_batch): the optimal
+ * SEMI-GLOBAL alignment -- the whole query against a part of the target, the
+ * target residues before and after that part unpenalised, gaps at the ends
+ * of the query penalised (paper, Background, "Semi-global algorithm (HW)").
+ * score = max_j G(n, j) of the DP with G(0, j) = 0, G(i, 0) = -(o + (i-1) e);
+ * t_end = the smallest such j (minus one); t_begin = the largest start of an
+ * optimal alignment ending there (found by the same DP on the reversed
+ * sequences); q_begin = 0, q_end = n-1; the CIGAR is the greedy walk of the
+ * global DP over query x target[t_begin .. t_end].  No target residue
+ * aligned: t_begin = t_end = -1, CIGAR "nI"; an empty query: score 0, all
+ * coordinates -1.  Limits as for SWH_GLOBAL.
+ */
+#define SWH_SEMIGLOBAL 0x200
+
 /* Per-call statistics; set struct_size = sizeof(swh_stats) before the call. */
 typedef struct {
     uint32_t struct_size;

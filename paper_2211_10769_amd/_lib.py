@@ -16,6 +16,7 @@ STATUS_NAMES = {0: "SWH_OK", -1: "SWH_E_INVAL", -2: "SWH_E_ALPHABET", -3: "SWH_E
                 -4: "SWH_E_RANGE", -5: "SWH_E_DEVICE", -6: "SWH_E_TIMEOUT", -7: "SWH_E_CANCELLED"}
 MODE_SCORE, MODE_COORDS, MODE_CIGAR = 0, 1, 2
 GLOBAL = 0x100          # OR'd into mode: global (Needleman-Wunsch) alignment
+SEMIGLOBAL = 0x200      # OR'd into mode: semi-global (whole query, free target ends)
 
 
 class swh_scoring(ctypes.Structure):

@@ -23,7 +23,7 @@ namespace swh {
 namespace {
 
 // misc buffer layout (int32 words)
-enum { kBadQ = 0, kBadT = 1, kMiscWords = 4 };
+enum { kBadQ = 0, kBadT = 1, kPick = 2, kMiscWords = 4 };   // kPick: 8-byte row pick key
 
 struct LocalPass {
     BestCell best{0, 0, 0, 0};
@@ -88,6 +88,67 @@ int band_stride(swh_ctx *ctx, int64_t n, int64_t m, int R)
     return (int)std::max<int64_t>(1, (nstrips + max_rows - 1) / max_rows);
 }
 
+// Copy a finished CIGAR string out (SWH_E_RANGE when it does not fit).
+swh_status put_cigar(swh_ctx *ctx, const std::string &cg, char *cigar, int64_t cigar_cap, int64_t *cigar_len)
+{
+    if (cigar_len) *cigar_len = (int64_t)cg.size();
+    if (!cigar || (int64_t)cg.size() + 1 > cigar_cap)
+        return fail(ctx, SWH_E_RANGE, "CIGAR needs " + std::to_string(cg.size() + 1) + " bytes");
+    std::memcpy(cigar, cg.c_str(), cg.size() + 1);
+    return SWH_OK;
+}
+
+// One global-mode pass of the semi-global alignment: rows = the n query codes
+// (read backwards from qc[n-1] when qstep < 0), columns = a pad column, then
+// count target codes tc[tstart + k * tstep]; top row of BorderInit kind
+// `kind`.  Leaves the last row G(n, 0..count) in ctx->bborder.
+swh_status edge_pass(swh_ctx *ctx, const uint8_t *qc, int64_t n, int32_t qstep, const uint8_t *tc, int64_t tstart,
+                     int64_t count, int32_t tstep, int32_t kind, const Scoring &sc, hipStream_t st, double &ms)
+{
+    const StripShape sh = tuned_shape(ctx, n);
+    const int64_t qpad = rows_padded(n, sh.R), tpad = cols_padded(count + 1);
+    swh_status s;
+    if ((s = ensure(ctx, ctx->bq, (size_t)qpad + 256, "semi-global row codes")) != SWH_OK ||
+        (s = ensure(ctx, ctx->bt, (size_t)tpad + 256, "semi-global column codes")) != SWH_OK ||
+        (s = ensure(ctx, ctx->bborder, sizeof(Border) * (size_t)tpad + 256, "semi-global border")) != SWH_OK ||
+        (s = ensure(ctx, ctx->tb_misc, 2 * sizeof(GatherDesc), "gather table")) != SWH_OK ||
+        (s = ensure(ctx, ctx->tb_leaf, sizeof(BorderInit), "border table")) != SWH_OK)
+        return s;
+    uint8_t *qp = (uint8_t *)ctx->bq.p, *tp = (uint8_t *)ctx->bt.p;
+    Border *bp = (Border *)ctx->bborder.p;
+    const GatherDesc gd[2] = {GatherDesc{qc, qp, qstep > 0 ? 0 : n - 1, n, qpad, qstep, 0},
+                              GatherDesc{tc, tp, tstart, count, tpad, tstep, 1}};
+    const BorderInit bi{bp, nullptr, count + 1, tpad, kind, 0, 0, 0};
+    hipError_t e;
+    if ((e = hipMemcpyAsync(ctx->tb_misc.p, gd, sizeof(gd), hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(ctx->tb_leaf.p, &bi, sizeof(bi), hipMemcpyHostToDevice, st)) != hipSuccess)
+        return hip_fail(ctx, e, "semi-global tables");
+    if ((e = launch_gather((const GatherDesc *)ctx->tb_misc.p, 2, (uint8_t)sc.asize, st)) != hipSuccess ||
+        (e = launch_border_init((const BorderInit *)ctx->tb_leaf.p, 1, sc.o, sc.e, st)) != hipSuccess)
+        return hip_fail(ctx, e, "semi-global setup launch");
+    // the host tables above are stack copies: finish the copies before returning
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(ctx, e, "semi-global setup");
+    std::vector<StripProblem> pr{StripProblem{qp, n, tp, count + 1, bp}};
+    float t = 0.f;
+    if ((s = run_strips(ctx, pr, sc, sh.R, false, st, nullptr, &t, sh.waves)) != SWH_OK) return s;
+    ms += t;
+    return SWH_OK;
+}
+
+// launch_row_pick over the count + 1 entries of ctx->bborder; returns the key.
+swh_status pick_row(swh_ctx *ctx, int64_t count, int32_t target, int32_t mode, hipStream_t st, uint64_t &key)
+{
+    uint64_t *slot = (uint64_t *)((int32_t *)ctx->misc.p + kPick);
+    const uint64_t init = mode == 0 ? 0ull : ~0ull;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(slot, &init, sizeof(init), hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = launch_row_pick((const Border *)ctx->bborder.p, count + 1, target, mode, slot, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(&key, slot, sizeof(key), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(ctx, e, "row pick");
+    return SWH_OK;
+}
+
 }  // namespace
 
 swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const char *t_dev, int64_t tlen,
@@ -100,7 +161,8 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
         stats->struct_size = size;
     }
     const bool global = (mode & SWH_GLOBAL) != 0;
-    mode &= ~SWH_GLOBAL;
+    const bool semi = (mode & SWH_SEMIGLOBAL) != 0;
+    mode &= ~(SWH_GLOBAL | SWH_SEMIGLOBAL);
     out->score = 0;
     out->flags = SWH_F_NONE;
     out->q_begin = out->q_end = out->t_begin = out->t_end = -1;
@@ -122,6 +184,16 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
                 return fail(ctx, SWH_E_RANGE, "CIGAR needs " + std::to_string(cg.size() + 1) + " bytes");
             std::memcpy(cigar, cg.c_str(), cg.size() + 1);
             return SWH_OK;
+        }
+    }
+    if (semi && qlen > 0) {
+        out->q_begin = 0;
+        out->q_end = qlen - 1;
+        if (tlen == 0) {
+            // nothing to align against: the whole query as one insertion run
+            out->score = -(int32_t)(sc.o + (qlen - 1) * (int64_t)sc.e);
+            if (mode != SWH_MODE_CIGAR) return SWH_OK;
+            return put_cigar(ctx, std::to_string(qlen) + "I", cigar, cigar_cap, cigar_len);
         }
     }
     if (qlen == 0 || tlen == 0) return SWH_OK;
@@ -160,6 +232,54 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
     if (bad[1] != INT32_MAX)
         return fail(ctx, SWH_E_ALPHABET, "target byte at position " + std::to_string(bad[1]) +
                                              " is not in the alphabet");
+
+    if (semi) {
+        // ---- semi-global alignment (whole query, free target ends).  Forward:
+        // G(0, j) = 0 over a pad column and the target, the last row gives the
+        // score and the smallest end column; backward: the reversed query
+        // against the target reversed from that end with both starts penalised,
+        // the smallest column of the last row holding the score is the
+        // largest start.
+        const uint8_t *qc = (const uint8_t *)ctx->qc.p, *tc = (const uint8_t *)ctx->tc.p;
+        double ms_f = 0.0, ms_r = 0.0;
+        uint64_t key = 0;
+        if ((s = edge_pass(ctx, qc, qlen, 1, tc, 0, tlen, 1, 4, sc, st, ms_f)) != SWH_OK ||
+            (s = pick_row(ctx, tlen, 0, 0, st, key)) != SWH_OK)
+            return s;
+        const int32_t S = (int32_t)((uint32_t)(key >> 32) - (1u << 30));
+        const int64_t je = (int64_t)(0xFFFFFFFFu - (uint32_t)key);
+        out->score = S;
+        if (stats) {
+            stats->cells_forward = (double)qlen * (double)(tlen + 1);
+            stats->ms_forward = ms_f;
+        }
+        if (je < 0 || je > tlen) return fail(ctx, SWH_E_DEVICE, "semi-global end column out of range");
+        if (je == 0) {
+            // no target residue pays: the query as one insertion run
+            if (mode != SWH_MODE_CIGAR) return SWH_OK;
+            return put_cigar(ctx, std::to_string(qlen) + "I", cigar, cigar_cap, cigar_len);
+        }
+        out->t_end = je - 1;
+        if (mode == SWH_MODE_SCORE) return SWH_OK;
+        if ((s = edge_pass(ctx, qc, qlen, -1, tc, je - 1, je, -1, 1, sc, st, ms_r)) != SWH_OK ||
+            (s = pick_row(ctx, je, S, 1, st, key)) != SWH_OK)
+            return s;
+        if (stats) stats->ms_reverse = ms_r;
+        if (key < 1 || key > (uint64_t)je)
+            return fail(ctx, SWH_E_DEVICE, "semi-global backward pass does not reach the score " + std::to_string(S));
+        out->t_begin = je - (int64_t)key;
+        if (mode == SWH_MODE_COORDS) return SWH_OK;
+        std::string cg;
+        TracebackStats ts;
+        if ((s = traceback(ctx, qc, qlen, tc + out->t_begin, out->t_end - out->t_begin + 1, sc, S, st, cg, ts)) !=
+            SWH_OK)
+            return s;
+        if (stats) {
+            stats->ms_traceback = ts.ms;
+            stats->cells_traceback = ts.cells;
+        }
+        return put_cigar(ctx, cg, cigar, cigar_cap, cigar_len);
+    }
 
     if (global) {
         // ---- global alignment: the forward pass in global mode gives G(n, m),

@@ -26,7 +26,8 @@ struct GatherDesc {
 //         D'(c) = G'(c) - o;
 // kind 2: backward pass whose end is an F cell: G' = -inf, D'(0) = -o,
 //         D'(c>0) = -inf;
-// kind 3: a single frontier node: entry 0 = (seed_h, seed_f), the rest -inf.
+// kind 3: a single frontier node: entry 0 = (seed_h, seed_f), the rest -inf;
+// kind 4: free leading target residues: G'(c) = 0, D'(c) = -o for every c.
 // Entries from count to padded are (-inf, -inf).
 struct BorderInit {
     Border *dst;
@@ -131,6 +132,14 @@ struct LeafOut {
     int32_t err;            // nonzero: the walk left the leaf, or the end value is not V
     int32_t pad_[3];
 };
+
+// One value picked from a row of border records row[0 .. count):
+// mode 0: the largest h, at the smallest index; *out = ((h + 2^30) << 32) |
+//         (0xFFFFFFFF - index) (zero on entry);
+// mode 1: the smallest index >= 1 with h == target; *out = that index
+//         (all ones on entry: none).
+hipError_t launch_row_pick(const Border *row, int64_t count, int32_t target, int32_t mode, uint64_t *out,
+                           hipStream_t st);
 
 // Synthetic codes (timing runs of the autotuner): n codes in [0, asize), pad code up to padded.
 hipError_t launch_random_codes(uint8_t *dst, int64_t n, int64_t padded, int32_t asize, uint64_t seed, hipStream_t st);

@@ -62,12 +62,35 @@ __global__ void border_init_kernel(const BorderInit *descs, int32_t o, int32_t e
                 v = Border{g, g - o};
             } else if (d.kind == 2) {
                 v = Border{kNeg, c == 0 ? -o : kNeg};
-            } else if (c == 0) {
-                v = Border{d.seed_h, d.seed_f};
+            } else if (d.kind == 3) {
+                if (c == 0) v = Border{d.seed_h, d.seed_f};
+            } else {
+                v = Border{0, -o};
             }
         }
         d.dst[c] = v;
     }
+}
+
+__global__ void __launch_bounds__(256) row_pick_kernel(const Border *row, int64_t count, int32_t target, int32_t mode,
+                                                       unsigned long long *out)
+{
+    unsigned long long best = mode == 0 ? 0ull : ~0ull;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < count; j += stride) {
+        const int32_t h = row[j].h;
+        if (mode == 0) {
+            const unsigned long long key = ((unsigned long long)(uint32_t)(h + (1 << 30)) << 32) |
+                                           (unsigned long long)(0xFFFFFFFFu - (uint32_t)j);
+            best = key > best ? key : best;
+        } else if (j >= 1 && h == target) {
+            best = (unsigned long long)j < best ? (unsigned long long)j : best;
+        }
+    }
+    if (mode == 0)
+        atomicMax(out, best);
+    else
+        atomicMin(out, best);
 }
 
 // A path from the frontier to the end crosses from mid row r into row r+1
@@ -468,6 +491,16 @@ hipError_t launch_random_codes(uint8_t *dst, int64_t n, int64_t padded, int32_t 
     if (padded <= 0) return hipSuccess;
     const int64_t blocks = std::min<int64_t>((padded + 255) / 256, 65536);
     hipLaunchKernelGGL(random_codes_kernel, dim3((unsigned)blocks), dim3(256), 0, st, dst, n, padded, asize, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_pick(const Border *row, int64_t count, int32_t target, int32_t mode, uint64_t *out,
+                           hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((count + 255) / 256, 1024));
+    hipLaunchKernelGGL(row_pick_kernel, dim3((unsigned)blocks), dim3(256), 0, st, row, count, target, mode,
+                       reinterpret_cast<unsigned long long *>(out));
     return hipGetLastError();
 }
 

@@ -55,13 +55,15 @@ def lib() -> ctypes.CDLL:
         L.orc_hw_align.argtypes = [cstr, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                    cstr, ctypes.c_int64, cstr, ctypes.c_int64, ctypes.c_int,
                                    i64p, i64p, ctypes.c_char_p, ctypes.c_int64, i64p]
+        L.orc_ov_align.argtypes = L.orc_hw_align.argtypes
         L.orc_db_scores.argtypes = [cstr, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_int, ctypes.c_void_p]
         L.orc_topk.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                ctypes.c_void_p, ctypes.c_void_p]
-        for f in (L.orc_sw_align, L.orc_sw_end, L.orc_global_cigar, L.orc_hw_align, L.orc_db_scores, L.orc_topk):
+        for f in (L.orc_sw_align, L.orc_sw_end, L.orc_global_cigar, L.orc_hw_align, L.orc_ov_align,
+                  L.orc_db_scores, L.orc_topk):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -150,6 +152,26 @@ def hw_align(a, b, scoring, want_cigar: bool = True):
                             1 if want_cigar else 0, ctypes.byref(S), co, cbuf, len(cbuf), ctypes.byref(clen))
     if rc != OK:
         raise OracleError(rc, "hw_align")
+    out = dict(score=S.value, q_begin=co[0], q_end=co[1], t_begin=co[2], t_end=co[3])
+    if want_cigar:
+        out["cigar"] = cbuf.value.decode()
+    return out
+
+
+def ov_align(a, b, scoring, want_cigar: bool = True):
+    """Overlap alignment (end gaps of both sequences free): dict(score,
+    q_begin, q_end, t_begin, t_end[, cigar]), the readings in swh_oracle.c."""
+    alphabet, matrix, o, e = scoring
+    a, b = _as_bytes(a), _as_bytes(b)
+    M = _mat(matrix)
+    S = ctypes.c_int64()
+    co = (ctypes.c_int64 * 4)()
+    clen = ctypes.c_int64()
+    cbuf = ctypes.create_string_buffer(2 * (len(a) + len(b)) + 16)
+    rc = lib().orc_ov_align(alphabet.encode(), len(alphabet), M.ctypes.data, o, e, a, len(a), b, len(b),
+                            1 if want_cigar else 0, ctypes.byref(S), co, cbuf, len(cbuf), ctypes.byref(clen))
+    if rc != OK:
+        raise OracleError(rc, "ov_align")
     out = dict(score=S.value, q_begin=co[0], q_end=co[1], t_begin=co[2], t_end=co[3])
     if want_cigar:
         out["cigar"] = cbuf.value.decode()

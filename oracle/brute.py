@@ -213,3 +213,40 @@ def hw_result(a, b, scoring):
     g, cig = global_canonical(a, b[start - 1:end], scoring)
     assert g == S
     return dict(score=S, q_begin=0, q_end=n - 1, t_begin=start - 1, t_end=end - 1, cigar=cig)
+
+
+def ov_result(a, b, scoring):
+    """Overlap result by enumeration: every rectangle a[i1..i2] x b[j1..j2]
+    that starts on the first row or column (i1 = 1 or j1 = 1) and ends on the
+    last (i2 = n or j2 = m), aligned end to end, the residues outside it
+    unpenalised; the empty overlap scores 0 and reports no alignment.  End =
+    the smallest (i2, j2) among the optima, start = the largest (i1, j1)
+    among those with that end; the CIGAR is the canonical path of the chosen
+    rectangle."""
+    alphabet, mat, o, e = scoring
+    A, B = _codes(a, alphabet), _codes(b, alphabet)
+    n, m = len(A), len(B)
+    none = dict(score=0, q_begin=-1, q_end=-1, t_begin=-1, t_end=-1, cigar="")
+    cands = []
+    for i1 in range(1, n + 1):
+        for j1 in range(1, m + 1):
+            if i1 != 1 and j1 != 1:
+                continue
+            for i2 in range(i1, n + 1):
+                for j2 in range(j1, m + 1):
+                    if i2 != n and j2 != m:
+                        continue
+                    sa, sb = A[i1 - 1:i2], B[j1 - 1:j2]
+                    best = max(score_ops(ops, sa, sb, mat, o, e) for ops in op_strings(len(sa), len(sb)))
+                    cands.append((best, i1, j1, i2, j2))
+    if not cands:
+        return none
+    S = max(c[0] for c in cands)
+    if S <= 0:
+        return none
+    end = min((c[3], c[4]) for c in cands if c[0] == S)
+    start = max((c[1], c[2]) for c in cands if c[0] == S and (c[3], c[4]) == end)
+    g, cig = global_canonical(a[start[0] - 1:end[0]], b[start[1] - 1:end[1]], scoring)
+    assert g == S
+    return dict(score=S, q_begin=start[0] - 1, q_end=end[0] - 1, t_begin=start[1] - 1, t_end=end[1] - 1,
+                cigar=cig)

@@ -479,6 +479,143 @@ int orc_hw_align(const char *alphabet, int asize, const int8_t *matrix, int o, i
     return ORC_OK;
 }
 
+/*
+ * Overlap alignment (paper, Background, "Overlap algorithm (OV)"): both
+ * sequences aligned end to end except that gaps before the first and after
+ * the last aligned residue of either sequence cost nothing.
+ *   G(0,j) = G(i,0) = 0, E and F as for the local DP, no zero floor;
+ *   S = the maximum over the last column G(i, m) and the last row G(n, j).
+ *   end: the first cell of that border in row-major order holding S (the
+ *   last column above row n, then the last row from the left).
+ *   start: the DP on the reversed prefixes a[1..ie], b[1..je] entered at its
+ *   corner (both borders penalised: G'(0,c) = -(o + (c-1) e), the same down
+ *   the first column); its last column and last row hold the best alignments
+ *   that start on the forward top row or left column and end at (ie, je);
+ *   the first of them in row-major order holding S gives the largest start.
+ *   path: the greedy walk of the global DP over a[is+1..ie] x b[js+1..je].
+ * S = 0 (the empty overlap is always available) reports no alignment, as the
+ * local form does: all coordinates -1 and an empty CIGAR.
+ */
+static int ov_borders(const scoring *sc, const uint8_t *A, int64_t n, const uint8_t *B, int64_t m,
+                      int free_start, int64_t *last_row, int64_t *last_col)
+{
+    int64_t *G = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 1));
+    int64_t *F = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 1));
+    if (!G || !F) { free(G); free(F); return ORC_E_NOMEM; }
+    G[0] = 0;
+    F[0] = NEG_INF;
+    for (int64_t j = 1; j <= m; ++j) {
+        G[j] = free_start ? 0 : -(sc->o + (j - 1) * sc->e);
+        F[j] = NEG_INF;
+    }
+    last_col[0] = G[m];
+    for (int64_t i = 1; i <= n; ++i) {
+        int64_t diag = G[0];
+        if (free_start) {
+            G[0] = 0;
+        } else {
+            F[0] = max2(F[0] - sc->e, G[0] - sc->o);
+            G[0] = F[0];
+        }
+        int64_t E = NEG_INF;
+        for (int64_t j = 1; j <= m; ++j) {
+            int64_t Ej = max2(E - sc->e, G[j - 1] - sc->o);
+            int64_t Fj = max2(F[j] - sc->e, G[j] - sc->o);
+            int64_t g = max2(diag + subst(sc, A[i - 1], B[j - 1]), max2(Ej, Fj));
+            diag = G[j];
+            G[j] = g;
+            F[j] = Fj;
+            E = Ej;
+        }
+        last_col[i] = G[m];
+    }
+    memcpy(last_row, G, sizeof(int64_t) * (size_t)(m + 1));
+    free(G);
+    free(F);
+    return ORC_OK;
+}
+
+/* First border cell in row-major order holding S: (row, col) of the cell. */
+static int ov_pick(const int64_t *last_row, const int64_t *last_col, int64_t n, int64_t m, int64_t S,
+                   int64_t *r, int64_t *c)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (last_col[i] == S) { *r = i; *c = m; return 1; }
+    for (int64_t j = 0; j <= m; ++j)
+        if (last_row[j] == S) { *r = n; *c = j; return 1; }
+    return 0;
+}
+
+int orc_ov_align(const char *alphabet, int asize, const int8_t *matrix, int o, int e,
+                 const char *a, int64_t n, const char *b, int64_t m, int want_cigar,
+                 int64_t *score, int64_t *coords, char *cigar, int64_t cigar_cap, int64_t *cigar_len)
+{
+    scoring sc;
+    int rc = make_scoring(&sc, alphabet, asize, matrix, o, e);
+    if (rc) return rc;
+    if (n < 0 || m < 0 || (!a && n) || (!b && m) || !score || !coords) return ORC_E_INVAL;
+    coords[0] = coords[1] = coords[2] = coords[3] = -1;
+    *score = 0;
+    if (cigar_len) *cigar_len = 0;
+    if (cigar && cigar_cap > 0) cigar[0] = '\0';
+    if (n == 0 || m == 0) return ORC_OK;
+    uint8_t *ca = (uint8_t *)malloc((size_t)n);
+    uint8_t *cb = (uint8_t *)malloc((size_t)m);
+    int64_t *row = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 1));
+    int64_t *col = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    if (!ca || !cb || !row || !col) { rc = ORC_E_NOMEM; goto out; }
+    int64_t bad;
+    if ((rc = encode(&sc, a, n, ca, &bad)) || (rc = encode(&sc, b, m, cb, &bad))) goto out;
+    if ((rc = ov_borders(&sc, ca, n, cb, m, 1, row, col))) goto out;
+    int64_t S = 0;
+    for (int64_t i = 0; i <= n; ++i) S = max2(S, col[i]);
+    for (int64_t j = 0; j <= m; ++j) S = max2(S, row[j]);
+    *score = S;
+    if (S == 0) goto out;
+    int64_t ie, je;
+    ov_pick(row, col, n, m, S, &ie, &je);
+    /* reversed prefixes: row r of the reversed DP is query residue ie - r + 1 */
+    {
+        uint8_t *ra = (uint8_t *)malloc((size_t)ie);
+        uint8_t *rb = (uint8_t *)malloc((size_t)je);
+        int64_t *rrow = (int64_t *)malloc(sizeof(int64_t) * (size_t)(je + 1));
+        int64_t *rcol = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ie + 1));
+        if (!ra || !rb || !rrow || !rcol) {
+            free(ra); free(rb); free(rrow); free(rcol);
+            rc = ORC_E_NOMEM;
+            goto out;
+        }
+        for (int64_t k = 0; k < ie; ++k) ra[k] = ca[ie - 1 - k];
+        for (int64_t k = 0; k < je; ++k) rb[k] = cb[je - 1 - k];
+        rc = ov_borders(&sc, ra, ie, rb, je, 0, rrow, rcol);
+        int64_t r = -1, c = -1;
+        const int found = rc == ORC_OK && ov_pick(rrow, rcol, ie, je, S, &r, &c);
+        free(ra); free(rb); free(rrow); free(rcol);
+        if (rc) goto out;
+        if (!found) { rc = ORC_E_INVAL; goto out; }   /* cannot happen */
+        const int64_t is = ie - r, js = je - c;
+        coords[0] = is;
+        coords[1] = ie - 1;
+        coords[2] = js;
+        coords[3] = je - 1;
+        if (want_cigar) {
+            char *ops = (char *)malloc((size_t)(ie - is + je - js + 1));
+            if (!ops) { rc = ORC_E_NOMEM; goto out; }
+            int64_t g;
+            int64_t nops = global_walk(&sc, ca + is, ie - is, cb + js, je - js, ops, &g);
+            if (nops < 0) { free(ops); rc = (int)nops; goto out; }
+            if (g != S) { free(ops); rc = ORC_E_INVAL; goto out; }
+            int64_t need = cigar_from_backward(ops, nops, cigar, cigar_cap);
+            free(ops);
+            if (cigar_len) *cigar_len = need;
+            if (!cigar || need + 1 > cigar_cap) rc = ORC_E_RANGE;
+        }
+    }
+out:
+    free(ca); free(cb); free(row); free(col);
+    return rc;
+}
+
 /* ---- many independent pairs / database search (threads over units) ---- */
 
 typedef struct {

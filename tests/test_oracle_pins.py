@@ -94,6 +94,38 @@ def test_semiglobal_closed_forms():
     assert oracle.hw_align(b"", b"ACG", sc)["score"] == 0
 
 
+@pytest.mark.parametrize("scheme", range(len(SCHEMES)))
+def test_overlap_matches_enumeration(scheme):
+    alphabet, mat, o, e = SCHEMES[scheme]
+    sc = (alphabet, mat, o, e)
+    rng = random.Random(4000 + scheme)
+    for _ in range(20):
+        a = _rand(rng, alphabet, 0, 4)
+        b = _rand(rng, alphabet, 0, 4)
+        assert oracle.ov_align(a, b, sc) == brute.ov_result(a, b, sc), (a, b)
+
+
+def test_overlap_closed_forms():
+    sc = seqgen.dna_scoring()
+    # a suffix of the query is a prefix of the target: the overlap alone, all matches
+    r = oracle.ov_align(b"TTTACGT", b"ACGTGGG", sc)
+    assert (r["score"], r["q_begin"], r["q_end"], r["t_begin"], r["t_end"], r["cigar"]) == (4, 3, 6, 0, 3, "4M")
+    # the target inside the query
+    r = oracle.ov_align(b"GGACGTACC", b"ACGTA", sc)
+    assert (r["score"], r["q_begin"], r["q_end"], r["t_begin"], r["t_end"], r["cigar"]) == (5, 2, 6, 0, 4, "5M")
+    # nothing overlaps with a positive score: no alignment
+    assert oracle.ov_align(b"AAAA", b"CCCC", sc) == dict(score=0, q_begin=-1, q_end=-1, t_begin=-1, t_end=-1,
+                                                          cigar="")
+    assert oracle.ov_align(b"", b"ACG", sc)["score"] == 0 and oracle.ov_align(b"ACG", b"", sc)["score"] == 0
+    # swapping the sequences under a symmetric matrix keeps the score
+    rng = random.Random(11)
+    for _ in range(20):
+        a, b = _rand(rng, "ACGT", 0, 30), _rand(rng, "ACGT", 0, 30)
+        assert oracle.ov_align(a, b, sc)["score"] == oracle.ov_align(b, a, sc)["score"]
+        # every overlap is a local alignment, and the overlap's score is bounded by the local optimum
+        assert oracle.ov_align(a, b, sc)["score"] <= oracle.sw_align(a, b, sc)["score"]
+
+
 def test_enumeration_counts_are_delannoy():
     # the op-string enumerator itself: Delannoy numbers D(p,q)
     assert len(brute.op_strings(2, 2)) == 13

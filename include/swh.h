@@ -107,6 +107,23 @@ enum { SWH_MODE_SCORE = 0,   /* score and end coordinates (forward pass only) */
  */
 #define SWH_SEMIGLOBAL 0x200
 
+/*
+ * OR'd into mode (swh_align, swh_align_dev; not swh_align_batch): the optimal
+ * OVERLAP alignment -- gaps before the first and after the last aligned
+ * residue of either sequence cost nothing (paper, Background, "Overlap
+ * algorithm (OV)").  DP with G(0, j) = G(i, 0) = 0; score = the maximum over
+ * the last row G(n, j) and the last column G(i, m); the end is the first of
+ * those cells in row-major order holding it (the last column above row n,
+ * then the last row from the left); the start is the largest one, on the top
+ * row or the left column, of an alignment of that score ending there; the
+ * CIGAR is the greedy walk of the global DP between the two.  Score 0 (only
+ * the empty overlap) reports no alignment: coordinates -1, empty CIGAR.
+ * Costs two score passes (the last column comes from the same DP with the
+ * sequences swapped) and two more for the start.  Limits as for SWH_GLOBAL;
+ * exactly one of SWH_GLOBAL, SWH_SEMIGLOBAL, SWH_OVERLAP may be set.
+ */
+#define SWH_OVERLAP 0x400
+
 /* Per-call statistics; set struct_size = sizeof(swh_stats) before the call. */
 typedef struct {
     uint32_t struct_size;

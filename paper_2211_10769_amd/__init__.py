@@ -18,7 +18,8 @@ from . import _lib
 from ._lib import MODE_CIGAR, MODE_COORDS, MODE_SCORE, STATUS_NAMES
 
 _MODES = {"score": MODE_SCORE, "coords": MODE_COORDS, "cigar": MODE_CIGAR}
-_ALIGNMENTS = {"local": 0, "global": _lib.GLOBAL, "semiglobal": _lib.SEMIGLOBAL}
+_ALIGNMENTS = {"local": 0, "global": _lib.GLOBAL, "semiglobal": _lib.SEMIGLOBAL,
+               "overlap": _lib.OVERLAP}
 
 
 class SwhError(RuntimeError):
@@ -90,7 +91,7 @@ class Engine:
 
     def align(self, query, target, scoring, mode: str = "cigar", stats: bool = False, alignment: str = "local"):
         """Local (or, alignment="global", Needleman-Wunsch; alignment="semiglobal",
-        the whole query against part of the target) alignment of host sequences;
+        the whole query against part of the target; alignment="overlap", end gaps free) alignment of host sequences;
         returns dict(score, q_begin, q_end, t_begin, t_end[, cigar])."""
         sc = Scoring.of(scoring)
         q, t = _bytes(query), _bytes(target)

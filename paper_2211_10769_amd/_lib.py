@@ -17,6 +17,7 @@ STATUS_NAMES = {0: "SWH_OK", -1: "SWH_E_INVAL", -2: "SWH_E_ALPHABET", -3: "SWH_E
 MODE_SCORE, MODE_COORDS, MODE_CIGAR = 0, 1, 2
 GLOBAL = 0x100          # OR'd into mode: global (Needleman-Wunsch) alignment
 SEMIGLOBAL = 0x200      # OR'd into mode: semi-global (whole query, free target ends)
+OVERLAP = 0x400         # OR'd into mode: overlap (end gaps of both sequences free)
 
 
 class swh_scoring(ctypes.Structure):

@@ -83,10 +83,11 @@ swh_status check_pair(swh_ctx *ctx, const void *q, int64_t qlen, const void *t, 
     if (!out) return fail(ctx, SWH_E_INVAL, "out is NULL");
     if (qlen < 0 || tlen < 0) return fail(ctx, SWH_E_INVAL, "negative sequence length");
     if ((qlen && !q) || (tlen && !t)) return fail(ctx, SWH_E_INVAL, "sequence pointer is NULL");
-    const bool global = (mode & (SWH_GLOBAL | SWH_SEMIGLOBAL)) != 0;
-    if ((mode & SWH_GLOBAL) && (mode & SWH_SEMIGLOBAL))
-        return fail(ctx, SWH_E_INVAL, "SWH_GLOBAL and SWH_SEMIGLOBAL exclude each other");
-    mode &= ~(SWH_GLOBAL | SWH_SEMIGLOBAL);
+    const int forms = mode & (SWH_GLOBAL | SWH_SEMIGLOBAL | SWH_OVERLAP);
+    const bool global = forms != 0;
+    if (forms & (forms - 1))
+        return fail(ctx, SWH_E_INVAL, "SWH_GLOBAL, SWH_SEMIGLOBAL and SWH_OVERLAP exclude each other");
+    mode &= ~(SWH_GLOBAL | SWH_SEMIGLOBAL | SWH_OVERLAP);
     if (mode < SWH_MODE_SCORE || mode > SWH_MODE_CIGAR) return fail(ctx, SWH_E_INVAL, "unknown mode");
     if (qlen >= (int64_t)1 << 31 || tlen >= (int64_t)1 << 31)
         return fail(ctx, SWH_E_RANGE, "sequence longer than 2^31 - 1");
@@ -213,7 +214,8 @@ swh_status swh_align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, cons
     if (s != SWH_OK) return s;
     if (npairs < 0) return fail(ctx, SWH_E_INVAL, "npairs is negative");
     if (npairs > 0 && (!q_off || !t_off || !out)) return fail(ctx, SWH_E_INVAL, "offsets or out is NULL");
-    if (mode & SWH_SEMIGLOBAL) return fail(ctx, SWH_E_INVAL, "SWH_SEMIGLOBAL is not available in batches");
+    if (mode & (SWH_SEMIGLOBAL | SWH_OVERLAP))
+        return fail(ctx, SWH_E_INVAL, "SWH_SEMIGLOBAL and SWH_OVERLAP are not available in batches");
     if (((mode & ~SWH_GLOBAL) < SWH_MODE_SCORE || (mode & ~SWH_GLOBAL) > SWH_MODE_CIGAR))
         return fail(ctx, SWH_E_INVAL, "unknown mode");
     if ((mode & ~SWH_GLOBAL) == SWH_MODE_CIGAR && !cigar_off) return fail(ctx, SWH_E_INVAL, "cigar_off is NULL");

@@ -248,11 +248,15 @@ __global__ void __launch_bounds__(256 * kWgPerSimd<R>) strip_kernel(StripArgs a)
         const bool ragged = !LOCAL && __builtin_amdgcn_readfirstlane(
                                           (int)((int64_t)(s + 1) * 64 * R > P.n));
 
+        // free left border (global mode): H = 0 and E = -o entering column 0;
+        // a lane's steps left of column 0 are reset to the same values below
+        const bool free_left = !LOCAL && P.free_left != 0;
+        const int B0 = free_left ? 0 : B;
         int hp[R], E[R];
 #pragma unroll
-        for (int k = 0; k < R; ++k) { hp[k] = B; E[k] = B; }
-        int hup_prev = B;          // H(row0-1, j-1): diag of the first row
-        int hbot = B, fbot = B;    // this lane's last row output of the previous step
+        for (int k = 0; k < R; ++k) { hp[k] = B0; E[k] = free_left ? -o : B; }
+        int hup_prev = B0;         // H(row0-1, j-1): diag of the first row
+        int hbot = B0, fbot = B;   // this lane's last row output of the previous step
         int oh = B, of = B;        // collected outputs of lane 63
         // best cell (local): key = (H << log2 R) | (R-1-k) orders cells of one
         // step by value, then smaller row; bkey keeps the largest key seen and
@@ -327,6 +331,10 @@ __global__ void __launch_bounds__(256 * kWgPerSimd<R>) strip_kernel(StripArgs a)
                     dp_step<R, LOCAL, false>(hp, E, sc, hup_prev, hup, f, o, e, nreal);
                 else
                     dp_step<R, LOCAL, true>(hp, E, sc, hup_prev, hup, f, o, e, nreal);
+                if (!LOCAL && free_left && b == 0 && u < lane) {
+#pragma unroll
+                    for (int k = 0; k < R; ++k) { hp[k] = 0; E[k] = -o; }
+                }
                 hup_prev = hup;
                 hbot = hp[R - 1];
                 fbot = f;

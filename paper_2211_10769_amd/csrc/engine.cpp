@@ -98,54 +98,80 @@ swh_status put_cigar(swh_ctx *ctx, const std::string &cg, char *cigar, int64_t c
     return SWH_OK;
 }
 
-// One global-mode pass of the semi-global alignment: rows = the n query codes
-// (read backwards from qc[n-1] when qstep < 0), columns = a pad column, then
-// count target codes tc[tstart + k * tstep]; top row of BorderInit kind
-// `kind`.  Leaves the last row G(n, 0..count) in ctx->bborder.
-swh_status edge_pass(swh_ctx *ctx, const uint8_t *qc, int64_t n, int32_t qstep, const uint8_t *tc, int64_t tstart,
-                     int64_t count, int32_t tstep, int32_t kind, const Scoring &sc, hipStream_t st, double &ms)
+// One global-mode pass of the semi-global and overlap forms: rows = the n
+// row codes (read backwards from rc[n-1] when rstep < 0), columns = an
+// optional pad column, then count codes cc[cstart + k * cstep]; top row of
+// BorderInit kind `kind`; free_left: H = 0 left of the first column.  Leaves
+// the last row in ctx->bborder (entry k = column k, the pad column first).
+swh_status edge_pass(swh_ctx *ctx, const uint8_t *rc, int64_t n, int32_t rstep, const uint8_t *cc, int64_t cstart,
+                     int64_t count, int32_t cstep, int32_t kind, bool pad_col, bool free_left, const Scoring &sc,
+                     hipStream_t st, double &ms)
 {
     const StripShape sh = tuned_shape(ctx, n);
-    const int64_t qpad = rows_padded(n, sh.R), tpad = cols_padded(count + 1);
+    const int64_t cols = count + (pad_col ? 1 : 0);
+    const int64_t qpad = rows_padded(n, sh.R), tpad = cols_padded(cols);
     swh_status s;
-    if ((s = ensure(ctx, ctx->bq, (size_t)qpad + 256, "semi-global row codes")) != SWH_OK ||
-        (s = ensure(ctx, ctx->bt, (size_t)tpad + 256, "semi-global column codes")) != SWH_OK ||
-        (s = ensure(ctx, ctx->bborder, sizeof(Border) * (size_t)tpad + 256, "semi-global border")) != SWH_OK ||
+    if ((s = ensure(ctx, ctx->bq, (size_t)qpad + 256, "edge pass row codes")) != SWH_OK ||
+        (s = ensure(ctx, ctx->bt, (size_t)tpad + 256, "edge pass column codes")) != SWH_OK ||
+        (s = ensure(ctx, ctx->bborder, sizeof(Border) * (size_t)tpad + 256, "edge pass border")) != SWH_OK ||
         (s = ensure(ctx, ctx->tb_misc, 2 * sizeof(GatherDesc), "gather table")) != SWH_OK ||
         (s = ensure(ctx, ctx->tb_leaf, sizeof(BorderInit), "border table")) != SWH_OK)
         return s;
     uint8_t *qp = (uint8_t *)ctx->bq.p, *tp = (uint8_t *)ctx->bt.p;
     Border *bp = (Border *)ctx->bborder.p;
-    const GatherDesc gd[2] = {GatherDesc{qc, qp, qstep > 0 ? 0 : n - 1, n, qpad, qstep, 0},
-                              GatherDesc{tc, tp, tstart, count, tpad, tstep, 1}};
-    const BorderInit bi{bp, nullptr, count + 1, tpad, kind, 0, 0, 0};
+    const GatherDesc gd[2] = {GatherDesc{rc, qp, rstep > 0 ? 0 : n - 1, n, qpad, rstep, 0},
+                              GatherDesc{cc, tp, cstart, count, tpad, cstep, pad_col ? 1 : 0}};
+    const BorderInit bi{bp, nullptr, cols, tpad, kind, 0, 0, 0};
     hipError_t e;
     if ((e = hipMemcpyAsync(ctx->tb_misc.p, gd, sizeof(gd), hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = hipMemcpyAsync(ctx->tb_leaf.p, &bi, sizeof(bi), hipMemcpyHostToDevice, st)) != hipSuccess)
-        return hip_fail(ctx, e, "semi-global tables");
+        return hip_fail(ctx, e, "edge pass tables");
     if ((e = launch_gather((const GatherDesc *)ctx->tb_misc.p, 2, (uint8_t)sc.asize, st)) != hipSuccess ||
         (e = launch_border_init((const BorderInit *)ctx->tb_leaf.p, 1, sc.o, sc.e, st)) != hipSuccess)
-        return hip_fail(ctx, e, "semi-global setup launch");
+        return hip_fail(ctx, e, "edge pass setup launch");
     // the host tables above are stack copies: finish the copies before returning
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(ctx, e, "semi-global setup");
-    std::vector<StripProblem> pr{StripProblem{qp, n, tp, count + 1, bp}};
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(ctx, e, "edge pass setup");
+    StripProblem sp{qp, n, tp, cols, bp};
+    sp.free_left = free_left ? 1 : 0;
+    std::vector<StripProblem> pr{sp};
     float t = 0.f;
     if ((s = run_strips(ctx, pr, sc, sh.R, false, st, nullptr, &t, sh.waves)) != SWH_OK) return s;
     ms += t;
     return SWH_OK;
 }
 
-// launch_row_pick over the count + 1 entries of ctx->bborder; returns the key.
-swh_status pick_row(swh_ctx *ctx, int64_t count, int32_t target, int32_t mode, hipStream_t st, uint64_t &key)
+// launch_row_pick over the first `entries` records of ctx->bborder; returns the key.
+swh_status pick_row(swh_ctx *ctx, int64_t entries, int32_t target, int32_t mode, hipStream_t st, uint64_t &key)
 {
     uint64_t *slot = (uint64_t *)((int32_t *)ctx->misc.p + kPick);
     const uint64_t init = mode == 0 ? 0ull : ~0ull;
+    key = init;
+    if (entries <= 0) return SWH_OK;
     hipError_t e;
     if ((e = hipMemcpyAsync(slot, &init, sizeof(init), hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (e = launch_row_pick((const Border *)ctx->bborder.p, count + 1, target, mode, slot, st)) != hipSuccess ||
+        (e = launch_row_pick((const Border *)ctx->bborder.p, entries, target, mode, slot, st)) != hipSuccess ||
         (e = hipMemcpyAsync(&key, slot, sizeof(key), hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
         return hip_fail(ctx, e, "row pick");
+    return SWH_OK;
+}
+
+// mode-0 key -> (value, index)
+inline int32_t key_value(uint64_t key) { return (int32_t)((uint32_t)(key >> 32) - (1u << 30)); }
+inline int64_t key_index(uint64_t key) { return (int64_t)(0xFFFFFFFFu - (uint32_t)key); }
+
+// The device substitution table, as given or transposed (passes that run the
+// target down the rows score s(b, a) with the table's rows and columns swapped).
+swh_status set_matrix(swh_ctx *ctx, const Scoring &sc, bool transposed, hipStream_t st)
+{
+    int8_t m[32 * 32];
+    const int A = sc.asize;
+    for (int x = 0; x < A; ++x)
+        for (int y = 0; y < A; ++y) m[x * A + y] = transposed ? sc.mat[y * A + x] : sc.mat[x * A + y];
+    hipError_t e;
+    if ((e = hipMemcpyAsync(ctx->mat.p, m, (size_t)A * A, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(ctx, e, "substitution table");
     return SWH_OK;
 }
 
@@ -162,7 +188,8 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
     }
     const bool global = (mode & SWH_GLOBAL) != 0;
     const bool semi = (mode & SWH_SEMIGLOBAL) != 0;
-    mode &= ~(SWH_GLOBAL | SWH_SEMIGLOBAL);
+    const bool overlap = (mode & SWH_OVERLAP) != 0;
+    mode &= ~(SWH_GLOBAL | SWH_SEMIGLOBAL | SWH_OVERLAP);
     out->score = 0;
     out->flags = SWH_F_NONE;
     out->q_begin = out->q_end = out->t_begin = out->t_end = -1;
@@ -243,11 +270,11 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
         const uint8_t *qc = (const uint8_t *)ctx->qc.p, *tc = (const uint8_t *)ctx->tc.p;
         double ms_f = 0.0, ms_r = 0.0;
         uint64_t key = 0;
-        if ((s = edge_pass(ctx, qc, qlen, 1, tc, 0, tlen, 1, 4, sc, st, ms_f)) != SWH_OK ||
-            (s = pick_row(ctx, tlen, 0, 0, st, key)) != SWH_OK)
+        if ((s = edge_pass(ctx, qc, qlen, 1, tc, 0, tlen, 1, 4, true, false, sc, st, ms_f)) != SWH_OK ||
+            (s = pick_row(ctx, tlen + 1, 0, 0, st, key)) != SWH_OK)
             return s;
-        const int32_t S = (int32_t)((uint32_t)(key >> 32) - (1u << 30));
-        const int64_t je = (int64_t)(0xFFFFFFFFu - (uint32_t)key);
+        const int32_t S = key_value(key);
+        const int64_t je = key_index(key);
         out->score = S;
         if (stats) {
             stats->cells_forward = (double)qlen * (double)(tlen + 1);
@@ -261,8 +288,8 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
         }
         out->t_end = je - 1;
         if (mode == SWH_MODE_SCORE) return SWH_OK;
-        if ((s = edge_pass(ctx, qc, qlen, -1, tc, je - 1, je, -1, 1, sc, st, ms_r)) != SWH_OK ||
-            (s = pick_row(ctx, je, S, 1, st, key)) != SWH_OK)
+        if ((s = edge_pass(ctx, qc, qlen, -1, tc, je - 1, je, -1, 1, true, false, sc, st, ms_r)) != SWH_OK ||
+            (s = pick_row(ctx, je + 1, S, 1, st, key)) != SWH_OK)
             return s;
         if (stats) stats->ms_reverse = ms_r;
         if (key < 1 || key > (uint64_t)je)
@@ -274,6 +301,71 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
         if ((s = traceback(ctx, qc, qlen, tc + out->t_begin, out->t_end - out->t_begin + 1, sc, S, st, cg, ts)) !=
             SWH_OK)
             return s;
+        if (stats) {
+            stats->ms_traceback = ts.ms;
+            stats->cells_traceback = ts.cells;
+        }
+        return put_cigar(ctx, cg, cigar, cigar_cap, cigar_len);
+    }
+
+    if (overlap) {
+        // ---- overlap alignment (end gaps of both sequences free).  The last
+        // row of the DP with both borders free, and its last column as the
+        // last row of the same DP with the sequences swapped (transposed
+        // scores); the end is the first border cell in row-major order holding
+        // the maximum.  The start: the same two edges of the DP on the
+        // reversed prefixes entered at its corner (both borders penalised).
+        const uint8_t *qc = (const uint8_t *)ctx->qc.p, *tc = (const uint8_t *)ctx->tc.p;
+        double ms_f = 0.0, ms_r = 0.0;
+        uint64_t krow = 0, kcol = 0;
+        if ((s = edge_pass(ctx, qc, qlen, 1, tc, 0, tlen, 1, 4, false, true, sc, st, ms_f)) != SWH_OK ||
+            (s = pick_row(ctx, tlen, 0, 0, st, krow)) != SWH_OK ||          // G(n, 1..m)
+            (s = set_matrix(ctx, sc, true, st)) != SWH_OK ||
+            (s = edge_pass(ctx, tc, tlen, 1, qc, 0, qlen, 1, 4, false, true, sc, st, ms_f)) != SWH_OK ||
+            (s = pick_row(ctx, qlen - 1, 0, 0, st, kcol)) != SWH_OK ||      // G(1..n-1, m)
+            (s = set_matrix(ctx, sc, false, st)) != SWH_OK)
+            return s;
+        if (stats) {
+            stats->cells_forward = 2.0 * (double)qlen * (double)tlen;
+            stats->ms_forward = ms_f;
+        }
+        const int32_t srow = key_value(krow);
+        const int32_t scol = qlen > 1 ? key_value(kcol) : INT32_MIN;
+        const int32_t S = std::max(0, std::max(srow, scol));
+        out->score = S;
+        if (S == 0) return SWH_OK;   // only the empty overlap: no alignment
+        const int64_t ie = scol == S ? key_index(kcol) + 1 : qlen;
+        const int64_t je = scol == S ? tlen : key_index(krow) + 1;
+        if (ie < 1 || ie > qlen || je < 1 || je > tlen)
+            return fail(ctx, SWH_E_DEVICE, "overlap end cell out of range");
+        out->q_end = ie - 1;
+        out->t_end = je - 1;
+        if (mode == SWH_MODE_SCORE) return SWH_OK;
+        uint64_t kr = 0, kc = 0;
+        if ((s = set_matrix(ctx, sc, true, st)) != SWH_OK ||
+            (s = edge_pass(ctx, tc, je, -1, qc, ie - 1, ie, -1, 1, true, false, sc, st, ms_r)) != SWH_OK ||
+            (s = pick_row(ctx, ie, S, 1, st, kr)) != SWH_OK ||              // G'(1..ie-1, je)
+            (s = set_matrix(ctx, sc, false, st)) != SWH_OK ||
+            (s = edge_pass(ctx, qc, ie, -1, tc, je - 1, je, -1, 1, true, false, sc, st, ms_r)) != SWH_OK ||
+            (s = pick_row(ctx, je + 1, S, 1, st, kc)) != SWH_OK)            // G'(ie, 1..je)
+            return s;
+        if (stats) stats->ms_reverse = ms_r;
+        int64_t is, js;
+        if (kr >= 1 && kr < (uint64_t)ie) {
+            is = ie - (int64_t)kr;
+            js = 0;
+        } else if (kc >= 1 && kc <= (uint64_t)je) {
+            is = 0;
+            js = je - (int64_t)kc;
+        } else {
+            return fail(ctx, SWH_E_DEVICE, "overlap backward passes do not reach the score " + std::to_string(S));
+        }
+        out->q_begin = is;
+        out->t_begin = js;
+        if (mode == SWH_MODE_COORDS) return SWH_OK;
+        std::string cg;
+        TracebackStats ts;
+        if ((s = traceback(ctx, qc + is, ie - is, tc + js, je - js, sc, S, st, cg, ts)) != SWH_OK) return s;
         if (stats) {
             stats->ms_traceback = ts.ms;
             stats->cells_traceback = ts.cells;

@@ -46,7 +46,9 @@ struct Problem {
     Border *save;
     int64_t save_stride;
     int32_t save_phase;
-    int32_t pad_;
+    // global mode only: H = 0 left of column 0 (free leading row residues,
+    // the overlap form) instead of the penalised boundary
+    int32_t free_left;
 };
 
 // Arguments of the strip-wavefront kernel (dp_strip.hip).

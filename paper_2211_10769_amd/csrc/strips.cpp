@@ -110,7 +110,7 @@ swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, cons
         P.save_every = q.save ? q.save_every : 0;
         P.save_stride = q.save_stride;
         P.save_phase = q.save_phase;
-        P.pad_ = 0;
+        P.free_left = q.free_left;
         total_strips += P.nstrips;
         total_flags += P.nblocks + 3;
         if (np > 1)

@@ -25,6 +25,7 @@ struct StripProblem {
     int64_t save_stride = 0;
     int32_t save_every = 0;
     int32_t save_phase = 0;
+    int32_t free_left = 0;   // global mode: H = 0 left of column 0 (Problem)
 };
 
 inline int64_t rows_padded(int64_t n, int R) { return ((n + 64 * R - 1) / (64 * R)) * 64 * R; }

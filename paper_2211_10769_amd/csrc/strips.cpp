@@ -55,14 +55,21 @@ int pick_rows_per_lane(int64_t n, int simds)
     if (forced == 4 || forced == 8 || forced == 16 || forced == 20 || forced == 24 || forced == 32) return forced;
     simds = std::max(simds, 1);
     auto strips = [&](int R) { return (n + 64 * R - 1) / (64 * R); };
-    if (strips(8) >= 4 * (int64_t)simds) {
+    if (strips(8) >= (int64_t)simds) {
+        // Every strip of a problem takes the same time and one wave keeps a
+        // SIMD busy, so the pass takes ceil(strips / SIMDs) strip times.  A
+        // strip time is proportional to the cycles one step (a 64-column
+        // diagonal of 64 R cells) takes; measured per R on a 2 Mbp pair, one
+        // wave per SIMD (R = 32 runs well above the linear trend of the others).
+        static const struct { int R; int64_t cycles; } kStep[] = {{8, 428}, {16, 734}, {20, 844}, {24, 960},
+                                                                   {32, 1581}};
         int best = 8;
         int64_t best_cost = INT64_MAX;
-        for (int R : {8, 16, 20, 24, 32}) {
-            const int64_t cost = (strips(R) + simds - 1) / simds * (15 * (int64_t)R + 48);
+        for (const auto &k : kStep) {
+            const int64_t cost = (strips(k.R) + simds - 1) / simds * k.cycles;
             if (cost < best_cost) {
                 best_cost = cost;
-                best = R;
+                best = k.R;
             }
         }
         return best;

@@ -56,6 +56,11 @@ __device__ __forceinline__ int shl1(int old, int src)
 
 __device__ __forceinline__ int max3i(int a, int b, int c) { return max(max(a, b), c); }
 
+template <bool V>
+struct BoolC {
+    static constexpr bool value = V;
+};
+
 // Border traffic goes through agent-scope relaxed atomics (coherent across
 // the XCDs' L2s per location); ordering is explicit: stores are drained with
 // s_waitcnt vmcnt(0) before the chunk counter is published.
@@ -307,58 +312,78 @@ __global__ void __launch_bounds__(256 * kWgPerSimd<R>) strip_kernel(StripArgs a)
             }
 
             const int tbase = 64 * b;
+            // One block of 64 steps.  The variants of global mode (ragged
+            // strip: pass-through rows; free left border: the steps left of
+            // column 0 reset) are separate loops, chosen once per block, so
+            // that no step carries a test or a select it does not need.
+            auto block_steps = [&](auto pass_c, auto fix_c) {
+                constexpr bool PASS = decltype(pass_c)::value;
+                constexpr bool FIX = decltype(fix_c)::value;
 #pragma unroll 2
-            for (int u = 0; u < 64; ++u) {
-                // next column's code (lane 0 from the feed, others from the lane above)
-                const int code_n = shr1(tfeed, code);
-                tfeed = shl1(tfeed, tfeed);
-                int sc_n[W];
-                // retire the previous profile read (issued a whole step ago) before
-                // issuing this one, so that the wait for `sc` below never has to
-                // include the read just issued
-                __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0), vmcnt/expcnt untouched
-                load_prof<W>(prof, A1, code_n, lane, sc_n);
-                // keep the profile read for the next column ahead of this column's
-                // arithmetic, so its LDS latency overlaps one whole step
-                __builtin_amdgcn_sched_barrier(0);
-                // row above this lane's first row at this column
-                const int hup = shr1(fh, hbot);
-                int f = shr1(ff, fbot);
-                fh = shl1(fh, fh);
-                ff = shl1(ff, ff);
+                for (int u = 0; u < 64; ++u) {
+                    // next column's code (lane 0 from the feed, others from the lane above)
+                    const int code_n = shr1(tfeed, code);
+                    tfeed = shl1(tfeed, tfeed);
+                    int sc_n[W];
+                    // retire the previous profile read (issued a whole step ago) before
+                    // issuing this one, so that the wait for `sc` below never has to
+                    // include the read just issued
+                    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0), vmcnt/expcnt untouched
+                    load_prof<W>(prof, A1, code_n, lane, sc_n);
+                    // keep the profile read for the next column ahead of this column's
+                    // arithmetic, so its LDS latency overlaps one whole step
+                    __builtin_amdgcn_sched_barrier(0);
+                    // row above this lane's first row at this column
+                    const int hup = shr1(fh, hbot);
+                    int f = shr1(ff, fbot);
+                    fh = shl1(fh, fh);
+                    ff = shl1(ff, ff);
 
-                if (LOCAL || !ragged)
-                    dp_step<R, LOCAL, false>(hp, E, sc, hup_prev, hup, f, o, e, nreal);
-                else
-                    dp_step<R, LOCAL, true>(hp, E, sc, hup_prev, hup, f, o, e, nreal);
-                if (!LOCAL && free_left && b == 0 && u < lane) {
+                    dp_step<R, LOCAL, PASS>(hp, E, sc, hup_prev, hup, f, o, e, nreal);
+                    if (FIX && u < lane) {
 #pragma unroll
-                    for (int k = 0; k < R; ++k) { hp[k] = 0; E[k] = -o; }
-                }
-                hup_prev = hup;
-                hbot = hp[R - 1];
-                fbot = f;
-                oh = shl1(hbot, oh);
-                of = shl1(fbot, of);
-
-                if (LOCAL) {
-                    constexpr int LOGR = Prof<R>::LOGR;
-                    int hm = hp[0];
-#pragma unroll
-                    for (int k = 1; k < R; ++k) hm = max(hm, hp[k]);
-                    if (__builtin_amdgcn_ballot_w64(hm >= bthr)) {   // wave-uniform
-                        int mx = (hp[0] << LOGR) | (R - 1);
-#pragma unroll
-                        for (int k = 1; k < R; ++k) mx = max(mx, (hp[k] << LOGR) | (R - 1 - k));
-                        const bool gt = mx > bkey;
-                        bkey = gt ? mx : bkey;
-                        bstep = gt ? tbase + u : bstep;
-                        bthr = max(bkey >> LOGR, 1);
+                        for (int k = 0; k < R; ++k) { hp[k] = 0; E[k] = -o; }
                     }
-                }
+                    hup_prev = hup;
+                    hbot = hp[R - 1];
+                    fbot = f;
+                    oh = shl1(hbot, oh);
+                    of = shl1(fbot, of);
+
+                    if (LOCAL) {
+                        constexpr int LOGR = Prof<R>::LOGR;
+                        int hm = hp[0];
 #pragma unroll
-                for (int w = 0; w < W; ++w) sc[w] = sc_n[w];
-                code = code_n;
+                        for (int k = 1; k < R; ++k) hm = max(hm, hp[k]);
+                        if (__builtin_amdgcn_ballot_w64(hm >= bthr)) {   // wave-uniform
+                            int mx = (hp[0] << LOGR) | (R - 1);
+#pragma unroll
+                            for (int k = 1; k < R; ++k) mx = max(mx, (hp[k] << LOGR) | (R - 1 - k));
+                            const bool gt = mx > bkey;
+                            bkey = gt ? mx : bkey;
+                            bstep = gt ? tbase + u : bstep;
+                            bthr = max(bkey >> LOGR, 1);
+                        }
+                    }
+#pragma unroll
+                    for (int w = 0; w < W; ++w) sc[w] = sc_n[w];
+                    code = code_n;
+                }
+            };
+            using T_ = BoolC<true>;
+            using F_ = BoolC<false>;
+            if (LOCAL) {
+                block_steps(F_{}, F_{});
+            } else if (ragged) {
+                if (free_left && b == 0)
+                    block_steps(T_{}, T_{});
+                else
+                    block_steps(T_{}, F_{});
+            } else {
+                if (free_left && b == 0)
+                    block_steps(F_{}, T_{});
+                else
+                    block_steps(F_{}, F_{});
             }
 
             // The previous block's border records (chunk b-2, columns

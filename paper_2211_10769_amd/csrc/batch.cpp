@@ -105,6 +105,7 @@ swh_status score_passes(swh_ctx *ctx, const std::vector<PairPass> &ps, const Sco
             gd.push_back(GatherDesc{p.q, qp, 0, p.n, qpad, p.step, (int32_t)p.lead});
             gd.push_back(GatherDesc{p.t, tp, 0, p.m, tpad, p.step, 0});
             StripProblem sp{qp, p.n + p.lead, tp, p.m, bp};
+            sp.prune = p.prune;
             if (p.keep) {
                 sp.save = p.keep;
                 sp.save_stride = tpad;
@@ -423,8 +424,10 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
         std::vector<PairPass> rp;
         rp.reserve(pos_pairs.size());
         int64_t rrecs = 0;
+        const bool prune = env_int("SWH_PRUNE", 1) != 0;
         for (int64_t i : pos_pairs) {
             PairPass p{ps[i].q + out[i].q_end, out[i].q_end + 1, ps[i].t + out[i].t_end, out[i].t_end + 1, -1};
+            p.prune = prune ? out[i].score : 0;   // the reverse maximum is the forward score
             BandKeep &k = bk[(size_t)i];
             if (k.every > 0) {
                 rrecs += band_reverse_layout(out[i].q_end, out[i].t_end, k);

@@ -21,6 +21,7 @@ struct PairPass {
     int64_t lead = 0;          // all-zero pad rows above row 0 (best rows count them)
     Border *keep = nullptr;    // kept rows (strips.h StripProblem), or NULL
     int32_t every = 0, phase = 0;
+    int32_t prune = 0;         // known maximum of a reverse pass (block pruning), or 0
 };
 // Score, end row and end column of every pass (launches grouped by strip
 // shape, most expensive first, chunked to bound device memory).

@@ -205,7 +205,9 @@ constexpr int kWgPerSimd = R <= 8 ? 4 : 2;
 
 // Each wave of a workgroup runs strips on its own (no barrier anywhere); the
 // workgroup only places waves evenly over the SIMDs of a CU.
-template <int R, bool LOCAL>
+// PRUNE (local passes with a known maximum: the reverse pass) is its own
+// instantiation, so the forward pass carries no pruning test at all.
+template <int R, bool LOCAL, bool PRUNE = false>
 __global__ void __launch_bounds__(256 * kWgPerSimd<R>) strip_kernel(StripArgs a)
 {
     extern __shared__ int prof_all[];
@@ -372,7 +374,42 @@ __global__ void __launch_bounds__(256 * kWgPerSimd<R>) strip_kernel(StripArgs a)
             };
             using T_ = BoolC<true>;
             using F_ = BoolC<false>;
-            if (LOCAL) {
+            // Block pruning (local passes whose maximum V is known): every
+            // value the block computes, and every value reachable through its
+            // cells, is at most max(0, largest input) + smax * min(rows, columns
+            // left from the block's first row and column).  Below V the block
+            // cannot hold or lead to a cell of value V, nor lie on a path to
+            // one, so it is skipped and its cells left at the floor (0): only
+            // cells below V can be underestimated, and every cell on an optimal
+            // path keeps its exact value.
+            bool pruned = false;
+            if (LOCAL && PRUNE && P.prune > 0) {
+                int hin = max(max(hup_prev, hbot), max(fbot, max(fh, ff)));
+#pragma unroll
+                for (int k = 0; k < R; ++k) hin = max(hin, max(hp[k], E[k]));
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) hin = max(hin, __shfl_xor(hin, off));
+                hin = __builtin_amdgcn_readfirstlane(hin);
+                const int64_t rows_left = (int64_t)P.n - (int64_t)s * 64 * R;
+                const int64_t cols_left = (int64_t)P.m - max(64 * b - 63, 0);
+                const int64_t bound = (int64_t)max(hin, 0) + (int64_t)max(a.smax, 0) * min(rows_left, cols_left);
+                pruned = bound < (int64_t)P.prune;
+            }
+            if (LOCAL && PRUNE && pruned) {
+                // the block's 64 steps at the floor: last-row outputs 0, state 0;
+                // lane 0's diagonal input of the next block is the chunk's last
+                // record (exact: it comes from the strip above)
+                const int last_h = __shfl(fh, 63);
+#pragma unroll
+                for (int k = 0; k < R; ++k) { hp[k] = 0; E[k] = 0; }
+                hbot = 0;
+                fbot = 0;
+                oh = 0;
+                of = 0;
+                hup_prev = lane == 0 ? last_h : 0;
+                code = __shfl(tfeed, 63 - lane);   // column 64 (b + 1) - lane
+                load_prof<W>(prof, A1, code, lane, sc);
+            } else if (LOCAL) {
                 block_steps(F_{}, F_{});
             } else if (ragged) {
                 if (free_left && b == 0)
@@ -541,9 +578,12 @@ int grid_for(int64_t work, int threads)
 }
 
 template <int R, bool LOCAL>
-hipError_t launch_strip_t(const StripArgs &a, const StripLaunch &l, hipStream_t st)
+hipError_t launch_strip_t(const StripArgs &a, const StripLaunch &l, hipStream_t st, bool prune)
 {
-    hipLaunchKernelGGL((strip_kernel<R, LOCAL>), dim3(l.nwg), dim3(64 * l.waves), l.lds, st, a);
+    if (LOCAL && prune)
+        hipLaunchKernelGGL((strip_kernel<R, true, true>), dim3(l.nwg), dim3(64 * l.waves), l.lds, st, a);
+    else
+        hipLaunchKernelGGL((strip_kernel<R, LOCAL>), dim3(l.nwg), dim3(64 * l.waves), l.lds, st, a);
     return hipGetLastError();
 }
 
@@ -644,14 +684,13 @@ bool strip_balanced_launch(int device, int R, bool local, int asize, int per_sim
     return false;
 }
 
-hipError_t launch_strip(const StripArgs &a, int R, bool local, const StripLaunch &grid, hipStream_t st)
+hipError_t launch_strip(const StripArgs &a, int R, bool local, const StripLaunch &grid, hipStream_t st, bool prune)
 {
-    if (R == 32) return local ? launch_strip_t<32, true>(a, grid, st) : launch_strip_t<32, false>(a, grid, st);
-    if (R == 24) return local ? launch_strip_t<24, true>(a, grid, st) : launch_strip_t<24, false>(a, grid, st);
-    if (R == 20) return local ? launch_strip_t<20, true>(a, grid, st) : launch_strip_t<20, false>(a, grid, st);
-    if (R == 16) return local ? launch_strip_t<16, true>(a, grid, st) : launch_strip_t<16, false>(a, grid, st);
-    if (R == 8) return local ? launch_strip_t<8, true>(a, grid, st) : launch_strip_t<8, false>(a, grid, st);
-    if (R == 4) return local ? launch_strip_t<4, true>(a, grid, st) : launch_strip_t<4, false>(a, grid, st);
+#define SWH_LAUNCH(RR)                                                                                      \
+    if (R == RR)                                                                                            \
+        return local ? launch_strip_t<RR, true>(a, grid, st, prune) : launch_strip_t<RR, false>(a, grid, st, false);
+    SWH_LAUNCH(32) SWH_LAUNCH(24) SWH_LAUNCH(20) SWH_LAUNCH(16) SWH_LAUNCH(8) SWH_LAUNCH(4)
+#undef SWH_LAUNCH
     return hipErrorInvalidValue;
 }
 

@@ -39,7 +39,8 @@ struct KeepRows {
 
 // One local score pass over encoded inputs already on the device.
 swh_status local_pass(swh_ctx *ctx, const uint8_t *qc, int64_t n, const uint8_t *tc, int64_t m,
-                      const Scoring &sc, StripShape shape, hipStream_t st, LocalPass &res, const KeepRows &kr = {})
+                      const Scoring &sc, StripShape shape, hipStream_t st, LocalPass &res, const KeepRows &kr = {},
+                      int32_t prune = 0)
 {
     const size_t bcount = (size_t)cols_padded(m);
     swh_status s;
@@ -48,6 +49,7 @@ swh_status local_pass(swh_ctx *ctx, const uint8_t *qc, int64_t n, const uint8_t 
     if ((e = hipMemsetAsync(ctx->border.p, 0, bcount * sizeof(Border), st)) != hipSuccess)
         return hip_fail(ctx, e, "hipMemsetAsync(border)");
     StripProblem sp{qc, n, tc, m, (Border *)ctx->border.p};
+    sp.prune = prune;
     if (kr.keep) {
         sp.save = kr.keep;
         sp.save_stride = (int64_t)bcount;
@@ -461,9 +463,11 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
             krev = KeepRows{(Border *)ctx->keep_r.p, bk.every, bk.phase};
         }
     }
+    // the reverse pass knows its maximum (the forward score): block pruning
+    const int32_t prune = env_int("SWH_PRUNE", 1) ? fwd.best.score : 0;
     LocalPass rev;
     if ((s = local_pass(ctx, (const uint8_t *)ctx->qr.p, rn + lead, (const uint8_t *)ctx->tr.p, rm, sc, rshape, st,
-                        rev, krev)) != SWH_OK)
+                        rev, krev, prune)) != SWH_OK)
         return s;
     if (stats) stats->ms_reverse = rev.ms;
     if (rev.best.score != fwd.best.score)

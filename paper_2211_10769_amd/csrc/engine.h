@@ -49,6 +49,11 @@ struct Problem {
     // global mode only: H = 0 left of column 0 (free leading row residues,
     // the overlap form) instead of the penalised boundary
     int32_t free_left;
+    // local mode only, > 0: the pass's maximum is known to be prune (a
+    // reverse pass); a block whose inputs cannot lead to that value is
+    // skipped, its cells left at the floor (block pruning, see the kernel)
+    int32_t prune;
+    int32_t pad_;
 };
 
 // Arguments of the strip-wavefront kernel (dp_strip.hip).
@@ -59,6 +64,7 @@ struct StripArgs {
     const int8_t *mat;           // asize x asize substitution scores
     int32_t asize;               // the pad code equals asize
     int32_t o, e;                // gap open, gap extend (> 0)
+    int32_t smax;                // largest substitution score (block pruning)
     int32_t *ticket;             // strip ticket, zero on entry
     int32_t *abort_flag;         // set when a bounded wait expires
     BestCell *strip_best;        // one entry per global strip (local mode)
@@ -83,7 +89,10 @@ struct StripLaunch {
 // waves the CU spreads over its four SIMDs, held to that count per CU by
 // their LDS request.  False when that placement cannot be made.
 bool strip_balanced_launch(int device, int R, bool local, int asize, int per_simd, int num_cu, StripLaunch &out);
-hipError_t launch_strip(const StripArgs &a, int R, bool local, const StripLaunch &grid, hipStream_t st);
+// prune: some problem of a local launch has Problem::prune set (the pruning
+// instantiation of the kernel runs)
+hipError_t launch_strip(const StripArgs &a, int R, bool local, const StripLaunch &grid, hipStream_t st,
+                        bool prune = false);
 hipError_t launch_reduce_best(const BestCell *in, int32_t count, BestCell *out, hipStream_t st);
 // Per problem: best cell over its strips (strip_best indexed by global strip).
 hipError_t launch_reduce_best_multi(const BestCell *strip_best, const Problem *probs, int32_t nprobs,

@@ -101,6 +101,7 @@ swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, cons
     tab.resize(np);
     sp.clear();
     int64_t total_strips = 0, total_flags = 0;
+    bool prune = false;
     for (int i = 0; i < np; ++i) {
         const StripProblem &q = probs[i];
         Problem &P = tab[i];
@@ -118,6 +119,9 @@ swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, cons
         P.save_stride = q.save_stride;
         P.save_phase = q.save_phase;
         P.free_left = q.free_left;
+        P.prune = local ? q.prune : 0;
+        P.pad_ = 0;
+        prune = prune || P.prune > 0;
         total_strips += P.nstrips;
         total_flags += P.nblocks + 3;
         if (np > 1)
@@ -154,6 +158,7 @@ swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, cons
     a.asize = sc.asize;
     a.o = sc.o;
     a.e = sc.e;
+    a.smax = sc.smax;
     a.ticket = (int32_t *)ctx->sync.p;
     a.abort_flag = (int32_t *)ctx->sync.p + 1;
     a.strip_best = (BestCell *)ctx->strip_best.p;
@@ -175,7 +180,8 @@ swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, cons
                            1, strip_lds_bytes(R, sc.asize)};
     }
     hipEventRecord(ctx->ev[0], st);
-    if ((e = launch_strip(a, R, local, grid, st)) != hipSuccess) return hip_fail(ctx, e, "strip kernel launch");
+    if ((e = launch_strip(a, R, local, grid, st, prune)) != hipSuccess)
+        return hip_fail(ctx, e, "strip kernel launch");
     hipEventRecord(ctx->ev[1], st);
     if (local && (e = launch_reduce_best_multi(a.strip_best, a.probs, np, (BestCell *)ctx->prob_best.p, st)) !=
                      hipSuccess)

@@ -39,15 +39,19 @@ int64_t band_forward_layout(int R, int every, int64_t n, int64_t m, BandKeep &k)
     return k.every ? k.kf * k.fstride : 0;
 }
 
-int64_t band_reverse_layout(int64_t q_end, int64_t t_end, BandKeep &k)
+int64_t band_reverse_layout(int64_t q_end, int64_t t_end, BandKeep &k, int rr)
 {
     if (k.every <= 0) return 0;
-    const int64_t H = 64 * (int64_t)k.R;
+    // kept rows every C forward rows; the reverse strips must end on them
+    const int64_t C = 64 * (int64_t)k.R * k.every;
+    k.Rr = (rr > 0 && C % (64 * (int64_t)rr) == 0) ? rr : k.R;
+    const int64_t H = 64 * (int64_t)k.Rr;
+    k.every_r = (int)(C / H);
     k.lead = (H - q_end % H) % H;
     k.T = (q_end + k.lead) / H;
-    k.phase = (int)((k.every - k.T % k.every) % k.every);
+    k.phase = (int)((k.every_r - k.T % k.every_r) % k.every_r);
     const int64_t nstrips = (q_end + 1 + k.lead + H - 1) / H;
-    k.kr = (nstrips + k.phase) / k.every;
+    k.kr = (nstrips + k.phase) / k.every_r;
     k.rstride = cols_padded(t_end + 1);
     return k.kr * k.rstride;
 }
@@ -61,9 +65,10 @@ void band_cuts(const BandKeep &k, const swh_alignment &al, int32_t S, const uint
     const int64_t k_lo = std::max<int64_t>(1, (qb + 1 + C - 1) / C), k_hi = qe / C;
     for (int64_t c = k_lo; c <= k_hi; ++c) {
         const int64_t x = c * C - 1;
-        const int64_t slot_r = (k.T + k.phase) / k.every - 1 - c;
-        // the reverse strip must exist (s' + 1 = T - c every >= 1)
-        if (x < qb || x + 1 > qe || c - 1 >= k.kf || slot_r < 0 || slot_r >= k.kr || c * k.every > k.T - 1) continue;
+        const int64_t slot_r = (k.T + k.phase) / k.every_r - 1 - c;
+        // the reverse strip must exist (s' + 1 = T - c every_r >= 1)
+        if (x < qb || x + 1 > qe || c - 1 >= k.kf || slot_r < 0 || slot_r >= k.kr || c * k.every_r > k.T - 1)
+            continue;
         cd.push_back(CutDesc{k.keep_f + (c - 1) * k.fstride, k.keep_r + slot_r * k.rstride, qcodes + x + 1, tcodes,
                              al.t_end, S, 0});
         rows.push_back(x);

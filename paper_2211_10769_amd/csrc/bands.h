@@ -25,13 +25,16 @@ struct BandKeep {
     int64_t kf = 0, fstride = 0;        // kept forward rows, records per row
     int64_t lead = 0, T = 0, kr = 0, rstride = 0;
     int phase = 0;
+    int Rr = 0, every_r = 0;            // reverse strip height and strips between its kept rows
     const Border *keep_f = nullptr, *keep_r = nullptr;
 };
 
 // Forward layout of an n x m pass; returns the records to keep (kf * fstride).
 int64_t band_forward_layout(int R, int every, int64_t n, int64_t m, BandKeep &k);
 // Reverse layout once the end cell is known; returns the records to keep.
-int64_t band_reverse_layout(int64_t q_end, int64_t t_end, BandKeep &k);
+// The reverse pass runs rows_per_lane rr when 64 rr divides the distance
+// between kept rows (else the forward height).
+int64_t band_reverse_layout(int64_t q_end, int64_t t_end, BandKeep &k, int rr = 0);
 
 // One CutDesc per kept row strictly inside the pair's rectangle (rows x with
 // q_begin <= x < q_end), with the cut row of each.  qcodes / tcodes: the

@@ -431,7 +431,7 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
             BandKeep &k = bk[(size_t)i];
             if (k.every > 0) {
                 rrecs += band_reverse_layout(out[i].q_end, out[i].t_end, k);
-                p.R = k.R;
+                p.R = k.Rr;
                 p.waves = ps[i].waves;
                 p.lead = k.lead;
             }
@@ -448,7 +448,7 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
                     if (k.every <= 0) continue;
                     k.keep_r = (const Border *)ctx->keep_r.p + off;
                     rp[j].keep = (Border *)ctx->keep_r.p + off;
-                    rp[j].every = k.every;
+                    rp[j].every = k.every_r;
                     rp[j].phase = k.phase;
                     off += k.kr * k.rstride;
                 }

@@ -436,14 +436,22 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
     if (mode == SWH_MODE_SCORE) return SWH_OK;
 
     // ---- reverse local pass on the prefixes ending at the end cell.  With kept
-    // rows it runs with the forward pass's strip height and `lead` pad rows on
-    // top (all-zero rows of the local DP, like the border) so that its strip
-    // boundaries fall on the rows the cuts need: reversed strip s' ends at row
-    // q_end - (s'+1) H + 1 + lead, which is x + 2 for the forward cut row x = k C - 1
-    // when (s'+1) = T - k every, T = (q_end + lead) / H.
+    // rows it runs with a strip height H that divides the distance C between the
+    // forward kept rows and `lead` pad rows on top (all-zero rows of the local
+    // DP, like the border) so that its strip boundaries fall on the rows the
+    // cuts need: reversed strip s' ends at row q_end - (s'+1) H + 1 + lead,
+    // which is x + 2 for the forward cut row x = k C - 1 when (s'+1) = T - k
+    // every_r, T = (q_end + lead) / H, every_r = C / H.
     const int64_t rn = out->q_end + 1, rm = out->t_end + 1;
-    const int64_t rrecs = band_reverse_layout(out->q_end, out->t_end, bk);
-    const StripShape rshape = bk.every > 0 ? shape : tuned_shape(ctx, rn);
+    // The reverse pass knows its maximum (the forward score) and is block
+    // pruned; what remains is bound by its diagonal dependency chain, whose
+    // steps are shortest at 8 rows per lane (long pair: 1.70 s against 2.41 s
+    // at 20).  With kept rows the reverse strips must still end on the cut rows.
+    const bool prune_rev = env_int("SWH_PRUNE", 1) != 0;
+    const int64_t rrecs = band_reverse_layout(out->q_end, out->t_end, bk, prune_rev ? 8 : shape.R);
+    const StripShape rshape = bk.every > 0 ? StripShape{bk.Rr, bk.Rr == shape.R ? shape.waves : 0}
+                              : (prune_rev && rn >= 512) ? StripShape{8, 0}
+                                                         : tuned_shape(ctx, rn);
     const int64_t lead = bk.every > 0 ? bk.lead : 0;
     const int64_t rqpad = rows_padded(rn + lead, rshape.R);
     const int64_t rtpad = cols_padded(rm);
@@ -460,11 +468,10 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
             ctx->err.clear();
         } else {
             bk.keep_r = (const Border *)ctx->keep_r.p;
-            krev = KeepRows{(Border *)ctx->keep_r.p, bk.every, bk.phase};
+            krev = KeepRows{(Border *)ctx->keep_r.p, bk.every_r, bk.phase};
         }
     }
-    // the reverse pass knows its maximum (the forward score): block pruning
-    const int32_t prune = env_int("SWH_PRUNE", 1) ? fwd.best.score : 0;
+    const int32_t prune = prune_rev ? fwd.best.score : 0;
     LocalPass rev;
     if ((s = local_pass(ctx, (const uint8_t *)ctx->qr.p, rn + lead, (const uint8_t *)ctx->tr.p, rm, sc, rshape, st,
                         rev, krev, prune)) != SWH_OK)

@@ -33,16 +33,15 @@ VALU_LANE_OPS = 256 * 64 * 2.4e9
 # Algorithmic integer operations per DP cell of the local pass:
 # add (diag + s), max3 (H), sub (H - o), sub + max3 (E), sub + max3 (F).
 OPS_PER_CELL = 7
-# HBM bytes per DP cell of the local strip kernel on the long pair, from two
-# rocprofv3 counter passes over one CIGAR step (forward launch 2.55e13 cells,
-# reverse launch 2.53e13, both keeping rows for the band traceback), each
-# scaled by the same counter on a 1 GiB plain copy (profiles/
-# strip_kernel_long_dna.md): FETCH_SIZE (96,075,669 + 95,050,279) KiB x 2.0 +
-# WRITE_SIZE (190,673,387 + 188,887,997) KiB x 1.0 = 780.1 GB over both.
-# Valid for the kernel those counters were taken on; the roofline's traffic
-# field is this figure times the cells of a launch.
-HBM_BYTES_PER_CELL = ((96_075_668.625 + 95_050_279.25) * 2.0 + 190_673_386.78125 + 188_887_996.59375) * 1024 / (
-    25_500_765_000_000 + 5_000_000 * 5_050_153)
+# HBM bytes per DP cell of the forward local strip kernel
+# (strip_kernel<20, true, false>) on the long pair, from two rocprofv3 counter
+# passes over one CIGAR step (forward launch 2.55e13 cells, keeping rows for the
+# band traceback), each scaled by the same counter on a 1 GiB plain copy
+# (profiles/strip_kernel_long_dna.md): FETCH_SIZE 96,351,829 KiB x 2.0 +
+# WRITE_SIZE 190,673,392 KiB x 1.0 = 392.6 GB per launch.  Valid for the kernel
+# those counters were taken on; the roofline's traffic field is this figure
+# times the cells of a launch.
+HBM_BYTES_PER_CELL = (96_351_828.75 * 2.0 + 190_673_392.09375) * 1024 / 25_500_765_000_000
 
 
 def log(msg: str):

@@ -39,3 +39,16 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.swh_alignment) == 40
     assert ctypes.sizeof(_lib.swh_scoring) == 32
     assert _lib.swh_alignment.q_begin.offset == 8
+
+
+def test_mode_constants_match_header():
+    # every #define of the header that the binding mirrors has the same value
+    from paper_2211_10769_amd import _lib
+    text = open(HEADER).read()
+    defs = {k: int(v, 0) for k, v in re.findall(r"#define\s+SWH_([A-Z_0-9]+)\s+(0x[0-9a-fA-F]+|\d+)\b", text)}
+    for name in ("GLOBAL", "SEMIGLOBAL", "OVERLAP"):
+        assert getattr(_lib, name) == defs[name], name
+    forms = [defs["GLOBAL"], defs["SEMIGLOBAL"], defs["OVERLAP"]]
+    # single bits, disjoint from each other and from the mode values
+    assert all(f & (f - 1) == 0 for f in forms) and len(set(forms)) == 3
+    assert all(f > 0xFF for f in forms)

@@ -70,7 +70,7 @@ void band_cuts(const BandKeep &k, const swh_alignment &al, int32_t S, const uint
         if (x < qb || x + 1 > qe || c - 1 >= k.kf || slot_r < 0 || slot_r >= k.kr || c * k.every_r > k.T - 1)
             continue;
         cd.push_back(CutDesc{k.keep_f + (c - 1) * k.fstride, k.keep_r + slot_r * k.rstride, qcodes + x + 1, tcodes,
-                             al.t_end, S, 0});
+                             al.t_end, S, k.global ? 1 : 0});
         rows.push_back(x);
     }
 }

@@ -26,6 +26,9 @@ struct BandKeep {
     int64_t lead = 0, T = 0, kr = 0, rstride = 0;
     int phase = 0;
     int Rr = 0, every_r = 0;            // reverse strip height and strips between its kept rows
+    // global passes: keep_f / keep_r point one record past the boundary
+    // column's record (DP column 0), which the cut scan reads at index -1
+    bool global = false;
     const Border *keep_f = nullptr, *keep_r = nullptr;
 };
 

@@ -172,11 +172,12 @@ __device__ __forceinline__ int prof_score(const int (&w)[W], int k)
 // One DP step for the lane's R rows at one column.
 //   dg   : H(row0-1, j-1)                f    : F handed down into row0 (in), out of row R-1 (out)
 //   hp[] : H(row, j-1) in, H(row, j) out E[]  : E(row, j) in (already the value for this column), E(row, j+1) out
-// PASS: rows with index >= nreal copy the row above (pass-through), so the
-// wave's last row reproduces the last real row (global mode, ragged strip).
+// PASS: rows with index < nlead or >= nreal copy the row above (pass-through),
+// so the wave's last row reproduces the last real row (global mode, ragged
+// strip) and real rows below leading pass-through rows see the top border.
 template <int R, bool LOCAL, bool PASS>
 __device__ __forceinline__ void dp_step(int (&hp)[R], int (&E)[R], const int (&sc)[R / 4], int dg, int hup,
-                                        int &f, int o, int e, int nreal)
+                                        int &f, int o, int e, int nreal, int nlead)
 {
     constexpr int B = LOCAL ? 0 : kNeg;
     int habove = hup;
@@ -188,7 +189,7 @@ __device__ __forceinline__ void dp_step(int (&hp)[R], int (&E)[R], const int (&s
         E[k] = max3i(E[k] - e, hop, B);
         dg = hp[k];
         if (PASS) {
-            const bool real = k < nreal;
+            const bool real = k >= nlead && k < nreal;
             h = real ? h : habove;
             fn = real ? fn : f;
             habove = h;
@@ -252,8 +253,9 @@ __global__ void __launch_bounds__(256 * kWgPerSimd<R>) strip_kernel(StripArgs a)
             if (t % P.save_every == 0) keep = P.save + (int64_t)(t / P.save_every - 1) * P.save_stride;
         }
         int nreal = (int)min<int64_t>(max<int64_t>(P.n - row0, 0), R);
+        const int nlead = LOCAL ? 0 : (int)min<int64_t>(max<int64_t>((int64_t)P.top_pass - row0, 0), R);
         const bool ragged = !LOCAL && __builtin_amdgcn_readfirstlane(
-                                          (int)((int64_t)(s + 1) * 64 * R > P.n));
+                                          (int)((int64_t)(s + 1) * 64 * R > P.n || (int64_t)s * 64 * R < P.top_pass));
 
         // free left border (global mode): H = 0 and E = -o entering column 0;
         // a lane's steps left of column 0 are reset to the same values below
@@ -341,7 +343,7 @@ __global__ void __launch_bounds__(256 * kWgPerSimd<R>) strip_kernel(StripArgs a)
                     fh = shl1(fh, fh);
                     ff = shl1(ff, ff);
 
-                    dp_step<R, LOCAL, PASS>(hp, E, sc, hup_prev, hup, f, o, e, nreal);
+                    dp_step<R, LOCAL, PASS>(hp, E, sc, hup_prev, hup, f, o, e, nreal, nlead);
                     if (FIX && u < lane) {
 #pragma unroll
                         for (int k = 0; k < R; ++k) { hp[k] = 0; E[k] = -o; }

@@ -105,13 +105,22 @@ swh_status put_cigar(swh_ctx *ctx, const std::string &cg, char *cigar, int64_t c
 // optional pad column, then count codes cc[cstart + k * cstep]; top row of
 // BorderInit kind `kind`; free_left: H = 0 left of the first column.  Leaves
 // the last row in ctx->bborder (entry k = column k, the pad column first).
+// Options of an edge pass: a fixed strip shape (R = 0: the rule), `lead`
+// pass-through rows above the rows (their strip boundaries then fall `lead`
+// rows lower), and kept rows.
+struct EdgeOpts {
+    StripShape shape{0, 0};
+    int64_t lead = 0;
+    KeepRows keep;
+};
+
 swh_status edge_pass(swh_ctx *ctx, const uint8_t *rc, int64_t n, int32_t rstep, const uint8_t *cc, int64_t cstart,
                      int64_t count, int32_t cstep, int32_t kind, bool pad_col, bool free_left, const Scoring &sc,
-                     hipStream_t st, double &ms)
+                     hipStream_t st, double &ms, const EdgeOpts &opt = {})
 {
-    const StripShape sh = tuned_shape(ctx, n);
+    const StripShape sh = opt.shape.R ? opt.shape : tuned_shape(ctx, n);
     const int64_t cols = count + (pad_col ? 1 : 0);
-    const int64_t qpad = rows_padded(n, sh.R), tpad = cols_padded(cols);
+    const int64_t qpad = rows_padded(n + opt.lead, sh.R), tpad = cols_padded(cols);
     swh_status s;
     if ((s = ensure(ctx, ctx->bq, (size_t)qpad + 256, "edge pass row codes")) != SWH_OK ||
         (s = ensure(ctx, ctx->bt, (size_t)tpad + 256, "edge pass column codes")) != SWH_OK ||
@@ -121,7 +130,7 @@ swh_status edge_pass(swh_ctx *ctx, const uint8_t *rc, int64_t n, int32_t rstep, 
         return s;
     uint8_t *qp = (uint8_t *)ctx->bq.p, *tp = (uint8_t *)ctx->bt.p;
     Border *bp = (Border *)ctx->bborder.p;
-    const GatherDesc gd[2] = {GatherDesc{rc, qp, rstep > 0 ? 0 : n - 1, n, qpad, rstep, 0},
+    const GatherDesc gd[2] = {GatherDesc{rc, qp, rstep > 0 ? 0 : n - 1, n, qpad, rstep, (int32_t)opt.lead},
                               GatherDesc{cc, tp, cstart, count, tpad, cstep, pad_col ? 1 : 0}};
     const BorderInit bi{bp, nullptr, cols, tpad, kind, 0, 0, 0};
     hipError_t e;
@@ -133,8 +142,15 @@ swh_status edge_pass(swh_ctx *ctx, const uint8_t *rc, int64_t n, int32_t rstep, 
         return hip_fail(ctx, e, "edge pass setup launch");
     // the host tables above are stack copies: finish the copies before returning
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(ctx, e, "edge pass setup");
-    StripProblem sp{qp, n, tp, cols, bp};
+    StripProblem sp{qp, n + opt.lead, tp, cols, bp};
     sp.free_left = free_left ? 1 : 0;
+    sp.top_pass = (int32_t)opt.lead;
+    if (opt.keep.keep) {
+        sp.save = opt.keep.keep;
+        sp.save_stride = tpad;
+        sp.save_every = opt.keep.every;
+        sp.save_phase = opt.keep.phase;
+    }
     std::vector<StripProblem> pr{sp};
     float t = 0.f;
     if ((s = run_strips(ctx, pr, sc, sh.R, false, st, nullptr, &t, sh.waves)) != SWH_OK) return s;
@@ -174,6 +190,90 @@ swh_status set_matrix(swh_ctx *ctx, const Scoring &sc, bool transposed, hipStrea
     if ((e = hipMemcpyAsync(ctx->mat.p, m, (size_t)A * A, hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
         return hip_fail(ctx, e, "substitution table");
+    return SWH_OK;
+}
+
+// Global alignment in CIGAR mode with band cuts (as for the local path): the
+// forward global pass keeps every `every`-th strip's last row, a global pass
+// over the reversed sequences from the corner keeps the matching rows (lead
+// pass-through rows put its strip ends on them), and the crossings found at
+// those rows cut the traceback into bands.  done = false (with S set when the
+// forward pass ran) when there is nothing to gain or no room for the rows.
+swh_status global_banded(swh_ctx *ctx, const uint8_t *qc, int64_t n, const uint8_t *tc, int64_t m, const Scoring &sc,
+                         hipStream_t st, int32_t &S, std::string &cg, TracebackStats &ts, double &ms_f, double &ms_r,
+                         int64_t &nbands, int64_t &retries, bool &done)
+{
+    done = false;
+    const StripShape shape = tuned_shape(ctx, n);
+    const int every = band_stride(ctx, n, m + 1, shape.R);
+    if (every <= 0) return SWH_OK;
+    BandKeep bk;
+    const int64_t frecs = band_forward_layout(shape.R, every, n, m + 1, bk);
+    if (bk.every <= 0) return SWH_OK;
+    if (ensure(ctx, ctx->keep_f, (size_t)frecs * sizeof(Border), "kept rows") != SWH_OK) {
+        ctx->err.clear();
+        return SWH_OK;
+    }
+    swh_status s;
+    hipError_t e;
+    EdgeOpts fo;
+    fo.shape = shape;
+    fo.keep = KeepRows{(Border *)ctx->keep_f.p, bk.every, 0};
+    if ((s = edge_pass(ctx, qc, n, 1, tc, 0, m, 1, 1, true, false, sc, st, ms_f, fo)) != SWH_OK) return s;
+    Border corner;
+    if ((e = hipMemcpyAsync(&corner, (const Border *)ctx->bborder.p + m, sizeof(Border), hipMemcpyDeviceToHost,
+                            st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(ctx, e, "global score");
+    S = corner.h;
+    const int64_t rrecs = band_reverse_layout(n - 1, m, bk, shape.R);
+    if (bk.kr < 1 || ensure(ctx, ctx->keep_r, (size_t)rrecs * sizeof(Border), "kept rows") != SWH_OK) {
+        ctx->err.clear();
+        return SWH_OK;
+    }
+    EdgeOpts ro;
+    ro.shape = StripShape{bk.Rr, bk.Rr == shape.R ? shape.waves : 0};
+    ro.lead = bk.lead;
+    ro.keep = KeepRows{(Border *)ctx->keep_r.p, bk.every_r, bk.phase};
+    if ((s = edge_pass(ctx, qc, n, -1, tc, m - 1, m, -1, 1, true, false, sc, st, ms_r, ro)) != SWH_OK) return s;
+    if ((e = hipMemcpyAsync(&corner, (const Border *)ctx->bborder.p + m, sizeof(Border), hipMemcpyDeviceToHost,
+                            st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(ctx, e, "global score");
+    if (corner.h != S)
+        return fail(ctx, SWH_E_DEVICE, "global reverse pass gives " + std::to_string(corner.h) +
+                                           ", the forward pass " + std::to_string(S));
+    // the records of both passes start with the boundary column (DP column 0)
+    bk.keep_f = (const Border *)ctx->keep_f.p + 1;
+    bk.keep_r = (const Border *)ctx->keep_r.p + 1;
+    bk.global = true;
+    swh_alignment al{};
+    al.score = S;
+    al.q_begin = 0;
+    al.q_end = n - 1;
+    al.t_begin = 0;
+    al.t_end = m - 1;
+    std::vector<CutDesc> cd;
+    std::vector<int64_t> rows;
+    std::vector<CutOut> co;
+    band_cuts(bk, al, S, qc, tc, cd, rows);
+    if ((s = resolve_cuts(ctx, sc, st, cd, co)) != SWH_OK) return s;
+    TbInput tin{qc, n, tc, m, S};
+    bands_from_cuts(co.data(), rows.data(), (int)co.size(), al, S, tin.bands);
+    std::vector<std::string> cgs;
+    s = traceback_batch(ctx, {tin}, sc, st, cgs, ts);
+    if (s != SWH_OK && ts.inconsistent && !tin.bands.empty()) {
+        // a band did not check out: the plain divide and conquer
+        ++retries;
+        ctx->err.clear();
+        tin.bands.clear();
+        ts = TracebackStats{};
+        s = traceback_batch(ctx, {tin}, sc, st, cgs, ts);
+    }
+    if (s != SWH_OK) return s;
+    nbands = retries ? 0 : (int64_t)tin.bands.size();
+    cg.swap(cgs[0]);
+    done = true;
     return SWH_OK;
 }
 
@@ -375,6 +475,33 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
         return put_cigar(ctx, cg, cigar, cigar_cap, cigar_len);
     }
 
+    if (global && mode == SWH_MODE_CIGAR && env_int("SWH_BAND_ROWS", 0) >= 0) {
+        std::string cg;
+        TracebackStats ts;
+        int32_t S = 0;
+        double ms_f = 0.0, ms_r = 0.0;
+        int64_t nbands = 0, retries = 0;
+        bool done = false;
+        const auto t0 = std::chrono::steady_clock::now();
+        if ((s = global_banded(ctx, (const uint8_t *)ctx->qc.p, qlen, (const uint8_t *)ctx->tc.p, tlen, sc, st, S, cg,
+                               ts, ms_f, ms_r, nbands, retries, done)) != SWH_OK)
+            return s;
+        if (done) {
+            out->score = S;
+            if (stats) {
+                stats->cells_forward = (double)qlen * (double)tlen;
+                stats->ms_forward = ms_f;
+                stats->ms_reverse = ms_r;
+                stats->ms_traceback =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() - ms_f -
+                    ms_r;
+                stats->cells_traceback = ts.cells;
+                stats->traceback_bands = nbands;
+                stats->traceback_retries = retries;
+            }
+            return put_cigar(ctx, cg, cigar, cigar_cap, cigar_len);
+        }
+    }
     if (global) {
         // ---- global alignment: the forward pass in global mode gives G(n, m),
         // the reconstruction is the divide and conquer over the whole matrix

@@ -53,7 +53,11 @@ struct Problem {
     // reverse pass); a block whose inputs cannot lead to that value is
     // skipped, its cells left at the floor (block pruning, see the kernel)
     int32_t prune;
-    int32_t pad_;
+    // global mode only: rows 0 .. top_pass-1 pass their input through (H and F
+    // of the row above unchanged), so the pass's real rows start below them
+    // with the top border as given (aligns strip boundaries, like the zero
+    // lead rows of a local pass)
+    int32_t top_pass;
 };
 
 // Arguments of the strip-wavefront kernel (dp_strip.hip).

@@ -120,7 +120,7 @@ swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, cons
         P.save_phase = q.save_phase;
         P.free_left = q.free_left;
         P.prune = local ? q.prune : 0;
-        P.pad_ = 0;
+        P.top_pass = local ? 0 : q.top_pass;
         prune = prune || P.prune > 0;
         total_strips += P.nstrips;
         total_flags += P.nblocks + 3;

@@ -27,6 +27,7 @@ struct StripProblem {
     int32_t save_phase = 0;
     int32_t free_left = 0;   // global mode: H = 0 left of column 0 (Problem)
     int32_t prune = 0;       // local mode: known maximum, enables block pruning (Problem)
+    int32_t top_pass = 0;    // global mode: pass-through rows on top (Problem)
 };
 
 inline int64_t rows_padded(int64_t n, int R) { return ((n + 64 * R - 1) / (64 * R)) * 64 * R; }

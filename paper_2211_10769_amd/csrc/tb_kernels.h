@@ -81,7 +81,9 @@ struct CutDesc {
     const uint8_t *tc;      // target codes, columns 0..te
     int64_t te;             // last column of the pair's rectangle
     int32_t S;              // the pair's optimum
-    int32_t pad_;
+    // global passes: fwd[-1] and rev[-1] are the records of the boundary
+    // column (DP column 0 of each pass) instead of the local floor
+    int32_t global;
 };
 
 // Resolved cut: clean = exactly one edge, and at a vertical edge the gap

@@ -183,12 +183,12 @@ __global__ void __launch_bounds__(256) cut_scan_kernel(const CutDesc *descs, con
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j <= te; j += stride) {
         // the rest of the path after a node in column j uses columns j+1 ..:
         // reverse record of column j+1 (none after the last column)
-        const Border rv = j < te ? d.rev[te - j - 1] : Border{0, kNeg};
+        const Border rv = (j < te || d.global) ? d.rev[te - j - 1] : Border{0, kNeg};
         if ((int64_t)d.fwd[j].f + rv.f + o == S) {
             ++count;
             key = min(key, (int)(j << 1) | 1);
         }
-        const int64_t hd = j >= 1 ? d.fwd[j - 1].h : 0;
+        const int64_t hd = (j >= 1 || d.global) ? d.fwd[j - 1].h : 0;
         if (hd + mrow[tc[j]] + rv.h == S) {
             ++count;
             key = min(key, (int)(j << 1));
@@ -223,7 +223,9 @@ __global__ void cut_resolve_kernel(const CutDesc *descs, int32_t nd, const int32
         const int j = r.key >> 1;
         if (r.key & 1) {
             const Border fw = d.fwd[j];
-            if (fw.h - o != fw.f) {
+            // (global: a vertical crossing in the last column is left
+            // unresolved; the path then runs down that column to the corner)
+            if (fw.h - o != fw.f && !(d.global && j == d.te)) {
                 r.clean = 1;
                 r.col = j;
                 r.state = 1;

@@ -113,3 +113,41 @@ def test_range_limit(eng):
     with pytest.raises(swh.SwhError) as ex:
         eng.align(b"A" * 2000, b"C" * 2000, sc, mode="score", alignment="global")
     assert ex.value.status == -4
+
+
+@pytest.mark.parametrize("band_rows", [512, 1024, 2560])
+def test_banded_traceback_matches_oracle(eng, monkeypatch, band_rows):
+    # kept rows of a forward and a corner-anchored reverse global pass cut the
+    # traceback into bands; the CIGAR must not change
+    monkeypatch.setenv("SWH_BAND_ROWS", str(band_rows))
+    rng = np.random.default_rng(band_rows)
+    sc = seqgen.dna_scoring()
+    a = seqgen.random_dna(rng, 6000)
+    cases = [(a, seqgen.mutate(rng, a, 0.05, 0.02)),
+             # long unaligned query ends: the path runs down column 0 and column m
+             (np.concatenate([seqgen.random_dna(rng, 1500), a[:3000], seqgen.random_dna(rng, 1200)]),
+              seqgen.mutate(rng, a[:3000], 0.03, 0.01)),
+             # long unaligned target ends: rows 0 and n carry long D runs
+             (a[:4000], np.concatenate([seqgen.random_dna(rng, 900), seqgen.mutate(rng, a[:4000], 0.03, 0.01),
+                                        seqgen.random_dna(rng, 700)]))]
+    for x, y in cases:
+        got = eng.align(bytes(x), bytes(y), sc, mode="cigar", alignment="global", stats=True)
+        assert {k: got[k] for k in KEYS} == _want(bytes(x), bytes(y), sc), (len(x), len(y))
+        assert got["stats"]["traceback_retries"] == 0
+    tie = ("AC", np.array([[1, -1], [-1, 1]], dtype=np.int8), 1, 1)
+    x = bytes(rng.choice(np.frombuffer(b"AC", np.uint8), 3000))
+    y = bytes(rng.choice(np.frombuffer(b"AC", np.uint8), 3100))
+    _cmp(eng, x, y, tie)
+
+
+def test_banded_equals_plain_at_300kbp(eng, monkeypatch):
+    rng = np.random.default_rng(21)
+    sc = seqgen.dna_scoring()
+    a = seqgen.random_dna(rng, 300_000)
+    b = seqgen.mutate(rng, a, 0.03, 0.01)
+    monkeypatch.setenv("SWH_BAND_ROWS", "-1")
+    plain = eng.align(bytes(a), bytes(b), sc, mode="cigar", alignment="global", stats=True)
+    monkeypatch.delenv("SWH_BAND_ROWS")
+    banded = eng.align(bytes(a), bytes(b), sc, mode="cigar", alignment="global", stats=True)
+    assert banded["stats"]["traceback_bands"] > 10 and banded["stats"]["traceback_retries"] == 0
+    assert {k: banded[k] for k in KEYS} == {k: plain[k] for k in KEYS}

@@ -93,7 +93,7 @@ enum { SWH_MODE_SCORE = 0,   /* score and end coordinates (forward pass only) */
 #define SWH_GLOBAL 0x100
 
 /*
- * OR'd into mode (swh_align, swh_align_dev; not swh_align_batch): the optimal
+ * OR'd into mode (swh_align, swh_align_dev, swh_align_batch): the optimal
  * SEMI-GLOBAL alignment -- the whole query against a part of the target, the
  * target residues before and after that part unpenalised, gaps at the ends
  * of the query penalised (paper, Background, "Semi-global algorithm (HW)").
@@ -108,7 +108,7 @@ enum { SWH_MODE_SCORE = 0,   /* score and end coordinates (forward pass only) */
 #define SWH_SEMIGLOBAL 0x200
 
 /*
- * OR'd into mode (swh_align, swh_align_dev; not swh_align_batch): the optimal
+ * OR'd into mode (swh_align, swh_align_dev, swh_align_batch): the optimal
  * OVERLAP alignment -- gaps before the first and after the last aligned
  * residue of either sequence cost nothing (paper, Background, "Overlap
  * algorithm (OV)").  DP with G(0, j) = G(i, 0) = 0; score = the maximum over

@@ -133,11 +133,13 @@ swh_status score_passes(swh_ctx *ctx, const std::vector<PairPass> &ps, const Sco
     return SWH_OK;
 }
 
-swh_status global_scores(swh_ctx *ctx, const std::vector<PairPass> &ps, const Scoring &sc, hipStream_t st,
-                         std::vector<int32_t> &scores, double &ms_total)
+swh_status edge_scores(swh_ctx *ctx, const std::vector<PairPass> &ps, int32_t kind, const std::vector<RowPick> &picks,
+                       const Scoring &sc, hipStream_t st, std::vector<uint64_t> &keys, double &ms_total, bool pad_col,
+                       bool free_left)
 {
+    const int64_t pc = pad_col ? 1 : 0;
     const size_t np = ps.size();
-    scores.assign(np, 0);
+    keys.assign(np, 0);
     std::vector<StripShape> sh(np);
     for (size_t i = 0; i < np; ++i) sh[i] = tuned_shape(ctx, ps[i].n);
     std::vector<size_t> order(np);
@@ -156,11 +158,11 @@ swh_status global_scores(swh_ctx *ctx, const std::vector<PairPass> &ps, const Sc
         int64_t bytes = 0, nq = 0, nt = 0;
         while (end < np && sh[order[end]].R == Rk && sh[order[end]].waves == sh[lead].waves) {
             const PairPass &p = ps[order[end]];
-            const int64_t b = rows_padded(p.n, Rk) + cols_padded(p.m + 1) * (1 + (int64_t)sizeof(Border));
+            const int64_t b = rows_padded(p.n, Rk) + cols_padded(p.m + pc) * (1 + (int64_t)sizeof(Border));
             if (bytes && bytes + b > kChunkBytes) break;
             bytes += b;
             nq += rows_padded(p.n, Rk);
-            nt += cols_padded(p.m + 1);
+            nt += cols_padded(p.m + pc);
             ++end;
         }
         const size_t nc = end - k;
@@ -168,24 +170,26 @@ swh_status global_scores(swh_ctx *ctx, const std::vector<PairPass> &ps, const Sc
         if ((s = ensure(ctx, ctx->bq, (size_t)nq + 256, "batch row codes")) != SWH_OK ||
             (s = ensure(ctx, ctx->bt, (size_t)nt + 256, "batch column codes")) != SWH_OK ||
             (s = ensure(ctx, ctx->bborder, sizeof(Border) * (size_t)nt + 256, "batch borders")) != SWH_OK ||
-            (s = ensure(ctx, ctx->gscores, sizeof(Border) * nc + 256, "global scores")) != SWH_OK)
+            (s = ensure(ctx, ctx->gscores, sizeof(uint64_t) * nc + 256, "row keys")) != SWH_OK)
             return s;
-        std::vector<GatherDesc> gd, ends;
+        std::vector<GatherDesc> gd;
         std::vector<BorderInit> bi;
         std::vector<StripProblem> probs;
+        std::vector<RowPickDesc> rd;
         uint8_t *qp = (uint8_t *)ctx->bq.p, *tp = (uint8_t *)ctx->bt.p;
         Border *bp = (Border *)ctx->bborder.p;
         for (size_t i = k; i < end; ++i) {
             const PairPass &p = ps[order[i]];
-            const int64_t qpad = rows_padded(p.n, Rk), tpad = cols_padded(p.m + 1);
-            gd.push_back(GatherDesc{p.q, qp, 0, p.n, qpad, 1, 0});
-            gd.push_back(GatherDesc{p.t, tp, 0, p.m, tpad, 1, 1});   // pad code first: column 0 is the border
-            bi.push_back(BorderInit{bp, nullptr, p.m + 1, tpad, 1, 0, 0, 0});
-            probs.push_back(StripProblem{qp, p.n, tp, p.m + 1, bp});
-            // G(n, m) is the last row's record of column m
-            ends.push_back(GatherDesc{reinterpret_cast<const uint8_t *>(bp + p.m), (uint8_t *)ctx->gscores.p +
-                                          sizeof(Border) * (i - k), 0, (int64_t)sizeof(Border),
-                                      (int64_t)sizeof(Border), 1, 0});
+            const RowPick &pk = picks[order[i]];
+            const int64_t qpad = rows_padded(p.n, Rk), tpad = cols_padded(p.m + pc);
+            gd.push_back(GatherDesc{p.q, qp, 0, p.n, qpad, p.step, 0});
+            // with a pad column first, column 0 is the border (DP column 0)
+            gd.push_back(GatherDesc{p.t, tp, 0, p.m, tpad, p.step, (int32_t)pc});
+            bi.push_back(BorderInit{bp, nullptr, p.m + pc, tpad, kind, 0, 0, 0});
+            StripProblem sp{qp, p.n, tp, p.m + pc, bp};
+            sp.free_left = free_left ? 1 : 0;
+            probs.push_back(sp);
+            rd.push_back(RowPickDesc{bp + pk.first, pk.count, pk.target, pk.mode});
             qp += qpad;
             tp += tpad;
             bp += tpad;
@@ -200,20 +204,48 @@ swh_status global_scores(swh_ctx *ctx, const std::vector<PairPass> &ps, const Sc
             return hip_fail(ctx, e, "border init launch");
         // the tables above are read by launches already queued on st before
         // the buffers are reused: synchronise before run_strips rewrites them
-        if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(ctx, e, "global setup");
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(ctx, e, "edge pass setup");
         float ms = 0.f;
         if ((s = run_strips(ctx, probs, sc, Rk, false, st, nullptr, &ms, sh[lead].waves)) != SWH_OK) return s;
         ms_total += ms;
-        if ((s = upload(ctx, ctx->tb_misc, ends, st, "end table")) != SWH_OK) return s;
-        std::vector<Border> res(nc);
-        if ((e = launch_gather((const GatherDesc *)ctx->tb_misc.p, (int32_t)ends.size(), pad, st)) != hipSuccess ||
-            (e = hipMemcpyAsync(res.data(), ctx->gscores.p, sizeof(Border) * nc, hipMemcpyDeviceToHost, st)) !=
+        if ((s = upload(ctx, ctx->tb_misc, rd, st, "row pick table")) != SWH_OK) return s;
+        std::vector<uint64_t> res(nc);
+        if ((e = launch_row_pick_multi((const RowPickDesc *)ctx->tb_misc.p, (int32_t)rd.size(),
+                                       (uint64_t *)ctx->gscores.p, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(res.data(), ctx->gscores.p, sizeof(uint64_t) * nc, hipMemcpyDeviceToHost, st)) !=
                 hipSuccess ||
             (e = hipStreamSynchronize(st)) != hipSuccess)
-            return hip_fail(ctx, e, "global scores");
-        for (size_t i = k; i < end; ++i) scores[order[i]] = res[i - k].h;
+            return hip_fail(ctx, e, "row pick");
+        for (size_t i = k; i < end; ++i) keys[order[i]] = res[i - k];
         k = end;
     }
+    return SWH_OK;
+}
+
+swh_status set_matrix(swh_ctx *ctx, const Scoring &sc, bool transposed, hipStream_t st)
+{
+    int8_t m[32 * 32];
+    const int A = sc.asize;
+    for (int x = 0; x < A; ++x)
+        for (int y = 0; y < A; ++y) m[x * A + y] = transposed ? sc.mat[y * A + x] : sc.mat[x * A + y];
+    hipError_t e;
+    if ((e = hipMemcpyAsync(ctx->mat.p, m, (size_t)A * A, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(ctx, e, "substitution table");
+    return SWH_OK;
+}
+
+swh_status global_scores(swh_ctx *ctx, const std::vector<PairPass> &ps, const Scoring &sc, hipStream_t st,
+                         std::vector<int32_t> &scores, double &ms_total)
+{
+    // G(n, m) is the last row's record of column m: a pick over that entry alone
+    std::vector<RowPick> picks(ps.size());
+    for (size_t i = 0; i < ps.size(); ++i) picks[i] = RowPick{ps[i].m, 1, 0, 0};
+    std::vector<uint64_t> keys;
+    swh_status s = edge_scores(ctx, ps, 1, picks, sc, st, keys, ms_total);
+    if (s != SWH_OK) return s;
+    scores.resize(ps.size());
+    for (size_t i = 0; i < ps.size(); ++i) scores[i] = row_key_value(keys[i]);
     return SWH_OK;
 }
 
@@ -227,7 +259,9 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
         stats->struct_size = size;
     }
     const bool global = (mode & SWH_GLOBAL) != 0;
-    mode &= ~SWH_GLOBAL;
+    const bool semi = (mode & SWH_SEMIGLOBAL) != 0;
+    const bool overlap = (mode & SWH_OVERLAP) != 0;
+    mode &= ~(SWH_GLOBAL | SWH_SEMIGLOBAL | SWH_OVERLAP);
     for (int64_t i = 0; i < npairs; ++i) {
         out[i].score = 0;
         out[i].flags = SWH_F_NONE;
@@ -295,7 +329,174 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
     }
     if (stats) stats->cells_forward = cells;
     std::vector<std::string> cig((size_t)npairs);
-    if (global) {
+    if (overlap) {
+        // ---- overlap alignments (end gaps of both sequences free): the last
+        // row of A x B and, from the swapped passes (transposed table), the
+        // last column; the reversed corner-anchored passes give the start; then
+        // the divide and conquer between start and end
+        std::vector<PairPass> fr, fc;
+        std::vector<RowPick> prow, pcol;
+        std::vector<int64_t> fi;
+        for (int64_t i = 0; i < npairs; ++i) {
+            const int64_t n = ps[i].n, m = ps[i].m;
+            if (n == 0 || m == 0) continue;   // only the empty overlap
+            fr.push_back(ps[i]);
+            prow.push_back(RowPick{0, m, 0, 0});                  // G(n, 1..m)
+            fc.push_back(PairPass{ps[i].t, m, ps[i].q, n, 1});
+            pcol.push_back(RowPick{0, n - 1, 0, 0});              // G(1..n-1, m)
+            fi.push_back(i);
+        }
+        std::vector<uint64_t> krow, kcol;
+        double ms_f = 0.0, ms_r = 0.0;
+        if ((s = edge_scores(ctx, fr, 4, prow, sc, st, krow, ms_f, false, true)) != SWH_OK ||
+            (s = set_matrix(ctx, sc, true, st)) != SWH_OK ||
+            (s = edge_scores(ctx, fc, 4, pcol, sc, st, kcol, ms_f, false, true)) != SWH_OK ||
+            (s = set_matrix(ctx, sc, false, st)) != SWH_OK)
+            return s;
+        std::vector<PairPass> rr, rc;
+        std::vector<RowPick> prr, prc;
+        std::vector<int64_t> ri;
+        for (size_t j = 0; j < fi.size(); ++j) {
+            const int64_t i = fi[j], n = ps[i].n, m = ps[i].m;
+            const int32_t srow = row_key_value(krow[j]);
+            const int32_t scol = n > 1 ? row_key_value(kcol[j]) : INT32_MIN;
+            const int32_t S = std::max(0, std::max(srow, scol));
+            out[i].score = S;
+            if (S == 0) continue;
+            const int64_t ie = scol == S ? row_key_index(kcol[j]) + 1 : n;
+            const int64_t je = scol == S ? m : row_key_index(krow[j]) + 1;
+            if (ie < 1 || ie > n || je < 1 || je > m) return fail(ctx, SWH_E_DEVICE, "overlap end cell out of range");
+            out[i].q_end = ie - 1;
+            out[i].t_end = je - 1;
+            rr.push_back(PairPass{ps[i].t + je - 1, je, ps[i].q + ie - 1, ie, -1});   // swapped: G'(1..ie-1, je)
+            prr.push_back(RowPick{0, ie, S, 1});
+            rc.push_back(PairPass{ps[i].q + ie - 1, ie, ps[i].t + je - 1, je, -1});   // G'(ie, 1..je)
+            prc.push_back(RowPick{0, je + 1, S, 1});
+            ri.push_back(i);
+        }
+        if (stats) stats->ms_forward = ms_f;
+        if (mode == SWH_MODE_SCORE) return SWH_OK;
+        if ((s = set_matrix(ctx, sc, true, st)) != SWH_OK ||
+            (s = edge_scores(ctx, rr, 1, prr, sc, st, krow, ms_r)) != SWH_OK ||
+            (s = set_matrix(ctx, sc, false, st)) != SWH_OK ||
+            (s = edge_scores(ctx, rc, 1, prc, sc, st, kcol, ms_r)) != SWH_OK)
+            return s;
+        for (size_t k = 0; k < ri.size(); ++k) {
+            const int64_t i = ri[k], ie = out[i].q_end + 1, je = out[i].t_end + 1;
+            if (krow[k] >= 1 && krow[k] < (uint64_t)ie) {
+                out[i].q_begin = ie - (int64_t)krow[k];
+                out[i].t_begin = 0;
+            } else if (kcol[k] >= 1 && kcol[k] <= (uint64_t)je) {
+                out[i].q_begin = 0;
+                out[i].t_begin = je - (int64_t)kcol[k];
+            } else {
+                return fail(ctx, SWH_E_DEVICE, "overlap backward passes of pair " + std::to_string(i) +
+                                                   " do not reach its score");
+            }
+        }
+        if (stats) stats->ms_reverse = ms_r;
+        if (mode != SWH_MODE_CIGAR) return SWH_OK;
+        TracebackStats ts;
+        size_t k = 0;
+        while (k < ri.size()) {
+            std::vector<TbInput> in;
+            std::vector<int64_t> ids;
+            int64_t cols = 0;
+            while (k < ri.size()) {
+                const int64_t i = ri[k], w = out[i].t_end - out[i].t_begin + 1;
+                if (!in.empty() && cols + w > kTracebackCols) break;
+                in.push_back(TbInput{ps[i].q + out[i].q_begin, out[i].q_end - out[i].q_begin + 1,
+                                     ps[i].t + out[i].t_begin, w, out[i].score});
+                ids.push_back(i);
+                cols += w;
+                ++k;
+            }
+            std::vector<std::string> cg;
+            if ((s = traceback_batch(ctx, in, sc, st, cg, ts)) != SWH_OK) return s;
+            for (size_t j = 0; j < ids.size(); ++j) cig[ids[j]].swap(cg[j]);
+        }
+        if (stats) {
+            stats->ms_traceback = ts.ms;
+            stats->cells_traceback = ts.cells;
+        }
+    } else if (semi) {
+        // ---- semi-global alignments (whole query, free target ends): forward
+        // passes from the free top border, the row pick gives the score and the
+        // smallest end column; reverse passes from the end give the largest
+        // start; then the divide and conquer over each read's rectangle
+        std::vector<PairPass> fp;
+        std::vector<RowPick> fpk;
+        std::vector<int64_t> fi;
+        for (int64_t i = 0; i < npairs; ++i) {
+            const int64_t n = ps[i].n, m = ps[i].m;
+            if (n == 0) continue;   // no query: score 0, no alignment
+            out[i].q_begin = 0;
+            out[i].q_end = n - 1;
+            if (m == 0) {
+                out[i].score = -(int32_t)(sc.o + (n - 1) * (int64_t)sc.e);
+                cig[i] = std::to_string(n) + "I";
+                continue;
+            }
+            fp.push_back(ps[i]);
+            fpk.push_back(RowPick{0, m + 1, 0, 0});
+            fi.push_back(i);
+        }
+        std::vector<uint64_t> keys;
+        double ms_f = 0.0, ms_r = 0.0;
+        if ((s = edge_scores(ctx, fp, 4, fpk, sc, st, keys, ms_f)) != SWH_OK) return s;
+        std::vector<PairPass> rp;
+        std::vector<RowPick> rpk;
+        std::vector<int64_t> ri;
+        for (size_t j = 0; j < fi.size(); ++j) {
+            const int64_t i = fi[j], n = ps[i].n;
+            const int32_t S = row_key_value(keys[j]);
+            const int64_t je = row_key_index(keys[j]);
+            if (je < 0 || je > ps[i].m) return fail(ctx, SWH_E_DEVICE, "semi-global end column out of range");
+            out[i].score = S;
+            if (je == 0) {
+                cig[i] = std::to_string(n) + "I";
+                continue;
+            }
+            out[i].t_end = je - 1;
+            rp.push_back(PairPass{ps[i].q + n - 1, n, ps[i].t + je - 1, je, -1});
+            rpk.push_back(RowPick{0, je + 1, S, 1});
+            ri.push_back(i);
+        }
+        if (stats) stats->ms_forward = ms_f;
+        if (mode == SWH_MODE_SCORE) return SWH_OK;
+        if ((s = edge_scores(ctx, rp, 1, rpk, sc, st, keys, ms_r)) != SWH_OK) return s;
+        for (size_t k = 0; k < ri.size(); ++k) {
+            const int64_t i = ri[k], je = out[i].t_end + 1;
+            if (keys[k] < 1 || keys[k] > (uint64_t)je)
+                return fail(ctx, SWH_E_DEVICE, "semi-global backward pass of pair " + std::to_string(i) +
+                                                   " does not reach its score");
+            out[i].t_begin = je - (int64_t)keys[k];
+        }
+        if (stats) stats->ms_reverse = ms_r;
+        if (mode != SWH_MODE_CIGAR) return SWH_OK;
+        TracebackStats ts;
+        size_t k = 0;
+        while (k < ri.size()) {
+            std::vector<TbInput> in;
+            std::vector<int64_t> ids;
+            int64_t cols = 0;
+            while (k < ri.size()) {
+                const int64_t i = ri[k], w = out[i].t_end - out[i].t_begin + 1;
+                if (!in.empty() && cols + w > kTracebackCols) break;
+                in.push_back(TbInput{ps[i].q, ps[i].n, ps[i].t + out[i].t_begin, w, out[i].score});
+                ids.push_back(i);
+                cols += w;
+                ++k;
+            }
+            std::vector<std::string> cg;
+            if ((s = traceback_batch(ctx, in, sc, st, cg, ts)) != SWH_OK) return s;
+            for (size_t j = 0; j < ids.size(); ++j) cig[ids[j]].swap(cg[j]);
+        }
+        if (stats) {
+            stats->ms_traceback = ts.ms;
+            stats->cells_traceback = ts.cells;
+        }
+    } else if (global) {
         // ---- global alignments: G(n, m) per pair, then the plain divide and
         // conquer over each whole matrix (an empty side: a single gap)
         std::vector<PairPass> gp;

@@ -28,6 +28,27 @@ struct PairPass {
 swh_status score_passes(swh_ctx *ctx, const std::vector<PairPass> &ps, const Scoring &sc, hipStream_t st,
                         std::vector<BestCell> &best, double &ms_total);
 
+// Part of a pass's last row to reduce with the row-pick key (tb_kernels.h):
+// entries first .. first+count-1 of the row (entry 0 = the pad column).
+struct RowPick {
+    int64_t first = 0, count = 0;
+    int32_t target = 0, mode = 0;
+};
+inline int32_t row_key_value(uint64_t key) { return (int32_t)((uint32_t)(key >> 32) - (1u << 30)); }
+inline int64_t row_key_index(uint64_t key) { return (int64_t)(0xFFFFFFFFu - (uint32_t)key); }
+
+// Global-mode passes over [pad] + t, or t alone (both sequences read with the
+// pass's step, n, m > 0) from a top border of BorderInit kind `kind`, with the
+// free left border when free_left; keys[i] = the row pick of pass i's last
+// row.  The device substitution table is used as it stands.
+swh_status edge_scores(swh_ctx *ctx, const std::vector<PairPass> &ps, int32_t kind, const std::vector<RowPick> &picks,
+                       const Scoring &sc, hipStream_t st, std::vector<uint64_t> &keys, double &ms_total,
+                       bool pad_col = true, bool free_left = false);
+
+// Upload the substitution table to the device, as given or transposed (passes
+// that run the target down the rows score s(b, a)).
+swh_status set_matrix(swh_ctx *ctx, const Scoring &sc, bool transposed, hipStream_t st);
+
 // Global alignment scores G(n, m) of every pass (n, m > 0; step must be 1):
 // the strip kernel in global mode over A against [pad] + B from the global
 // top border G(0, j) = -(o + (j-1) e), G(0, 0) = 0.

@@ -214,11 +214,12 @@ swh_status swh_align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, cons
     if (s != SWH_OK) return s;
     if (npairs < 0) return fail(ctx, SWH_E_INVAL, "npairs is negative");
     if (npairs > 0 && (!q_off || !t_off || !out)) return fail(ctx, SWH_E_INVAL, "offsets or out is NULL");
-    if (mode & (SWH_SEMIGLOBAL | SWH_OVERLAP))
-        return fail(ctx, SWH_E_INVAL, "SWH_SEMIGLOBAL and SWH_OVERLAP are not available in batches");
-    if (((mode & ~SWH_GLOBAL) < SWH_MODE_SCORE || (mode & ~SWH_GLOBAL) > SWH_MODE_CIGAR))
-        return fail(ctx, SWH_E_INVAL, "unknown mode");
-    if ((mode & ~SWH_GLOBAL) == SWH_MODE_CIGAR && !cigar_off) return fail(ctx, SWH_E_INVAL, "cigar_off is NULL");
+    const int forms = mode & (SWH_GLOBAL | SWH_SEMIGLOBAL | SWH_OVERLAP);
+    if (forms & (forms - 1))
+        return fail(ctx, SWH_E_INVAL, "SWH_GLOBAL, SWH_SEMIGLOBAL and SWH_OVERLAP exclude each other");
+    const int base = mode & ~(SWH_GLOBAL | SWH_SEMIGLOBAL | SWH_OVERLAP);
+    if (base < SWH_MODE_SCORE || base > SWH_MODE_CIGAR) return fail(ctx, SWH_E_INVAL, "unknown mode");
+    if (base == SWH_MODE_CIGAR && !cigar_off) return fail(ctx, SWH_E_INVAL, "cigar_off is NULL");
     if (stats && stats->struct_size < sizeof(swh_stats)) return fail(ctx, SWH_E_INVAL, "stats->struct_size too small");
     if (npairs >= ((int64_t)1 << 31)) return fail(ctx, SWH_E_RANGE, "more than 2^31 - 1 pairs");
     for (int64_t i = 0; i < npairs; ++i) {

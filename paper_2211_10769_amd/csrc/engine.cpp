@@ -178,20 +178,6 @@ swh_status pick_row(swh_ctx *ctx, int64_t entries, int32_t target, int32_t mode,
 inline int32_t key_value(uint64_t key) { return (int32_t)((uint32_t)(key >> 32) - (1u << 30)); }
 inline int64_t key_index(uint64_t key) { return (int64_t)(0xFFFFFFFFu - (uint32_t)key); }
 
-// The device substitution table, as given or transposed (passes that run the
-// target down the rows score s(b, a) with the table's rows and columns swapped).
-swh_status set_matrix(swh_ctx *ctx, const Scoring &sc, bool transposed, hipStream_t st)
-{
-    int8_t m[32 * 32];
-    const int A = sc.asize;
-    for (int x = 0; x < A; ++x)
-        for (int y = 0; y < A; ++y) m[x * A + y] = transposed ? sc.mat[y * A + x] : sc.mat[x * A + y];
-    hipError_t e;
-    if ((e = hipMemcpyAsync(ctx->mat.p, m, (size_t)A * A, hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (e = hipStreamSynchronize(st)) != hipSuccess)
-        return hip_fail(ctx, e, "substitution table");
-    return SWH_OK;
-}
 
 // Global alignment in CIGAR mode with band cuts (as for the local path): the
 // forward global pass keeps every `every`-th strip's last row, a global pass

@@ -143,6 +143,17 @@ struct LeafOut {
 hipError_t launch_row_pick(const Border *row, int64_t count, int32_t target, int32_t mode, uint64_t *out,
                            hipStream_t st);
 
+// The same reduction for many rows at once, one workgroup per row: out[k] =
+// the key of descriptor k (mode 0: 0 when count is 0; mode 1: all ones when
+// no entry matches).
+struct RowPickDesc {
+    const Border *row;
+    int64_t count;
+    int32_t target;
+    int32_t mode;
+};
+hipError_t launch_row_pick_multi(const RowPickDesc *d, int32_t nd, uint64_t *out, hipStream_t st);
+
 // Synthetic codes (timing runs of the autotuner): n codes in [0, asize), pad code up to padded.
 hipError_t launch_random_codes(uint8_t *dst, int64_t n, int64_t padded, int32_t asize, uint64_t seed, hipStream_t st);
 hipError_t launch_gather(const GatherDesc *d, int32_t nd, uint8_t pad, hipStream_t st);

@@ -93,6 +93,32 @@ __global__ void __launch_bounds__(256) row_pick_kernel(const Border *row, int64_
         atomicMin(out, best);
 }
 
+__global__ void __launch_bounds__(256) row_pick_multi_kernel(const RowPickDesc *descs, unsigned long long *out)
+{
+    __shared__ unsigned long long s_best;
+    const RowPickDesc d = descs[blockIdx.x];
+    const unsigned long long init = d.mode == 0 ? 0ull : ~0ull;
+    if (threadIdx.x == 0) s_best = init;
+    __syncthreads();
+    unsigned long long best = init;
+    for (int64_t j = threadIdx.x; j < d.count; j += blockDim.x) {
+        const int32_t h = d.row[j].h;
+        if (d.mode == 0) {
+            const unsigned long long key = ((unsigned long long)(uint32_t)(h + (1 << 30)) << 32) |
+                                           (unsigned long long)(0xFFFFFFFFu - (uint32_t)j);
+            best = key > best ? key : best;
+        } else if (j >= 1 && h == d.target) {
+            best = (unsigned long long)j < best ? (unsigned long long)j : best;
+        }
+    }
+    if (d.mode == 0)
+        atomicMax(&s_best, best);
+    else
+        atomicMin(&s_best, best);
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = s_best;
+}
+
 // A path from the frontier to the end crosses from mid row r into row r+1
 // through exactly one edge: vertical into F(r+1, j) (forward value D(j),
 // backward value from F(r+1, j) = D'+o) or diagonal G(r, j-1) -> G(r+1, j).
@@ -502,6 +528,14 @@ hipError_t launch_row_pick(const Border *row, int64_t count, int32_t target, int
     if (count <= 0) return hipSuccess;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((count + 255) / 256, 1024));
     hipLaunchKernelGGL(row_pick_kernel, dim3((unsigned)blocks), dim3(256), 0, st, row, count, target, mode,
+                       reinterpret_cast<unsigned long long *>(out));
+    return hipGetLastError();
+}
+
+hipError_t launch_row_pick_multi(const RowPickDesc *d, int32_t nd, uint64_t *out, hipStream_t st)
+{
+    if (nd <= 0) return hipSuccess;
+    hipLaunchKernelGGL(row_pick_multi_kernel, dim3((unsigned)nd), dim3(256), 0, st, d,
                        reinterpret_cast<unsigned long long *>(out));
     return hipGetLastError();
 }

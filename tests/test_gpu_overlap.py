@@ -124,18 +124,49 @@ def test_large_dovetail_rescores(eng):
     assert {k: part[k] for k in KEYS} == want
 
 
-def test_batch_rejects_and_exclusive_flags(eng):
+def test_batch_matches_oracle(eng):
+    sc = seqgen.dna_scoring()
+    rng = np.random.default_rng(99)
+    qs, ts = [b"", b"ACGT", b"", b"AAAA", b"C"], [b"GG", b"", b"", b"CCCC", b"ACGTC"]
+    for _ in range(30):
+        n, m = (int(x) for x in rng.integers(100, 3000, size=2))
+        k = int(rng.integers(50, min(n, m)))
+        a, b = _dovetail(rng, n, m, k)
+        if rng.random() < 0.5:
+            a, b = b, a
+        qs.append(a)
+        ts.append(b)
+    core = seqgen.random_dna(rng, 800)
+    qs.append(bytes(core))
+    ts.append(bytes(np.concatenate([seqgen.random_dna(rng, 300), seqgen.mutate(rng, core, 0.03, 0.01),
+                                    seqgen.random_dna(rng, 200)])))
+    want = [oracle.ov_align(a, b, sc) for a, b in zip(qs, ts)]
+    got = eng.align_batch(qs, ts, sc, mode="cigar", alignment="overlap")
+    assert [{k: g[k] for k in KEYS} for g in got] == want
+    for mode, keys in (("score", ["score", "q_end", "t_end"]),
+                       ("coords", ["score", "q_begin", "q_end", "t_begin", "t_end"])):
+        got = eng.align_batch(qs, ts, sc, mode=mode, alignment="overlap")
+        assert [{k: g[k] for k in keys} for g in got] == [{k: w[k] for k in keys} for w in want], mode
+    # an asymmetric table through the swapped passes of a batch
+    asym = ("ACG", np.array([[3, -4, 1], [-1, 2, -5], [-3, 0, 4]], dtype=np.int8), 4, 1)
+    xs = [bytes(rng.choice(np.frombuffer(b"ACG", np.uint8), int(L))) for L in rng.integers(30, 900, size=12)]
+    ys = [bytes(rng.choice(np.frombuffer(b"ACG", np.uint8), int(L))) for L in rng.integers(30, 900, size=12)]
+    got = eng.align_batch(xs, ys, asym, mode="cigar", alignment="overlap")
+    assert [{k: g[k] for k in KEYS} for g in got] == [oracle.ov_align(x, y, asym) for x, y in zip(xs, ys)]
+
+
+def test_exclusive_flags(eng):
     import paper_2211_10769_amd as swh
     from paper_2211_10769_amd import _lib
     sc = seqgen.dna_scoring()
-    with pytest.raises(swh.SwhError) as ex:
-        eng.align_batch([b"ACGT"], [b"ACGT"], sc, mode="score", alignment="overlap")
-    assert ex.value.status == -1
     saved = dict(swh._ALIGNMENTS)
     try:
         swh._ALIGNMENTS["both"] = _lib.OVERLAP | _lib.GLOBAL
         with pytest.raises(swh.SwhError) as ex:
             eng.align(b"ACGT", b"ACGT", sc, mode="score", alignment="both")
+        assert ex.value.status == -1
+        with pytest.raises(swh.SwhError) as ex:
+            eng.align_batch([b"ACGT"], [b"ACGT"], sc, mode="score", alignment="both")
         assert ex.value.status == -1
     finally:
         swh._ALIGNMENTS.clear()

@@ -109,9 +109,28 @@ def test_large_read_rescores(eng):
     assert {k: part[k] for k in KEYS} == want
 
 
-def test_batch_rejects(eng):
-    import paper_2211_10769_amd as swh
+def test_batch_matches_oracle(eng):
+    # reads against reference windows (workload-4 shape), plus empty sides and
+    # reads that align to no target residue
     sc = seqgen.dna_scoring()
-    with pytest.raises(swh.SwhError) as ex:
-        eng.align_batch([b"ACGT"], [b"ACGT"], sc, mode="score", alignment="semiglobal")
-    assert ex.value.status == -1
+    rng = seqgen.rng_for(4, 55)
+    qs, ts = [b"", b"ACGT", b"", b"AAAA"], [b"GG", b"", b"", b"CCCCCC"]
+    for L in np.rint(np.exp(rng.uniform(np.log(150), np.log(4000), size=40))).astype(int):
+        a = seqgen.random_dna(rng, int(L))
+        div = rng.uniform(0.01, 0.15)
+        pad = int(0.1 * L) + 1
+        qs.append(bytes(a))
+        ts.append(bytes(np.concatenate([seqgen.random_dna(rng, pad), seqgen.mutate(rng, a, 0.8 * div, 0.2 * div),
+                                        seqgen.random_dna(rng, pad)])))
+    qs.append(bytes(seqgen.random_dna(rng, 300)))
+    ts.append(bytes(seqgen.random_dna(rng, 5000)))
+    hard = ("AC", np.array([[1, -30], [-30, 1]], dtype=np.int8), 2, 1)
+    want = [oracle.hw_align(a, b, sc) for a, b in zip(qs, ts)]
+    got = eng.align_batch(qs, ts, sc, mode="cigar", alignment="semiglobal")
+    assert [{k: g[k] for k in KEYS} for g in got] == want
+    for mode, keys in (("score", ["score", "t_end"]), ("coords", ["score", "q_begin", "q_end", "t_begin", "t_end"])):
+        got = eng.align_batch(qs, ts, sc, mode=mode, alignment="semiglobal")
+        assert [{k: g[k] for k in keys} for g in got] == [{k: w[k] for k in keys} for w in want], mode
+    got = eng.align_batch([b"AAAA", b"ACAC"], [b"CCCCCC", b"CACA"], hard, mode="cigar", alignment="semiglobal")
+    assert [{k: g[k] for k in KEYS} for g in got] == [oracle.hw_align(b"AAAA", b"CCCCCC", hard),
+                                                     oracle.hw_align(b"ACAC", b"CACA", hard)]

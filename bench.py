@@ -57,7 +57,7 @@ def parse():
     p.add_argument("--n", type=int, default=5_000_000, help="query length of the long pair")
     p.add_argument("--flank", type=int, default=50_000)
     p.add_argument("--mode", default="cigar", choices=["score", "coords", "cigar"])
-    p.add_argument("--cpu-rows", type=int, default=500,
+    p.add_argument("--cpu-rows", type=int, default=1500,
                    help="rows of the query used for the timed CPU-oracle sample")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-db", action="store_true", help="skip the protein database-search leg")

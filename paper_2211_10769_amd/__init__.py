@@ -53,6 +53,11 @@ class Scoring:
         return sc if isinstance(sc, Scoring) else cls(*sc)
 
 
+# numpy view of swh_alignment (include/swh.h): score, flags, four int64 coordinates
+_ALIGNMENT_DTYPE = np.dtype([("score", "<i4"), ("flags", "<u4"), ("q_begin", "<i8"), ("q_end", "<i8"),
+                             ("t_begin", "<i8"), ("t_end", "<i8")])
+
+
 class Engine:
     """One library context (device, stream, grow-only device buffers)."""
 
@@ -100,13 +105,13 @@ class Engine:
         out = _lib.swh_alignment()
         st_obj = _lib.swh_stats(ctypes.sizeof(_lib.swh_stats)) if stats else None
         cap = 2 * (len(q) + len(t)) + 16 if m == MODE_CIGAR else 0
-        buf = ctypes.create_string_buffer(cap) if cap else None
+        buf = np.empty(cap, dtype=np.uint8) if cap else None    # written up to the CIGAR's length only
         clen = ctypes.c_int64()
         st = self.L.swh_align(self.h, q, len(q), t, len(t), ctypes.byref(sc.c), m | g, ctypes.byref(out),
-                              buf, cap, ctypes.byref(clen),
+                              buf.ctypes.data if buf is not None else None, cap, ctypes.byref(clen),
                               ctypes.byref(st_obj) if st_obj is not None else None)
         self._check(st)
-        return self._result(out, buf.value.decode() if buf is not None else None, st_obj)
+        return self._result(out, buf[:clen.value].tobytes().decode() if buf is not None else None, st_obj)
 
     def align_dev(self, q_tensor, t_tensor, scoring, mode: str = "score", stream=None, stats: bool = False,
                   alignment: str = "local"):
@@ -117,17 +122,17 @@ class Engine:
         out = _lib.swh_alignment()
         st_obj = _lib.swh_stats(ctypes.sizeof(_lib.swh_stats)) if stats else None
         cap = 2 * (q_tensor.numel() + t_tensor.numel()) + 16 if m == MODE_CIGAR else 0
-        buf = ctypes.create_string_buffer(cap) if cap else None
+        buf = np.empty(cap, dtype=np.uint8) if cap else None    # written up to the CIGAR's length only
         clen = ctypes.c_int64()
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
         st = self.L.swh_align_dev(self.h, q_tensor.data_ptr(), q_tensor.numel(), t_tensor.data_ptr(),
-                                  t_tensor.numel(), ctypes.byref(sc.c), m | g, stream, ctypes.byref(out), buf,
-                                  cap, ctypes.byref(clen),
+                                  t_tensor.numel(), ctypes.byref(sc.c), m | g, stream, ctypes.byref(out),
+                                  buf.ctypes.data if buf is not None else None, cap, ctypes.byref(clen),
                                   ctypes.byref(st_obj) if st_obj is not None else None)
         self._check(st)
-        return self._result(out, buf.value.decode() if buf is not None else None, st_obj)
+        return self._result(out, buf[:clen.value].tobytes().decode() if buf is not None else None, st_obj)
 
     def align_batch(self, queries, targets, scoring, mode: str = "cigar", stats: bool = False,
                     alignment: str = "local"):
@@ -141,27 +146,29 @@ class Engine:
             raise ValueError("queries and targets differ in count")
         m = _MODES[mode]
         g = _ALIGNMENTS[alignment]
-        out = (_lib.swh_alignment * max(1, n))()
+        out = np.zeros(max(1, n), dtype=_ALIGNMENT_DTYPE)
         st_obj = _lib.swh_stats(ctypes.sizeof(_lib.swh_stats)) if stats else None
         coff = np.zeros(n + 1, dtype=np.int64)
+        # the CIGAR bound (two characters per residue) can run to gigabytes:
+        # np.empty reserves it without touching it, and only the bytes the
+        # library writes are read back
         cap = int(2 * (qoff[-1] - qoff[0] + toff[-1] - toff[0]) + 16) if m == MODE_CIGAR else 0
-        buf = ctypes.create_string_buffer(cap) if cap else None
+        buf = np.empty(cap, dtype=np.uint8) if cap else None
         args = [self.h, n, qcat.ctypes.data if len(qcat) else None, qoff.ctypes.data,
-                tcat.ctypes.data if len(tcat) else None, toff.ctypes.data, ctypes.byref(sc.c), m | g, out,
-                buf, cap, coff.ctypes.data if m == MODE_CIGAR else None,
+                tcat.ctypes.data if len(tcat) else None, toff.ctypes.data, ctypes.byref(sc.c), m | g,
+                out.ctypes.data, buf.ctypes.data if buf is not None else None, cap,
+                coff.ctypes.data if m == MODE_CIGAR else None,
                 ctypes.byref(st_obj) if st_obj is not None else None]
-        rc = self.L.swh_align_batch(*args)
-        if rc == -4 and m == MODE_CIGAR and coff[-1] > cap:      # grow to the reported size once
-            cap = int(coff[-1]) + 1
-            buf = ctypes.create_string_buffer(cap)
-            args[8], args[9] = buf, cap
-            rc = self.L.swh_align_batch(*args)
-        self._check(rc)
-        raw = buf.raw if buf is not None else b""
-        res = []
-        for i in range(n):
-            cg = raw[coff[i]:coff[i + 1]].decode() if m == MODE_CIGAR else None
-            res.append(self._result(out[i], cg, None))
+        self._check(self.L.swh_align_batch(*args))
+        cols = [out[k][:n].tolist() for k in ("score", "q_begin", "q_end", "t_begin", "t_end", "flags")]
+        if m == MODE_CIGAR:
+            text = buf[:int(coff[n])].tobytes().decode()
+            offs = coff.tolist()
+            cigars = [text[offs[i]:offs[i + 1]] for i in range(n)]
+            res = [dict(score=a, q_begin=b, q_end=c, t_begin=d, t_end=e, flags=f, cigar=cg)
+                   for a, b, c, d, e, f, cg in zip(*cols, cigars)]
+        else:
+            res = [dict(score=a, q_begin=b, q_end=c, t_begin=d, t_end=e, flags=f) for a, b, c, d, e, f in zip(*cols)]
         if stats:
             return res, {k: getattr(st_obj, k) for k, _ in st_obj._fields_[2:]}
         return res

@@ -87,10 +87,10 @@ SIGNATURES = {
     "swh_destroy": (None, [_P]),
     "swh_last_error": (ctypes.c_char_p, [_P]),
     "swh_align": (ctypes.c_int, [_P, _P, _I64, _P, _I64, ctypes.POINTER(swh_scoring), ctypes.c_int,
-                                 ctypes.POINTER(swh_alignment), ctypes.c_char_p, _I64, _I64P,
+                                 ctypes.POINTER(swh_alignment), _P, _I64, _I64P,
                                  ctypes.POINTER(swh_stats)]),
     "swh_align_dev": (ctypes.c_int, [_P, _P, _I64, _P, _I64, ctypes.POINTER(swh_scoring), ctypes.c_int,
-                                     _P, ctypes.POINTER(swh_alignment), ctypes.c_char_p, _I64, _I64P,
+                                     _P, ctypes.POINTER(swh_alignment), _P, _I64, _I64P,
                                      ctypes.POINTER(swh_stats)]),
     "swh_align_batch": (ctypes.c_int, [_P, _I64, _P, _P, _P, _P, ctypes.POINTER(swh_scoring), ctypes.c_int,
                                        _P, _P, _I64, _P, ctypes.POINTER(swh_stats)]),

@@ -48,21 +48,37 @@ __device__ __forceinline__ u16x2 smax3(i16x2 t, u16x2 e, u16x2 f)
 constexpr int kChunk = 32;                 // query rows per register chunk
 constexpr unsigned kSatLimit = 32767 - 127;
 
-__global__ void db_pack_kernel(const uint8_t *codes, const int64_t *offs, const int32_t *perm,
-                               const DbGroup *groups, uint8_t pad, uint8_t *res)
+// Interleave a group's 128 sequences position-major (res[j * 128 + s]),
+// 64 positions at a time through an LDS tile: a wave reads 64 consecutive
+// residues of one sequence and writes one 128-byte row per position.
+__global__ void __launch_bounds__(256) db_pack_kernel(const uint8_t *codes, const int64_t *offs, const int32_t *perm,
+                                                      const DbGroup *groups, uint8_t pad, uint8_t *res)
 {
+    __shared__ uint8_t tile[64][132];   // [position][sequence]; the odd dword stride avoids bank conflicts
+    __shared__ int64_t sbase[128];
+    __shared__ int64_t slen[128];
     const DbGroup g = groups[blockIdx.x];
-    const int64_t total = (int64_t)g.maxlen * 128;
-    for (int64_t t = threadIdx.x; t < total; t += blockDim.x) {
-        const int64_t j = t >> 7;
-        const int s = (int)(t & 127);
-        const int32_t idx = perm[g.first + s];
-        uint8_t c = pad;
-        if (idx >= 0) {
-            const int64_t b = offs[idx], len = offs[idx + 1] - b;
-            if (j < len) c = codes[b + j];
+    const int tid = threadIdx.x;
+    if (tid < 128) {
+        const int32_t idx = perm[g.first + tid];
+        sbase[tid] = idx >= 0 ? offs[idx] : 0;
+        slen[tid] = idx >= 0 ? offs[idx + 1] - offs[idx] : 0;
+    }
+    __syncthreads();
+    uint8_t *out = res + g.offset;
+    for (int64_t j0 = 0; j0 < g.maxlen; j0 += 64) {
+        for (int k = tid; k < 64 * 128; k += 256) {
+            const int s = k >> 6, jj = k & 63;
+            const int64_t j = j0 + jj;
+            tile[jj][s] = j < slen[s] ? codes[sbase[s] + j] : pad;
         }
-        res[g.offset + t] = c;
+        __syncthreads();
+        const int rows = (int)min<int64_t>(64, (int64_t)g.maxlen - j0);
+        for (int k = tid; k < rows * 128; k += 256) {
+            const int jj = k >> 7, s = k & 127;
+            out[(j0 + jj) * 128 + s] = tile[jj][s];
+        }
+        __syncthreads();
     }
 }
 

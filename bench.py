@@ -242,7 +242,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the pairwise path has no "
-              "multi-GPU mode in this build", file=sys.stderr)
+              "multi-GPU mode", file=sys.stderr)
         sys.exit(2)
 
     log("starting (imports)")

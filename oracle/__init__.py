@@ -49,6 +49,12 @@ def lib() -> ctypes.CDLL:
                                    ctypes.c_int64, i64p, i64p, ctypes.c_char_p, ctypes.c_int64, i64p]
         L.orc_sw_end.argtypes = [cstr, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                  cstr, ctypes.c_int64, cstr, ctypes.c_int64, i64p, i64p, i64p]
+        L.orc_sw_coords_mt.argtypes = [cstr, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                       cstr, ctypes.c_int64, cstr, ctypes.c_int64, ctypes.c_int,
+                                       ctypes.c_int64, ctypes.c_int64, i64p, i64p]
+        L.orc_sw_end_mt.argtypes = [cstr, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                    cstr, ctypes.c_int64, cstr, ctypes.c_int64, ctypes.c_int,
+                                    ctypes.c_int64, ctypes.c_int64, i64p, i64p, i64p]
         L.orc_global_cigar.argtypes = [cstr, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                        cstr, ctypes.c_int64, cstr, ctypes.c_int64, i64p,
                                        ctypes.c_char_p, ctypes.c_int64, i64p]
@@ -62,7 +68,7 @@ def lib() -> ctypes.CDLL:
                                     ctypes.c_int, ctypes.c_void_p]
         L.orc_topk.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                ctypes.c_void_p, ctypes.c_void_p]
-        for f in (L.orc_sw_align, L.orc_sw_end, L.orc_global_cigar, L.orc_hw_align, L.orc_ov_align,
+        for f in (L.orc_sw_align, L.orc_sw_end, L.orc_sw_coords_mt, L.orc_sw_end_mt, L.orc_global_cigar, L.orc_hw_align, L.orc_ov_align,
                   L.orc_db_scores, L.orc_topk):
             f.restype = ctypes.c_int
         _lib = L
@@ -119,6 +125,37 @@ def sw_end(a, b, scoring):
                           ctypes.byref(s), ctypes.byref(qe), ctypes.byref(te))
     if rc != OK:
         raise OracleError(rc, "sw_end")
+    return s.value, qe.value, te.value
+
+
+def sw_coords_mt(a, b, scoring, threads: int | None = None, band: int = 256, chunk: int = 4096):
+    """Score, end and start of one (long) pair with the banded threaded pass:
+    dict(score, q_begin, q_end, t_begin, t_end), the same values as
+    sw_align(..., want_cigar=False).  band / chunk / threads set only the
+    running time (rows per band, columns per hand-over chunk, worker threads)."""
+    alphabet, matrix, o, e = scoring
+    a, b = _as_bytes(a), _as_bytes(b)
+    M = _mat(matrix)
+    s = ctypes.c_int64()
+    co = (ctypes.c_int64 * 4)()
+    rc = lib().orc_sw_coords_mt(alphabet.encode(), len(alphabet), M.ctypes.data, o, e, a, len(a), b, len(b),
+                                int(threads or os.cpu_count() or 1), band, chunk, ctypes.byref(s), co)
+    if rc != OK:
+        raise OracleError(rc, "sw_coords_mt")
+    return dict(score=s.value, q_begin=co[0], q_end=co[1], t_begin=co[2], t_end=co[3])
+
+
+def sw_end_mt(a, b, scoring, threads: int | None = None, band: int = 256, chunk: int = 4096):
+    """Score-only banded threaded pass: (score, q_end, t_end), as sw_end."""
+    alphabet, matrix, o, e = scoring
+    a, b = _as_bytes(a), _as_bytes(b)
+    M = _mat(matrix)
+    s, qe, te = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    rc = lib().orc_sw_end_mt(alphabet.encode(), len(alphabet), M.ctypes.data, o, e, a, len(a), b, len(b),
+                             int(threads or os.cpu_count() or 1), band, chunk, ctypes.byref(s), ctypes.byref(qe),
+                             ctypes.byref(te))
+    if rc != OK:
+        raise OracleError(rc, "sw_end_mt")
     return s.value, qe.value, te.value
 
 

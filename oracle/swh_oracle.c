@@ -37,6 +37,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <pthread.h>
+#include <sched.h>
 
 #define ORC_OK 0
 #define ORC_E_INVAL (-1)
@@ -310,6 +311,227 @@ int orc_sw_align(const char *alphabet, int asize, const int8_t *matrix, int o, i
     }
     free(ca);
     free(cb);
+    return ORC_OK;
+}
+
+/*
+ * The resolution-phase DP of local_best, split over threads for one long
+ * pair (the same recurrences, cell for cell; only the order in which cells
+ * are visited changes).  Rows are cut into bands of `band` rows, columns into
+ * chunks of `chunk` columns.  Band k visits its chunks left to right; chunk c
+ * of band k needs the last row of band k-1 over the chunk's columns and the
+ * left neighbours of its own rows, which band k carries from chunk c-1.  The
+ * last row of a band is handed to the next band through one shared row,
+ * overwritten in place one chunk at a time: band k reads chunk c, computes
+ * it, writes its own last row over it and publishes progress[k] = c + 1;
+ * band k+1 starts chunk c only once it sees that.  Threads take bands in
+ * increasing order, so every band waits only on a band already taken.
+ *
+ * Because a band visits its cells chunk by chunk, the first cell in
+ * row-major order holding the maximum is found by comparison (value desc,
+ * row asc, column asc) rather than by visiting order.
+ */
+typedef struct {
+    int64_t v, i, j;
+} cell_pick;
+
+/* b better than a: larger value, or equal positive value earlier in row-major order */
+static int pick_better(const cell_pick *b, const cell_pick *a)
+{
+    if (b->v != a->v) return b->v > a->v;
+    if (b->v == 0) return 0;
+    if (b->i != a->i) return b->i < a->i;
+    return b->j < a->j;
+}
+
+typedef struct {
+    const scoring *sc;
+    const uint8_t *a, *b;
+    int64_t n, m, band, chunk, nbands, nchunks;
+    int64_t *rowH, *rowF;          /* shared hand-over row: H, F of a band's last row, columns 1..m */
+    int64_t *progress;             /* per band: chunks published (atomic) */
+    int64_t next_band;             /* atomic band ticket */
+    cell_pick *band_best;          /* per band */
+    int status;                    /* atomic: nonzero once a worker failed */
+} band_job;
+
+static void *band_worker(void *arg)
+{
+    band_job *jb = (band_job *)arg;
+    const scoring *sc = jb->sc;
+    const int64_t B = jb->band, C = jb->chunk;
+    int64_t *Hl = (int64_t *)malloc(sizeof(int64_t) * (size_t)B);     /* H(i, c0-1) of the band's rows */
+    int64_t *El = (int64_t *)malloc(sizeof(int64_t) * (size_t)B);     /* E(i, c0-1) */
+    int64_t *H = (int64_t *)malloc(sizeof(int64_t) * (size_t)(C + 1)); /* working row over the chunk */
+    int64_t *F = (int64_t *)malloc(sizeof(int64_t) * (size_t)(C + 1));
+    if (!Hl || !El || !H || !F) {
+        __atomic_store_n(&jb->status, ORC_E_NOMEM, __ATOMIC_RELAXED);
+        free(Hl); free(El); free(H); free(F);
+        return NULL;
+    }
+    for (;;) {
+        const int64_t k = __atomic_fetch_add(&jb->next_band, 1, __ATOMIC_RELAXED);
+        if (k >= jb->nbands) break;
+        const int64_t top = k * B + 1, bot = (k + 1) * B < jb->n ? (k + 1) * B : jb->n;   /* rows top..bot, 1-based */
+        cell_pick best = {0, 0, 0};
+        for (int64_t r = 0; r < B; ++r) { Hl[r] = 0; El[r] = NEG_INF; }   /* column 0 */
+        int64_t corner = 0;   /* H(top-1, c0-1): 0 on column 0 */
+        for (int64_t c = 0; c < jb->nchunks; ++c) {
+            const int64_t c0 = c * C + 1, c1 = (c + 1) * C < jb->m ? (c + 1) * C : jb->m;   /* columns c0..c1 */
+            const int64_t w = c1 - c0 + 1;
+            if (k > 0) {
+                while (__atomic_load_n(&jb->progress[k - 1], __ATOMIC_ACQUIRE) <= c) {
+                    if (__atomic_load_n(&jb->status, __ATOMIC_RELAXED)) goto out;
+                    sched_yield();
+                }
+            }
+            /* the row above the band over columns c0-1 .. c1: H(top-1, .), F(top-1, .) */
+            H[0] = corner;
+            F[0] = NEG_INF;
+            for (int64_t t = 0; t < w; ++t) {
+                H[t + 1] = k > 0 ? jb->rowH[c0 + t] : 0;
+                F[t + 1] = k > 0 ? jb->rowF[c0 + t] : NEG_INF;
+            }
+            corner = H[w];   /* H(top-1, c1): the next chunk's corner */
+            for (int64_t i = top; i <= bot; ++i) {
+                const int64_t r = i - top;
+                int64_t diag = H[0];     /* H(i-1, c0-1) */
+                H[0] = Hl[r];            /* H(i, c0-1) */
+                int64_t E = El[r];       /* E(i, c0-1) */
+                for (int64_t t = 1; t <= w; ++t) {
+                    const int64_t j = c0 + t - 1;
+                    const int64_t Eij = max2(E - sc->e, H[t - 1] - sc->o);
+                    const int64_t Fij = max2(F[t] - sc->e, H[t] - sc->o);
+                    const int64_t h = max2(max2(0, diag + subst(sc, jb->a[i - 1], jb->b[j - 1])), max2(Eij, Fij));
+                    diag = H[t];
+                    H[t] = h;
+                    F[t] = Fij;
+                    E = Eij;
+                    if (h >= best.v) {   /* only such cells can change the pick */
+                        const cell_pick cp = {h, i, j};
+                        if (pick_better(&cp, &best)) best = cp;
+                    }
+                }
+                Hl[r] = H[w];
+                El[r] = E;
+            }
+            /* hand the band's last row over this chunk to the next band */
+            for (int64_t t = 0; t < w; ++t) {
+                jb->rowH[c0 + t] = H[t + 1];
+                jb->rowF[c0 + t] = F[t + 1];
+            }
+            __atomic_store_n(&jb->progress[k], c + 1, __ATOMIC_RELEASE);
+        }
+        jb->band_best[k] = best;
+    }
+out:
+    free(Hl); free(El); free(H); free(F);
+    return NULL;
+}
+
+static int local_best_bands(const scoring *sc, const uint8_t *a, int64_t n, const uint8_t *b, int64_t m,
+                            int threads, int64_t band, int64_t chunk,
+                            int64_t *S, int64_t *ibest, int64_t *jbest)
+{
+    *S = 0; *ibest = 0; *jbest = 0;
+    if (n == 0 || m == 0) return ORC_OK;
+    if (band < 1 || chunk < 1) return ORC_E_INVAL;
+    band_job jb;
+    memset(&jb, 0, sizeof(jb));
+    jb.sc = sc; jb.a = a; jb.b = b; jb.n = n; jb.m = m; jb.band = band; jb.chunk = chunk;
+    jb.nbands = (n + band - 1) / band;
+    jb.nchunks = (m + chunk - 1) / chunk;
+    jb.rowH = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 1));
+    jb.rowF = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m + 1));
+    jb.progress = (int64_t *)calloc((size_t)jb.nbands, sizeof(int64_t));
+    jb.band_best = (cell_pick *)calloc((size_t)jb.nbands, sizeof(cell_pick));
+    if (!jb.rowH || !jb.rowF || !jb.progress || !jb.band_best) {
+        free(jb.rowH); free(jb.rowF); free(jb.progress); free(jb.band_best);
+        return ORC_E_NOMEM;
+    }
+    if (threads < 1) threads = 1;
+    if (threads > 256) threads = 256;
+    pthread_t tid[256];
+    int started = 0;
+    for (int t = 0; t < threads; ++t)
+        if (pthread_create(&tid[t], NULL, band_worker, &jb) == 0) ++started;
+    if (started == 0) band_worker(&jb);
+    for (int t = 0; t < started; ++t) pthread_join(tid[t], NULL);
+    int rc = jb.status;
+    if (!rc) {
+        cell_pick best = {0, 0, 0};
+        for (int64_t k = 0; k < jb.nbands; ++k)
+            if (pick_better(&jb.band_best[k], &best)) best = jb.band_best[k];
+        *S = best.v; *ibest = best.i; *jbest = best.j;
+    }
+    free(jb.rowH); free(jb.rowF); free(jb.progress); free(jb.band_best);
+    return rc;
+}
+
+/*
+ * Score, end and start of one long pair through the banded threaded pass:
+ * coords = {q_begin, q_end, t_begin, t_end} (0-based, -1 when S == 0), as
+ * orc_sw_align without the CIGAR.  threads, band and chunk change the
+ * running time only.
+ */
+int orc_sw_coords_mt(const char *alphabet, int asize, const int8_t *matrix, int o, int e,
+                     const char *a, int64_t n, const char *b, int64_t m,
+                     int threads, int64_t band, int64_t chunk, int64_t *score, int64_t *coords)
+{
+    scoring sc;
+    int rc = make_scoring(&sc, alphabet, asize, matrix, o, e);
+    if (rc) return rc;
+    if (n < 0 || m < 0 || (!a && n) || (!b && m) || !score || !coords) return ORC_E_INVAL;
+    uint8_t *ca = (uint8_t *)malloc((size_t)(n + 1));
+    uint8_t *cb = (uint8_t *)malloc((size_t)(m + 1));
+    if (!ca || !cb) { free(ca); free(cb); return ORC_E_NOMEM; }
+    int64_t bad;
+    if ((rc = encode(&sc, a, n, ca, &bad)) || (rc = encode(&sc, b, m, cb, &bad))) {
+        free(ca); free(cb); return rc;
+    }
+    int64_t S, ie, je;
+    rc = local_best_bands(&sc, ca, n, cb, m, threads, band, chunk, &S, &ie, &je);
+    *score = S;
+    coords[0] = coords[1] = coords[2] = coords[3] = -1;
+    if (rc || S == 0) { free(ca); free(cb); return rc; }
+    uint8_t *ra = (uint8_t *)malloc((size_t)ie);
+    uint8_t *rb = (uint8_t *)malloc((size_t)je);
+    if (!ra || !rb) { free(ca); free(cb); free(ra); free(rb); return ORC_E_NOMEM; }
+    for (int64_t k = 0; k < ie; ++k) ra[k] = ca[ie - 1 - k];
+    for (int64_t k = 0; k < je; ++k) rb[k] = cb[je - 1 - k];
+    int64_t S2, ri, rj;
+    rc = local_best_bands(&sc, ra, ie, rb, je, threads, band, chunk, &S2, &ri, &rj);
+    free(ra); free(rb); free(ca); free(cb);
+    if (rc) return rc;
+    if (S2 != S) return ORC_E_INVAL;   /* cannot happen (start lemma) */
+    coords[0] = ie - ri; coords[1] = ie - 1; coords[2] = je - rj; coords[3] = je - 1;
+    return ORC_OK;
+}
+
+/* Score-only banded threaded pass: S and the 0-based end cell (-1 when S == 0). */
+int orc_sw_end_mt(const char *alphabet, int asize, const int8_t *matrix, int o, int e,
+                  const char *a, int64_t n, const char *b, int64_t m,
+                  int threads, int64_t band, int64_t chunk,
+                  int64_t *score, int64_t *q_end, int64_t *t_end)
+{
+    scoring sc;
+    int rc = make_scoring(&sc, alphabet, asize, matrix, o, e);
+    if (rc) return rc;
+    if (n < 0 || m < 0 || (!a && n) || (!b && m) || !score || !q_end || !t_end) return ORC_E_INVAL;
+    uint8_t *ca = (uint8_t *)malloc((size_t)(n + 1));
+    uint8_t *cb = (uint8_t *)malloc((size_t)(m + 1));
+    if (!ca || !cb) { free(ca); free(cb); return ORC_E_NOMEM; }
+    int64_t bad;
+    if ((rc = encode(&sc, a, n, ca, &bad)) || (rc = encode(&sc, b, m, cb, &bad))) {
+        free(ca); free(cb); return rc;
+    }
+    int64_t S, ie, je;
+    rc = local_best_bands(&sc, ca, n, cb, m, threads, band, chunk, &S, &ie, &je);
+    free(ca); free(cb);
+    if (rc) return rc;
+    *score = S;
+    *q_end = ie - 1;
+    *t_end = je - 1;
     return ORC_OK;
 }
 

@@ -175,6 +175,27 @@ def workload1(n: int = 5_000_000, flank: int = 50_000):
     return q, t
 
 
+def high_score_dna_scoring():
+    """DNA scoring with the extreme int8 scores (match +127, mismatch -127),
+    gap open 200, extend 50: a related pair scores about 125 per base, so a
+    pair of half a megabase reaches scores near 2^26."""
+    m = np.full((4, 4), -127, dtype=np.int8)
+    np.fill_diagonal(m, 127)
+    return DNA_ALPHABET, m, 200, 50
+
+
+def workload1_high(n: int = 528_000, flank: int = 5_000):
+    """A related DNA pair for the high-score range: a uniform query and its
+    copy with 1% substitutions and 0.2% indel events (geometric, mean 3)
+    between random flanks (seed streams 10-12 of the long-pair workload, apart
+    from the ones workload1 uses)."""
+    q = random_dna(rng_for(1, 10), n)
+    core = mutate(rng_for(1, 12), q, 0.01, 0.002)
+    fr = rng_for(1, 11)
+    t = np.concatenate([random_dna(fr, flank), core, random_dna(fr, flank)])
+    return q, t
+
+
 def query_lengths(rng, count: int = 20, lo: int = 100, hi: int = 5000) -> np.ndarray:
     return np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), size=count))).astype(np.int64)
 

@@ -13,14 +13,17 @@ forward score pass (score + end), reverse pass (start) and, when the mode is
 "cigar", the linear-space traceback.  value = forward DP cells per step x
 steps / timed seconds (GCUPS, the paper's metric: billion cell updates per
 second).  The JSON line also carries the forward kernel alone (HIP events on
-the stream it runs on), its roofline against the integer-VALU peak, and the
-CPU oracle timed on a bounded sample of the same workload.
+the stream it runs on), its roofline against the integer-VALU peak, the
+other workloads (10 kbp pair, protein database search, 200,000 read pairs,
+learned prefilter, global alignment) and the CPU oracle timed on a bounded
+sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -28,20 +31,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz = 39.3e12 32-bit integer lane-ops/s.
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz = 39.3e12 32-bit integer lane-ops/s
+# (packed 16-bit operations: twice as many cell updates per lane-op).
 VALU_LANE_OPS = 256 * 64 * 2.4e9
-# Algorithmic integer operations per DP cell of the local pass:
-# add (diag + s), max3 (H), sub (H - o), sub + max3 (E), sub + max3 (F).
-OPS_PER_CELL = 7
+# Algorithmic integer operations per DP cell of the local pass: the
+# substitution fetch, add (diag + s), sub + max (E), sub + max (F), max3 and
+# the zero floor (H), sub (H - o) and the running maximum for the end cell:
+# about 10, which gives 3,932 GCUPS in 32-bit arithmetic.
+OPS_PER_CELL = 10
+# The recurrence alone, without the fetch, floor and running maximum (the
+# kernel folds the fetch into the add and the floor into E and F): 7.
+OPS_PER_CELL_CORE = 7
+# VALU lane-ops the forward strip kernel issues per cell (SQ_INSTS_VALU x 64
+# over the cells of a launch; profiles/strip_kernel_long_dna.md).
+ISSUED_OPS_PER_CELL = 8.66
 # HBM bytes per DP cell of the forward local strip kernel
 # (strip_kernel<20, true, false>) on the long pair, from two rocprofv3 counter
 # passes over one CIGAR step (forward launch 2.55e13 cells, keeping rows for the
 # band traceback), each scaled by the same counter on a 1 GiB plain copy
 # (profiles/strip_kernel_long_dna.md): FETCH_SIZE 96,351,829 KiB x 2.0 +
-# WRITE_SIZE 190,673,392 KiB x 1.0 = 392.6 GB per launch.  Valid for the kernel
-# those counters were taken on; the roofline's traffic field is this figure
-# times the cells of a launch.
+# WRITE_SIZE 190,673,392 KiB x 1.0 = 392.6 GB per launch.
 HBM_BYTES_PER_CELL = (96_351_828.75 * 2.0 + 190_673_392.09375) * 1024 / 25_500_765_000_000
+TRAFFIC_SOURCE = "profiles/strip_kernel_long_dna.md (rocprofv3 FETCH_SIZE and WRITE_SIZE of the forward launch)"
 
 
 def log(msg: str):
@@ -57,15 +68,18 @@ def parse():
     p.add_argument("--n", type=int, default=5_000_000, help="query length of the long pair")
     p.add_argument("--flank", type=int, default=50_000)
     p.add_argument("--mode", default="cigar", choices=["score", "coords", "cigar"])
-    p.add_argument("--cpu-rows", type=int, default=1500,
-                   help="rows of the query used for the timed CPU-oracle sample")
+    p.add_argument("--cpu-rows", type=int, default=24000,
+                   help="query rows of the threaded CPU-oracle sample")
+    p.add_argument("--cpu-rows-single", type=int, default=600,
+                   help="query rows of the single-thread CPU-oracle sample")
+    p.add_argument("--no-pair10k", action="store_true", help="skip the 10 kbp pair leg")
+    p.add_argument("--reps", type=int, default=20, help="repetitions of the 10 kbp pair leg")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-db", action="store_true", help="skip the protein database-search leg")
     p.add_argument("--db-size", type=int, default=500_000, help="database sequences of the search leg")
     p.add_argument("--db-steps", type=int, default=3)
     p.add_argument("--no-pairs", action="store_true", help="skip the batched read-pairs leg")
-    p.add_argument("--pairs", type=int, default=20_000,
-                   help="read/reference pairs of the batched leg (the full configuration has 200,000)")
+    p.add_argument("--pairs", type=int, default=200_000, help="read/reference pairs of the batched leg")
     p.add_argument("--no-prefilter", action="store_true", help="skip the learned-prefilter leg")
     p.add_argument("--pf-db", type=int, default=2_000_000, help="database sequences of the prefilter leg")
     p.add_argument("--pf-train-pairs", type=int, default=1_000_000)
@@ -79,19 +93,93 @@ def parse():
     return p.parse_args()
 
 
-def cpu_baseline(q, t, rows):
+def host_info():
+    """CPU model, usable cores and ROCm version of the timing host."""
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    rocm = None
+    try:
+        with open("/opt/rocm/.info/version") as f:
+            rocm = f.read().strip()
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": cores, "rocm": rocm}
+
+
+def cpu_baseline(q, t, rows_mt, rows_st):
+    """The oracle as it stands, on a bounded sample of the long pair: the
+    forward score pass of the first rows_mt query rows against the whole
+    target with the oracle's banded threads (at most 16, the host share of one
+    GPU), and of the first rows_st rows on one thread."""
     import oracle
     import seqgen
     sc = seqgen.dna_scoring()
-    a = bytes(q[:rows])
+    info = host_info()
+    threads = max(1, min(16, info["nproc"]))
     b = bytes(t)
+    a = bytes(q[:rows_mt])
     t0 = time.perf_counter()
-    oracle.sw_end(a, b, sc)
+    oracle.sw_end_mt(a, b, sc, threads=threads)
     dt = time.perf_counter() - t0
     cells = len(a) * len(b)
-    return {"value": cells / dt / 1e9, "unit": "GCUPS", "cores": 1, "kind": "oracle",
-            "sample": f"score pass of the first {rows} query rows against the full target "
-                      f"({cells:.3e} cells, {dt:.1f} s, single thread)"}
+    a1 = bytes(q[:rows_st])
+    t0 = time.perf_counter()
+    oracle.sw_end(a1, b, sc)
+    dt1 = time.perf_counter() - t0
+    cells1 = len(a1) * len(b)
+    return {"value": round(cells / dt / 1e9, 4), "unit": "GCUPS", "cores": threads, "kind": "oracle",
+            "sample": f"forward score pass of the first {rows_mt} query rows against the full target "
+                      f"({cells:.3e} cells, {dt:.1f} s, {threads} threads, banded oracle)",
+            "single_thread": {"value": round(cells1 / dt1 / 1e9, 4), "unit": "GCUPS",
+                              "sample": f"first {rows_st} rows, {cells1:.3e} cells, {dt1:.1f} s"},
+            **info}
+
+
+def bench_pair10k(args, swh, eng):
+    """The 10 kbp x 10 kbp uniform DNA pair (+1/-3, open 5, extend 2): the
+    forward score pass alone and the whole call with CIGAR, 20 repetitions
+    each, beside its latency bound (a 1e8-cell matrix has a dependency chain
+    of n + m anti-diagonals)."""
+    import numpy as np
+    import seqgen
+
+    q, t = seqgen.workload0()
+    q, t = bytes(q), bytes(t)
+    sc = swh.Scoring(*seqgen.dna_scoring())
+    cells = len(q) * len(t)
+    for _ in range(3):
+        eng.align(q, t, sc, mode="cigar")
+    fwd, tot = [], []
+    for _ in range(args.reps):
+        r = eng.align(q, t, sc, mode="score", stats=True)
+        fwd.append(r["stats"]["ms_forward"])
+    res = None
+    for _ in range(args.reps):
+        t0 = time.perf_counter()
+        res = eng.align(q, t, sc, mode="cigar")
+        tot.append((time.perf_counter() - t0) * 1e3)
+    fm, tm = float(np.mean(fwd)), float(np.mean(tot))
+    # n + m anti-diagonals at about 55 cycles per dependent anti-diagonal step
+    bound_ms = (len(q) + len(t)) * 55 / 2.4e9 * 1e3
+    return {"workload": "10,000 x 10,000 bp uniform DNA, +1/-3, open 5, extend 2",
+            "forward_ms_mean": round(fm, 3), "forward_ms_median": round(float(np.median(fwd)), 3),
+            "forward_gcups": round(cells / fm / 1e6, 2),
+            "cigar_call_ms_mean": round(tm, 3), "cigar_call_ms_median": round(float(np.median(tot)), 3),
+            "cigar_call_gcups": round(cells / tm / 1e6, 2),
+            "latency_bound": {"ms": round(bound_ms, 3), "gcups": round(cells / bound_ms / 1e6, 1),
+                              "model": "(n + m) anti-diagonals x 55 cycles / 2.4 GHz"},
+            "reps": args.reps, "score": res["score"], "cigar_len": len(res["cigar"])}
 
 
 def bench_db(args, swh, eng):
@@ -104,8 +192,10 @@ def bench_db(args, swh, eng):
 
     qs, (cat, off) = seqgen.workload2(n_db=args.db_size)
     sc = swh.Scoring(*seqgen.protein_scoring())
+    t0 = time.perf_counter()
     db = swh.Database(eng, (cat, off), sc)
-    log(f"database search: {args.db_size} proteins encoded")
+    create_s = time.perf_counter() - t0
+    log(f"database search: {args.db_size} proteins encoded ({create_s:.2f} s)")
     qcat, qoff = swh._concat(qs)
     db.search((qcat, qoff), k=10)   # warm-up: buffers grow once
     t0 = time.perf_counter()
@@ -125,7 +215,8 @@ def bench_db(args, swh, eng):
             "inter_kernel_gcups": round(cells / (inter / 1e3) / 1e9, 2) if inter > 0 else None,
             "intra_ms": round(sum(x["ms_intra"] for x in stats) / len(stats), 2),
             "topk_ms": round(sum(x["ms_topk"] for x in stats) / len(stats), 2),
-            "saturated_pairs": int(stats[0]["saturated"]), "intra_pairs": int(stats[0]["intra_pairs"])}
+            "saturated_pairs": int(stats[0]["saturated"]), "intra_pairs": int(stats[0]["intra_pairs"]),
+            "one_time": {"db_upload_and_layout_s": round(create_s, 3)}}
 
 
 def bench_pairs(args, swh, eng):
@@ -211,12 +302,15 @@ def bench_prefilter(args, swh, eng):
     ex_idx, ex_sco, ex_st = db.search((qcat, qoff), k=10)
     t_ex = time.perf_counter() - t0
     log(f"prefilter: exhaustive search {t_ex:.2f} s")
+    t0 = time.perf_counter()
     model.search(db, (qcat, qoff), k=10, rescore_frac=0.05, audit_frac=0.002)   # warm-up: database features
+    first_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     pf_idx, pf_sco, pf_st = model.search(db, (qcat, qoff), k=10, rescore_frac=0.05, audit_frac=0.002)
     t_pf = time.perf_counter() - t0
     log(f"prefilter: prefilter search {t_pf:.2f} s")
     recall = float(np.mean([len(set(a) & set(b)) / 10.0 for a, b in zip(pf_idx.tolist(), ex_idx.tolist())]))
+    gain = gain_test(args, swh, eng, model, db, (qcat, qoff), ex_idx, t_ex, pf_st)
     flops = 2.0 * len(qs) * args.pf_db * (416 * 256 + 256 * 256)
     pred_ms = pf_st["ms_predict"]
     db.close()
@@ -235,7 +329,70 @@ def bench_prefilter(args, swh, eng):
             "training": {"pairs": args.pf_train_pairs, "epochs": args.pf_epochs, "steps": int(tst["steps"]),
                          "s": round(train_s, 2), "label_ms": round(tst["ms_label"], 1),
                          "train_ms": round(tst["ms_train"], 1), "first_loss": round(tst["first_epoch_loss"], 4),
-                         "final_loss": round(tst["final_epoch_loss"], 4), "generate_s": round(gen_train, 1)}}
+                         "final_loss": round(tst["final_epoch_loss"], 4), "generate_s": round(gen_train, 1)},
+            "one_time": {"db_features_s": round(max(first_s - t_pf, 0.0), 3),
+                         "first_search_s": round(first_s, 3)},
+            "gain_test": gain}
+
+
+def baseline_models(swh, eng, sc, trained):
+    """The non-learned rankings as parameter sets of the same network, so that
+    they run through the same search (same budget, rescoring, audit and
+    fallback): (i) length only -- one hidden unit carrying the normalised
+    ln(min(Lq, Lt)), monotone in the database length up to the query's; (ii)
+    the raw dipeptide dot product D2 = sum_k f_q[k] f_t[k], rebuilt exactly
+    from the normalised inputs; (iii) an untrained network (He-normal
+    weights) with the trained normalisation."""
+    import numpy as np
+    theta, mu, sd = trained.get()
+    H, K = 256, 401
+    def layout():
+        th = np.zeros(swh._lib.MODEL_PARAMS, np.float32)
+        W1 = th[:H * K].reshape(H, K)
+        b1 = th[H * K:H * K + H]
+        o2 = H * K + H
+        W2 = th[o2:o2 + H * H].reshape(H, H)
+        b2 = th[o2 + H * H:o2 + H * H + H]
+        w3 = th[o2 + H * H + H:o2 + H * H + 2 * H]
+        return th, W1, b1, W2, b2, w3
+    out = {}
+    th, W1, b1, W2, b2, w3 = layout()
+    W1[0, 400] = 1.0
+    b1[0] = 4.0            # keeps the unit above zero for any length (|z| < 4)
+    W2[0, 0] = 1.0
+    w3[0] = 1.0
+    out["length_only"] = swh.Model(eng, sc, theta=th, mu=mu, sd=sd)
+    th, W1, b1, W2, b2, w3 = layout()
+    W1[0, :400] = sd[:400]                 # sum_k sd_k z_k = D2 - sum_k mu_k
+    b1[0] = float(np.sum(mu[:400], dtype=np.float64))
+    W2[0, 0] = 1.0
+    w3[0] = 1.0
+    out["raw_d2"] = swh.Model(eng, sc, theta=th, mu=mu, sd=sd)
+    out["untrained"] = swh.Model(eng, sc, seed=12345, mu=mu, sd=sd)
+    return out
+
+
+def gain_test(args, swh, eng, model, db, queries, ex_idx, t_ex, pf_st):
+    """recall@10 and speedup of the trained network and of the non-learned
+    rankings at the same rescoring budget."""
+    import numpy as np
+    res = {}
+    sc = model.sc if model.sc is not None else swh.Scoring(*__import__("seqgen").protein_scoring())
+    for name, m in baseline_models(swh, eng, sc, model).items():
+        m.search(db, queries, k=10, rescore_frac=0.05, audit_frac=0.002)
+        t0 = time.perf_counter()
+        idx, _, st = m.search(db, queries, k=10, rescore_frac=0.05, audit_frac=0.002)
+        dt = time.perf_counter() - t0
+        # recall of the ranking itself: the audit's fallback (an exhaustive
+        # search of the query) repairs a missed hit, so report both
+        rec = float(np.mean([len(set(a) & set(b)) / 10.0 for a, b in zip(idx.tolist(), ex_idx.tolist())]))
+        res[name] = {"recall_at_10": rec, "speedup": round(t_ex / dt, 2), "fallbacks": int(st["fallbacks"]),
+                     "rescored_cell_fraction": round(st["cells_rescored"] / st["cells_exhaustive"], 4)}
+        m.close()
+        log(f"prefilter gain test: {name} done")
+    res["trained"] = {"fallbacks": int(pf_st["fallbacks"]),
+                      "rescored_cell_fraction": round(pf_st["cells_rescored"] / pf_st["cells_exhaustive"], 4)}
+    return res
 
 
 def main():
@@ -301,6 +458,8 @@ def main():
     k_ms = sum(fwd_ms)
     k_gcups = k_cells / (k_ms / 1e3) / 1e9
     peak_gcups = VALU_LANE_OPS / OPS_PER_CELL / 1e9
+    peak_core = VALU_LANE_OPS / OPS_PER_CELL_CORE / 1e9
+    peak_issued = VALU_LANE_OPS / ISSUED_OPS_PER_CELL / 1e9
     launches = len(fwd_ms)
     traffic = HBM_BYTES_PER_CELL * k_cells / launches
     out = {
@@ -329,12 +488,21 @@ def main():
         "traceback_cells": res["stats"]["cells_traceback"],
         "traceback_bands": res["stats"]["traceback_bands"],
         "traceback_retries": res["stats"]["traceback_retries"],
-        "roofline": {"bound": "alu", "kernel": "strip_kernel (local, forward pass)",
+        "roofline": {"bound": "alu", "kernel": "strip_kernel<R, local> (forward pass, 32-bit)",
                      "achieved": round(k_gcups, 2), "peak": round(peak_gcups, 1), "unit": "GCUPS",
-                     "frac": round(k_gcups / peak_gcups, 4), "traffic": round(traffic),
-                     "traffic_unit": "bytes per launch (HBM, from counters)",
+                     "frac": round(k_gcups / peak_gcups, 4),
+                     "ops_per_cell": OPS_PER_CELL,
+                     "peak_basis": "256 CU x 64 lanes x 2.4 GHz 32-bit integer lane-ops / 10 ops per cell",
+                     "frac_vs_7op_recurrence": round(k_gcups / peak_core, 4),
+                     "frac_vs_issued_ops": round(k_gcups / peak_issued, 4),
+                     "traffic": round(traffic),
+                     "traffic_unit": "HBM bytes per launch",
+                     "traffic_source": TRAFFIC_SOURCE,
                      "traffic_gbps": round(traffic / (k_ms / launches / 1e3) / 1e9, 1)},
     }
+    if not args.no_pair10k:
+        out["pair_10k"] = bench_pair10k(args, swh, eng)
+        log("10 kbp pair done")
     if not args.no_db:
         out["db_search"] = bench_db(args, swh, eng)
     if not args.no_pairs:
@@ -344,7 +512,7 @@ def main():
     if not args.no_prefilter:
         out["prefilter"] = bench_prefilter(args, swh, eng)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(q, t, args.cpu_rows)
+        out["cpu_baseline"] = cpu_baseline(q, t, args.cpu_rows, args.cpu_rows_single)
         log("CPU oracle sample done")
     print(json.dumps(out))
 

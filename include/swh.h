@@ -28,7 +28,9 @@
  *  - The caller owns every buffer.  Nothing keeps a caller pointer after the
  *    call returns.  Host-pointer calls are synchronous.
  *  - Every call returns a status; on failure swh_last_error() describes it.
- *    No entry point aborts, exits or throws.
+ *    No entry point aborts, exits or throws: a failed host allocation inside
+ *    the library returns SWH_E_NOMEM, any other internal exception
+ *    SWH_E_DEVICE.
  *  - A context belongs to one host thread at a time.
  */
 #ifndef SWH_H
@@ -146,6 +148,71 @@ void        swh_destroy(swh_ctx *ctx);
 const char *swh_last_error(const swh_ctx *ctx);
 
 /*
+ * Cancellation (the paper's migration notes single out error handling as the
+ * part of the port that needed most attention, Migration process; a caller
+ * that can stop a long call is part of that contract).  swh_cancel may be
+ * called from any host thread while another thread runs a call on ctx: the
+ * running call stops at its next unit of work (a strip of rows, a
+ * (query, database group) unit, a traceback level, a training step) and
+ * returns SWH_E_CANCELLED; its outputs are then undefined.  Kernels see the
+ * request through a flag in pinned host memory and drain normally.  Every
+ * entry point clears the flag when it starts, so a request made while no
+ * call runs is dropped.  The context stays usable after a cancelled call.
+ */
+swh_status  swh_cancel(swh_ctx *ctx);
+
+/*
+ * Context options.  Every option changes speed, memory or diagnostics only,
+ * never a result.  Values:
+ *   SWH_OPT_ROWS_PER_LANE  strip height of every pass: 4, 8, 16, 20, 24 or 32
+ *                          rows per lane; 0 (default) = the tuned table or the
+ *                          built-in rule
+ *   SWH_OPT_GRID           > 0: run the strip kernel as this many single-wave
+ *                          workgroups instead of the balanced placement; 0 default
+ *   SWH_OPT_BAND_ROWS      rows between the rows the score passes keep for the
+ *                          band traceback: 0 (default) = built-in, -1 = no band
+ *                          traceback, > 0 = that many (rounded up to strips)
+ *   SWH_OPT_TB_LEAF        largest leaf of the linear-space traceback, in DP
+ *                          cells (1 .. 524288); 0 (default) = the largest
+ *   SWH_OPT_GRAPH          1 (default): the prefilter's training step runs as a
+ *                          captured HIP graph; 0: plain launches
+ *   SWH_OPT_PRUNE          1 (default): block pruning of reverse passes; 0: off
+ *   SWH_OPT_MEM_CAP        bytes of device memory the context's own working
+ *                          buffers may hold (database and model handles are
+ *                          not counted); 0 (default) = no cap.  A call that
+ *                          would need more fails with SWH_E_NOMEM; optional
+ *                          buffers (rows kept for the band traceback) shrink
+ *                          to fit instead.
+ *   SWH_OPT_INT16          1 (default): local score passes of pairs run in
+ *                          packed 16-bit arithmetic where that is exact, with a
+ *                          32-bit recomputation of any pair that may have
+ *                          saturated; 0: 32-bit only
+ *   SWH_OPT_INTER_MAX      database sequences up to this length go to the
+ *                          inter-task kernel, longer ones to the single-pair
+ *                          kernel (applies to databases created afterwards);
+ *                          0 (default) = the built-in or autotuned threshold
+ *   SWH_OPT_FAULT_NOMEM    1: the next entry point on ctx fails as if a host
+ *                          allocation had thrown std::bad_alloc (after its
+ *                          argument checks), then the option resets; a test
+ *                          of the error path
+ * swh_set_option: SWH_E_INVAL for an unknown option or a value out of range.
+ */
+enum {
+    SWH_OPT_ROWS_PER_LANE = 1,
+    SWH_OPT_GRID = 2,
+    SWH_OPT_BAND_ROWS = 3,
+    SWH_OPT_TB_LEAF = 4,
+    SWH_OPT_GRAPH = 5,
+    SWH_OPT_PRUNE = 6,
+    SWH_OPT_MEM_CAP = 7,
+    SWH_OPT_INT16 = 8,
+    SWH_OPT_INTER_MAX = 9,
+    SWH_OPT_FAULT_NOMEM = 10
+};
+swh_status  swh_set_option(swh_ctx *ctx, int32_t option, int64_t value);
+swh_status  swh_get_option(const swh_ctx *ctx, int32_t option, int64_t *value);
+
+/*
  * One local alignment of query q (qlen bytes) against target t (tlen bytes),
  * host pointers.  Resolution: forward score pass (score, end).  mode >=
  * COORDS adds the reverse pass over the reversed prefixes ending at the end
@@ -198,6 +265,19 @@ swh_status swh_align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, cons
                            const char *t_cat, const int64_t *t_off, const swh_scoring *scoring,
                            int mode, swh_alignment *out, char *cigar_cat, int64_t cigar_cap,
                            int64_t *cigar_off, swh_stats *stats);
+
+/*
+ * Same as swh_align_batch with the concatenated sequences q_cat and t_cat in
+ * device memory (for example torch tensor data pointers); the offsets and
+ * every output stay in host memory.  stream is a hipStream_t (NULL = the
+ * default stream): the call's work is ordered after prior work on that
+ * stream, runs on the context's own stream, and the call returns when the
+ * results are on the host.  Inputs must stay valid until the call returns.
+ */
+swh_status swh_align_batch_dev(swh_ctx *ctx, int64_t npairs, const char *q_cat_dev, const int64_t *q_off,
+                               const char *t_cat_dev, const int64_t *t_off, const swh_scoring *scoring,
+                               int mode, void *stream, swh_alignment *out, char *cigar_cat,
+                               int64_t cigar_cap, int64_t *cigar_off, swh_stats *stats);
 
 /*
  * Strip shape of the intra-task kernel, per bucket of query rows: problems
@@ -270,6 +350,16 @@ void       swh_db_destroy(swh_db *db);
  */
 swh_status swh_db_search(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat,
                          const int64_t *q_off, int32_t k, swh_hit *hits, swh_search_stats *stats);
+
+/*
+ * Same as swh_db_search with the concatenated queries q_cat_dev in device
+ * memory (q_off, hits and stats in host memory); ordered after prior work on
+ * stream (a hipStream_t, NULL = the default stream), returns when the hits
+ * are on the host.
+ */
+swh_status swh_db_search_dev(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat_dev,
+                             const int64_t *q_off, int32_t k, void *stream, swh_hit *hits,
+                             swh_search_stats *stats);
 
 /* All scores, scores[q * ndb + i] (host buffer of nq * ndb int32). */
 swh_status swh_db_scores(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat,

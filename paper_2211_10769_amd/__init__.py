@@ -84,6 +84,21 @@ class Engine:
         if st != 0:
             raise SwhError(st, self.L.swh_last_error(self.h).decode(errors="replace"))
 
+    def set_option(self, name: str, value: int):
+        """Set a context option (speed, memory or diagnostics only): rows_per_lane,
+        grid, band_rows, tb_leaf, graph, prune, mem_cap, int16, inter_max, fault_nomem."""
+        self._check(self.L.swh_set_option(self.h, _lib.OPTIONS[name], int(value)))
+
+    def get_option(self, name: str) -> int:
+        v = ctypes.c_int64()
+        self._check(self.L.swh_get_option(self.h, _lib.OPTIONS[name], ctypes.byref(v)))
+        return v.value
+
+    def cancel(self) -> int:
+        """Ask the call running on this context (in another thread) to stop; it then
+        raises SwhError with status SWH_E_CANCELLED."""
+        return self.L.swh_cancel(self.h)
+
     @staticmethod
     def _result(a: _lib.swh_alignment, cigar, stats):
         r = dict(score=a.score, q_begin=a.q_begin, q_end=a.q_end, t_begin=a.t_begin, t_end=a.t_end,
@@ -141,7 +156,24 @@ class Engine:
         sc = Scoring.of(scoring)
         qcat, qoff = _concat(queries)
         tcat, toff = _concat(targets)
-        n = len(qoff) - 1
+        return self._batch(len(qoff) - 1, qcat.ctypes.data if len(qcat) else None, qoff,
+                           tcat.ctypes.data if len(tcat) else None, toff, sc, mode, stats, alignment, None)
+
+    def align_batch_dev(self, q_tensor, q_off, t_tensor, t_off, scoring, mode: str = "cigar", stream=None,
+                        stats: bool = False, alignment: str = "local"):
+        """Many pairs from concatenated uint8 ASCII torch tensors on the GPU; q_off and
+        t_off are host int64 offsets (pair i = q[q_off[i]:q_off[i+1]] vs t[t_off[i]:t_off[i+1]])."""
+        sc = Scoring.of(scoring)
+        qoff = np.ascontiguousarray(q_off, dtype=np.int64)
+        toff = np.ascontiguousarray(t_off, dtype=np.int64)
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        return self._batch(len(qoff) - 1, q_tensor.data_ptr() if q_tensor.numel() else None, qoff,
+                           t_tensor.data_ptr() if t_tensor.numel() else None, toff, sc, mode, stats, alignment,
+                           stream)
+
+    def _batch(self, n, qptr, qoff, tptr, toff, sc, mode, stats, alignment, stream):
         if len(toff) - 1 != n:
             raise ValueError("queries and targets differ in count")
         m = _MODES[mode]
@@ -154,12 +186,13 @@ class Engine:
         # library writes are read back
         cap = int(2 * (qoff[-1] - qoff[0] + toff[-1] - toff[0]) + 16) if m == MODE_CIGAR else 0
         buf = np.empty(cap, dtype=np.uint8) if cap else None
-        args = [self.h, n, qcat.ctypes.data if len(qcat) else None, qoff.ctypes.data,
-                tcat.ctypes.data if len(tcat) else None, toff.ctypes.data, ctypes.byref(sc.c), m | g,
-                out.ctypes.data, buf.ctypes.data if buf is not None else None, cap,
-                coff.ctypes.data if m == MODE_CIGAR else None,
-                ctypes.byref(st_obj) if st_obj is not None else None]
-        self._check(self.L.swh_align_batch(*args))
+        tail = [out.ctypes.data, buf.ctypes.data if buf is not None else None, cap,
+                coff.ctypes.data if m == MODE_CIGAR else None, ctypes.byref(st_obj) if st_obj is not None else None]
+        head = [self.h, n, qptr, qoff.ctypes.data, tptr, toff.ctypes.data, ctypes.byref(sc.c), m | g]
+        if stream is None:
+            self._check(self.L.swh_align_batch(*head, *tail))
+        else:
+            self._check(self.L.swh_align_batch_dev(*head, stream, *tail))
         cols = [out[k][:n].tolist() for k in ("score", "q_begin", "q_end", "t_begin", "t_end", "flags")]
         if m == MODE_CIGAR:
             text = buf[:int(coff[n])].tobytes().decode()
@@ -244,6 +277,23 @@ class Database:
         st = _lib.swh_search_stats(ctypes.sizeof(_lib.swh_search_stats))
         rc = self.eng.L.swh_db_search(self.eng.h, self.h, nq, cat.ctypes.data if len(cat) else None,
                                       off.ctypes.data, k, hits, ctypes.byref(st))
+        self.eng._check(rc)
+        idx = np.array([hits[i].db_index for i in range(nq * k)], dtype=np.int64).reshape(nq, k)
+        sco = np.array([hits[i].score for i in range(nq * k)], dtype=np.int32).reshape(nq, k)
+        return idx, sco, self._stats(st)
+
+    def search_dev(self, q_tensor, q_off, k: int = 10, stream=None):
+        """search() with the concatenated queries in a uint8 ASCII torch tensor on the GPU
+        (q_off: host int64 offsets)."""
+        off = np.ascontiguousarray(q_off, dtype=np.int64)
+        nq = len(off) - 1
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        hits = (_lib.swh_hit * max(1, nq * k))()
+        st = _lib.swh_search_stats(ctypes.sizeof(_lib.swh_search_stats))
+        rc = self.eng.L.swh_db_search_dev(self.eng.h, self.h, nq, q_tensor.data_ptr() if q_tensor.numel() else None,
+                                          off.ctypes.data, k, stream, hits, ctypes.byref(st))
         self.eng._check(rc)
         idx = np.array([hits[i].db_index for i in range(nq * k)], dtype=np.int64).reshape(nq, k)
         sco = np.array([hits[i].score for i in range(nq * k)], dtype=np.int32).reshape(nq, k)

@@ -15,6 +15,9 @@ SWH_OK = 0
 STATUS_NAMES = {0: "SWH_OK", -1: "SWH_E_INVAL", -2: "SWH_E_ALPHABET", -3: "SWH_E_NOMEM",
                 -4: "SWH_E_RANGE", -5: "SWH_E_DEVICE", -6: "SWH_E_TIMEOUT", -7: "SWH_E_CANCELLED"}
 MODE_SCORE, MODE_COORDS, MODE_CIGAR = 0, 1, 2
+# context options (swh_set_option)
+OPTIONS = {"rows_per_lane": 1, "grid": 2, "band_rows": 3, "tb_leaf": 4, "graph": 5, "prune": 6, "mem_cap": 7,
+           "int16": 8, "inter_max": 9, "fault_nomem": 10}
 GLOBAL = 0x100          # OR'd into mode: global (Needleman-Wunsch) alignment
 SEMIGLOBAL = 0x200      # OR'd into mode: semi-global (whole query, free target ends)
 OVERLAP = 0x400         # OR'd into mode: overlap (end gaps of both sequences free)
@@ -86,6 +89,9 @@ SIGNATURES = {
     "swh_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_P)]),
     "swh_destroy": (None, [_P]),
     "swh_last_error": (ctypes.c_char_p, [_P]),
+    "swh_cancel": (ctypes.c_int, [_P]),
+    "swh_set_option": (ctypes.c_int, [_P, ctypes.c_int32, _I64]),
+    "swh_get_option": (ctypes.c_int, [_P, ctypes.c_int32, _I64P]),
     "swh_align": (ctypes.c_int, [_P, _P, _I64, _P, _I64, ctypes.POINTER(swh_scoring), ctypes.c_int,
                                  ctypes.POINTER(swh_alignment), _P, _I64, _I64P,
                                  ctypes.POINTER(swh_stats)]),
@@ -94,6 +100,8 @@ SIGNATURES = {
                                      ctypes.POINTER(swh_stats)]),
     "swh_align_batch": (ctypes.c_int, [_P, _I64, _P, _P, _P, _P, ctypes.POINTER(swh_scoring), ctypes.c_int,
                                        _P, _P, _I64, _P, ctypes.POINTER(swh_stats)]),
+    "swh_align_batch_dev": (ctypes.c_int, [_P, _I64, _P, _P, _P, _P, ctypes.POINTER(swh_scoring), ctypes.c_int,
+                                           _P, _P, _P, _I64, _P, ctypes.POINTER(swh_stats)]),
     "swh_autotune": (ctypes.c_int, [_P, ctypes.POINTER(swh_scoring), _I64, ctypes.c_double]),
     "swh_tune_get": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "swh_tune_set": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
@@ -117,6 +125,8 @@ SIGNATURES = {
     "swh_db_destroy": (None, [_P]),
     "swh_db_search": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P,
                                      ctypes.POINTER(swh_search_stats)]),
+    "swh_db_search_dev": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P,
+                                         ctypes.POINTER(swh_search_stats)]),
     "swh_db_scores": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P, _P, ctypes.POINTER(swh_search_stats)]),
 }
 
@@ -130,6 +140,15 @@ def load() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library {LIB_PATH} is not built; run "
                                "`python -c 'import __graft_entry__ as g; g.build()'`")
+        # PyTorch ships its own HIP runtime under the same soname
+        # (libamdhip64.so.7).  Loaded first, it is the one libswh.so binds to,
+        # so the process holds a single runtime and device pointers and
+        # streams from torch are valid in the library; loaded after libswh.so
+        # it would be a second runtime that cannot initialise the device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)

@@ -251,7 +251,7 @@ swh_status global_scores(swh_ctx *ctx, const std::vector<PairPass> &ps, const Sc
 
 swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const int64_t *q_off, const char *t_cat,
                        const int64_t *t_off, const Scoring &sc, int mode, swh_alignment *out, char *cigar_cat,
-                       int64_t cigar_cap, int64_t *cigar_off, swh_stats *stats)
+                       int64_t cigar_cap, int64_t *cigar_off, swh_stats *stats, bool dev)
 {
     if (stats) {
         const uint32_t size = stats->struct_size;
@@ -276,9 +276,10 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
     swh_status s;
     hipError_t e;
 
-    // ---- encode both concatenations once
-    if ((s = ensure(ctx, ctx->qraw, (size_t)qtot + 1, "query copy")) != SWH_OK ||
-        (s = ensure(ctx, ctx->traw, (size_t)ttot + 1, "target copy")) != SWH_OK ||
+    // ---- encode both concatenations once (host inputs through a device copy,
+    // device inputs in place)
+    if ((!dev && (s = ensure(ctx, ctx->qraw, (size_t)qtot + 1, "query copy")) != SWH_OK) ||
+        (!dev && (s = ensure(ctx, ctx->traw, (size_t)ttot + 1, "target copy")) != SWH_OK) ||
         (s = ensure(ctx, ctx->qc, (size_t)qtot + 1, "query codes")) != SWH_OK ||
         (s = ensure(ctx, ctx->tc, (size_t)ttot + 1, "target codes")) != SWH_OK ||
         (s = ensure(ctx, ctx->misc, 64, "scratch words")) != SWH_OK ||
@@ -288,19 +289,21 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
     static const int32_t init[2] = {INT32_MAX, INT32_MAX};
     int32_t *misc = (int32_t *)ctx->misc.p;
     const uint8_t pad = (uint8_t)sc.asize;
-    if ((qtot && (e = hipMemcpyAsync(ctx->qraw.p, q_cat + qbase, (size_t)qtot, hipMemcpyHostToDevice, st)) !=
-                     hipSuccess) ||
-        (ttot && (e = hipMemcpyAsync(ctx->traw.p, t_cat + tbase, (size_t)ttot, hipMemcpyHostToDevice, st)) !=
-                     hipSuccess) ||
+    if ((!dev && qtot &&
+         (e = hipMemcpyAsync(ctx->qraw.p, q_cat + qbase, (size_t)qtot, hipMemcpyHostToDevice, st)) != hipSuccess) ||
+        (!dev && ttot &&
+         (e = hipMemcpyAsync(ctx->traw.p, t_cat + tbase, (size_t)ttot, hipMemcpyHostToDevice, st)) != hipSuccess) ||
         (e = hipMemcpyAsync(misc, init, sizeof(init), hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = hipMemcpyAsync(ctx->mat.p, sc.mat, (size_t)sc.asize * sc.asize, hipMemcpyHostToDevice, st)) !=
             hipSuccess ||
         (e = hipMemcpyAsync(ctx->lut.p, sc.lut, 256, hipMemcpyHostToDevice, st)) != hipSuccess)
         return hip_fail(ctx, e, "batch upload");
-    if ((e = launch_encode((const char *)ctx->qraw.p, qtot, (uint8_t *)ctx->qc.p, qtot, (const uint8_t *)ctx->lut.p,
-                           pad, misc, st)) != hipSuccess ||
-        (e = launch_encode((const char *)ctx->traw.p, ttot, (uint8_t *)ctx->tc.p, ttot, (const uint8_t *)ctx->lut.p,
-                           pad, misc + 1, st)) != hipSuccess)
+    const char *qsrc = dev ? q_cat + qbase : (const char *)ctx->qraw.p;
+    const char *tsrc = dev ? t_cat + tbase : (const char *)ctx->traw.p;
+    if ((e = launch_encode(qsrc, qtot, (uint8_t *)ctx->qc.p, qtot, (const uint8_t *)ctx->lut.p, pad, misc, st)) !=
+            hipSuccess ||
+        (e = launch_encode(tsrc, ttot, (uint8_t *)ctx->tc.p, ttot, (const uint8_t *)ctx->lut.p, pad, misc + 1,
+                           st)) != hipSuccess)
         return hip_fail(ctx, e, "encode kernel launch");
     int32_t bad[2];
     if ((e = hipMemcpyAsync(bad, misc, 8, hipMemcpyDeviceToHost, st)) != hipSuccess ||
@@ -544,7 +547,7 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
             stats->cells_traceback = ts.cells;
         }
     } else {
-    const int forced = env_int("SWH_BAND_ROWS", 0);
+    const int forced = ctx->opt.band_rows;
     const bool banded = mode == SWH_MODE_CIGAR && forced >= 0;
     std::vector<BandKeep> bk((size_t)npairs);
     std::vector<int64_t> frecs((size_t)npairs, 0);
@@ -565,6 +568,7 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
             budget = std::min<int64_t>(budget, (int64_t)(free_b / 8 / sizeof(Border)));
         else
             (void)hipGetLastError();
+        budget = std::min<int64_t>(budget, (int64_t)std::min<size_t>(cap_room(ctx) / 4 / sizeof(Border), INT64_MAX));
     }
     TracebackStats ts;
     double ms_fwd = 0.0, ms_rev = 0.0;
@@ -625,7 +629,7 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
         std::vector<PairPass> rp;
         rp.reserve(pos_pairs.size());
         int64_t rrecs = 0;
-        const bool prune = env_int("SWH_PRUNE", 1) != 0;
+        const bool prune = ctx->opt.prune != 0;
         for (int64_t i : pos_pairs) {
             PairPass p{ps[i].q + out[i].q_end, out[i].q_end + 1, ps[i].t + out[i].t_end, out[i].t_end + 1, -1};
             p.prune = prune ? out[i].score : 0;   // the reverse maximum is the forward score

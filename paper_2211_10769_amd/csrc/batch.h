@@ -55,8 +55,9 @@ swh_status set_matrix(swh_ctx *ctx, const Scoring &sc, bool transposed, hipStrea
 swh_status global_scores(swh_ctx *ctx, const std::vector<PairPass> &ps, const Scoring &sc, hipStream_t st,
                          std::vector<int32_t> &scores, double &ms_total);
 
+// dev: q_cat and t_cat are device pointers (encoded in place), else host pointers.
 swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const int64_t *q_off, const char *t_cat,
                        const int64_t *t_off, const Scoring &sc, int mode, swh_alignment *out, char *cigar_cat,
-                       int64_t cigar_cap, int64_t *cigar_off, swh_stats *stats);
+                       int64_t cigar_cap, int64_t *cigar_off, swh_stats *stats, bool dev = false);
 
 }  // namespace swh

@@ -1,8 +1,17 @@
 // capi.cpp -- the extern "C" entry points of libswh.so (declared in
 // include/swh.h): argument validation, context lifetime, error text.
+//
+// Every entry point runs its body inside guarded(): nothing thrown inside the
+// library (std::bad_alloc from a host container, anything else) crosses the
+// C ABI.  A failed host allocation becomes SWH_E_NOMEM, any other exception
+// SWH_E_DEVICE; device work already queued is drained first, so no queued
+// copy can still write into a host buffer of the aborted call.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdint>
 #include <cstring>
+#include <exception>
 #include <new>
 #include <string>
 
@@ -28,13 +37,24 @@ swh_status hip_fail(swh_ctx *ctx, hipError_t e, const char *what)
 swh_status ensure(swh_ctx *ctx, DevBuf &buf, size_t bytes, const char *what)
 {
     if (buf.cap >= bytes && buf.p) return SWH_OK;
+    // buffers that are members of the context count towards its memory cap
+    const bool own = (const char *)&buf >= (const char *)ctx && (const char *)&buf < (const char *)(ctx + 1);
     if (buf.p) {
         hipDeviceSynchronize();
         hipFree(buf.p);
+        if (own) ctx->held -= buf.cap;
         buf.p = nullptr;
         buf.cap = 0;
     }
     size_t want = bytes < 4096 ? 4096 : bytes + bytes / 8;
+    if (own && ctx->opt.mem_cap > 0) {
+        const size_t cap = (size_t)ctx->opt.mem_cap;
+        if (ctx->held + want > cap) want = std::max<size_t>(bytes, 1);
+        if (ctx->held + want > cap)
+            return fail(ctx, SWH_E_NOMEM, std::string(what) + " needs " + std::to_string(want) +
+                                              " bytes beyond the context's memory cap of " + std::to_string(cap) +
+                                              " (" + std::to_string(ctx->held) + " held)");
+    }
     hipError_t e = hipMalloc(&buf.p, want);
     if (e != hipSuccess) {
         buf.p = nullptr;
@@ -42,8 +62,18 @@ swh_status ensure(swh_ctx *ctx, DevBuf &buf, size_t bytes, const char *what)
         return fail(ctx, SWH_E_NOMEM, std::string("cannot allocate ") + std::to_string(want) + " bytes for " + what);
     }
     buf.cap = want;
+    if (own) ctx->held += want;
     return SWH_OK;
 }
+
+size_t cap_room(const swh_ctx *ctx)
+{
+    if (ctx->opt.mem_cap <= 0) return SIZE_MAX;
+    const size_t cap = (size_t)ctx->opt.mem_cap;
+    return ctx->held >= cap ? 0 : cap - ctx->held;
+}
+
+swh_status cancel_status(swh_ctx *ctx) { return fail(ctx, SWH_E_CANCELLED, "cancelled by swh_cancel"); }
 
 swh_status make_scoring(swh_ctx *ctx, const swh_scoring *in, Scoring &out)
 {
@@ -76,6 +106,66 @@ swh_status make_scoring(swh_ctx *ctx, const swh_scoring *in, Scoring &out)
 }
 
 namespace {
+
+void set_err_noexcept(swh_ctx *ctx, const char *msg) noexcept
+{
+    if (!ctx) return;
+    try {
+        ctx->err = msg;
+    } catch (...) {
+        ctx->err.clear();
+    }
+}
+
+// The exception barrier of every entry point (see the file comment).
+template <class F>
+swh_status guarded(swh_ctx *ctx, F &&body) noexcept
+{
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        (void)hipDeviceSynchronize();
+        set_err_noexcept(ctx, "host memory allocation failed inside the library (std::bad_alloc)");
+        return SWH_E_NOMEM;
+    } catch (const std::exception &x) {
+        (void)hipDeviceSynchronize();
+        if (ctx) {
+            try {
+                ctx->err = std::string("internal error: ") + x.what();
+            } catch (...) {
+                ctx->err.clear();
+            }
+        }
+        return SWH_E_DEVICE;
+    } catch (...) {
+        (void)hipDeviceSynchronize();
+        set_err_noexcept(ctx, "internal error (unknown exception)");
+        return SWH_E_DEVICE;
+    }
+}
+
+// Start of the work of an entry point, after its argument checks: the
+// device, a cleared cancellation flag, and the fault-injection option.
+swh_status begin_call(swh_ctx *ctx)
+{
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SWH_E_DEVICE, "hipSetDevice failed");
+    if (ctx->cancel_host) __atomic_store_n(ctx->cancel_host, 0, __ATOMIC_RELEASE);
+    if (ctx->opt.fault_nomem) {
+        ctx->opt.fault_nomem = 0;
+        throw std::bad_alloc();
+    }
+    return SWH_OK;
+}
+
+// Make the context's stream wait for the work queued so far on the caller's stream.
+swh_status order_after(swh_ctx *ctx, void *stream)
+{
+    hipError_t e;
+    if ((e = hipEventRecord(ctx->ev_in, (hipStream_t)stream)) != hipSuccess ||
+        (e = hipStreamWaitEvent(ctx->own_stream, ctx->ev_in, 0)) != hipSuccess)
+        return hip_fail(ctx, e, "stream ordering");
+    return SWH_OK;
+}
 
 swh_status check_pair(swh_ctx *ctx, const void *q, int64_t qlen, const void *t, int64_t tlen, const Scoring &sc,
                       int mode, swh_alignment *out)
@@ -112,102 +202,48 @@ swh_status check_pair(swh_ctx *ctx, const void *q, int64_t qlen, const void *t, 
 
 using namespace swh;
 
-extern "C" {
+namespace {
 
-swh_status swh_create(int device, swh_ctx **out)
+swh_status search_common(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off,
+                         int32_t k, swh_hit *hits, int32_t *scores, swh_search_stats *stats, void *dev_stream,
+                         bool dev)
 {
-    if (!out) return SWH_E_INVAL;
-    *out = nullptr;
-    int count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
-        (void)hipGetLastError();
-        return SWH_E_DEVICE;
+    ctx->err.clear();
+    if (!db) return fail(ctx, SWH_E_INVAL, "database is NULL");
+    if (db->device != ctx->device) return fail(ctx, SWH_E_INVAL, "database lives on another device");
+    if (nq < 0 || (nq > 0 && (!q_off || (!q_cat && q_off[nq] > q_off[0]))))
+        return fail(ctx, SWH_E_INVAL, "bad query arguments");
+    if (hits && (k < 1 || k > 32)) return fail(ctx, SWH_E_INVAL, "k must be in 1..32");
+    if (stats && stats->struct_size < sizeof(swh_search_stats))
+        return fail(ctx, SWH_E_INVAL, "stats->struct_size too small");
+    swh_status s = begin_call(ctx);
+    if (s != SWH_OK) return s;
+    if (dev && (s = order_after(ctx, dev_stream)) != SWH_OK) return s;
+    DbStats ds;
+    s = db_search(ctx, db, nq, q_cat, q_off, k, hits, scores, ds, dev);
+    if (s == SWH_OK && stats) {
+        stats->cells = ds.cells;
+        stats->ms_inter = ds.ms_inter;
+        stats->ms_intra = ds.ms_intra;
+        stats->ms_topk = ds.ms_topk;
+        stats->saturated = ds.redo;
+        stats->intra_pairs = ds.intra_pairs;
     }
-    if (device < 0 || device >= count) return SWH_E_INVAL;
-    swh_ctx *ctx = new (std::nothrow) swh_ctx();
-    if (!ctx) return SWH_E_NOMEM;
-    ctx->device = device;
-    if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking) != hipSuccess) {
-        delete ctx;
-        return SWH_E_DEVICE;
-    }
-    for (auto &ev : ctx->ev) {
-        if (hipEventCreate(&ev) != hipSuccess) {
-            swh_destroy(ctx);
-            return SWH_E_DEVICE;
-        }
-    }
-    hipDeviceProp_t p;
-    if (hipGetDeviceProperties(&p, device) == hipSuccess) ctx->num_cu = p.multiProcessorCount;
-    *out = ctx;
+    return s;
+}
+
+swh_status model_ok(swh_ctx *ctx, const swh_model *m)
+{
+    if (!m) return fail(ctx, SWH_E_INVAL, "model is NULL");
+    if (m->device != ctx->device) return fail(ctx, SWH_E_INVAL, "model lives on another device");
     return SWH_OK;
 }
 
-void swh_destroy(swh_ctx *ctx)
+swh_status batch_common(swh_ctx *ctx, int64_t npairs, const char *q_cat, const int64_t *q_off, const char *t_cat,
+                        const int64_t *t_off, const swh_scoring *scoring, int mode, swh_alignment *out,
+                        char *cigar_cat, int64_t cigar_cap, int64_t *cigar_off, swh_stats *stats, void *dev_stream,
+                        bool dev)
 {
-    if (!ctx) return;
-    hipSetDevice(ctx->device);
-    if (ctx->own_stream) hipStreamSynchronize(ctx->own_stream);
-    for (DevBuf *b : ctx->all())
-        if (b->p) hipFree(b->p);
-    ctx->tb_arena.free_all();
-    for (auto &ev : ctx->ev)
-        if (ev) hipEventDestroy(ev);
-    if (ctx->own_stream) hipStreamDestroy(ctx->own_stream);
-    delete ctx;
-}
-
-const char *swh_last_error(const swh_ctx *ctx)
-{
-    if (!ctx) return "no context";
-    return ctx->err.c_str();
-}
-
-swh_status swh_align(swh_ctx *ctx, const char *q, int64_t qlen, const char *t, int64_t tlen,
-                     const swh_scoring *scoring, int mode, swh_alignment *out, char *cigar, int64_t cigar_cap,
-                     int64_t *cigar_len, swh_stats *stats)
-{
-    if (!ctx) return SWH_E_INVAL;
-    ctx->err.clear();
-    Scoring sc;
-    swh_status s = make_scoring(ctx, scoring, sc);
-    if (s != SWH_OK) return s;
-    if ((s = check_pair(ctx, q, qlen, t, tlen, sc, mode, out)) != SWH_OK) return s;
-    if (stats && stats->struct_size < sizeof(swh_stats)) return fail(ctx, SWH_E_INVAL, "stats->struct_size too small");
-    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SWH_E_DEVICE, "hipSetDevice failed");
-    hipStream_t st = ctx->own_stream;
-    if ((s = ensure(ctx, ctx->qraw, (size_t)qlen + 1, "query copy")) != SWH_OK) return s;
-    if ((s = ensure(ctx, ctx->traw, (size_t)tlen + 1, "target copy")) != SWH_OK) return s;
-    hipError_t e;
-    if (qlen && (e = hipMemcpyAsync(ctx->qraw.p, q, (size_t)qlen, hipMemcpyHostToDevice, st)) != hipSuccess)
-        return hip_fail(ctx, e, "hipMemcpyAsync(query)");
-    if (tlen && (e = hipMemcpyAsync(ctx->traw.p, t, (size_t)tlen, hipMemcpyHostToDevice, st)) != hipSuccess)
-        return hip_fail(ctx, e, "hipMemcpyAsync(target)");
-    return align_device(ctx, (const char *)ctx->qraw.p, qlen, (const char *)ctx->traw.p, tlen, sc, mode, st, out,
-                        cigar, cigar_cap, cigar_len, stats);
-}
-
-swh_status swh_align_dev(swh_ctx *ctx, const char *q_dev, int64_t qlen, const char *t_dev, int64_t tlen,
-                         const swh_scoring *scoring, int mode, void *stream, swh_alignment *out, char *cigar,
-                         int64_t cigar_cap, int64_t *cigar_len, swh_stats *stats)
-{
-    if (!ctx) return SWH_E_INVAL;
-    ctx->err.clear();
-    Scoring sc;
-    swh_status s = make_scoring(ctx, scoring, sc);
-    if (s != SWH_OK) return s;
-    if ((s = check_pair(ctx, q_dev, qlen, t_dev, tlen, sc, mode, out)) != SWH_OK) return s;
-    if (stats && stats->struct_size < sizeof(swh_stats)) return fail(ctx, SWH_E_INVAL, "stats->struct_size too small");
-    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SWH_E_DEVICE, "hipSetDevice failed");
-    return align_device(ctx, q_dev, qlen, t_dev, tlen, sc, mode, (hipStream_t)stream, out, cigar, cigar_cap,
-                        cigar_len, stats);
-}
-
-swh_status swh_align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const int64_t *q_off, const char *t_cat,
-                           const int64_t *t_off, const swh_scoring *scoring, int mode, swh_alignment *out,
-                           char *cigar_cat, int64_t cigar_cap, int64_t *cigar_off, swh_stats *stats)
-{
-    if (!ctx) return SWH_E_INVAL;
     ctx->err.clear();
     Scoring sc;
     swh_status s = make_scoring(ctx, scoring, sc);
@@ -230,23 +266,248 @@ swh_status swh_align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, cons
             SWH_OK)
             return fail(ctx, s, "pair " + std::to_string(i) + ": " + ctx->err);
     }
-    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SWH_E_DEVICE, "hipSetDevice failed");
-    return align_batch(ctx, npairs, q_cat, q_off, t_cat, t_off, sc, mode, out, cigar_cat, cigar_cap, cigar_off,
-                       stats);
+    if ((s = begin_call(ctx)) != SWH_OK) return s;
+    if (dev && (s = order_after(ctx, dev_stream)) != SWH_OK) return s;
+    return align_batch(ctx, npairs, q_cat, q_off, t_cat, t_off, sc, mode, out, cigar_cat, cigar_cap, cigar_off, stats,
+                       dev);
+}
+
+}  // namespace
+
+extern "C" {
+
+swh_status swh_create(int device, swh_ctx **out)
+{
+    return guarded(nullptr, [&]() -> swh_status {
+        if (!out) return SWH_E_INVAL;
+        *out = nullptr;
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+            (void)hipGetLastError();
+            return SWH_E_DEVICE;
+        }
+        if (device < 0 || device >= count) return SWH_E_INVAL;
+        swh_ctx *ctx = new (std::nothrow) swh_ctx();
+        if (!ctx) return SWH_E_NOMEM;
+        ctx->device = device;
+        if (hipSetDevice(device) != hipSuccess ||
+            hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx;
+            return SWH_E_DEVICE;
+        }
+        bool ok = hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming) == hipSuccess;
+        for (auto &ev : ctx->ev) ok = ok && hipEventCreate(&ev) == hipSuccess;
+        // the cancellation flag: pinned, coherent host memory the kernels read uncached
+        void *hp = nullptr, *dp = nullptr;
+        ok = ok && hipHostMalloc(&hp, 64, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess;
+        if (hp) {
+            ctx->cancel_host = (int32_t *)hp;
+            *ctx->cancel_host = 0;
+            ok = ok && hipHostGetDevicePointer(&dp, hp, 0) == hipSuccess;
+            ctx->cancel_dev = (int32_t *)dp;
+        }
+        if (!ok) {
+            (void)hipGetLastError();
+            swh_destroy(ctx);
+            return SWH_E_DEVICE;
+        }
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, device) == hipSuccess) ctx->num_cu = p.multiProcessorCount;
+        *out = ctx;
+        return SWH_OK;
+    });
+}
+
+void swh_destroy(swh_ctx *ctx)
+{
+    if (!ctx) return;
+    try {
+        hipSetDevice(ctx->device);
+        if (ctx->own_stream) hipStreamSynchronize(ctx->own_stream);
+        for (DevBuf *b : ctx->all())
+            if (b->p) hipFree(b->p);
+        ctx->tb_arena.free_all(ctx->held);
+        for (auto &ev : ctx->ev)
+            if (ev) hipEventDestroy(ev);
+        if (ctx->ev_in) hipEventDestroy(ctx->ev_in);
+        if (ctx->cancel_host) hipHostFree(ctx->cancel_host);
+        if (ctx->own_stream) hipStreamDestroy(ctx->own_stream);
+        delete ctx;
+    } catch (...) {
+    }
+}
+
+const char *swh_last_error(const swh_ctx *ctx)
+{
+    if (!ctx) return "no context";
+    return ctx->err.c_str();
+}
+
+swh_status swh_cancel(swh_ctx *ctx)
+{
+    // may run on another thread than the call it stops: touches only the flag
+    if (!ctx || !ctx->cancel_host) return SWH_E_INVAL;
+    __atomic_store_n(ctx->cancel_host, 1, __ATOMIC_RELEASE);
+    return SWH_OK;
+}
+
+swh_status swh_set_option(swh_ctx *ctx, int32_t option, int64_t value)
+{
+    if (!ctx) return SWH_E_INVAL;
+    return guarded(ctx, [&]() -> swh_status {
+        ctx->err.clear();
+        Options &o = ctx->opt;
+        auto bad = [&](const char *what) { return fail(ctx, SWH_E_INVAL, std::string("option value: ") + what); };
+        switch (option) {
+        case SWH_OPT_ROWS_PER_LANE:
+            if (value != 0 && value != 4 && value != 8 && value != 16 && value != 20 && value != 24 && value != 32)
+                return bad("rows per lane must be 0, 4, 8, 16, 20, 24 or 32");
+            o.rows = (int32_t)value;
+            return SWH_OK;
+        case SWH_OPT_GRID:
+            if (value < 0 || value > (1 << 20)) return bad("grid must be in 0 .. 2^20");
+            o.grid = (int32_t)value;
+            return SWH_OK;
+        case SWH_OPT_BAND_ROWS:
+            if (value < -1 || value > (1 << 30)) return bad("band rows must be -1, 0 or a positive row count");
+            o.band_rows = (int32_t)value;
+            return SWH_OK;
+        case SWH_OPT_TB_LEAF:
+            if (value < 0 || value > 524288) return bad("leaf cells must be in 0 .. 524288");
+            o.tb_leaf = value;
+            return SWH_OK;
+        case SWH_OPT_GRAPH:
+            if (value != 0 && value != 1) return bad("graph must be 0 or 1");
+            o.graph = (int32_t)value;
+            return SWH_OK;
+        case SWH_OPT_PRUNE:
+            if (value != 0 && value != 1) return bad("prune must be 0 or 1");
+            o.prune = (int32_t)value;
+            return SWH_OK;
+        case SWH_OPT_MEM_CAP:
+            if (value < 0) return bad("memory cap must be >= 0");
+            o.mem_cap = value;
+            return SWH_OK;
+        case SWH_OPT_INT16:
+            if (value != 0 && value != 1) return bad("int16 must be 0 or 1");
+            o.int16 = (int32_t)value;
+            return SWH_OK;
+        case SWH_OPT_INTER_MAX:
+            if (value != 0 && (value < 32 || value > 8192)) return bad("inter-task maximum must be 0 or 32 .. 8192");
+            o.inter_max = (int32_t)value;
+            return SWH_OK;
+        case SWH_OPT_FAULT_NOMEM:
+            if (value != 0 && value != 1) return bad("fault injection must be 0 or 1");
+            o.fault_nomem = (int32_t)value;
+            return SWH_OK;
+        default:
+            return fail(ctx, SWH_E_INVAL, "unknown option " + std::to_string(option));
+        }
+    });
+}
+
+swh_status swh_get_option(const swh_ctx *ctx, int32_t option, int64_t *value)
+{
+    if (!ctx || !value) return SWH_E_INVAL;
+    const Options &o = ctx->opt;
+    switch (option) {
+    case SWH_OPT_ROWS_PER_LANE: *value = o.rows; return SWH_OK;
+    case SWH_OPT_GRID: *value = o.grid; return SWH_OK;
+    case SWH_OPT_BAND_ROWS: *value = o.band_rows; return SWH_OK;
+    case SWH_OPT_TB_LEAF: *value = o.tb_leaf; return SWH_OK;
+    case SWH_OPT_GRAPH: *value = o.graph; return SWH_OK;
+    case SWH_OPT_PRUNE: *value = o.prune; return SWH_OK;
+    case SWH_OPT_MEM_CAP: *value = o.mem_cap; return SWH_OK;
+    case SWH_OPT_INT16: *value = o.int16; return SWH_OK;
+    case SWH_OPT_INTER_MAX: *value = o.inter_max; return SWH_OK;
+    case SWH_OPT_FAULT_NOMEM: *value = o.fault_nomem; return SWH_OK;
+    default: return SWH_E_INVAL;
+    }
+}
+
+swh_status swh_align(swh_ctx *ctx, const char *q, int64_t qlen, const char *t, int64_t tlen,
+                     const swh_scoring *scoring, int mode, swh_alignment *out, char *cigar, int64_t cigar_cap,
+                     int64_t *cigar_len, swh_stats *stats)
+{
+    if (!ctx) return SWH_E_INVAL;
+    return guarded(ctx, [&]() -> swh_status {
+        ctx->err.clear();
+        Scoring sc;
+        swh_status s = make_scoring(ctx, scoring, sc);
+        if (s != SWH_OK) return s;
+        if ((s = check_pair(ctx, q, qlen, t, tlen, sc, mode, out)) != SWH_OK) return s;
+        if (stats && stats->struct_size < sizeof(swh_stats))
+            return fail(ctx, SWH_E_INVAL, "stats->struct_size too small");
+        if ((s = begin_call(ctx)) != SWH_OK) return s;
+        hipStream_t st = ctx->own_stream;
+        if ((s = ensure(ctx, ctx->qraw, (size_t)qlen + 1, "query copy")) != SWH_OK) return s;
+        if ((s = ensure(ctx, ctx->traw, (size_t)tlen + 1, "target copy")) != SWH_OK) return s;
+        hipError_t e;
+        if (qlen && (e = hipMemcpyAsync(ctx->qraw.p, q, (size_t)qlen, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return hip_fail(ctx, e, "hipMemcpyAsync(query)");
+        if (tlen && (e = hipMemcpyAsync(ctx->traw.p, t, (size_t)tlen, hipMemcpyHostToDevice, st)) != hipSuccess)
+            return hip_fail(ctx, e, "hipMemcpyAsync(target)");
+        return align_device(ctx, (const char *)ctx->qraw.p, qlen, (const char *)ctx->traw.p, tlen, sc, mode, st, out,
+                            cigar, cigar_cap, cigar_len, stats);
+    });
+}
+
+swh_status swh_align_dev(swh_ctx *ctx, const char *q_dev, int64_t qlen, const char *t_dev, int64_t tlen,
+                         const swh_scoring *scoring, int mode, void *stream, swh_alignment *out, char *cigar,
+                         int64_t cigar_cap, int64_t *cigar_len, swh_stats *stats)
+{
+    if (!ctx) return SWH_E_INVAL;
+    return guarded(ctx, [&]() -> swh_status {
+        ctx->err.clear();
+        Scoring sc;
+        swh_status s = make_scoring(ctx, scoring, sc);
+        if (s != SWH_OK) return s;
+        if ((s = check_pair(ctx, q_dev, qlen, t_dev, tlen, sc, mode, out)) != SWH_OK) return s;
+        if (stats && stats->struct_size < sizeof(swh_stats))
+            return fail(ctx, SWH_E_INVAL, "stats->struct_size too small");
+        if ((s = begin_call(ctx)) != SWH_OK) return s;
+        return align_device(ctx, q_dev, qlen, t_dev, tlen, sc, mode, (hipStream_t)stream, out, cigar, cigar_cap,
+                            cigar_len, stats);
+    });
+}
+
+swh_status swh_align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const int64_t *q_off, const char *t_cat,
+                           const int64_t *t_off, const swh_scoring *scoring, int mode, swh_alignment *out,
+                           char *cigar_cat, int64_t cigar_cap, int64_t *cigar_off, swh_stats *stats)
+{
+    if (!ctx) return SWH_E_INVAL;
+    return guarded(ctx, [&]() -> swh_status {
+        return batch_common(ctx, npairs, q_cat, q_off, t_cat, t_off, scoring, mode, out, cigar_cat, cigar_cap,
+                            cigar_off, stats, nullptr, false);
+    });
+}
+
+swh_status swh_align_batch_dev(swh_ctx *ctx, int64_t npairs, const char *q_cat_dev, const int64_t *q_off,
+                               const char *t_cat_dev, const int64_t *t_off, const swh_scoring *scoring, int mode,
+                               void *stream, swh_alignment *out, char *cigar_cat, int64_t cigar_cap,
+                               int64_t *cigar_off, swh_stats *stats)
+{
+    if (!ctx) return SWH_E_INVAL;
+    return guarded(ctx, [&]() -> swh_status {
+        return batch_common(ctx, npairs, q_cat_dev, q_off, t_cat_dev, t_off, scoring, mode, out, cigar_cat,
+                            cigar_cap, cigar_off, stats, stream, true);
+    });
 }
 
 swh_status swh_autotune(swh_ctx *ctx, const swh_scoring *scoring, int64_t max_rows, double cells_per_trial)
 {
     if (!ctx) return SWH_E_INVAL;
-    ctx->err.clear();
-    Scoring sc;
-    swh_status s = make_scoring(ctx, scoring, sc);
-    if (s != SWH_OK) return s;
-    if (max_rows < 1 || max_rows >= ((int64_t)1 << 31)) return fail(ctx, SWH_E_INVAL, "max_rows out of range");
-    if (!(cells_per_trial > 0.0) || cells_per_trial > 1e13)
-        return fail(ctx, SWH_E_INVAL, "cells_per_trial must be in (0, 1e13]");
-    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SWH_E_DEVICE, "hipSetDevice failed");
-    return autotune(ctx, sc, max_rows, cells_per_trial);
+    return guarded(ctx, [&]() -> swh_status {
+        ctx->err.clear();
+        Scoring sc;
+        swh_status s = make_scoring(ctx, scoring, sc);
+        if (s != SWH_OK) return s;
+        if (max_rows < 1 || max_rows >= ((int64_t)1 << 31)) return fail(ctx, SWH_E_INVAL, "max_rows out of range");
+        if (!(cells_per_trial > 0.0) || cells_per_trial > 1e13)
+            return fail(ctx, SWH_E_INVAL, "cells_per_trial must be in (0, 1e13]");
+        if ((s = begin_call(ctx)) != SWH_OK) return s;
+        return autotune(ctx, sc, max_rows, cells_per_trial);
+    });
 }
 
 swh_status swh_tune_get(const swh_ctx *ctx, swh_tune_entry *out, int32_t cap, int32_t *count)
@@ -260,140 +521,147 @@ swh_status swh_tune_get(const swh_ctx *ctx, swh_tune_entry *out, int32_t cap, in
 swh_status swh_tune_set(swh_ctx *ctx, const swh_tune_entry *entries, int32_t count)
 {
     if (!ctx) return SWH_E_INVAL;
-    ctx->err.clear();
-    if (count < 0 || count > 64 || (count > 0 && !entries)) return fail(ctx, SWH_E_INVAL, "bad table size");
-    for (int32_t i = 0; i < count; ++i) {
-        const swh_tune_entry &t = entries[i];
-        const int R = t.rows_per_lane;
-        if (R != 4 && R != 8 && R != 16 && R != 20 && R != 24 && R != 32)
-            return fail(ctx, SWH_E_INVAL, "rows_per_lane must be 4, 8, 16, 20, 24 or 32");
-        if (t.waves_per_simd < 0 || t.waves_per_simd > 8) return fail(ctx, SWH_E_INVAL, "waves_per_simd must be in 0..8");
-        if (t.max_rows < 1 || (i > 0 && t.max_rows <= entries[i - 1].max_rows))
-            return fail(ctx, SWH_E_INVAL, "max_rows must be positive and increasing");
-    }
-    ctx->tune.assign(entries, entries + count);
-    return SWH_OK;
+    return guarded(ctx, [&]() -> swh_status {
+        ctx->err.clear();
+        if (count < 0 || count > 64 || (count > 0 && !entries)) return fail(ctx, SWH_E_INVAL, "bad table size");
+        for (int32_t i = 0; i < count; ++i) {
+            const swh_tune_entry &t = entries[i];
+            const int R = t.rows_per_lane;
+            if (R != 4 && R != 8 && R != 16 && R != 20 && R != 24 && R != 32)
+                return fail(ctx, SWH_E_INVAL, "rows_per_lane must be 4, 8, 16, 20, 24 or 32");
+            if (t.waves_per_simd < 0 || t.waves_per_simd > 8)
+                return fail(ctx, SWH_E_INVAL, "waves_per_simd must be in 0..8");
+            if (t.max_rows < 1 || (i > 0 && t.max_rows <= entries[i - 1].max_rows))
+                return fail(ctx, SWH_E_INVAL, "max_rows must be positive and increasing");
+        }
+        ctx->tune.assign(entries, entries + count);
+        return SWH_OK;
+    });
 }
 
 swh_status swh_db_create(swh_ctx *ctx, int64_t ndb, const char *db_cat, const int64_t *db_off,
                          const swh_scoring *scoring, swh_db **out)
 {
     if (!ctx) return SWH_E_INVAL;
-    ctx->err.clear();
-    if (!out) return fail(ctx, SWH_E_INVAL, "out is NULL");
-    *out = nullptr;
-    if (ndb > 0 && (!db_cat || !db_off)) return fail(ctx, SWH_E_INVAL, "database pointers are NULL");
-    Scoring sc;
-    swh_status s = make_scoring(ctx, scoring, sc);
-    if (s != SWH_OK) return s;
-    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SWH_E_DEVICE, "hipSetDevice failed");
-    return db_create(ctx, ndb, db_cat, db_off, sc, out);
+    return guarded(ctx, [&]() -> swh_status {
+        ctx->err.clear();
+        if (!out) return fail(ctx, SWH_E_INVAL, "out is NULL");
+        *out = nullptr;
+        if (ndb > 0 && (!db_cat || !db_off)) return fail(ctx, SWH_E_INVAL, "database pointers are NULL");
+        Scoring sc;
+        swh_status s = make_scoring(ctx, scoring, sc);
+        if (s != SWH_OK) return s;
+        if ((s = begin_call(ctx)) != SWH_OK) return s;
+        return db_create(ctx, ndb, db_cat, db_off, sc, out);
+    });
 }
 
-void swh_db_destroy(swh_db *db) { db_destroy(db); }
-
-static swh_status search_common(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off,
-                                int32_t k, swh_hit *hits, int32_t *scores, swh_search_stats *stats)
+void swh_db_destroy(swh_db *db)
 {
-    if (!ctx) return SWH_E_INVAL;
-    ctx->err.clear();
-    if (!db) return fail(ctx, SWH_E_INVAL, "database is NULL");
-    if (db->device != ctx->device) return fail(ctx, SWH_E_INVAL, "database lives on another device");
-    if (nq < 0 || (nq > 0 && (!q_off || (!q_cat && q_off[nq] > q_off[0]))))
-        return fail(ctx, SWH_E_INVAL, "bad query arguments");
-    if (hits && (k < 1 || k > 32)) return fail(ctx, SWH_E_INVAL, "k must be in 1..32");
-    if (stats && stats->struct_size < sizeof(swh_search_stats))
-        return fail(ctx, SWH_E_INVAL, "stats->struct_size too small");
-    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SWH_E_DEVICE, "hipSetDevice failed");
-    DbStats ds;
-    swh_status s = db_search(ctx, db, nq, q_cat, q_off, k, hits, scores, ds);
-    if (s == SWH_OK && stats) {
-        stats->cells = ds.cells;
-        stats->ms_inter = ds.ms_inter;
-        stats->ms_intra = ds.ms_intra;
-        stats->ms_topk = ds.ms_topk;
-        stats->saturated = ds.redo;
-        stats->intra_pairs = ds.intra_pairs;
+    try {
+        db_destroy(db);
+    } catch (...) {
     }
-    return s;
 }
 
 swh_status swh_db_search(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off,
                          int32_t k, swh_hit *hits, swh_search_stats *stats)
 {
-    if (ctx && !hits) return fail(ctx, SWH_E_INVAL, "hits is NULL");
-    return search_common(ctx, db, nq, q_cat, q_off, k, hits, nullptr, stats);
+    if (!ctx) return SWH_E_INVAL;
+    return guarded(ctx, [&]() -> swh_status {
+        if (!hits) return fail(ctx, SWH_E_INVAL, "hits is NULL");
+        return search_common(ctx, db, nq, q_cat, q_off, k, hits, nullptr, stats, nullptr, false);
+    });
+}
+
+swh_status swh_db_search_dev(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat_dev, const int64_t *q_off,
+                             int32_t k, void *stream, swh_hit *hits, swh_search_stats *stats)
+{
+    if (!ctx) return SWH_E_INVAL;
+    return guarded(ctx, [&]() -> swh_status {
+        if (!hits) return fail(ctx, SWH_E_INVAL, "hits is NULL");
+        return search_common(ctx, db, nq, q_cat_dev, q_off, k, hits, nullptr, stats, stream, true);
+    });
 }
 
 swh_status swh_db_scores(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off,
                          int32_t *scores, swh_search_stats *stats)
 {
-    if (ctx && !scores) return fail(ctx, SWH_E_INVAL, "scores is NULL");
-    return search_common(ctx, db, nq, q_cat, q_off, 0, nullptr, scores, stats);
-}
-
-static swh_status model_ok(swh_ctx *ctx, const swh_model *m)
-{
-    if (!m) return fail(ctx, SWH_E_INVAL, "model is NULL");
-    if (m->device != ctx->device) return fail(ctx, SWH_E_INVAL, "model lives on another device");
-    return SWH_OK;
-}
-
-static swh_status enter(swh_ctx *ctx)
-{
-    ctx->err.clear();
-    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SWH_E_DEVICE, "hipSetDevice failed");
-    return SWH_OK;
+    if (!ctx) return SWH_E_INVAL;
+    return guarded(ctx, [&]() -> swh_status {
+        if (!scores) return fail(ctx, SWH_E_INVAL, "scores is NULL");
+        return search_common(ctx, db, nq, q_cat, q_off, 0, nullptr, scores, stats, nullptr, false);
+    });
 }
 
 swh_status swh_model_create(swh_ctx *ctx, const swh_scoring *scoring, const float *theta, const float *mu,
                             const float *sd, uint64_t seed, swh_model **out)
 {
     if (!ctx) return SWH_E_INVAL;
-    swh_status s = enter(ctx);
-    if (s != SWH_OK) return s;
-    if (!out) return fail(ctx, SWH_E_INVAL, "out is NULL");
-    *out = nullptr;
-    Scoring sc;
-    if ((s = make_scoring(ctx, scoring, sc)) != SWH_OK) return s;
-    return model_create(ctx, sc, theta, mu, sd, seed, out);
+    return guarded(ctx, [&]() -> swh_status {
+        ctx->err.clear();
+        if (!out) return fail(ctx, SWH_E_INVAL, "out is NULL");
+        *out = nullptr;
+        Scoring sc;
+        swh_status s = make_scoring(ctx, scoring, sc);
+        if (s != SWH_OK) return s;
+        if ((s = begin_call(ctx)) != SWH_OK) return s;
+        return model_create(ctx, sc, theta, mu, sd, seed, out);
+    });
 }
 
-void swh_model_destroy(swh_model *model) { model_destroy(model); }
+void swh_model_destroy(swh_model *model)
+{
+    try {
+        model_destroy(model);
+    } catch (...) {
+    }
+}
 
 swh_status swh_model_get(swh_ctx *ctx, const swh_model *model, float *theta, float *mu, float *sd)
 {
     if (!ctx) return SWH_E_INVAL;
-    swh_status s = enter(ctx);
-    if (s == SWH_OK) s = model_ok(ctx, model);
-    return s != SWH_OK ? s : model_get(ctx, model, theta, mu, sd);
+    return guarded(ctx, [&]() -> swh_status {
+        ctx->err.clear();
+        swh_status s = model_ok(ctx, model);
+        if (s == SWH_OK) s = begin_call(ctx);
+        return s != SWH_OK ? s : model_get(ctx, model, theta, mu, sd);
+    });
 }
 
 swh_status swh_model_set(swh_ctx *ctx, swh_model *model, const float *theta, const float *mu, const float *sd)
 {
     if (!ctx) return SWH_E_INVAL;
-    swh_status s = enter(ctx);
-    if (s == SWH_OK) s = model_ok(ctx, model);
-    return s != SWH_OK ? s : model_set(ctx, model, theta, mu, sd);
+    return guarded(ctx, [&]() -> swh_status {
+        ctx->err.clear();
+        swh_status s = model_ok(ctx, model);
+        if (s == SWH_OK) s = begin_call(ctx);
+        return s != SWH_OK ? s : model_set(ctx, model, theta, mu, sd);
+    });
 }
 
 swh_status swh_model_save(swh_ctx *ctx, const swh_model *model, const char *path)
 {
     if (!ctx) return SWH_E_INVAL;
-    swh_status s = enter(ctx);
-    if (s == SWH_OK) s = model_ok(ctx, model);
-    if (s == SWH_OK && !path) s = fail(ctx, SWH_E_INVAL, "path is NULL");
-    return s != SWH_OK ? s : model_save(ctx, model, path);
+    return guarded(ctx, [&]() -> swh_status {
+        ctx->err.clear();
+        swh_status s = model_ok(ctx, model);
+        if (s == SWH_OK && !path) s = fail(ctx, SWH_E_INVAL, "path is NULL");
+        if (s == SWH_OK) s = begin_call(ctx);
+        return s != SWH_OK ? s : model_save(ctx, model, path);
+    });
 }
 
 swh_status swh_model_load(swh_ctx *ctx, const char *path, swh_model **out)
 {
     if (!ctx) return SWH_E_INVAL;
-    swh_status s = enter(ctx);
-    if (s != SWH_OK) return s;
-    if (!path || !out) return fail(ctx, SWH_E_INVAL, "path or out is NULL");
-    *out = nullptr;
-    return model_load(ctx, path, out);
+    return guarded(ctx, [&]() -> swh_status {
+        ctx->err.clear();
+        if (!path || !out) return fail(ctx, SWH_E_INVAL, "path or out is NULL");
+        *out = nullptr;
+        swh_status s = begin_call(ctx);
+        return s != SWH_OK ? s : model_load(ctx, path, out);
+    });
 }
 
 swh_status swh_prefilter_train(swh_ctx *ctx, swh_model *model, const swh_scoring *scoring, int64_t nseq,
@@ -402,33 +670,37 @@ swh_status swh_prefilter_train(swh_ctx *ctx, swh_model *model, const swh_scoring
                                int32_t *labels_out, swh_train_stats *stats)
 {
     if (!ctx) return SWH_E_INVAL;
-    swh_status s = enter(ctx);
-    if (s == SWH_OK) s = model_ok(ctx, model);
-    if (s != SWH_OK) return s;
-    Scoring sc;
-    if ((s = make_scoring(ctx, scoring, sc)) != SWH_OK) return s;
-    if (sc.asize != model->asize) return fail(ctx, SWH_E_INVAL, "scoring alphabet differs from the model's");
-    if (!cfg || cfg->struct_size < sizeof(swh_train_cfg)) return fail(ctx, SWH_E_INVAL, "cfg missing or too small");
-    if (cfg->epochs < 1 || cfg->batch < 64 || cfg->batch % 64 != 0 || !(cfg->lr > 0.0))
-        return fail(ctx, SWH_E_INVAL, "cfg: epochs >= 1, batch a positive multiple of 64, lr > 0");
-    if (nseq < 0 || npairs < cfg->batch || (nseq > 0 && !seq_off) || !pair_row || !pair_col)
-        return fail(ctx, SWH_E_INVAL, "need a sequence pool and at least one batch of pairs");
-    if (stats && stats->struct_size < sizeof(swh_train_stats)) return fail(ctx, SWH_E_INVAL, "stats too small");
-    if (npairs >= ((int64_t)1 << 31)) return fail(ctx, SWH_E_RANGE, "more than 2^31 - 1 pairs");
-    TrainStats ts;
-    s = prefilter_train(ctx, sc, nseq, seq_cat, seq_off, npairs, pair_row, pair_col, scores, cfg->epochs, cfg->batch,
-                        cfg->lr, cfg->seed, model, labels_out, ts);
-    if (s == SWH_OK && stats) {
-        stats->first_epoch_loss = ts.first_loss;
-        stats->final_epoch_loss = ts.final_loss;
-        stats->ms_label = ts.ms_label;
-        stats->ms_features = ts.ms_features;
-        stats->ms_train = ts.ms_train;
-        stats->cells_label = ts.cells_label;
-        stats->steps = ts.steps;
-        stats->graph = ts.graph ? 1 : 0;
-    }
-    return s;
+    return guarded(ctx, [&]() -> swh_status {
+        ctx->err.clear();
+        swh_status s = model_ok(ctx, model);
+        if (s != SWH_OK) return s;
+        Scoring sc;
+        if ((s = make_scoring(ctx, scoring, sc)) != SWH_OK) return s;
+        if (sc.asize != model->asize) return fail(ctx, SWH_E_INVAL, "scoring alphabet differs from the model's");
+        if (!cfg || cfg->struct_size < sizeof(swh_train_cfg))
+            return fail(ctx, SWH_E_INVAL, "cfg missing or too small");
+        if (cfg->epochs < 1 || cfg->batch < 64 || cfg->batch % 64 != 0 || !(cfg->lr > 0.0))
+            return fail(ctx, SWH_E_INVAL, "cfg: epochs >= 1, batch a positive multiple of 64, lr > 0");
+        if (nseq < 0 || npairs < cfg->batch || (nseq > 0 && !seq_off) || !pair_row || !pair_col)
+            return fail(ctx, SWH_E_INVAL, "need a sequence pool and at least one batch of pairs");
+        if (stats && stats->struct_size < sizeof(swh_train_stats)) return fail(ctx, SWH_E_INVAL, "stats too small");
+        if (npairs >= ((int64_t)1 << 31)) return fail(ctx, SWH_E_RANGE, "more than 2^31 - 1 pairs");
+        if ((s = begin_call(ctx)) != SWH_OK) return s;
+        TrainStats ts;
+        s = prefilter_train(ctx, sc, nseq, seq_cat, seq_off, npairs, pair_row, pair_col, scores, cfg->epochs,
+                            cfg->batch, cfg->lr, cfg->seed, model, labels_out, ts);
+        if (s == SWH_OK && stats) {
+            stats->first_epoch_loss = ts.first_loss;
+            stats->final_epoch_loss = ts.final_loss;
+            stats->ms_label = ts.ms_label;
+            stats->ms_features = ts.ms_features;
+            stats->ms_train = ts.ms_train;
+            stats->cells_label = ts.cells_label;
+            stats->steps = ts.steps;
+            stats->graph = ts.graph ? 1 : 0;
+        }
+        return s;
+    });
 }
 
 swh_status swh_prefilter_search(swh_ctx *ctx, const swh_model *model, swh_db *db, int32_t nq, const char *q_cat,
@@ -436,80 +708,96 @@ swh_status swh_prefilter_search(swh_ctx *ctx, const swh_model *model, swh_db *db
                                 uint64_t audit_seed, swh_hit *hits, swh_prefilter_stats *stats)
 {
     if (!ctx) return SWH_E_INVAL;
-    swh_status s = enter(ctx);
-    if (s == SWH_OK) s = model_ok(ctx, model);
-    if (s != SWH_OK) return s;
-    if (!db || db->device != ctx->device) return fail(ctx, SWH_E_INVAL, "database missing or on another device");
-    if (db->sc.asize != model->asize) return fail(ctx, SWH_E_INVAL, "database alphabet differs from the model's");
-    if (nq < 0 || (nq > 0 && (!q_off || !hits))) return fail(ctx, SWH_E_INVAL, "bad query arguments");
-    if (k < 1 || k > 32) return fail(ctx, SWH_E_INVAL, "k must be in 1..32");
-    if (!(rescore_frac > 0.0 && rescore_frac <= 1.0) || !(audit_frac >= 0.0 && audit_frac <= 1.0))
-        return fail(ctx, SWH_E_INVAL, "rescore_frac must be in (0, 1], audit_frac in [0, 1]");
-    if (stats && stats->struct_size < sizeof(swh_prefilter_stats)) return fail(ctx, SWH_E_INVAL, "stats too small");
-    PrefilterStats ps;
-    s = prefilter_search(ctx, model, db, nq, q_cat, q_off, k, rescore_frac, audit_frac, audit_seed, hits, ps);
-    if (s == SWH_OK && stats) {
-        stats->candidates = ps.candidates;
-        stats->audited = ps.audited;
-        stats->fallbacks = ps.fallbacks;
-        stats->cells_rescored = ps.cells_rescored;
-        stats->cells_exhaustive = ps.cells_exhaustive;
-        stats->ms_features = ps.ms_features;
-        stats->ms_predict = ps.ms_predict;
-        stats->ms_select = ps.ms_select;
-        stats->ms_rescore = ps.ms_rescore;
-        stats->ms_topk = ps.ms_topk;
-        stats->ms_fallback = ps.ms_fallback;
-    }
-    return s;
+    return guarded(ctx, [&]() -> swh_status {
+        ctx->err.clear();
+        swh_status s = model_ok(ctx, model);
+        if (s != SWH_OK) return s;
+        if (!db || db->device != ctx->device) return fail(ctx, SWH_E_INVAL, "database missing or on another device");
+        if (db->sc.asize != model->asize) return fail(ctx, SWH_E_INVAL, "database alphabet differs from the model's");
+        if (nq < 0 || (nq > 0 && (!q_off || !hits))) return fail(ctx, SWH_E_INVAL, "bad query arguments");
+        if (k < 1 || k > 32) return fail(ctx, SWH_E_INVAL, "k must be in 1..32");
+        if (!(rescore_frac > 0.0 && rescore_frac <= 1.0) || !(audit_frac >= 0.0 && audit_frac <= 1.0))
+            return fail(ctx, SWH_E_INVAL, "rescore_frac must be in (0, 1], audit_frac in [0, 1]");
+        if (stats && stats->struct_size < sizeof(swh_prefilter_stats))
+            return fail(ctx, SWH_E_INVAL, "stats too small");
+        if ((s = begin_call(ctx)) != SWH_OK) return s;
+        PrefilterStats ps;
+        s = prefilter_search(ctx, model, db, nq, q_cat, q_off, k, rescore_frac, audit_frac, audit_seed, hits, ps);
+        if (s == SWH_OK && stats) {
+            stats->candidates = ps.candidates;
+            stats->audited = ps.audited;
+            stats->fallbacks = ps.fallbacks;
+            stats->cells_rescored = ps.cells_rescored;
+            stats->cells_exhaustive = ps.cells_exhaustive;
+            stats->ms_features = ps.ms_features;
+            stats->ms_predict = ps.ms_predict;
+            stats->ms_select = ps.ms_select;
+            stats->ms_rescore = ps.ms_rescore;
+            stats->ms_topk = ps.ms_topk;
+            stats->ms_fallback = ps.ms_fallback;
+        }
+        return s;
+    });
 }
 
 swh_status swh_prefilter_predict(swh_ctx *ctx, const swh_model *model, swh_db *db, int32_t nq, const char *q_cat,
                                  const int64_t *q_off, float *pred)
 {
     if (!ctx) return SWH_E_INVAL;
-    swh_status s = enter(ctx);
-    if (s == SWH_OK) s = model_ok(ctx, model);
-    if (s != SWH_OK) return s;
-    if (!db || db->device != ctx->device) return fail(ctx, SWH_E_INVAL, "database missing or on another device");
-    if (db->sc.asize != model->asize) return fail(ctx, SWH_E_INVAL, "database alphabet differs from the model's");
-    if (nq < 0 || (nq > 0 && (!q_off || !pred))) return fail(ctx, SWH_E_INVAL, "bad query arguments");
-    return prefilter_predict(ctx, model, db, nq, q_cat, q_off, pred);
+    return guarded(ctx, [&]() -> swh_status {
+        ctx->err.clear();
+        swh_status s = model_ok(ctx, model);
+        if (s != SWH_OK) return s;
+        if (!db || db->device != ctx->device) return fail(ctx, SWH_E_INVAL, "database missing or on another device");
+        if (db->sc.asize != model->asize) return fail(ctx, SWH_E_INVAL, "database alphabet differs from the model's");
+        if (nq < 0 || (nq > 0 && (!q_off || !pred))) return fail(ctx, SWH_E_INVAL, "bad query arguments");
+        if ((s = begin_call(ctx)) != SWH_OK) return s;
+        return prefilter_predict(ctx, model, db, nq, q_cat, q_off, pred);
+    });
 }
 
 swh_status swh_dipeptide_counts(swh_ctx *ctx, const swh_scoring *scoring, int64_t nseq, const char *seq_cat,
                                 const int64_t *seq_off, int32_t *counts)
 {
     if (!ctx) return SWH_E_INVAL;
-    swh_status s = enter(ctx);
-    if (s != SWH_OK) return s;
-    Scoring sc;
-    if ((s = make_scoring(ctx, scoring, sc)) != SWH_OK) return s;
-    if (nseq < 0 || (nseq > 0 && (!seq_off || !counts))) return fail(ctx, SWH_E_INVAL, "bad sequence arguments");
-    return dipeptide_counts(ctx, sc, nseq, seq_cat, seq_off, counts);
+    return guarded(ctx, [&]() -> swh_status {
+        ctx->err.clear();
+        Scoring sc;
+        swh_status s = make_scoring(ctx, scoring, sc);
+        if (s != SWH_OK) return s;
+        if (nseq < 0 || (nseq > 0 && (!seq_off || !counts))) return fail(ctx, SWH_E_INVAL, "bad sequence arguments");
+        if ((s = begin_call(ctx)) != SWH_OK) return s;
+        return dipeptide_counts(ctx, sc, nseq, seq_cat, seq_off, counts);
+    });
 }
 
 swh_status swh_mlp_grad(swh_ctx *ctx, swh_model *model, int32_t B, const float *z, const float *y, double *loss,
                         float *grad)
 {
     if (!ctx) return SWH_E_INVAL;
-    swh_status s = enter(ctx);
-    if (s == SWH_OK) s = model_ok(ctx, model);
-    if (s != SWH_OK) return s;
-    if (B < 64 || B % 64 != 0 || !z || !y || !grad) return fail(ctx, SWH_E_INVAL, "B a positive multiple of 64");
-    return mlp_grad(ctx, model, B, z, y, loss, grad);
+    return guarded(ctx, [&]() -> swh_status {
+        ctx->err.clear();
+        swh_status s = model_ok(ctx, model);
+        if (s != SWH_OK) return s;
+        if (B < 64 || B % 64 != 0 || !z || !y || !grad) return fail(ctx, SWH_E_INVAL, "B a positive multiple of 64");
+        if ((s = begin_call(ctx)) != SWH_OK) return s;
+        return mlp_grad(ctx, model, B, z, y, loss, grad);
+    });
 }
 
 swh_status swh_mlp_train_steps(swh_ctx *ctx, swh_model *model, int32_t B, const float *z, const float *y,
                                int32_t steps, double lr)
 {
     if (!ctx) return SWH_E_INVAL;
-    swh_status s = enter(ctx);
-    if (s == SWH_OK) s = model_ok(ctx, model);
-    if (s != SWH_OK) return s;
-    if (B < 64 || B % 64 != 0 || !z || !y || steps < 0 || !(lr > 0.0))
-        return fail(ctx, SWH_E_INVAL, "B a positive multiple of 64, steps >= 0, lr > 0");
-    return mlp_train_steps(ctx, model, B, z, y, steps, lr);
+    return guarded(ctx, [&]() -> swh_status {
+        ctx->err.clear();
+        swh_status s = model_ok(ctx, model);
+        if (s != SWH_OK) return s;
+        if (B < 64 || B % 64 != 0 || !z || !y || steps < 0 || !(lr > 0.0))
+            return fail(ctx, SWH_E_INVAL, "B a positive multiple of 64, steps >= 0, lr > 0");
+        if ((s = begin_call(ctx)) != SWH_OK) return s;
+        return mlp_train_steps(ctx, model, B, z, y, steps, lr);
+    });
 }
 
 }  // extern "C"

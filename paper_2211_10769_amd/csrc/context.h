@@ -27,9 +27,25 @@ struct Scoring {
     int smax = 0, smin = 0;    // extreme matrix entries
 };
 
+// Context options (swh_set_option): speed, memory and diagnostics only.
+struct Options {
+    int32_t rows = 0;        // forced rows per lane (0: tuned table or rule)
+    int32_t grid = 0;        // > 0: single-wave workgroups of this count
+    int32_t band_rows = 0;   // rows between kept rows (0: rule, -1: no band traceback)
+    int64_t tb_leaf = 0;     // largest traceback leaf in cells (0: built-in)
+    int32_t graph = 1;       // prefilter training step as a HIP graph
+    int32_t prune = 1;       // block pruning of reverse passes
+    int64_t mem_cap = 0;     // bytes the context's own buffers may hold (0: no cap)
+    int32_t int16 = 1;       // packed 16-bit local score passes where exact
+    int32_t inter_max = 0;   // database length switch (0: built-in / tuned)
+    int32_t fault_nomem = 0; // the next entry point throws std::bad_alloc
+};
+
 // Device memory handed out in pieces that never move during one use (the
 // traceback keeps pointers across levels); chunks are kept for the next use,
 // so a call allocates only when it needs more than any call before it.
+// held / cap: the owning context's byte count of device memory and its cap
+// (0: none); chunks count towards it.
 struct Arena {
     static constexpr size_t kChunk = (size_t)256 << 20;
     std::vector<void *> chunks;
@@ -40,7 +56,7 @@ struct Arena {
         cur = 0;
         used = 0;
     }
-    void *get(size_t bytes)
+    void *get(size_t bytes, size_t &held, int64_t cap)
     {
         bytes = (bytes + 255) & ~(size_t)255;
         while (cur < chunks.size() && used + bytes > caps[cur]) {
@@ -48,23 +64,29 @@ struct Arena {
             used = 0;
         }
         if (cur == chunks.size()) {
-            const size_t cap = bytes > kChunk ? bytes : kChunk;
+            size_t want = bytes > kChunk ? bytes : kChunk;
+            if (cap > 0 && held + want > (size_t)cap) want = bytes;
+            if (cap > 0 && held + want > (size_t)cap) return nullptr;
             void *p = nullptr;
-            if (hipMalloc(&p, cap) != hipSuccess) {
+            if (hipMalloc(&p, want) != hipSuccess) {
                 (void)hipGetLastError();
                 return nullptr;
             }
             chunks.push_back(p);
-            caps.push_back(cap);
+            caps.push_back(want);
+            held += want;
             used = 0;
         }
         void *r = (char *)chunks[cur] + used;
         used += bytes;
         return r;
     }
-    void free_all()
+    void free_all(size_t &held)
     {
-        for (void *p : chunks) hipFree(p);
+        for (size_t k = 0; k < chunks.size(); ++k) {
+            hipFree(chunks[k]);
+            held -= caps[k];
+        }
         chunks.clear();
         caps.clear();
         reset();
@@ -79,6 +101,13 @@ struct swh_ctx {
     int num_cu = 0;
     std::string err;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev_in = nullptr;   // orders the context's stream after a caller's stream
+    swh::Options opt;
+    // cancellation flag in pinned host memory (host view and device view)
+    int32_t *cancel_host = nullptr;
+    int32_t *cancel_dev = nullptr;
+    // device bytes held by the context's own buffers (the memory cap counts these)
+    size_t held = 0;
 
     // pairwise buffers
     swh::DevBuf qraw, traw;        // ASCII copies of host inputs
@@ -123,8 +152,18 @@ namespace swh {
 // Status helpers: set ctx->err and return the status.
 swh_status fail(swh_ctx *ctx, swh_status st, const std::string &msg);
 swh_status hip_fail(swh_ctx *ctx, hipError_t e, const char *what);
-// Make sure buf holds at least bytes; on failure sets the error and returns SWH_E_NOMEM.
+// Make sure buf holds at least bytes; on failure sets the error and returns
+// SWH_E_NOMEM.  Buffers that are members of ctx count towards its memory cap.
 swh_status ensure(swh_ctx *ctx, DevBuf &buf, size_t bytes, const char *what);
+// Device bytes the context may still take under its memory cap (SIZE_MAX: no cap).
+size_t cap_room(const swh_ctx *ctx);
+// True once swh_cancel has been called during the current entry point.
+inline bool cancelled(const swh_ctx *ctx)
+{
+    return ctx->cancel_host && __atomic_load_n(ctx->cancel_host, __ATOMIC_ACQUIRE) != 0;
+}
+// SWH_E_CANCELLED with its message
+swh_status cancel_status(swh_ctx *ctx);
 swh_status make_scoring(swh_ctx *ctx, const swh_scoring *in, Scoring &out);
 
 // Pairwise alignment on device-resident ASCII inputs (engine.cpp).

@@ -1,5 +1,6 @@
 // db.cpp -- exhaustive query-vs-database search: database layout, the
-// inter-task kernel for sequences up to kInterMax residues, the single-pair
+// inter-task kernel for sequences up to the length switch (2,048 residues by
+// default, a context option otherwise), the single-pair
 // strip kernel for longer ones (the length-dependent choice between
 // inter-task and intra-task parallelism of SW#, paper, Background) and for
 // pairs whose 16-bit scores may have saturated, then the top-k.
@@ -31,23 +32,25 @@ void free_buf(DevBuf &b)
     b.cap = 0;
 }
 
-// Encode ASCII host sequences into device codes (original order); reports the
-// first bad byte of the concatenation.
+// Encode ASCII sequences into device codes (original order); reports the
+// first bad byte of the concatenation.  cat is a host pointer (copied through
+// raw first) or, with dev, a device pointer encoded in place.
 swh_status encode_host(swh_ctx *ctx, const Scoring &sc, const char *cat, int64_t total, DevBuf &raw, DevBuf &codes,
-                       hipStream_t st, const char *what)
+                       hipStream_t st, const char *what, bool dev = false)
 {
     swh_status s;
-    if ((s = ensure(ctx, raw, (size_t)total + 1, what)) != SWH_OK) return s;
+    if (!dev && (s = ensure(ctx, raw, (size_t)total + 1, what)) != SWH_OK) return s;
     if ((s = ensure(ctx, codes, (size_t)total + 1, what)) != SWH_OK) return s;
     if ((s = ensure(ctx, ctx->lut, 256, "symbol table")) != SWH_OK) return s;
     if ((s = ensure(ctx, ctx->misc, 64, "scratch words")) != SWH_OK) return s;
     hipError_t e;
     const int32_t init = INT32_MAX;
-    if ((total && (e = hipMemcpyAsync(raw.p, cat, (size_t)total, hipMemcpyHostToDevice, st)) != hipSuccess) ||
+    if ((!dev && total && (e = hipMemcpyAsync(raw.p, cat, (size_t)total, hipMemcpyHostToDevice, st)) != hipSuccess) ||
         (e = hipMemcpyAsync(ctx->lut.p, sc.lut, 256, hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = hipMemcpyAsync(ctx->misc.p, &init, 4, hipMemcpyHostToDevice, st)) != hipSuccess)
         return hip_fail(ctx, e, "upload");
-    if ((e = launch_encode((const char *)raw.p, total, (uint8_t *)codes.p, total, (const uint8_t *)ctx->lut.p,
+    const char *src = dev ? cat : (const char *)raw.p;
+    if ((e = launch_encode(src, total, (uint8_t *)codes.p, total, (const uint8_t *)ctx->lut.p,
                            (uint8_t)sc.asize, (int32_t *)ctx->misc.p, st)) != hipSuccess)
         return hip_fail(ctx, e, "encode launch");
     int32_t bad = 0;
@@ -98,6 +101,7 @@ swh_status db_create(swh_ctx *ctx, int64_t ndb, const char *cat, const int64_t *
     if (!db) return fail(ctx, SWH_E_NOMEM, "database handle");
     db->device = ctx->device;
     db->sc = sc;
+    db->inter_max = ctx->opt.inter_max > 0 ? ctx->opt.inter_max : kInterMax;
     db->ndb = ndb;
     const int64_t base = ndb ? off[0] : 0, total = ndb ? off[ndb] - base : 0;
     db->h_off.resize((size_t)ndb + 1);
@@ -122,7 +126,7 @@ swh_status db_create(swh_ctx *ctx, int64_t ndb, const char *cat, const int64_t *
     order.reserve((size_t)ndb);
     for (int64_t i = 0; i < ndb; ++i) {
         const int64_t L = db->h_off[i + 1] - db->h_off[i];
-        if (L > kInterMax)
+        if (L > db->inter_max)
             db->long_idx.push_back((int32_t)i);
         else
             order.push_back((int32_t)i);
@@ -183,7 +187,7 @@ void db_destroy(swh_db *db)
 }
 
 swh_status prepare_queries(swh_ctx *ctx, const Scoring &sc, int32_t nq, const char *q_cat, const int64_t *q_off,
-                           QuerySet &qs)
+                           QuerySet &qs, bool dev)
 {
     swh_status s;
     if ((s = check_offsets(ctx, nq, q_off, "queries")) != SWH_OK) return s;
@@ -196,7 +200,7 @@ swh_status prepare_queries(swh_ctx *ctx, const Scoring &sc, int32_t nq, const ch
     for (int32_t i = 0; i < nq; ++i) qs.maxq = std::max(qs.maxq, qs.qo[i + 1] - qs.qo[i]);
     if (qs.maxq * std::max(sc.smax, 1) >= ((int64_t)1 << 26))
         return fail(ctx, SWH_E_RANGE, "query length * max|s| must stay below 2^26");
-    if ((s = encode_host(ctx, sc, q_cat ? q_cat + qbase : nullptr, qtotal, ctx->qraw, ctx->qc, st, "queries")) !=
+    if ((s = encode_host(ctx, sc, q_cat ? q_cat + qbase : nullptr, qtotal, ctx->qraw, ctx->qc, st, "queries", dev)) !=
         SWH_OK)
         return s;
     hipError_t e;
@@ -259,6 +263,7 @@ swh_status score_units(swh_ctx *ctx, const swh_db *db, const QuerySet &qs, const
     a.ticket = (int32_t *)ctx->sync.p;
     a.border = (uint32_t *)ctx->db_border.p;
     a.max_len = max_len;
+    a.cancel = ctx->cancel_dev;
     hipEventRecord(ctx->ev[2], st);
     if (!work.empty() && (e = launch_db_search(a, grid, st)) != hipSuccess) return hip_fail(ctx, e, "search launch");
     hipEventRecord(ctx->ev[3], st);
@@ -266,6 +271,7 @@ swh_status score_units(swh_ctx *ctx, const swh_db *db, const QuerySet &qs, const
     if ((e = hipMemcpyAsync(&nredo, a.nredo, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
         return hip_fail(ctx, e, "search");
+    if (cancelled(ctx)) return cancel_status(ctx);
     float ms = 0.f;
     hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]);
     stats.ms_inter += ms;
@@ -350,17 +356,22 @@ swh_status score_units(swh_ctx *ctx, const swh_db *db, const QuerySet &qs, const
 }
 
 swh_status db_scores_device(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off,
-                            int32_t *scores_dev, DbStats &stats)
+                            int32_t *scores_dev, DbStats &stats, bool dev)
 {
     QuerySet qs;
-    swh_status s = prepare_queries(ctx, db->sc, nq, q_cat, q_off, qs);
+    swh_status s = prepare_queries(ctx, db->sc, nq, q_cat, q_off, qs, dev);
     if (s != SWH_OK) return s;
     const int64_t ngroups = (int64_t)db->h_groups.size();
     std::vector<DbWork> work;
     work.reserve((size_t)(nq * ngroups));
     std::vector<std::pair<int32_t, int32_t>> long_pairs;
     for (int32_t q = 0; q < nq; ++q) {
-        if (qs.qo[q + 1] == qs.qo[q]) continue;
+        if (qs.qo[q + 1] == qs.qo[q]) {
+            // an empty query aligns with nothing: every score is 0
+            hipError_t e = launch_fill_i32(scores_dev + (int64_t)q * db->ndb, db->ndb, 0, ctx->own_stream);
+            if (e != hipSuccess) return hip_fail(ctx, e, "score fill");
+            continue;
+        }
         for (int64_t g = 0; g < ngroups; ++g) work.push_back(DbWork{q, (int32_t)g});
         for (int32_t d : db->long_idx) long_pairs.push_back({q, d});
         stats.cells += (double)(qs.qo[q + 1] - qs.qo[q]) * (double)db->total_residues;
@@ -371,7 +382,7 @@ swh_status db_scores_device(swh_ctx *ctx, const swh_db *db, int32_t nq, const ch
 }
 
 swh_status db_search(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off, int32_t k,
-                     swh_hit *hits, int32_t *scores_host, DbStats &stats)
+                     swh_hit *hits, int32_t *scores_host, DbStats &stats, bool dev)
 {
     swh_status s;
     hipError_t e;
@@ -380,7 +391,7 @@ swh_status db_search(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_c
                     "score matrix")) != SWH_OK)
         return s;
     int32_t *scores = (int32_t *)ctx->db_scores.p;
-    if ((s = db_scores_device(ctx, db, nq, q_cat, q_off, scores, stats)) != SWH_OK) return s;
+    if ((s = db_scores_device(ctx, db, nq, q_cat, q_off, scores, stats, dev)) != SWH_OK) return s;
     if (scores_host && nq && db->ndb &&
         ((e = hipMemcpyAsync(scores_host, scores, sizeof(int32_t) * (size_t)nq * db->ndb, hipMemcpyDeviceToHost,
                              st)) != hipSuccess ||

@@ -14,6 +14,7 @@ struct swh_db {
     swh::Scoring sc;
     int64_t ndb = 0;
     int64_t total_residues = 0;
+    int32_t inter_max = 0;                 // longest sequence of the inter-task kernel
     std::vector<int64_t> h_off;            // per database index, rebased to 0
     std::vector<swh::DbGroup> h_groups;
     std::vector<int32_t> h_perm;           // sorted position -> database index, -1 padding
@@ -51,8 +52,9 @@ struct QuerySet {
     std::vector<int64_t> qo;
     int64_t maxq = 1;
 };
+// dev: q_cat is a device pointer (encoded in place), else a host pointer.
 swh_status prepare_queries(swh_ctx *ctx, const Scoring &sc, int32_t nq, const char *q_cat, const int64_t *q_off,
-                           QuerySet &qs);
+                           QuerySet &qs, bool dev = false);
 
 // A set of interleaved 128-sequence groups (device) with the host copy of the
 // group table.
@@ -72,8 +74,8 @@ swh_status db_create(swh_ctx *ctx, int64_t ndb, const char *cat, const int64_t *
                      swh_db **out);
 void db_destroy(swh_db *db);
 swh_status db_scores_device(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off,
-                            int32_t *scores_dev, DbStats &stats);
+                            int32_t *scores_dev, DbStats &stats, bool dev = false);
 swh_status db_search(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off, int32_t k,
-                     swh_hit *hits, int32_t *scores_host, DbStats &stats);
+                     swh_hit *hits, int32_t *scores_host, DbStats &stats, bool dev = false);
 
 }  // namespace swh

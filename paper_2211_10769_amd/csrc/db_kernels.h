@@ -39,6 +39,7 @@ struct DbSearchArgs {
     int32_t *ticket;
     uint32_t *border;          // per persistent wave: max_len * 64 lanes * 2 words
     int32_t max_len;           // longest group handled here
+    const int32_t *cancel;     // pinned host flag: nonzero = take no further unit (NULL: none)
 };
 
 hipError_t launch_db_pack(const uint8_t *codes, const int64_t *offs, const int32_t *perm, const DbGroup *groups,
@@ -49,6 +50,8 @@ int db_search_grid_limit(int device);
 hipError_t launch_topk(const int32_t *scores, int32_t nq, int64_t ndb, int32_t k, int32_t *cand_idx,
                        int32_t *cand_score, int64_t *out_idx, int32_t *out_score, hipStream_t st);
 size_t topk_scratch_entries(int32_t nq, int64_t ndb, int32_t k);
+// dst[i] = v for i < n (a kernel, so that it may sit inside a captured graph)
+hipError_t launch_fill_i32(int32_t *dst, int64_t n, int32_t v, hipStream_t st);
 // dst[pos[i]] = val[i]
 hipError_t launch_scatter(const int64_t *pos, const int32_t *val, int64_t n, int32_t *dst, hipStream_t st);
 

@@ -1,6 +1,7 @@
-// db_kernels.hip -- exhaustive query-vs-database scoring (inter-task), the
-// paper's database-similarity search ("many independent matrices, no
-// communication between processing elements", Background).
+// db_kernels.hip -- exhaustive query-vs-database scoring with inter-task
+// parallelism: every (query, database sequence) matrix is independent of the
+// others, so each is computed whole by one lane (paper, Background: database
+// similarity search).
 //
 // Each lane aligns one query against two database sequences at once: the
 // two DP values live in the two halves of a 32-bit register and every
@@ -96,6 +97,10 @@ __global__ void __launch_bounds__(64) db_search_kernel(DbSearchArgs a)
                                               __HIP_MEMORY_SCOPE_AGENT);
         const int w = __builtin_amdgcn_readfirstlane(tv);
         if (w >= a.nwork) break;
+        // cancellation (pinned host flag, read uncached): no further unit is run
+        if (a.cancel &&
+            __builtin_amdgcn_readfirstlane(__hip_atomic_load(a.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)))
+            break;
         const DbWork wk = a.work[w];
         const DbGroup g = a.groups[wk.g];
         const int64_t q0 = a.qoff[wk.q];
@@ -277,6 +282,12 @@ __global__ void scatter_kernel(const int64_t *pos, const int32_t *val, int64_t n
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[pos[i]] = val[i];
 }
 
+__global__ void fill_i32_kernel(int32_t *dst, int64_t n, int32_t v)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = v;
+}
+
 }  // namespace
 
 hipError_t launch_scatter(const int64_t *pos, const int32_t *val, int64_t n, int32_t *dst, hipStream_t st)
@@ -284,6 +295,14 @@ hipError_t launch_scatter(const int64_t *pos, const int32_t *val, int64_t n, int
     if (n <= 0) return hipSuccess;
     const int64_t g = std::min<int64_t>(4096, (n + 255) / 256);
     hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)g), dim3(256), 0, st, pos, val, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *dst, int64_t n, int32_t v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t g = std::min<int64_t>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)g), dim3(256), 0, st, dst, n, v);
     return hipGetLastError();
 }
 

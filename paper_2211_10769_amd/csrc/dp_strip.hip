@@ -227,6 +227,13 @@ __global__ void __launch_bounds__(256 * kWgPerSimd<R>) strip_kernel(StripArgs a)
                                               __HIP_MEMORY_SCOPE_AGENT);
         const int sg = __builtin_amdgcn_readfirstlane(sv);
         if (sg >= a.total_strips) break;
+        // cancellation (pinned host flag, read uncached): this strip is not
+        // run, and the abort flag releases every wave waiting on it
+        if (a.cancel &&
+            __builtin_amdgcn_readfirstlane(__hip_atomic_load(a.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM))) {
+            __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
         const int pi = a.strip_prob ? __builtin_amdgcn_readfirstlane((int)a.strip_prob[sg]) : 0;
         const Problem P = a.probs[pi];
         const int s = sg - P.strip0;                                      // strip within the problem

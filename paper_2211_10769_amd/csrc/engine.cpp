@@ -74,7 +74,7 @@ int band_stride(swh_ctx *ctx, int64_t n, int64_t m, int R)
 {
     const int64_t H = 64 * (int64_t)R;
     const int64_t nstrips = (n + H - 1) / H;
-    const int forced = env_int("SWH_BAND_ROWS", 0);
+    const int forced = ctx->opt.band_rows;
     if (forced < 0) return 0;
     if (forced > 0) return (int)std::max<int64_t>(1, (forced + H - 1) / H);
     if (nstrips < 32) return 0;
@@ -83,7 +83,8 @@ int band_stride(swh_ctx *ctx, int64_t n, int64_t m, int R)
         (void)hipGetLastError();
         return 0;
     }
-    const int64_t budget = std::min<int64_t>(kKeepBudget, (int64_t)(free_b / 4));
+    const int64_t budget = std::min<int64_t>(std::min<int64_t>(kKeepBudget, (int64_t)(free_b / 4)),
+                                             (int64_t)std::min<size_t>(cap_room(ctx) / 4, INT64_MAX));
     const int64_t row_bytes = cols_padded(m) * (int64_t)sizeof(Border);
     const int64_t max_rows = budget / row_bytes;
     if (max_rows < kKeepMinRows) return 0;
@@ -461,7 +462,7 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
         return put_cigar(ctx, cg, cigar, cigar_cap, cigar_len);
     }
 
-    if (global && mode == SWH_MODE_CIGAR && env_int("SWH_BAND_ROWS", 0) >= 0) {
+    if (global && mode == SWH_MODE_CIGAR && ctx->opt.band_rows >= 0) {
         std::string cg;
         TracebackStats ts;
         int32_t S = 0;
@@ -560,7 +561,7 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
     // pruned; what remains is bound by its diagonal dependency chain, whose
     // steps are shortest at 8 rows per lane (long pair: 1.70 s against 2.41 s
     // at 20).  With kept rows the reverse strips must still end on the cut rows.
-    const bool prune_rev = env_int("SWH_PRUNE", 1) != 0;
+    const bool prune_rev = ctx->opt.prune != 0;
     const int64_t rrecs = band_reverse_layout(out->q_end, out->t_end, bk, prune_rev ? 8 : shape.R);
     const StripShape rshape = bk.every > 0 ? StripShape{bk.Rr, bk.Rr == shape.R ? shape.waves : 0}
                               : (prune_rev && rn >= 512) ? StripShape{8, 0}

@@ -70,7 +70,8 @@ struct StripArgs {
     int32_t o, e;                // gap open, gap extend (> 0)
     int32_t smax;                // largest substitution score (block pruning)
     int32_t *ticket;             // strip ticket, zero on entry
-    int32_t *abort_flag;         // set when a bounded wait expires
+    int32_t *abort_flag;         // set when a bounded wait expires (or on cancellation)
+    const int32_t *cancel;       // pinned host flag: nonzero = stop taking strips (NULL: none)
     BestCell *strip_best;        // one entry per global strip (local mode)
     uint64_t wait_ticks;         // wall-clock ticks one wait may last before it gives up
 };

@@ -691,7 +691,7 @@ swh_status prefilter_train(swh_ctx *ctx, const Scoring &sc, int64_t nseq, const 
     };
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    if (nb > 0 && env_int("SWH_NO_GRAPH", 0) == 0) {
+    if (nb > 0 && ctx->opt.graph != 0) {
         if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
             const hipError_t ce = step(st);
             const hipError_t ee = hipStreamEndCapture(st, &graph);
@@ -721,6 +721,10 @@ swh_status prefilter_train(swh_ctx *ctx, const Scoring &sc, int64_t nseq, const 
             (e = hipMemsetAsync(w.loss, 0, 8, st)) != hipSuccess || (e = hipMemsetAsync(ctr, 0, 4, st)) != hipSuccess)
             return hip_fail(ctx, e, "epoch setup");
         for (int64_t b = 0; b < nb; ++b) {
+            if (cancelled(ctx)) {
+                (void)hipStreamSynchronize(st);
+                return cancel_status(ctx);
+            }
             if ((e = exec ? hipGraphLaunch(exec, st) : step(st)) != hipSuccess) return hip_fail(ctx, e, "training step");
             ++ts.steps;
             ++model->steps;
@@ -876,9 +880,14 @@ swh_status prefilter_search(swh_ctx *ctx, const swh_model *m, swh_db *db, int32_
                              (const int32_t *)ctx->pf_perm.p, (const DbGroup *)ctx->pf_groups.p,
                              (int32_t)groups.size(), (uint8_t)db->sc.asize, (uint8_t *)ctx->pf_res.p, st)) !=
              hipSuccess) ||
-        (e = hipMemsetAsync(ctx->db_scores.p, 0xFF, sizeof(int32_t) * (size_t)nq * ndb, st)) != hipSuccess ||
-        (e = hipStreamSynchronize(st)) != hipSuccess)
+        (e = launch_fill_i32((int32_t *)ctx->db_scores.p, (int64_t)nq * ndb, -1, st)) != hipSuccess)
         return hip_fail(ctx, e, "candidate layout");
+    // an empty query aligns with nothing: every score is 0, as in the exhaustive search
+    for (int32_t q = 0; q < nq; ++q)
+        if (qs.qo[q + 1] == qs.qo[q] &&
+            (e = launch_fill_i32((int32_t *)ctx->db_scores.p + (int64_t)q * ndb, ndb, 0, st)) != hipSuccess)
+            return hip_fail(ctx, e, "score fill");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(ctx, e, "candidate layout");
     ps.ms_select += ms_since(t0);
 
     t0 = Clock::now();

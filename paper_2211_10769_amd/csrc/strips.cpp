@@ -31,13 +31,6 @@ uint64_t wait_ticks(int device)
 
 }  // namespace
 
-int env_int(const char *name, int dflt)
-{
-    const char *v = std::getenv(name);
-    if (!v || !*v) return dflt;
-    return std::atoi(v);
-}
-
 // Strip height for a launch whose problems hold n rows in all.  The strips of
 // one problem form a chain that moves at the pace of its slowest wave, so a
 // long problem runs with one wave per SIMD; each SIMD then runs
@@ -51,8 +44,6 @@ int env_int(const char *name, int dflt)
 // waves per SIMD 23% slower.
 int pick_rows_per_lane(int64_t n, int simds)
 {
-    const int forced = env_int("SWH_ROWS", 0);
-    if (forced == 4 || forced == 8 || forced == 16 || forced == 20 || forced == 24 || forced == 32) return forced;
     simds = std::max(simds, 1);
     auto strips = [&](int R) { return (n + 64 * R - 1) / (64 * R); };
     if (strips(8) >= (int64_t)simds) {
@@ -80,11 +71,10 @@ int pick_rows_per_lane(int64_t n, int simds)
 }
 
 // Grid of single-wave workgroups (used when the balanced placement cannot be
-// made, or SWH_GRID forces it): a whole number of waves per SIMD on average,
-// 8 for R=4, 4 for R=8 and 1 for taller strips.
-int strip_grid(int64_t nstrips, int R, int limit, int num_cu, int waves)
+// made, or the grid option forces it): a whole number of waves per SIMD on
+// average, 8 for R=4, 4 for R=8 and 1 for taller strips.
+int strip_grid(int64_t nstrips, int R, int limit, int num_cu, int waves, int forced)
 {
-    const int forced = env_int("SWH_GRID", 0);
     if (forced > 0) return (int)std::min<int64_t>(forced, nstrips);
     const int per_simd = waves > 0 ? waves : R <= 4 ? 8 : R <= 8 ? 4 : 1;
     const int want = std::min(limit, per_simd * 4 * std::max(num_cu, 1));
@@ -161,14 +151,15 @@ swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, cons
     a.smax = sc.smax;
     a.ticket = (int32_t *)ctx->sync.p;
     a.abort_flag = (int32_t *)ctx->sync.p + 1;
+    a.cancel = ctx->cancel_dev;
     a.strip_best = (BestCell *)ctx->strip_best.p;
     a.wait_ticks = wait_ticks(ctx->device);
     // Strips of one problem form a chain that moves at the pace of its slowest
     // wave, so every SIMD must hold the same number of waves: a balanced
     // placement when it can be made (with fewer waves per SIMD when there are
-    // few strips), else single-wave workgroups (SWH_GRID forces those).
+    // few strips), else single-wave workgroups (the grid option forces those).
     StripLaunch grid{0, 1, strip_lds_bytes(R, sc.asize)};
-    const int forced = env_int("SWH_GRID", 0);
+    const int forced = ctx->opt.grid;
     // long chains (a few big problems) want one wave per SIMD; many short
     // ones want several to hide latency (read-pair batch: 4 for R = 8)
     const bool long_chains = total_strips >= 16 * (int64_t)np;
@@ -176,7 +167,7 @@ swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, cons
     while (per_simd > 1 && (int64_t)per_simd / 2 * 4 * ctx->num_cu >= total_strips) per_simd /= 2;
     if (forced > 0 || !strip_balanced_launch(ctx->device, R, local, sc.asize, per_simd, ctx->num_cu, grid)) {
         grid = StripLaunch{strip_grid(total_strips, R, strip_grid_limit(ctx->device, R, local, sc.asize), ctx->num_cu,
-                                      waves),
+                                      waves, forced),
                            1, strip_lds_bytes(R, sc.asize)};
     }
     hipEventRecord(ctx->ev[0], st);
@@ -197,7 +188,11 @@ swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, cons
     }
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(ctx, e, "strip pass");
     if (ms) hipEventElapsedTime(ms, ctx->ev[0], ctx->ev[1]);
-    if (flags_host[1]) return fail(ctx, SWH_E_TIMEOUT, "strip wavefront wait expired");
+    if (flags_host[1]) {
+        if (cancelled(ctx)) return cancel_status(ctx);
+        return fail(ctx, SWH_E_TIMEOUT, "strip wavefront wait expired");
+    }
+    if (cancelled(ctx)) return cancel_status(ctx);
     return SWH_OK;
 }
 

@@ -33,9 +33,8 @@ struct StripProblem {
 inline int64_t rows_padded(int64_t n, int R) { return ((n + 64 * R - 1) / (64 * R)) * 64 * R; }
 inline int64_t cols_padded(int64_t m) { return 64 * (sweep_blocks(m) + 3); }
 
-int env_int(const char *name, int dflt);
 int pick_rows_per_lane(int64_t n, int simds);
-int strip_grid(int64_t nstrips, int R, int limit, int num_cu, int waves = 0);
+int strip_grid(int64_t nstrips, int R, int limit, int num_cu, int waves = 0, int forced = 0);
 
 // One launch over all problems; local mode fills best (one entry per problem).
 // waves: waves per SIMD of the persistent grid, 0 = the rule for R.

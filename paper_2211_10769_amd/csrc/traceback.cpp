@@ -118,7 +118,7 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
     std::vector<BorderInit> bi0;
     for (int k = 0; k < npairs; ++k) {
         const TbInput &x = in[k];
-        uint8_t *bpad = (uint8_t *)arena.get((size_t)x.q + 2);
+        uint8_t *bpad = (uint8_t *)arena.get((size_t)x.q + 2, ctx->held, ctx->opt.mem_cap);
         if (!bpad) return fail(ctx, SWH_E_NOMEM, "traceback arena");
         gd0.push_back(GatherDesc{x.B, bpad, 0, x.q, x.q + 1, 1, 1});
         std::vector<TbBand> bands = x.bands;
@@ -130,7 +130,7 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
                 return fail(ctx, SWH_E_DEVICE, "traceback: malformed band (internal error)");
             }
             const int64_t cnt = b.seeded ? b.J - b.L + 1 : x.q + 1;
-            Border *front = (Border *)arena.get(sizeof(Border) * (size_t)cnt);
+            Border *front = (Border *)arena.get(sizeof(Border) * (size_t)cnt, ctx->held, ctx->opt.mem_cap);
             if (!front) return fail(ctx, SWH_E_NOMEM, "traceback arena");
             bi0.push_back(BorderInit{front, nullptr, cnt, cnt, b.seeded ? 3 : 1, b.seed_h, b.seed_f, 0});
             Node root;
@@ -162,9 +162,9 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
     std::vector<char> ops_host;
     std::vector<int> ready((size_t)nodes.size());
     for (size_t k = 0; k < nodes.size(); ++k) ready[k] = (int)k;
-    // SWH_TB_LEAF lowers the leaf size (tests use it to force deep recursion on small inputs)
+    // the leaf-size option lowers it (tests use it to force deep recursion on small inputs)
     const int64_t leaf_cells =
-        std::max<int64_t>(1, std::min<int64_t>(kLeafCellsMax, env_int("SWH_TB_LEAF", (int)kLeafCellsMax)));
+        std::max<int64_t>(1, std::min<int64_t>(kLeafCellsMax, ctx->opt.tb_leaf > 0 ? ctx->opt.tb_leaf : kLeafCellsMax));
 
     // exit of node k is known: tell its parent chain and release a waiting top sibling
     auto propagate = [&](int k) {
@@ -194,6 +194,7 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
     };
 
     while (!ready.empty()) {
+        if (cancelled(ctx)) return cancel_status(ctx);
         std::vector<int> cur;
         cur.swap(ready);
         std::vector<int> leaves, splits;
@@ -216,7 +217,7 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
             for (int k : splits) allrows += nodes[k].r_bot - nodes[k].r_top;
             StripShape shape = tuned_shape(ctx, allrows);
             const int64_t mean_pass = allrows / (2 * (int64_t)splits.size()) + 1;
-            while (shape.R > 4 && 64 * shape.R > mean_pass && env_int("SWH_ROWS", 0) == 0)
+            while (shape.R > 4 && 64 * shape.R > mean_pass && ctx->opt.rows == 0)
                 shape.R = shape.R > 16 ? 16 : shape.R / 2;
             const int R = shape.R;
             std::vector<GatherDesc> gd;
@@ -254,7 +255,7 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
                 // backward pass rows A_{r_bot}..A_{r+2}, columns J..L reversed, pad first
                 gd.push_back(GatherDesc{n.A, bq, n.r_bot - 1, Pb, rows_padded(std::max<int64_t>(Pb, 1), R), -1, 0});
                 gd.push_back(GatherDesc{n.bpad, bt, n.J, w - 1, cols_padded(w), -1, 1});
-                Border *fo = (Border *)arena.get(sizeof(Border) * (size_t)cols_padded(w));
+                Border *fo = (Border *)arena.get(sizeof(Border) * (size_t)cols_padded(w), ctx->held, ctx->opt.mem_cap);
                 if (!fo) return fail(ctx, SWH_E_NOMEM, "traceback frontier arena");
                 fwd_out[i] = fo;
                 bwd_out[i] = bp;

@@ -17,7 +17,7 @@ namespace swh {
 
 StripShape tuned_shape(swh_ctx *ctx, int64_t n)
 {
-    const int forced = env_int("SWH_ROWS", 0);
+    const int forced = ctx->opt.rows;
     if (forced == 4 || forced == 8 || forced == 16 || forced == 20 || forced == 24 || forced == 32)
         return StripShape{forced, 0};
     for (const swh_tune_entry &t : ctx->tune)

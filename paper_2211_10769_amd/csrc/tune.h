@@ -14,7 +14,7 @@ struct StripShape {
 };
 
 // Shape for a problem of n rows: the context's tuned table when it has one,
-// else the built-in rule.  SWH_ROWS overrides R.
+// else the built-in rule.  The rows-per-lane option overrides R.
 StripShape tuned_shape(swh_ctx *ctx, int64_t n);
 inline int tuned_rows_per_lane(swh_ctx *ctx, int64_t n, int64_t) { return tuned_shape(ctx, n).R; }
 

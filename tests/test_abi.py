@@ -52,3 +52,74 @@ def test_mode_constants_match_header():
     # single bits, disjoint from each other and from the mode values
     assert all(f & (f - 1) == 0 for f in forms) and len(set(forms)) == 3
     assert all(f > 0xFF for f in forms)
+
+
+def _lib():
+    from paper_2211_10769_amd import _lib as L
+    return L.load()
+
+
+def test_null_context_is_rejected_everywhere():
+    # every entry point that takes a context answers SWH_E_INVAL to NULL
+    # before touching the device (runs without a GPU)
+    from paper_2211_10769_amd import _lib as L
+    lib = _lib()
+    skip = {"swh_create", "swh_destroy", "swh_last_error", "swh_db_destroy", "swh_model_destroy"}
+    for name, (res, args) in L.SIGNATURES.items():
+        if name in skip:
+            continue
+        assert args[0] is ctypes.c_void_p, name
+        fn = getattr(lib, name)
+        call = [None] + [0 if a in (ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64) else
+                         0.0 if a is ctypes.c_double else None for a in args[1:]]
+        assert fn(*call) == -1, name
+    assert lib.swh_last_error(None) == b"no context"
+    assert lib.swh_create(0, None) == -1
+    lib.swh_destroy(None)
+    lib.swh_db_destroy(None)
+    lib.swh_model_destroy(None)
+
+
+def test_option_constants_match_header():
+    from paper_2211_10769_amd import _lib as L
+    text = open(HEADER).read()
+    vals = dict(re.findall(r"SWH_OPT_([A-Z_0-9]+)\s*=\s*(\d+)", text))
+    assert {k.lower(): int(v) for k, v in vals.items()} == {
+        {"rows_per_lane": "rows_per_lane"}.get(k, k): v for k, v in L.OPTIONS.items()}
+
+
+def _extern_c_functions():
+    src = open(os.path.join(ROOT, "paper_2211_10769_amd", "csrc", "capi.cpp")).read()
+    body = src[src.index('extern "C" {'):]
+    funcs = {}
+    for m in re.finditer(r"\n(swh_status|void|const char \*)\s*(swh_[a-z_0-9]+)\(", body):
+        start = m.end()
+        depth, i = 0, body.index("{", start)
+        j = i
+        while True:
+            if body[j] == "{":
+                depth += 1
+            elif body[j] == "}":
+                depth -= 1
+                if depth == 0:
+                    break
+            j += 1
+        funcs[m.group(2)] = (m.group(1), body[i:j + 1])
+    return funcs
+
+
+def test_every_entry_point_sits_behind_the_exception_barrier():
+    # no exception may cross the C ABI: every entry point either runs its body
+    # in guarded() (std::bad_alloc -> SWH_E_NOMEM, anything else ->
+    # SWH_E_DEVICE), or is a void destructor wrapped in try/catch(...), or
+    # does nothing that can throw (flag stores, reads of plain fields)
+    funcs = _extern_c_functions()
+    assert set(funcs) == set(_declared()), set(funcs) ^ set(_declared())
+    no_throw = {"swh_last_error", "swh_cancel", "swh_get_option", "swh_tune_get"}
+    for name, (ret, body) in funcs.items():
+        if name in no_throw:
+            assert "std::string" not in body and "new " not in body and "vector" not in body, name
+        elif ret == "void":
+            assert "catch (...)" in body, name
+        else:
+            assert "guarded(" in body, name

@@ -96,10 +96,10 @@ def test_bad_symbol(eng):
 
 @pytest.mark.parametrize("rows,grid", [(4, 0), (8, 0), (16, 0), (20, 0), (24, 0), (32, 0), (16, 1), (8, 3), (20, 3),
                                        (24, 2), (32, 2)])
-def test_forced_strip_shapes(eng, rows, grid, monkeypatch):
+def test_forced_strip_shapes(eng, rows, grid, opt):
     # every strip height and tiny persistent grids (one wave doing every strip in turn)
-    monkeypatch.setenv("SWH_ROWS", str(rows))
-    monkeypatch.setenv("SWH_GRID", str(grid))
+    opt("rows_per_lane", rows)
+    opt("grid", grid)
     rng = np.random.default_rng(rows * 100 + grid)
     sc = seqgen.dna_scoring()
     a = seqgen.random_dna(rng, 6000)

@@ -1,5 +1,5 @@
 """GPU parity of the band traceback: the first split of the reconstruction
-taken from rows kept by the two score passes.  SWH_BAND_ROWS forces kept
+taken from rows kept by the two score passes.  The band-rows option forces kept
 rows every few strips on inputs small enough for the oracle; the CIGAR must
 equal the oracle's full-matrix greedy walk byte for byte, and the bands must
 be used (no fall back to the plain divide and conquer)."""
@@ -33,11 +33,11 @@ def _cmp(eng, a, b, sc, min_bands=2):
 
 
 @pytest.fixture
-def bands(monkeypatch):
+def bands(opt):
     def set_(rows, R=None):
-        monkeypatch.setenv("SWH_BAND_ROWS", str(rows))
+        opt("band_rows", rows)
         if R is not None:
-            monkeypatch.setenv("SWH_ROWS", str(R))
+            opt("rows_per_lane", R)
     return set_
 
 

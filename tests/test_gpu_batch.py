@@ -85,9 +85,9 @@ def test_protein_pairs(eng):
     _check(eng.align_batch(qs, ts, sc, mode="cigar"), _oracle_all(qs, ts, sc))
 
 
-def test_tie_heavy_batch(eng, monkeypatch):
+def test_tie_heavy_batch(eng, opt):
     # deep recursion inside every pair of the batch (tiny leaves), binary alphabet, o = e = 1
-    monkeypatch.setenv("SWH_TB_LEAF", "16")
+    opt("tb_leaf", 16)
     tie = ("AC", np.array([[1, -1], [-1, 1]], dtype=np.int8), 1, 1)
     rng = np.random.default_rng(11)
     qs = [bytes(rng.choice(np.frombuffer(b"AC", np.uint8), n)) for n in (20, 70, 150, 333)]
@@ -144,24 +144,24 @@ def test_tuned_shapes_keep_results(eng):
 
 
 @pytest.mark.parametrize("rows", [256, 1024])
-def test_band_traceback_in_batches(eng, monkeypatch, rows):
+def test_band_traceback_in_batches(eng, opt, rows):
     # kept rows every few strips in both passes of every pair; CIGARs unchanged
-    monkeypatch.setenv("SWH_BAND_ROWS", str(rows))
+    opt("band_rows", rows)
     qs, ts = _read_pairs(120, 6000, seed_stream=12)
     sc = seqgen.dna_scoring()
     got, st = eng.align_batch(qs, ts, sc, mode="cigar", stats=True)
     _check(got, _oracle_all(qs, ts, sc))
     assert st["traceback_retries"] == 0
     assert st["traceback_bands"] > len(qs)
-    monkeypatch.setenv("SWH_BAND_ROWS", "-1")
+    opt("band_rows", -1)
     got2, st2 = eng.align_batch(qs, ts, sc, mode="cigar", stats=True)
     assert st2["traceback_bands"] == 0 and st2["cells_traceback"] > 2 * st["cells_traceback"]
     _check(got2, got)
 
 
-def test_band_traceback_tie_heavy_batch(eng, monkeypatch):
-    monkeypatch.setenv("SWH_BAND_ROWS", "256")
-    monkeypatch.setenv("SWH_ROWS", "4")
+def test_band_traceback_tie_heavy_batch(eng, opt):
+    opt("band_rows", 256)
+    opt("rows_per_lane", 4)
     tie = ("AC", np.array([[1, -1], [-1, 1]], dtype=np.int8), 1, 1)
     rng = np.random.default_rng(13)
     qs, ts = [], []

@@ -51,15 +51,15 @@ def test_random_and_related(eng, n, m):
     _cmp(eng, bytes(a), bytes(b), sc)
 
 
-def test_tie_heavy_and_protein(eng, monkeypatch):
-    monkeypatch.setenv("SWH_TB_LEAF", "16")
+def test_tie_heavy_and_protein(eng, opt):
+    opt("tb_leaf", 16)
     tie = ("AC", np.array([[1, -1], [-1, 1]], dtype=np.int8), 1, 1)
     rng = np.random.default_rng(3)
     for n in (50, 333):
         a = bytes(rng.choice(np.frombuffer(b"AC", np.uint8), n))
         b = bytes(rng.choice(np.frombuffer(b"AC", np.uint8), n + 11))
         _cmp(eng, a, b, tie)
-    monkeypatch.delenv("SWH_TB_LEAF")
+    opt("tb_leaf", 0)
     sc = seqgen.protein_scoring()
     q = seqgen.random_protein(rng, 800)
     _cmp(eng, bytes(q), bytes(seqgen.homolog(rng, q)), sc)
@@ -116,10 +116,10 @@ def test_range_limit(eng):
 
 
 @pytest.mark.parametrize("band_rows", [512, 1024, 2560])
-def test_banded_traceback_matches_oracle(eng, monkeypatch, band_rows):
+def test_banded_traceback_matches_oracle(eng, opt, band_rows):
     # kept rows of a forward and a corner-anchored reverse global pass cut the
     # traceback into bands; the CIGAR must not change
-    monkeypatch.setenv("SWH_BAND_ROWS", str(band_rows))
+    opt("band_rows", band_rows)
     rng = np.random.default_rng(band_rows)
     sc = seqgen.dna_scoring()
     a = seqgen.random_dna(rng, 6000)
@@ -140,14 +140,14 @@ def test_banded_traceback_matches_oracle(eng, monkeypatch, band_rows):
     _cmp(eng, x, y, tie)
 
 
-def test_banded_equals_plain_at_300kbp(eng, monkeypatch):
+def test_banded_equals_plain_at_300kbp(eng, opt):
     rng = np.random.default_rng(21)
     sc = seqgen.dna_scoring()
     a = seqgen.random_dna(rng, 300_000)
     b = seqgen.mutate(rng, a, 0.03, 0.01)
-    monkeypatch.setenv("SWH_BAND_ROWS", "-1")
+    opt("band_rows", -1)
     plain = eng.align(bytes(a), bytes(b), sc, mode="cigar", alignment="global", stats=True)
-    monkeypatch.delenv("SWH_BAND_ROWS")
+    opt("band_rows", 0)
     banded = eng.align(bytes(a), bytes(b), sc, mode="cigar", alignment="global", stats=True)
     assert banded["stats"]["traceback_bands"] > 10 and banded["stats"]["traceback_retries"] == 0
     assert {k: banded[k] for k in KEYS} == {k: plain[k] for k in KEYS}

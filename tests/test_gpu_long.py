@@ -60,13 +60,13 @@ def test_full_size_pair(eng):
     assert _rescore(q, t, res, sc) == res["score"]
 
 
-def test_bands_equal_plain_at_1mbp(eng, monkeypatch):
+def test_bands_equal_plain_at_1mbp(eng, opt):
     q, t = seqgen.workload1(1_000_000, flank=10_000)
     q, t = bytes(q), bytes(t)
     sc = seqgen.dna_scoring()
-    monkeypatch.setenv("SWH_BAND_ROWS", "8192")
+    opt("band_rows", 8192)
     banded = eng.align(q, t, sc, mode="cigar", stats=True)
-    monkeypatch.setenv("SWH_BAND_ROWS", "-1")
+    opt("band_rows", -1)
     plain = eng.align(q, t, sc, mode="cigar", stats=True)
     assert banded["stats"]["traceback_bands"] > 50 and plain["stats"]["traceback_bands"] == 0
     keys = ["score", "q_begin", "q_end", "t_begin", "t_end", "cigar"]

@@ -70,8 +70,8 @@ def test_containment(eng):
     _cmp(eng, bytes(b), bytes(a), sc)
 
 
-def test_tie_heavy_asymmetric_and_protein(eng, monkeypatch):
-    monkeypatch.setenv("SWH_TB_LEAF", "16")
+def test_tie_heavy_asymmetric_and_protein(eng, opt):
+    opt("tb_leaf", 16)
     tie = ("AC", np.array([[1, -1], [-1, 1]], dtype=np.int8), 1, 1)
     rng = np.random.default_rng(6)
     for n, m in ((50, 61), (333, 900), (200, 150), (700, 700)):
@@ -85,7 +85,7 @@ def test_tie_heavy_asymmetric_and_protein(eng, monkeypatch):
         b = bytes(rng.choice(np.frombuffer(b"ACG", np.uint8), m))
         _cmp(eng, a, b, asym)
         _cmp(eng, b, a, asym)
-    monkeypatch.delenv("SWH_TB_LEAF")
+    opt("tb_leaf", 0)
     sc = seqgen.protein_scoring()
     q = seqgen.random_protein(rng, 600)
     h = seqgen.homolog(rng, q)

@@ -172,18 +172,18 @@ def test_training_labels_are_exact(eng, swh):
     assert stats["steps"] == 4
 
 
-def test_graph_replay_matches_eager_steps(eng, swh, monkeypatch):
+def test_graph_replay_matches_eager_steps(eng, swh, opt):
     # the captured training step replayed across epochs (with eager copies and
     # synchronisations between replays) gives exactly the eagerly launched result
     cat, off, rows, cols = seqgen.prefilter_training_set(n_pairs=2048, n_queries=40, homologs=5, n_background=400)
     sc = seqgen.protein_scoring()
     labels = np.random.default_rng(1).integers(0, 500, size=len(rows)).astype(np.int32)
     out = []
-    for no_graph in ("0", "1"):
-        monkeypatch.setenv("SWH_NO_GRAPH", no_graph)
+    for graph in (1, 0):
+        opt("graph", graph)
         model = swh.Model(eng, sc, seed=4)
         st = model.train((cat, off), rows, cols, sc, scores=labels, epochs=3, batch=256, seed=9)
-        assert st["steps"] == 24 and st["graph"] == (1 if no_graph == "0" else 0)
+        assert st["steps"] == 24 and st["graph"] == graph
         out.append(model.get()[0])
     assert np.array_equal(out[0], out[1])
 

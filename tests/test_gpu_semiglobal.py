@@ -54,15 +54,15 @@ def test_random_and_embedded(eng, n, m):
     assert got["t_begin"] >= 0
 
 
-def test_tie_heavy_and_protein(eng, monkeypatch):
-    monkeypatch.setenv("SWH_TB_LEAF", "16")
+def test_tie_heavy_and_protein(eng, opt):
+    opt("tb_leaf", 16)
     tie = ("AC", np.array([[1, -1], [-1, 1]], dtype=np.int8), 1, 1)
     rng = np.random.default_rng(5)
     for n, m in ((50, 61), (333, 900), (200, 150)):
         a = bytes(rng.choice(np.frombuffer(b"AC", np.uint8), n))
         b = bytes(rng.choice(np.frombuffer(b"AC", np.uint8), m))
         _cmp(eng, a, b, tie)
-    monkeypatch.delenv("SWH_TB_LEAF")
+    opt("tb_leaf", 0)
     sc = seqgen.protein_scoring()
     q = seqgen.random_protein(rng, 600)
     t = np.concatenate([seqgen.random_protein(rng, 300), seqgen.homolog(rng, q), seqgen.random_protein(rng, 200)])

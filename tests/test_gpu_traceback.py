@@ -47,9 +47,9 @@ def test_similar_dna(eng, n):
 
 
 @pytest.mark.parametrize("leaf", [1, 7, 64, 1000])
-def test_leaf_size_sweep(eng, leaf, monkeypatch):
+def test_leaf_size_sweep(eng, leaf, opt):
     # tiny leaves force deep recursion on small inputs; tie-heavy scoring
-    monkeypatch.setenv("SWH_TB_LEAF", str(leaf))
+    opt("tb_leaf", leaf)
     rng = np.random.default_rng(leaf)
     tie = ("AC", np.array([[1, -1], [-1, 1]], dtype=np.int8), 1, 1)
     for n in (40, 200):

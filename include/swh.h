@@ -242,6 +242,31 @@ swh_status swh_align_dev(swh_ctx *ctx, const char *q_dev, int64_t qlen, const ch
                          int64_t *cigar_len, swh_stats *stats);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the score
+ * pass, and with SWH_MODE_COORDS the start pass, of swh_align_dev, with no
+ * allocation of any kind -- no hipMalloc or hipFree, no host heap, no
+ * context.  Every buffer the passes need beyond the inputs and `out` comes
+ * from one static device array of 64 MiB per GPU, held from the library's
+ * load on that GPU until the process ends.  q_dev, t_dev: device pointers;
+ * stream: a hipStream_t (NULL = default stream); the call orders its work
+ * after prior work on it and returns when *out is on the host.  mode:
+ * SWH_MODE_SCORE or SWH_MODE_COORDS only (no CIGAR, no global forms).
+ * Results equal swh_align_dev's in the same mode.  Size limit: about
+ * 2 qlen + 10 tlen bytes of the array (a 5 Mbp query against a 5.1 Mbp
+ * target fits); beyond it SWH_E_RANGE.  Other errors: SWH_E_INVAL (bad
+ * device, NULL pointers, bad scoring or mode), SWH_E_ALPHABET,
+ * SWH_E_DEVICE, SWH_E_TIMEOUT; there is no context and so no error text.
+ * Calls on one GPU share the array: the library serialises them with a host
+ * mutex per device, so concurrent calls from several threads of a process
+ * wait for each other (the array keeps the last call's contents; everything
+ * that must start at zero is cleared on each call).
+ */
+swh_status swh_align_dev_noalloc(int device, const char *q_dev, int64_t qlen, const char *t_dev,
+                                 int64_t tlen, const swh_scoring *scoring, int mode, void *stream,
+                                 swh_alignment *out);
+
+/*
  * Many independent local alignments in one call (paper, Background: SW# and
  * CUDASW++ both run many independent matrices; the library batches them).
  * Pair i is query q_cat[q_off[i] .. q_off[i+1]) against target

@@ -98,6 +98,8 @@ SIGNATURES = {
     "swh_align_dev": (ctypes.c_int, [_P, _P, _I64, _P, _I64, ctypes.POINTER(swh_scoring), ctypes.c_int,
                                      _P, ctypes.POINTER(swh_alignment), _P, _I64, _I64P,
                                      ctypes.POINTER(swh_stats)]),
+    "swh_align_dev_noalloc": (ctypes.c_int, [ctypes.c_int, _P, _I64, _P, _I64, ctypes.POINTER(swh_scoring),
+                                             ctypes.c_int, _P, ctypes.POINTER(swh_alignment)]),
     "swh_align_batch": (ctypes.c_int, [_P, _I64, _P, _P, _P, _P, ctypes.POINTER(swh_scoring), ctypes.c_int,
                                        _P, _P, _I64, _P, ctypes.POINTER(swh_stats)]),
     "swh_align_batch_dev": (ctypes.c_int, [_P, _I64, _P, _P, _P, _P, ctypes.POINTER(swh_scoring), ctypes.c_int,

@@ -138,6 +138,9 @@ typedef struct {
     int64_t  traceback_bands;   /* bands the traceback was cut into at rows kept by the
                                    score passes (0: one divide and conquer over the rectangle) */
     int64_t  traceback_retries; /* band traceback abandoned for the plain one (expected 0) */
+    int64_t  passes_int16;      /* local score passes run in packed 16-bit arithmetic */
+    int64_t  saturated_int16;   /* of those, passes whose maximum reached 32767 - max s and that were
+                                   recomputed in 32 bits (every reported value is exact) */
 } swh_stats;
 
 /* Context on HIP device `device` (ordinal).  Allocates nothing large; device

@@ -40,7 +40,8 @@ class swh_stats(ctypes.Structure):
                 ("cells_forward", ctypes.c_double), ("ms_forward", ctypes.c_double),
                 ("ms_reverse", ctypes.c_double), ("ms_traceback", ctypes.c_double),
                 ("cells_traceback", ctypes.c_double), ("traceback_bands", ctypes.c_int64),
-                ("traceback_retries", ctypes.c_int64)]
+                ("traceback_retries", ctypes.c_int64), ("passes_int16", ctypes.c_int64),
+                ("saturated_int16", ctypes.c_int64)]
 
 
 class swh_hit(ctypes.Structure):

@@ -54,12 +54,20 @@ swh_status score_passes(swh_ctx *ctx, const std::vector<PairPass> &ps, const Sco
     const size_t np = ps.size();
     best.assign(np, BestCell{0, 0, 0, 0});
     std::vector<StripShape> sh(np);
-    for (size_t i = 0; i < np; ++i) sh[i] = ps[i].R ? StripShape{ps[i].R, ps[i].waves} : tuned_shape(ctx, ps[i].n);
-    auto same = [&](size_t a, size_t b) { return sh[a].R == sh[b].R && sh[a].waves == sh[b].waves; };
-    // by strip shape, then most expensive first
+    std::vector<char> w16(np, 0);
+    for (size_t i = 0; i < np; ++i) {
+        sh[i] = ps[i].R ? StripShape{ps[i].R, ps[i].waves} : tuned_shape(ctx, ps[i].n);
+        if (ps[i].int16 && !ps[i].R) sh[i] = StripShape{r16_of(sh[i].R), 0};
+        w16[i] = ps[i].int16 && r16_of(sh[i].R) == sh[i].R && int16_usable(ctx, sc, sh[i].R);
+    }
+    auto same = [&](size_t a, size_t b) {
+        return sh[a].R == sh[b].R && sh[a].waves == sh[b].waves && w16[a] == w16[b];
+    };
+    // by precision and strip shape, then most expensive first
     std::vector<size_t> order(np);
     std::iota(order.begin(), order.end(), (size_t)0);
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+        if (w16[a] != w16[b]) return w16[a] > w16[b];
         if (sh[a].R != sh[b].R) return sh[a].R > sh[b].R;
         if (sh[a].waves != sh[b].waves) return sh[a].waves > sh[b].waves;
         return (double)ps[a].n * (double)ps[a].m > (double)ps[b].n * (double)ps[b].m;
@@ -125,10 +133,33 @@ swh_status score_passes(swh_ctx *ctx, const std::vector<PairPass> &ps, const Sco
             return hip_fail(ctx, e, "batch setup");
         std::vector<BestCell> b;
         float ms = 0.f;
-        if ((s = run_strips(ctx, probs, sc, Rk, true, st, &b, &ms, sh[lead].waves)) != SWH_OK) return s;
+        const bool i16 = w16[lead] != 0;
+        if ((s = run_strips(ctx, probs, sc, Rk, true, st, &b, &ms, sh[lead].waves, i16)) != SWH_OK) return s;
         ms_total += ms;
         for (size_t i = 0; i < idx.size(); ++i) best[idx[i]] = b[i];
+        if (i16) ctx->passes16 += (int64_t)idx.size();
         k = end;
+    }
+    // 16-bit passes whose maximum reached the limit may have saturated: again in
+    // 32 bits, same strip height and kept rows
+    const int32_t lim = sat16_limit(sc.smax);
+    std::vector<PairPass> redo;
+    std::vector<size_t> ridx;
+    for (size_t i = 0; i < np; ++i)
+        if (w16[i] && best[i].score >= lim) {
+            PairPass p = ps[i];
+            p.R = sh[i].R;
+            p.waves = 0;
+            p.int16 = false;
+            redo.push_back(p);
+            ridx.push_back(i);
+        }
+    if (!redo.empty()) {
+        std::vector<BestCell> b;
+        swh_status s = score_passes(ctx, redo, sc, st, b, ms_total);
+        if (s != SWH_OK) return s;
+        for (size_t j = 0; j < ridx.size(); ++j) best[ridx[j]] = b[j];
+        ctx->saturated16 += (int64_t)redo.size();
     }
     return SWH_OK;
 }
@@ -549,17 +580,21 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
     } else {
     const int forced = ctx->opt.band_rows;
     const bool banded = mode == SWH_MODE_CIGAR && forced >= 0;
+    const bool want16 = ctx->opt.int16 != 0;
     std::vector<BandKeep> bk((size_t)npairs);
     std::vector<int64_t> frecs((size_t)npairs, 0);
+    for (int64_t i = 0; i < npairs; ++i) ps[i].int16 = want16;
     if (banded)
         for (int64_t i = 0; i < npairs; ++i) {
             const StripShape sh = tuned_shape(ctx, ps[i].n);
-            const int64_t H = 64 * (int64_t)sh.R;
+            // the forward pass's strip height (16-bit passes: the packed kernel's)
+            const int R = want16 && int16_usable(ctx, sc, r16_of(sh.R)) ? r16_of(sh.R) : sh.R;
+            const int64_t H = 64 * (int64_t)R;
             const int64_t want = forced > 0 ? forced : kBatchBandRows;
             const int every = (int)std::max<int64_t>(1, (want + H - 1) / H);
-            frecs[i] = band_forward_layout(sh.R, every, ps[i].n, ps[i].m, bk[i]);
-            ps[i].R = sh.R;
-            ps[i].waves = sh.waves;
+            frecs[i] = band_forward_layout(R, every, ps[i].n, ps[i].m, bk[i]);
+            ps[i].R = R;
+            ps[i].waves = R == sh.R ? sh.waves : 0;
         }
     int64_t budget = kBatchKeepBytes / (int64_t)sizeof(Border);
     {
@@ -633,6 +668,7 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
         for (int64_t i : pos_pairs) {
             PairPass p{ps[i].q + out[i].q_end, out[i].q_end + 1, ps[i].t + out[i].t_end, out[i].t_end + 1, -1};
             p.prune = prune ? out[i].score : 0;   // the reverse maximum is the forward score
+            p.int16 = want16 && out[i].score < sat16_limit(sc.smax);
             BandKeep &k = bk[(size_t)i];
             if (k.every > 0) {
                 rrecs += band_reverse_layout(out[i].q_end, out[i].t_end, k);

@@ -22,9 +22,13 @@ struct PairPass {
     Border *keep = nullptr;    // kept rows (strips.h StripProblem), or NULL
     int32_t every = 0, phase = 0;
     int32_t prune = 0;         // known maximum of a reverse pass (block pruning), or 0
+    bool int16 = false;        // packed 16-bit pass where the shape allows it (saturated passes are redone)
 };
 // Score, end row and end column of every pass (launches grouped by strip
-// shape, most expensive first, chunked to bound device memory).
+// shape and precision, most expensive first, chunked to bound device memory).
+// Passes asking for 16 bits run in the packed kernel when their strip height
+// allows it; any whose maximum reaches sat16_limit is run again in 32 bits
+// with the same strip height (so kept rows land on the same rows).
 swh_status score_passes(swh_ctx *ctx, const std::vector<PairPass> &ps, const Scoring &sc, hipStream_t st,
                         std::vector<BestCell> &best, double &ms_total);
 

@@ -150,6 +150,8 @@ swh_status begin_call(swh_ctx *ctx)
 {
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SWH_E_DEVICE, "hipSetDevice failed");
     if (ctx->cancel_host) __atomic_store_n(ctx->cancel_host, 0, __ATOMIC_RELEASE);
+    ctx->passes16 = 0;
+    ctx->saturated16 = 0;
     if (ctx->opt.fault_nomem) {
         ctx->opt.fault_nomem = 0;
         throw std::bad_alloc();
@@ -268,8 +270,13 @@ swh_status batch_common(swh_ctx *ctx, int64_t npairs, const char *q_cat, const i
     }
     if ((s = begin_call(ctx)) != SWH_OK) return s;
     if (dev && (s = order_after(ctx, dev_stream)) != SWH_OK) return s;
-    return align_batch(ctx, npairs, q_cat, q_off, t_cat, t_off, sc, mode, out, cigar_cat, cigar_cap, cigar_off, stats,
-                       dev);
+    s = align_batch(ctx, npairs, q_cat, q_off, t_cat, t_off, sc, mode, out, cigar_cat, cigar_cap, cigar_off, stats,
+                    dev);
+    if (stats) {
+        stats->passes_int16 = ctx->passes16;
+        stats->saturated_int16 = ctx->saturated16;
+    }
+    return s;
 }
 
 }  // namespace
@@ -447,8 +454,13 @@ swh_status swh_align(swh_ctx *ctx, const char *q, int64_t qlen, const char *t, i
             return hip_fail(ctx, e, "hipMemcpyAsync(query)");
         if (tlen && (e = hipMemcpyAsync(ctx->traw.p, t, (size_t)tlen, hipMemcpyHostToDevice, st)) != hipSuccess)
             return hip_fail(ctx, e, "hipMemcpyAsync(target)");
-        return align_device(ctx, (const char *)ctx->qraw.p, qlen, (const char *)ctx->traw.p, tlen, sc, mode, st, out,
-                            cigar, cigar_cap, cigar_len, stats);
+        s = align_device(ctx, (const char *)ctx->qraw.p, qlen, (const char *)ctx->traw.p, tlen, sc, mode, st, out,
+                         cigar, cigar_cap, cigar_len, stats);
+        if (stats) {
+            stats->passes_int16 = ctx->passes16;
+            stats->saturated_int16 = ctx->saturated16;
+        }
+        return s;
     });
 }
 
@@ -466,8 +478,13 @@ swh_status swh_align_dev(swh_ctx *ctx, const char *q_dev, int64_t qlen, const ch
         if (stats && stats->struct_size < sizeof(swh_stats))
             return fail(ctx, SWH_E_INVAL, "stats->struct_size too small");
         if ((s = begin_call(ctx)) != SWH_OK) return s;
-        return align_device(ctx, q_dev, qlen, t_dev, tlen, sc, mode, (hipStream_t)stream, out, cigar, cigar_cap,
-                            cigar_len, stats);
+        s = align_device(ctx, q_dev, qlen, t_dev, tlen, sc, mode, (hipStream_t)stream, out, cigar, cigar_cap,
+                         cigar_len, stats);
+        if (stats) {
+            stats->passes_int16 = ctx->passes16;
+            stats->saturated_int16 = ctx->saturated16;
+        }
+        return s;
     });
 }
 

@@ -108,6 +108,9 @@ struct swh_ctx {
     int32_t *cancel_dev = nullptr;
     // device bytes held by the context's own buffers (the memory cap counts these)
     size_t held = 0;
+    // local passes of the current call run in packed 16 bits, and those redone
+    // in 32 bits after a possible saturation
+    int64_t passes16 = 0, saturated16 = 0;
 
     // pairwise buffers
     swh::DevBuf qraw, traw;        // ASCII copies of host inputs

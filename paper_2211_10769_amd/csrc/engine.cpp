@@ -40,7 +40,7 @@ struct KeepRows {
 // One local score pass over encoded inputs already on the device.
 swh_status local_pass(swh_ctx *ctx, const uint8_t *qc, int64_t n, const uint8_t *tc, int64_t m,
                       const Scoring &sc, StripShape shape, hipStream_t st, LocalPass &res, const KeepRows &kr = {},
-                      int32_t prune = 0)
+                      int32_t prune = 0, bool int16 = false)
 {
     const size_t bcount = (size_t)cols_padded(m);
     swh_status s;
@@ -58,8 +58,9 @@ swh_status local_pass(swh_ctx *ctx, const uint8_t *qc, int64_t n, const uint8_t 
     }
     std::vector<StripProblem> pr{sp};
     std::vector<BestCell> best;
-    if ((s = run_strips(ctx, pr, sc, shape.R, true, st, &best, &res.ms, shape.waves)) != SWH_OK) return s;
+    if ((s = run_strips(ctx, pr, sc, shape.R, true, st, &best, &res.ms, shape.waves, int16)) != SWH_OK) return s;
     res.best = best[0];
+    if (int16) ++ctx->passes16;
     return SWH_OK;
 }
 
@@ -519,12 +520,15 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
         return SWH_OK;
     }
 
-    // ---- resolution: forward local pass (keeping rows for the band traceback in CIGAR mode)
+    // ---- resolution: forward local pass (keeping rows for the band traceback in
+    // CIGAR mode), in packed 16-bit arithmetic when no cell can reach its limit
+    const bool f16 = never_saturates(qlen, tlen, sc) && int16_usable(ctx, sc, r16_of(shape.R));
+    const StripShape fshape = f16 ? StripShape{r16_of(shape.R), 0} : shape;
     BandKeep bk;
     KeepRows kfwd;
     {
-        const int every = mode == SWH_MODE_CIGAR ? band_stride(ctx, qlen, tlen, shape.R) : 0;
-        const int64_t recs = band_forward_layout(shape.R, every, qlen, tlen, bk);
+        const int every = mode == SWH_MODE_CIGAR ? band_stride(ctx, qlen, tlen, fshape.R) : 0;
+        const int64_t recs = band_forward_layout(fshape.R, every, qlen, tlen, bk);
         if (bk.every > 0) {
             if (ensure(ctx, ctx->keep_f, (size_t)recs * sizeof(Border), "kept rows") != SWH_OK) {
                 bk.every = 0;
@@ -536,8 +540,8 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
         }
     }
     LocalPass fwd;
-    if ((s = local_pass(ctx, (const uint8_t *)ctx->qc.p, qlen, (const uint8_t *)ctx->tc.p, tlen, sc, shape, st, fwd,
-                        kfwd)) != SWH_OK)
+    if ((s = local_pass(ctx, (const uint8_t *)ctx->qc.p, qlen, (const uint8_t *)ctx->tc.p, tlen, sc, fshape, st, fwd,
+                        kfwd, 0, f16)) != SWH_OK)
         return s;
     if (stats) {
         stats->cells_forward = (double)qlen * (double)tlen;
@@ -562,10 +566,13 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
     // steps are shortest at 8 rows per lane (long pair: 1.70 s against 2.41 s
     // at 20).  With kept rows the reverse strips must still end on the cut rows.
     const bool prune_rev = ctx->opt.prune != 0;
-    const int64_t rrecs = band_reverse_layout(out->q_end, out->t_end, bk, prune_rev ? 8 : shape.R);
-    const StripShape rshape = bk.every > 0 ? StripShape{bk.Rr, bk.Rr == shape.R ? shape.waves : 0}
+    const int64_t rrecs = band_reverse_layout(out->q_end, out->t_end, bk, prune_rev ? 8 : fshape.R);
+    const StripShape rshape = bk.every > 0 ? StripShape{bk.Rr, bk.Rr == fshape.R ? fshape.waves : 0}
                               : (prune_rev && rn >= 512) ? StripShape{8, 0}
                                                          : tuned_shape(ctx, rn);
+    // the reverse pass's maximum is the forward score: 16 bits are exact below the limit
+    const bool r16 = fwd.best.score < sat16_limit(sc.smax) && r16_of(rshape.R) == rshape.R &&
+                     int16_usable(ctx, sc, rshape.R);
     const int64_t lead = bk.every > 0 ? bk.lead : 0;
     const int64_t rqpad = rows_padded(rn + lead, rshape.R);
     const int64_t rtpad = cols_padded(rm);
@@ -588,7 +595,7 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
     const int32_t prune = prune_rev ? fwd.best.score : 0;
     LocalPass rev;
     if ((s = local_pass(ctx, (const uint8_t *)ctx->qr.p, rn + lead, (const uint8_t *)ctx->tr.p, rm, sc, rshape, st,
-                        rev, krev, prune)) != SWH_OK)
+                        rev, krev, prune, r16)) != SWH_OK)
         return s;
     if (stats) stats->ms_reverse = rev.ms;
     if (rev.best.score != fwd.best.score)

@@ -103,6 +103,17 @@ hipError_t launch_reduce_best(const BestCell *in, int32_t count, BestCell *out, 
 hipError_t launch_reduce_best_multi(const BestCell *strip_best, const Problem *probs, int32_t nprobs,
                                     BestCell *out, hipStream_t st);
 
+// Packed 16-bit local passes (dp_strip16.hip).  R = rows per lane of the
+// strip height 64 R as in the 32-bit kernel (4, 8, 16 or 32; each half of a
+// register holds R / 2 of them); the sweep takes one block more.  Results are
+// exact when the pass's maximum stays below sat16_limit.
+size_t strip16_lds_bytes(int R, int asize);
+bool strip16_supported(int R, int asize, int device);
+bool strip16_balanced_launch(int device, int R, int asize, int per_simd, int num_cu, StripLaunch &out);
+int strip16_grid_limit(int device, int R, int asize);
+hipError_t launch_strip16(const StripArgs &a, int R, const StripLaunch &grid, hipStream_t st, bool prune);
+inline int32_t sat16_limit(int smax) { return 32767 - (smax > 0 ? smax : 0); }
+
 // Blocks of 64 steps that sweep m columns with the 63-step lane skew:
 // ceil((m + 63) / 64).  Code and border buffers hold 64 * (blocks + 3) entries.
 inline int64_t sweep_blocks(int64_t m) { return (m + 63 + 63) / 64; }

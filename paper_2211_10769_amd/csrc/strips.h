@@ -37,8 +37,22 @@ int pick_rows_per_lane(int64_t n, int simds);
 int strip_grid(int64_t nstrips, int R, int limit, int num_cu, int waves = 0, int forced = 0);
 
 // One launch over all problems; local mode fills best (one entry per problem).
-// waves: waves per SIMD of the persistent grid, 0 = the rule for R.
+// waves: waves per SIMD of the persistent grid, 0 = the rule for R.  int16
+// (local mode, R in 4, 8, 16, 32): the packed 16-bit kernel; a problem whose
+// best score reaches sat16_limit(smax) may have saturated and must be redone
+// in 32 bits by the caller.
 swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, const Scoring &sc, int R, bool local,
-                      hipStream_t st, std::vector<BestCell> *best, float *ms, int waves = 0);
+                      hipStream_t st, std::vector<BestCell> *best, float *ms, int waves = 0, bool int16 = false);
+
+// Strip height (rows per lane) of a packed 16-bit pass standing in for a
+// 32-bit pass of R rows per lane, and whether the context may run one.
+inline int r16_of(int R) { return R <= 4 ? 4 : R <= 8 ? 8 : R <= 20 ? 16 : 32; }
+bool int16_usable(const swh_ctx *ctx, const Scoring &sc, int R);
+// No cell of an n x m local pass can reach sat16_limit (S <= min(n, m) max s).
+inline bool never_saturates(int64_t n, int64_t m, const Scoring &sc)
+{
+    const int64_t smax = sc.smax > 0 ? sc.smax : 1;
+    return (n < m ? n : m) * smax < sat16_limit(sc.smax);
+}
 
 }  // namespace swh

@@ -186,10 +186,12 @@ swh_status  swh_cancel(swh_ctx *ctx);
  *                          would need more fails with SWH_E_NOMEM; optional
  *                          buffers (rows kept for the band traceback) shrink
  *                          to fit instead.
- *   SWH_OPT_INT16          1 (default): local score passes of pairs run in
- *                          packed 16-bit arithmetic where that is exact, with a
- *                          32-bit recomputation of any pair that may have
- *                          saturated; 0: 32-bit only
+ *   SWH_OPT_INT16          local score passes in packed 16-bit arithmetic
+ *                          (two cells per lane operation), exact: a pass whose
+ *                          maximum reaches 32767 - max s is recomputed in 32
+ *                          bits.  1 (default): batches, and single passes large
+ *                          enough to fill the GPU; 2: also every single pass
+ *                          that cannot reach the limit; 0: 32-bit only
  *   SWH_OPT_INTER_MAX      database sequences up to this length go to the
  *                          inter-task kernel, longer ones to the single-pair
  *                          kernel (applies to databases created afterwards);

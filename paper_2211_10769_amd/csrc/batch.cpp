@@ -57,8 +57,8 @@ swh_status score_passes(swh_ctx *ctx, const std::vector<PairPass> &ps, const Sco
     std::vector<char> w16(np, 0);
     for (size_t i = 0; i < np; ++i) {
         sh[i] = ps[i].R ? StripShape{ps[i].R, ps[i].waves} : tuned_shape(ctx, ps[i].n);
-        if (ps[i].int16 && !ps[i].R) sh[i] = StripShape{r16_of(sh[i].R), 0};
-        w16[i] = ps[i].int16 && r16_of(sh[i].R) == sh[i].R && int16_usable(ctx, sc, sh[i].R);
+        w16[i] = ps[i].int16 && int16_usable(ctx, sc, sh[i].R);
+        if (w16[i]) sh[i].waves = 0;   // the rule for the 16-bit kernel's strips
     }
     auto same = [&](size_t a, size_t b) {
         return sh[a].R == sh[b].R && sh[a].waves == sh[b].waves && w16[a] == w16[b];
@@ -79,6 +79,7 @@ swh_status score_passes(swh_ctx *ctx, const std::vector<PairPass> &ps, const Sco
         if (k == np) break;
         const size_t lead = order[k];
         const int Rk = sh[lead].R;
+        const int Rpad = w16[lead] ? 2 * Rk : Rk;   // the 16-bit kernel reads rows of strips twice as tall
         // a chunk: one strip shape, bounded bytes
         size_t end = k;
         int64_t bytes = 0, nb = 0, nq = 0, nt = 0;
@@ -88,10 +89,10 @@ swh_status score_passes(swh_ctx *ctx, const std::vector<PairPass> &ps, const Sco
                 ++end;
                 continue;
             }
-            const int64_t b = rows_padded(p.n + p.lead, Rk) + cols_padded(p.m) * (1 + (int64_t)sizeof(Border));
+            const int64_t b = rows_padded(p.n + p.lead, Rpad) + cols_padded(p.m) * (1 + (int64_t)sizeof(Border));
             if (bytes && bytes + b > kChunkBytes) break;
             bytes += b;
-            nq += rows_padded(p.n + p.lead, Rk);
+            nq += rows_padded(p.n + p.lead, Rpad);
             nt += cols_padded(p.m);
             nb += cols_padded(p.m);
             ++end;
@@ -109,7 +110,7 @@ swh_status score_passes(swh_ctx *ctx, const std::vector<PairPass> &ps, const Sco
         for (size_t i = k; i < end; ++i) {
             const PairPass &p = ps[order[i]];
             if (p.n == 0 || p.m == 0) continue;
-            const int64_t qpad = rows_padded(p.n + p.lead, Rk), tpad = cols_padded(p.m);
+            const int64_t qpad = rows_padded(p.n + p.lead, Rpad), tpad = cols_padded(p.m);
             gd.push_back(GatherDesc{p.q, qp, 0, p.n, qpad, p.step, (int32_t)p.lead});
             gd.push_back(GatherDesc{p.t, tp, 0, p.m, tpad, p.step, 0});
             StripProblem sp{qp, p.n + p.lead, tp, p.m, bp};
@@ -587,14 +588,12 @@ swh_status align_batch(swh_ctx *ctx, int64_t npairs, const char *q_cat, const in
     if (banded)
         for (int64_t i = 0; i < npairs; ++i) {
             const StripShape sh = tuned_shape(ctx, ps[i].n);
-            // the forward pass's strip height (16-bit passes: the packed kernel's)
-            const int R = want16 && int16_usable(ctx, sc, r16_of(sh.R)) ? r16_of(sh.R) : sh.R;
-            const int64_t H = 64 * (int64_t)R;
+            const int64_t H = 64 * (int64_t)sh.R;
             const int64_t want = forced > 0 ? forced : kBatchBandRows;
             const int every = (int)std::max<int64_t>(1, (want + H - 1) / H);
-            frecs[i] = band_forward_layout(R, every, ps[i].n, ps[i].m, bk[i]);
-            ps[i].R = R;
-            ps[i].waves = R == sh.R ? sh.waves : 0;
+            frecs[i] = band_forward_layout(sh.R, every, ps[i].n, ps[i].m, bk[i]);
+            ps[i].R = sh.R;
+            ps[i].waves = sh.waves;
         }
     int64_t budget = kBatchKeepBytes / (int64_t)sizeof(Border);
     {

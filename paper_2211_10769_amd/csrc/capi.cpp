@@ -396,7 +396,7 @@ swh_status swh_set_option(swh_ctx *ctx, int32_t option, int64_t value)
             o.mem_cap = value;
             return SWH_OK;
         case SWH_OPT_INT16:
-            if (value != 0 && value != 1) return bad("int16 must be 0 or 1");
+            if (value < 0 || value > 2) return bad("int16 must be 0, 1 or 2");
             o.int16 = (int32_t)value;
             return SWH_OK;
         case SWH_OPT_INTER_MAX:

@@ -177,10 +177,16 @@ __global__ void __launch_bounds__(256 * kWg16PerSimd<RH>) strip16_kernel(StripAr
                 }
             }
         }
-        Border *keep = nullptr;
+        // kept rows count half strips (64 RH rows): half strip 2 s ends with the
+        // upper sub-strip (lane 63's low halves), 2 s + 1 with the lower one; a
+        // lower sub-strip that starts below the last row is not a strip of the
+        // pass and keeps nothing (its slot would lie past the kept rows)
+        Border *keep_lo = nullptr, *keep_hi = nullptr;
         if (P.save_every > 0) {
-            const int t = s + 1 + P.save_phase;
-            if (t % P.save_every == 0) keep = P.save + (int64_t)(t / P.save_every - 1) * P.save_stride;
+            const int t0 = 2 * s + 1 + P.save_phase, t1 = 2 * s + 2 + P.save_phase;
+            if (t0 % P.save_every == 0) keep_lo = P.save + (int64_t)(t0 / P.save_every - 1) * P.save_stride;
+            if (t1 % P.save_every == 0 && (int64_t)(2 * s + 1) * 64 * RH < (int64_t)P.n)
+                keep_hi = P.save + (int64_t)(t1 / P.save_every - 1) * P.save_stride;
         }
 
         unsigned hp[RH], E[RH];
@@ -335,8 +341,12 @@ __global__ void __launch_bounds__(256 * kWg16PerSimd<RH>) strip16_kernel(StripAr
             if (idx >= 0 && idx < P.m) {
                 const int h32 = (int)((unsigned)oh >> 16), f32 = (int)((unsigned)of >> 16);
                 store_border(P.border + idx, h32, f32);
-                if (keep) keep[idx] = Border{h32, f32};
+                if (keep_hi) keep_hi[idx] = Border{h32, f32};
             }
+            // the upper sub-strip's last row (low halves) runs 64 columns ahead
+            const int idx_lo = 64 * b + lane - 63;
+            if (keep_lo && idx_lo >= 0 && idx_lo < P.m)
+                keep_lo[idx_lo] = Border{(int)((unsigned)oh & 0xFFFFu), (int)((unsigned)of & 0xFFFFu)};
         }
         drain_stores();
         {
@@ -390,7 +400,6 @@ int blocks16_t(int threads, size_t lds)
 
 int blocks16(int RH, int threads, size_t lds)
 {
-    if (RH == 2) return blocks16_t<2>(threads, lds);
     if (RH == 4) return blocks16_t<4>(threads, lds);
     if (RH == 8) return blocks16_t<8>(threads, lds);
     if (RH == 16) return blocks16_t<16>(threads, lds);
@@ -403,7 +412,7 @@ size_t strip16_lds_bytes(int R, int asize) { return (size_t)(asize + 1) * 64 * (
 
 bool strip16_supported(int R, int asize, int device)
 {
-    if (R != 4 && R != 8 && R != 16 && R != 32) return false;
+    if (R != 8 && R != 16 && R != 32) return false;
     int lds_wg = 0;
     if (hipDeviceGetAttribute(&lds_wg, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) {
         (void)hipGetLastError();
@@ -448,7 +457,6 @@ int strip16_grid_limit(int device, int R, int asize)
 
 hipError_t launch_strip16(const StripArgs &a, int R, const StripLaunch &grid, hipStream_t st, bool prune)
 {
-    if (R == 4) return launch16_t<2>(a, grid, st, prune);
     if (R == 8) return launch16_t<4>(a, grid, st, prune);
     if (R == 16) return launch16_t<8>(a, grid, st, prune);
     if (R == 32) return launch16_t<16>(a, grid, st, prune);

@@ -316,7 +316,7 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
     if (qlen == 0 || tlen == 0) return SWH_OK;
 
     const StripShape shape = tuned_shape(ctx, qlen);
-    const int64_t qpad = rows_padded(qlen, shape.R);
+    const int64_t qpad = rows_padded(qlen, 2 * shape.R);   // room for 16-bit strips of twice the height
     const int64_t tpad = cols_padded(tlen);
     swh_status s;
     if ((s = ensure(ctx, ctx->qc, (size_t)qpad, "query codes")) != SWH_OK) return s;
@@ -522,8 +522,16 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
 
     // ---- resolution: forward local pass (keeping rows for the band traceback in
     // CIGAR mode), in packed 16-bit arithmetic when no cell can reach its limit
-    const bool f16 = never_saturates(qlen, tlen, sc) && int16_usable(ctx, sc, r16_of(shape.R));
-    const StripShape fshape = f16 ? StripShape{r16_of(shape.R), 0} : shape;
+    // (the 16-bit kernel runs strips of two sub-strips of the nominal height; a
+    // short pair keeps 512-row strips, as its 32-bit pass would).  A pass with
+    // fewer strips than the GPU has SIMDs is bound by its dependency chain,
+    // whose steps are shorter in 32 bits: 16 bits only for passes that fill
+    // the GPU, unless the option asks for them everywhere.
+    const int R16 = shape.R == 8 && ctx->opt.rows == 0 ? 4 : shape.R;
+    auto fills = [&](int64_t rows, int R) { return (rows + 64 * R - 1) / (64 * R) >= 4 * (int64_t)ctx->num_cu; };
+    const bool f16 = never_saturates(qlen, tlen, sc) && int16_usable(ctx, sc, R16) &&
+                     (ctx->opt.int16 == 2 || fills(qlen, R16));
+    const StripShape fshape = f16 ? StripShape{R16, 0} : shape;
     BandKeep bk;
     KeepRows kfwd;
     {
@@ -570,11 +578,11 @@ swh_status align_device(swh_ctx *ctx, const char *q_dev, int64_t qlen, const cha
     const StripShape rshape = bk.every > 0 ? StripShape{bk.Rr, bk.Rr == fshape.R ? fshape.waves : 0}
                               : (prune_rev && rn >= 512) ? StripShape{8, 0}
                                                          : tuned_shape(ctx, rn);
-    // the reverse pass's maximum is the forward score: 16 bits are exact below the limit
-    const bool r16 = fwd.best.score < sat16_limit(sc.smax) && r16_of(rshape.R) == rshape.R &&
-                     int16_usable(ctx, sc, rshape.R);
     const int64_t lead = bk.every > 0 ? bk.lead : 0;
-    const int64_t rqpad = rows_padded(rn + lead, rshape.R);
+    // the reverse pass's maximum is the forward score: 16 bits are exact below the limit
+    const bool r16 = fwd.best.score < sat16_limit(sc.smax) && int16_usable(ctx, sc, rshape.R) &&
+                     (ctx->opt.int16 == 2 || fills(rn + lead, rshape.R));
+    const int64_t rqpad = rows_padded(rn + lead, r16 ? 2 * rshape.R : rshape.R);
     const int64_t rtpad = cols_padded(rm);
     if ((s = ensure(ctx, ctx->qr, (size_t)rqpad, "reversed query")) != SWH_OK) return s;
     if ((s = ensure(ctx, ctx->tr, (size_t)rtpad, "reversed target")) != SWH_OK) return s;

@@ -104,9 +104,10 @@ hipError_t launch_reduce_best_multi(const BestCell *strip_best, const Problem *p
                                     BestCell *out, hipStream_t st);
 
 // Packed 16-bit local passes (dp_strip16.hip).  R = rows per lane of the
-// strip height 64 R as in the 32-bit kernel (4, 8, 16 or 32; each half of a
-// register holds R / 2 of them); the sweep takes one block more.  Results are
-// exact when the pass's maximum stays below sat16_limit.
+// kernel's strip (8, 16 or 32; each half of a register holds R / 2 of them,
+// one sub-strip of 32 R rows per half); the sweep takes one block more.  Rows
+// kept for the band traceback are counted in sub-strips.  Results are exact
+// when the pass's maximum stays below sat16_limit.
 size_t strip16_lds_bytes(int R, int asize);
 bool strip16_supported(int R, int asize, int device);
 bool strip16_balanced_launch(int device, int R, int asize, int per_simd, int num_cu, StripLaunch &out);

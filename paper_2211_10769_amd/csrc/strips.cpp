@@ -83,7 +83,7 @@ int strip_grid(int64_t nstrips, int R, int limit, int num_cu, int waves, int for
 
 bool int16_usable(const swh_ctx *ctx, const Scoring &sc, int R)
 {
-    return ctx->opt.int16 != 0 && strip16_supported(R, sc.asize, ctx->device);
+    return ctx->opt.int16 != 0 && (R == 4 || R == 8 || R == 16) && strip16_supported(2 * R, sc.asize, ctx->device);
 }
 
 swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, const Scoring &sc, int R, bool local,
@@ -91,8 +91,10 @@ swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, cons
 {
     const int np = (int)probs.size();
     if (np == 0) return SWH_OK;
-    if (int16 && (!local || !strip16_supported(R, sc.asize, ctx->device)))
+    if (int16 && (!local || (R != 4 && R != 8 && R != 16) || !strip16_supported(2 * R, sc.asize, ctx->device)))
         return fail(ctx, SWH_E_INVAL, "packed 16-bit pass requested for an unsupported shape");
+    // the 16-bit kernel's strips hold two sub-strips of the nominal height
+    const int RK = int16 ? 2 * R : R;
     std::vector<Problem> &tab = ctx->h_probs;
     std::vector<int32_t> &sp = ctx->h_strip_prob;
     tab.resize(np);
@@ -107,7 +109,7 @@ swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, cons
         P.border = q.border;
         P.n = (int32_t)q.n;
         P.m = (int32_t)q.m;
-        P.nstrips = (int32_t)((q.n + 64 * R - 1) / (64 * R));
+        P.nstrips = (int32_t)((q.n + 64 * RK - 1) / (64 * RK));
         P.nblocks = (int32_t)sweep_blocks(q.m) + (int16 ? 1 : 0);   // the 16-bit high halves trail by a block
         P.strip0 = (int32_t)total_strips;
         P.flags = (int32_t *)(intptr_t)total_flags;   // offset, fixed up below
@@ -165,23 +167,23 @@ swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, cons
     // wave, so every SIMD must hold the same number of waves: a balanced
     // placement when it can be made (with fewer waves per SIMD when there are
     // few strips), else single-wave workgroups (the grid option forces those).
-    const size_t wave_lds = int16 ? strip16_lds_bytes(R, sc.asize) : strip_lds_bytes(R, sc.asize);
+    const size_t wave_lds = int16 ? strip16_lds_bytes(RK, sc.asize) : strip_lds_bytes(R, sc.asize);
     StripLaunch grid{0, 1, wave_lds};
     const int forced = ctx->opt.grid;
     // long chains (a few big problems) want one wave per SIMD; many short
     // ones want several to hide latency (read-pair batch: 4 for R = 8)
     const bool long_chains = total_strips >= 16 * (int64_t)np;
-    int per_simd = waves > 0 ? waves : long_chains ? 1 : (R <= 4 ? 8 : 4);
+    int per_simd = waves > 0 ? waves : long_chains ? 1 : (RK <= 4 ? 8 : 4);
     while (per_simd > 1 && (int64_t)per_simd / 2 * 4 * ctx->num_cu >= total_strips) per_simd /= 2;
-    const bool balanced = int16 ? strip16_balanced_launch(ctx->device, R, sc.asize, per_simd, ctx->num_cu, grid)
+    const bool balanced = int16 ? strip16_balanced_launch(ctx->device, RK, sc.asize, per_simd, ctx->num_cu, grid)
                                 : strip_balanced_launch(ctx->device, R, local, sc.asize, per_simd, ctx->num_cu, grid);
     if (forced > 0 || !balanced) {
-        const int limit = int16 ? strip16_grid_limit(ctx->device, R, sc.asize)
+        const int limit = int16 ? strip16_grid_limit(ctx->device, RK, sc.asize)
                                 : strip_grid_limit(ctx->device, R, local, sc.asize);
-        grid = StripLaunch{strip_grid(total_strips, R, limit, ctx->num_cu, waves, forced), 1, wave_lds};
+        grid = StripLaunch{strip_grid(total_strips, RK, limit, ctx->num_cu, waves, forced), 1, wave_lds};
     }
     hipEventRecord(ctx->ev[0], st);
-    if ((e = int16 ? launch_strip16(a, R, grid, st, prune) : launch_strip(a, R, local, grid, st, prune)) !=
+    if ((e = int16 ? launch_strip16(a, RK, grid, st, prune) : launch_strip(a, R, local, grid, st, prune)) !=
         hipSuccess)
         return hip_fail(ctx, e, "strip kernel launch");
     hipEventRecord(ctx->ev[1], st);

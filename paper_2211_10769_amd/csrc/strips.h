@@ -38,15 +38,16 @@ int strip_grid(int64_t nstrips, int R, int limit, int num_cu, int waves = 0, int
 
 // One launch over all problems; local mode fills best (one entry per problem).
 // waves: waves per SIMD of the persistent grid, 0 = the rule for R.  int16
-// (local mode, R in 4, 8, 16, 32): the packed 16-bit kernel; a problem whose
-// best score reaches sat16_limit(smax) may have saturated and must be redone
-// in 32 bits by the caller.
+// (local mode, R in 4, 8, 16): the packed 16-bit kernel with strips of 128 R
+// rows made of two sub-strips of 64 R rows, so that rows kept every
+// save_every strips of 64 R rows land where the 32-bit kernel's would (row
+// codes must then be padded to rows_padded(n, 2 R)); a problem whose best
+// score reaches sat16_limit(smax) may have saturated and must be redone in 32
+// bits by the caller, at the same R.
 swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, const Scoring &sc, int R, bool local,
                       hipStream_t st, std::vector<BestCell> *best, float *ms, int waves = 0, bool int16 = false);
 
-// Strip height (rows per lane) of a packed 16-bit pass standing in for a
-// 32-bit pass of R rows per lane, and whether the context may run one.
-inline int r16_of(int R) { return R <= 4 ? 4 : R <= 8 ? 8 : R <= 20 ? 16 : 32; }
+// Whether the context may run a 16-bit pass of nominal height R (4, 8 or 16).
 bool int16_usable(const swh_ctx *ctx, const Scoring &sc, int R);
 // No cell of an n x m local pass can reach sat16_limit (S <= min(n, m) max s).
 inline bool never_saturates(int64_t n, int64_t m, const Scoring &sc)

@@ -48,13 +48,26 @@ def _check_batch(eng, pairs, sc_tuple, mode="cigar"):
     return st
 
 
-@pytest.mark.parametrize("rows", [0, 4, 8, 16, 32])
+@pytest.mark.parametrize("rows", [0, 4, 8, 16, 20])
 def test_batch_every_height(eng, opt, rows):
+    # nominal heights 4, 8 and 16 rows per lane run the 16-bit kernel (strips of
+    # two sub-strips of that height); 20 has no 16-bit form and runs in 32 bits
     rng = np.random.default_rng(300 + rows)
     opt("rows_per_lane", rows)
     lens = [1, 7, 63, 64, 65, 200, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 2047, 3000, 5100]
     st = _check_batch(eng, _pairs(rng, lens), seqgen.dna_scoring())
-    assert st["passes_int16"] > 0 and st["saturated_int16"] == 0, st
+    assert (st["passes_int16"] > 0) == (rows != 20) and st["saturated_int16"] == 0, st
+
+
+@pytest.mark.parametrize("band_rows", [256, 512, 1024])
+def test_batch_kept_rows_at_sub_strips(eng, opt, band_rows):
+    # kept rows every 256 rows with 16-bit strips of 512 or 1,024 rows: rows at
+    # the end of an upper sub-strip come from the packed kernel's low halves
+    rng = np.random.default_rng(305 + band_rows)
+    opt("band_rows", band_rows)
+    opt("tb_leaf", 4096)
+    st = _check_batch(eng, _pairs(rng, [900, 2600, 4100, 7000], div=(0.01, 0.05)), seqgen.dna_scoring())
+    assert st["traceback_bands"] > 4 and st["traceback_retries"] == 0, st
 
 
 def test_batch_int16_equals_int32(eng, opt):
@@ -130,13 +143,15 @@ def test_saturation_with_cigar_and_kept_rows(eng, opt):
         assert {k: g[k] for k in KEYS} == {k: want[k] for k in KEYS}
 
 
-@pytest.mark.parametrize("rows", [0, 8, 16, 32])
+@pytest.mark.parametrize("rows", [0, 4, 8, 16])
 def test_single_pair_int16(eng, opt, rows):
-    # a 30 kbp related pair can never reach the limit: both passes in 16 bits
+    # a 30 kbp related pair can never reach the limit: with the option at 2
+    # both passes run in 16 bits (at 1 only passes that fill the GPU do)
     rng = np.random.default_rng(360 + rows)
     a = seqgen.random_dna(rng, 30_000)
     b = np.concatenate([seqgen.random_dna(rng, 700), seqgen.mutate(rng, a, 0.03, 0.005), seqgen.random_dna(rng, 500)])
     opt("rows_per_lane", rows)
+    opt("int16", 2)
     import paper_2211_10769_amd as swh
     got = eng.align(bytes(a), bytes(b), swh.dna_scoring(), mode="cigar", stats=True)
     assert got["stats"]["passes_int16"] == 2, got["stats"]
@@ -150,6 +165,7 @@ def test_single_pair_pruned_and_unpruned(eng, opt):
     b = np.concatenate([seqgen.random_dna(rng, 3000), seqgen.mutate(rng, a, 0.05, 0.01), seqgen.random_dna(rng, 100)])
     import paper_2211_10769_amd as swh
     sc = swh.dna_scoring()
+    opt("int16", 2)
     pruned = eng.align(bytes(a), bytes(b), sc, mode="coords")
     opt("prune", 0)
     plain = eng.align(bytes(a), bytes(b), sc, mode="coords")
@@ -160,10 +176,11 @@ def test_single_pair_pruned_and_unpruned(eng, opt):
         assert {k: r[k] for k in KEYS[:-1]} == {k: want[k] for k in KEYS[:-1]}
 
 
-def test_long_unrelated_pair_and_no_hit(eng):
-    # unrelated 200 kbp sequences: tiny score, both passes in 16 bits by the
-    # limit rule only when min(n, m) stays below it -- here the forward pass
-    # runs in 32 bits and the reverse pass in 16 bits
+def test_long_unrelated_pair_and_no_hit(eng, opt):
+    # unrelated 200 kbp sequences: the forward pass could reach the 16-bit limit
+    # (min(n, m) is above it) and runs in 32 bits; its score is tiny, so the
+    # reverse pass runs in 16 bits
+    opt("int16", 2)
     rng = np.random.default_rng(380)
     a = seqgen.random_dna(rng, 200_000)
     b = seqgen.random_dna(rng, 180_000)

@@ -374,24 +374,33 @@ def baseline_models(swh, eng, sc, trained):
 
 def gain_test(args, swh, eng, model, db, queries, ex_idx, t_ex, pf_st):
     """recall@10 and speedup of the trained network and of the non-learned
-    rankings at the same rescoring budget."""
+    rankings at the same 5% rescoring budget, under both orderings of the
+    search: by the excess of a prediction over the mean of same-length
+    database sequences (the default) and by the prediction itself."""
     import numpy as np
     res = {}
     sc = model.sc if model.sc is not None else swh.Scoring(*__import__("seqgen").protein_scoring())
-    for name, m in baseline_models(swh, eng, sc, model).items():
-        m.search(db, queries, k=10, rescore_frac=0.05, audit_frac=0.002)
-        t0 = time.perf_counter()
-        idx, _, st = m.search(db, queries, k=10, rescore_frac=0.05, audit_frac=0.002)
-        dt = time.perf_counter() - t0
-        # recall of the ranking itself: the audit's fallback (an exhaustive
-        # search of the query) repairs a missed hit, so report both
-        rec = float(np.mean([len(set(a) & set(b)) / 10.0 for a, b in zip(idx.tolist(), ex_idx.tolist())]))
-        res[name] = {"recall_at_10": rec, "speedup": round(t_ex / dt, 2), "fallbacks": int(st["fallbacks"]),
-                     "rescored_cell_fraction": round(st["cells_rescored"] / st["cells_exhaustive"], 4)}
-        m.close()
-        log(f"prefilter gain test: {name} done")
-    res["trained"] = {"fallbacks": int(pf_st["fallbacks"]),
-                      "rescored_cell_fraction": round(pf_st["cells_rescored"] / pf_st["cells_exhaustive"], 4)}
+    models = dict(trained=model, **baseline_models(swh, eng, sc, model))
+    for rank, label in ((2, "length_z"), (1, "length_excess"), (0, "raw")):
+        eng.set_option("pf_rank", rank)
+        part = {}
+        for name, m in models.items():
+            m.search(db, queries, k=10, rescore_frac=0.05, audit_frac=0.002)
+            t0 = time.perf_counter()
+            idx, _, st = m.search(db, queries, k=10, rescore_frac=0.05, audit_frac=0.002)
+            dt = time.perf_counter() - t0
+            # the audit's fallback (an exhaustive search of the query) repairs
+            # missed hits at the cost of speed; both are reported
+            rec = float(np.mean([len(set(a) & set(b)) / 10.0 for a, b in zip(idx.tolist(), ex_idx.tolist())]))
+            part[name] = {"recall_at_10": rec, "speedup": round(t_ex / dt, 2), "fallbacks": int(st["fallbacks"]),
+                          "candidates": int(st["candidates"]),
+                          "rescored_cell_fraction": round(st["cells_rescored"] / st["cells_exhaustive"], 4)}
+        res[label] = part
+        log(f"prefilter gain test: {label} ranking done")
+    eng.set_option("pf_rank", 1)
+    for name, m in models.items():
+        if m is not model:
+            m.close()
     return res
 
 

@@ -196,6 +196,16 @@ swh_status  swh_cancel(swh_ctx *ctx);
  *                          inter-task kernel, longer ones to the single-pair
  *                          kernel (applies to databases created afterwards);
  *                          0 (default) = the built-in or autotuned threshold
+ *   SWH_OPT_PF_RANK        how swh_prefilter_search ranks the database for a
+ *                          query: 1 (default) by the predicted score's excess
+ *                          over the mean prediction of database sequences of
+ *                          similar length (the length-sorted groups of 128 the
+ *                          database is stored in), so that long sequences do not
+ *                          take the rescoring budget by length alone; 2 by that
+ *                          excess divided by the group's deviation (fewer
+ *                          rescored cells, but noise in groups of near-equal
+ *                          predictions is amplified); 0 by the predicted score
+ *                          itself.  Reported scores are exact either way.
  *   SWH_OPT_FAULT_NOMEM    1: the next entry point on ctx fails as if a host
  *                          allocation had thrown std::bad_alloc (after its
  *                          argument checks), then the option resets; a test
@@ -212,7 +222,8 @@ enum {
     SWH_OPT_MEM_CAP = 7,
     SWH_OPT_INT16 = 8,
     SWH_OPT_INTER_MAX = 9,
-    SWH_OPT_FAULT_NOMEM = 10
+    SWH_OPT_FAULT_NOMEM = 10,
+    SWH_OPT_PF_RANK = 11
 };
 swh_status  swh_set_option(swh_ctx *ctx, int32_t option, int64_t value);
 swh_status  swh_get_option(const swh_ctx *ctx, int32_t option, int64_t *value);

@@ -403,6 +403,10 @@ swh_status swh_set_option(swh_ctx *ctx, int32_t option, int64_t value)
             if (value != 0 && (value < 32 || value > 8192)) return bad("inter-task maximum must be 0 or 32 .. 8192");
             o.inter_max = (int32_t)value;
             return SWH_OK;
+        case SWH_OPT_PF_RANK:
+            if (value < 0 || value > 2) return bad("prefilter ranking must be 0, 1 or 2");
+            o.pf_rank = (int32_t)value;
+            return SWH_OK;
         case SWH_OPT_FAULT_NOMEM:
             if (value != 0 && value != 1) return bad("fault injection must be 0 or 1");
             o.fault_nomem = (int32_t)value;
@@ -427,6 +431,7 @@ swh_status swh_get_option(const swh_ctx *ctx, int32_t option, int64_t *value)
     case SWH_OPT_MEM_CAP: *value = o.mem_cap; return SWH_OK;
     case SWH_OPT_INT16: *value = o.int16; return SWH_OK;
     case SWH_OPT_INTER_MAX: *value = o.inter_max; return SWH_OK;
+    case SWH_OPT_PF_RANK: *value = o.pf_rank; return SWH_OK;
     case SWH_OPT_FAULT_NOMEM: *value = o.fault_nomem; return SWH_OK;
     default: return SWH_E_INVAL;
     }

@@ -38,6 +38,7 @@ struct Options {
     int64_t mem_cap = 0;     // bytes the context's own buffers may hold (0: no cap)
     int32_t int16 = 1;       // packed 16-bit local passes: 0 off, 1 batches and GPU-filling passes, 2 always
     int32_t inter_max = 0;   // database length switch (0: built-in / tuned)
+    int32_t pf_rank = 1;     // prefilter ranking: 1 excess over same-length mean, 2 its z-score, 0 raw
     int32_t fault_nomem = 0; // the next entry point throws std::bad_alloc
 };
 

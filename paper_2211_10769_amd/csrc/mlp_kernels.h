@@ -119,6 +119,10 @@ hipError_t launch_mark(const float *pred, int64_t nrows, int nq, const uint32_t 
                        uint64_t seed, uint32_t audit_threshold, uint8_t *marks, int32_t *chunk_counts,
                        hipStream_t st);
 constexpr int kMarkChunk = 256;
+// pred[q][r] -= mean of pred[q][.] over the valid rows (row_db >= 0) of r's
+// group of 128 rows; standardise: then divided by their deviation
+hipError_t launch_excess(float *pred, int64_t nrows, int nq, const int32_t *row_db, bool standardise,
+                         hipStream_t st);
 hipError_t launch_compact(const uint8_t *marks, int64_t nrows, int nq, const int64_t *chunk_base, int32_t *out_rows,
                           uint8_t *out_kind, hipStream_t st);
 

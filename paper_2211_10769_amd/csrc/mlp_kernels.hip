@@ -603,6 +603,42 @@ __global__ void __launch_bounds__(256) compact_kernel(const uint8_t *marks, int6
     }
 }
 
+// Length-group excess: the database rows are stored length-sorted, 128 to a
+// group, so the mean prediction of a group's sequences estimates what a
+// sequence of that length scores against the query by chance; each
+// prediction becomes its excess over that mean.  One block per (group, query).
+__global__ void __launch_bounds__(128) excess_kernel(float *pred, int64_t nrows, const int32_t *row_db,
+                                                     int standardise)
+{
+    __shared__ float psum[2], psq[2];
+    __shared__ int pcnt[2];
+    const int q = blockIdx.y;
+    const int64_t r = (int64_t)blockIdx.x * 128 + threadIdx.x;
+    const bool valid = r < nrows && row_db[r] >= 0;
+    float v = valid ? pred[(int64_t)q * nrows + r] : 0.0f;
+    int c = valid ? 1 : 0;
+    float sum = v, sq = v * v;
+    for (int off = 32; off >= 1; off >>= 1) {
+        sum += __shfl_xor(sum, off);
+        sq += __shfl_xor(sq, off);
+        c += __shfl_xor(c, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        psum[threadIdx.x >> 6] = sum;
+        psq[threadIdx.x >> 6] = sq;
+        pcnt[threadIdx.x >> 6] = c;
+    }
+    __syncthreads();
+    const int n = pcnt[0] + pcnt[1];
+    const float mean = n ? (psum[0] + psum[1]) / (float)n : 0.0f;
+    float scale = 1.0f;
+    if (standardise && n > 1) {
+        const float var = fmaxf((psq[0] + psq[1]) / (float)n - mean * mean, 0.0f);
+        scale = 1.0f / fmaxf(sqrtf(var), 1e-3f);
+    }
+    if (valid) pred[(int64_t)q * nrows + r] = (v - mean) * scale;
+}
+
 __global__ void step_end_kernel(int32_t *ctr)
 {
     if (threadIdx.x == 0) {
@@ -764,6 +800,15 @@ hipError_t launch_mark(const float *pred, int64_t nrows, int nq, const uint32_t 
 {
     hipLaunchKernelGGL(mark_kernel, dim3(blocks_for(nrows, kMarkChunk), nq), dim3(256), 0, st, pred, nrows, thr,
                        row_db, seed, audit_threshold, marks, chunk_counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_excess(float *pred, int64_t nrows, int nq, const int32_t *row_db, bool standardise,
+                         hipStream_t st)
+{
+    if (nrows <= 0 || nq <= 0) return hipSuccess;
+    hipLaunchKernelGGL(excess_kernel, dim3((unsigned)((nrows + 127) / 128), nq), dim3(128), 0, st, pred, nrows,
+                       row_db, standardise ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -781,8 +781,13 @@ swh_status prefilter_search(swh_ctx *ctx, const swh_model *m, swh_db *db, int32_
     if ((s = predict_rows(ctx, m, db, qs, &ps)) != SWH_OK) return s;
     const int64_t nrows = db->pf_nrows, ndb = db->ndb;
 
-    // ---- candidates: predictions at or above each query's n-th largest
+    // ---- candidates: predictions (or their excess over the mean of sequences
+    // of the same length) at or above each query's n-th largest
     auto t0 = Clock::now();
+    if (ctx->opt.pf_rank > 0 &&
+        (e = launch_excess((float *)ctx->pf_pred.p, nrows, nq, (const int32_t *)db->pf_row_db.p, ctx->opt.pf_rank == 2,
+                           st)) != hipSuccess)
+        return hip_fail(ctx, e, "length-group excess");
     const int64_t want = std::min<int64_t>(ndb, std::max<int64_t>(k, (int64_t)std::ceil(rescore_frac * (double)ndb)));
     std::vector<uint32_t> thr;
     if ((s = select_thresholds(ctx, nq, nrows, want, thr)) != SWH_OK) return s;

@@ -269,3 +269,26 @@ def test_audit_sample_matches_its_definition(swh, eng, planted):
         z ^= z >> np.uint64(31)
     drawn = int(((z >> np.uint64(32)) < np.uint64(int(frac * 2 ** 32))).sum())
     assert drawn - st["candidates"] <= st["audited"] <= drawn
+
+
+def test_rankings_exact_and_length_standardised_rescores_fewer_cells(swh, eng, planted, trained, opt):
+    # the three orderings of the candidates (raw prediction, excess over the
+    # same-length group mean, standardised within the group) all give exact
+    # scores; the first two full recall at this budget (the standardised one
+    # amplifies noise in groups of near-equal predictions and may miss a weak
+    # homolog here); the length-corrected ones spend fewer rescoring cells on
+    # long sequences than the raw prediction does
+    qs, db, sdb, exact_idx, exact_sc = planted
+    model, _ = trained
+    cells = {}
+    for rank in (0, 1, 2):
+        opt("pf_rank", rank)
+        idx, sco, st = model.search(sdb, [bytes(q) for q in qs], k=10, rescore_frac=0.05, audit_frac=0.01)
+        assert mlp.recall_at_k(idx, exact_idx) >= (0.99 if rank < 2 else 0.95), rank
+        for qi in range(len(qs)):
+            for j in range(10):
+                hit = np.nonzero(exact_idx[qi] == idx[qi, j])[0]
+                if len(hit):
+                    assert sco[qi, j] == exact_sc[qi, hit[0]]
+        cells[rank] = st["cells_rescored"]
+    assert cells[1] < cells[0] and cells[2] < cells[0], cells

@@ -197,26 +197,40 @@ def bench_db(args, swh, eng):
     create_s = time.perf_counter() - t0
     log(f"database search: {args.db_size} proteins encoded ({create_s:.2f} s)")
     qcat, qoff = swh._concat(qs)
-    db.search((qcat, qoff), k=10)   # warm-up: buffers grow once
+    t0 = time.perf_counter()
+    db.search((qcat, qoff), k=10)   # warm-up: buffers grow once, the launch sequence is captured
+    first_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     stats = []
     for i in range(args.db_steps):
         _, _, st = db.search((qcat, qoff), k=10)
         stats.append(st)
-        log(f"database search {i + 1}/{args.db_steps} done")
+        log(f"database search {i + 1}/{args.db_steps} done (graph replay: {bool(st['graph'])})")
     dt = (time.perf_counter() - t0) / args.db_steps
     cells = stats[0]["cells"]
-    inter = sum(x["ms_inter"] for x in stats) / len(stats)
+    # per-kernel split from eager searches (a replay times the graph as a whole)
+    eng.set_option("graph", 0)
+    try:
+        db.search((qcat, qoff), k=10)
+        t1 = time.perf_counter()
+        eager = [db.search((qcat, qoff), k=10)[2] for _ in range(2)]
+        dt_eager = (time.perf_counter() - t1) / 2
+    finally:
+        eng.set_option("graph", 1)
+    inter = sum(x["ms_inter"] for x in eager) / len(eager)
     db.close()
     return {"workload": f"{len(qs)} protein queries ({int(np.diff(qoff).sum())} residues) vs "
                         f"{args.db_size} db proteins ({int(off[-1])} residues), BLOSUM62 10/2, top-10",
             "gcups": round(cells / dt / 1e9, 2), "ms_per_search": round(dt * 1e3, 2), "cells": cells,
+            "graph_replay": bool(stats[0]["graph"]),
+            "eager_ms_per_search": round(dt_eager * 1e3, 2),
             "inter_kernel_ms": round(inter, 2),
             "inter_kernel_gcups": round(cells / (inter / 1e3) / 1e9, 2) if inter > 0 else None,
-            "intra_ms": round(sum(x["ms_intra"] for x in stats) / len(stats), 2),
-            "topk_ms": round(sum(x["ms_topk"] for x in stats) / len(stats), 2),
+            "intra_ms": round(sum(x["ms_intra"] for x in eager) / len(eager), 2),
+            "topk_ms": round(sum(x["ms_topk"] for x in eager) / len(eager), 2),
             "saturated_pairs": int(stats[0]["saturated"]), "intra_pairs": int(stats[0]["intra_pairs"]),
-            "one_time": {"db_upload_and_layout_s": round(create_s, 3)}}
+            "one_time": {"db_upload_and_layout_s": round(create_s, 3),
+                         "first_search_with_capture_s": round(first_s, 3)}}
 
 
 def bench_pairs(args, swh, eng):

@@ -177,8 +177,10 @@ swh_status  swh_cancel(swh_ctx *ctx);
  *                          traceback, > 0 = that many (rounded up to strips)
  *   SWH_OPT_TB_LEAF        largest leaf of the linear-space traceback, in DP
  *                          cells (1 .. 524288); 0 (default) = the largest
- *   SWH_OPT_GRAPH          1 (default): the prefilter's training step runs as a
- *                          captured HIP graph; 0: plain launches
+ *   SWH_OPT_GRAPH          1 (default): the prefilter's training step and
+ *                          repeated database searches (swh_db_search with the
+ *                          same database, k and query lengths) run as replays of
+ *                          captured HIP graphs; 0: plain launches
  *   SWH_OPT_PRUNE          1 (default): block pruning of reverse passes; 0: off
  *   SWH_OPT_MEM_CAP        bytes of device memory the context's own working
  *                          buffers may hold (database and model handles are
@@ -346,6 +348,27 @@ swh_status swh_tune_get(const swh_ctx *ctx, swh_tune_entry *out, int32_t cap, in
  * an entry with an unsupported shape or max_rows not increasing. */
 swh_status swh_tune_set(swh_ctx *ctx, const swh_tune_entry *entries, int32_t count);
 
+/*
+ * Measure the database length switch (paper, Background: SW# picks
+ * inter-task parallelism for short and intra-task parallelism for long
+ * sequences): for lengths 512 .. 8192, time a search of synthetic sequences
+ * of that length range (scored with `scoring`) on the inter-task kernel and
+ * on the single-pair kernel, and keep the largest length at which the
+ * inter-task kernel is still the faster.  The value goes into ctx (used by
+ * databases created afterwards while SWH_OPT_INTER_MAX is 0) and *inter_max
+ * (may be NULL).  Results never depend on it.
+ */
+swh_status swh_autotune_db(swh_ctx *ctx, const swh_scoring *scoring, int32_t *inter_max);
+
+/*
+ * The context's tuning -- strip-shape table and database length switch -- as
+ * a small text file tagged with the device's name, so that a later process
+ * can skip the measurements.  swh_tune_load fails with SWH_E_INVAL when the
+ * file was written on a device of another name or is not such a file.
+ */
+swh_status swh_tune_save(const swh_ctx *ctx, const char *path);
+swh_status swh_tune_load(swh_ctx *ctx, const char *path);
+
 /* ------------------------------------------------------------------------
  * Database search (paper, Background: database similarity search, many
  * independent matrices; Experimental Work: 20 protein queries against
@@ -369,6 +392,9 @@ typedef struct {
     double   ms_topk;            /* device time of the top-k selection */
     int64_t  saturated;          /* pairs recomputed in 32 bits after a 16-bit saturation */
     int64_t  intra_pairs;        /* pairs scored by the single-pair kernel */
+    int32_t  graph;              /* 1: the search ran as the replay of a captured HIP graph (ms_inter then
+                                    times the whole graph; ms_intra and ms_topk are 0) */
+    int32_t  reserved2;
 } swh_search_stats;
 
 /*
@@ -388,6 +414,11 @@ void       swh_db_destroy(swh_db *db);
  * (score descending, database index ascending), hits[q * k + r].  Scores
  * are exact 32-bit optima: pairs whose packed 16-bit values may have
  * saturated are recomputed.  1 <= k <= 32.  stats may be NULL.
+ * With SWH_OPT_GRAPH on (the default) the whole launch sequence of a search
+ * is captured once as a HIP graph per (database, k, query lengths) and
+ * replayed by later searches with the same lengths (new query contents); a
+ * replay that meets a 16-bit saturation, an empty query, or any change of the
+ * context's buffers runs the search eagerly instead.  Results are identical.
  */
 swh_status swh_db_search(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat,
                          const int64_t *q_off, int32_t k, swh_hit *hits, swh_search_stats *stats);

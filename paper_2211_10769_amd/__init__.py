@@ -212,6 +212,21 @@ class Engine:
         self._check(self.L.swh_autotune(self.h, ctypes.byref(sc.c), int(max_rows), float(cells_per_trial)))
         return self.tune_table()
 
+    def autotune_db(self, scoring) -> int:
+        """Measure and install the database length switch; returns it."""
+        sc = Scoring.of(scoring)
+        v = ctypes.c_int32()
+        self._check(self.L.swh_autotune_db(self.h, ctypes.byref(sc.c), ctypes.byref(v)))
+        return v.value
+
+    def tune_save(self, path: str):
+        st = self.L.swh_tune_save(self.h, path.encode())
+        if st != 0:
+            raise SwhError(st, f"cannot write {path}")
+
+    def tune_load(self, path: str):
+        self._check(self.L.swh_tune_load(self.h, path.encode()))
+
     def tune_table(self):
         arr = (_lib.swh_tune_entry * 64)()
         cnt = ctypes.c_int32()

@@ -51,7 +51,8 @@ class swh_hit(ctypes.Structure):
 class swh_search_stats(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("cells", ctypes.c_double), ("ms_inter", ctypes.c_double), ("ms_intra", ctypes.c_double),
-                ("ms_topk", ctypes.c_double), ("saturated", ctypes.c_int64), ("intra_pairs", ctypes.c_int64)]
+                ("ms_topk", ctypes.c_double), ("saturated", ctypes.c_int64), ("intra_pairs", ctypes.c_int64),
+                ("graph", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 class swh_tune_entry(ctypes.Structure):
@@ -106,6 +107,9 @@ SIGNATURES = {
     "swh_align_batch_dev": (ctypes.c_int, [_P, _I64, _P, _P, _P, _P, ctypes.POINTER(swh_scoring), ctypes.c_int,
                                            _P, _P, _P, _I64, _P, ctypes.POINTER(swh_stats)]),
     "swh_autotune": (ctypes.c_int, [_P, ctypes.POINTER(swh_scoring), _I64, ctypes.c_double]),
+    "swh_autotune_db": (ctypes.c_int, [_P, ctypes.POINTER(swh_scoring), ctypes.POINTER(ctypes.c_int32)]),
+    "swh_tune_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
+    "swh_tune_load": (ctypes.c_int, [_P, ctypes.c_char_p]),
     "swh_tune_get": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "swh_tune_set": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "swh_model_create": (ctypes.c_int, [_P, ctypes.POINTER(swh_scoring), _P, _P, _P, ctypes.c_uint64,

@@ -62,7 +62,10 @@ swh_status ensure(swh_ctx *ctx, DevBuf &buf, size_t bytes, const char *what)
         return fail(ctx, SWH_E_NOMEM, std::string("cannot allocate ") + std::to_string(want) + " bytes for " + what);
     }
     buf.cap = want;
-    if (own) ctx->held += want;
+    if (own) {
+        ctx->held += want;
+        ++ctx->gen;
+    }
     return SWH_OK;
 }
 
@@ -230,6 +233,8 @@ swh_status search_common(swh_ctx *ctx, const swh_db *db, int32_t nq, const char 
         stats->ms_topk = ds.ms_topk;
         stats->saturated = ds.redo;
         stats->intra_pairs = ds.intra_pairs;
+        stats->graph = ds.graph ? 1 : 0;
+        stats->reserved2 = 0;
     }
     return s;
 }
@@ -319,7 +324,11 @@ swh_status swh_create(int device, swh_ctx **out)
             return SWH_E_DEVICE;
         }
         hipDeviceProp_t p;
-        if (hipGetDeviceProperties(&p, device) == hipSuccess) ctx->num_cu = p.multiProcessorCount;
+        if (hipGetDeviceProperties(&p, device) == hipSuccess) {
+            ctx->num_cu = p.multiProcessorCount;
+            ctx->device_name = std::string(p.name) + " " + p.gcnArchName + " " +
+                               std::to_string(p.multiProcessorCount) + "cu";
+        }
         *out = ctx;
         return SWH_OK;
     });
@@ -334,6 +343,7 @@ void swh_destroy(swh_ctx *ctx)
         for (DevBuf *b : ctx->all())
             if (b->p) hipFree(b->p);
         ctx->tb_arena.free_all(ctx->held);
+        destroy_search_plan(ctx);
         for (auto &ev : ctx->ev)
             if (ev) hipEventDestroy(ev);
         if (ctx->ev_in) hipEventDestroy(ctx->ev_in);
@@ -529,6 +539,42 @@ swh_status swh_autotune(swh_ctx *ctx, const swh_scoring *scoring, int64_t max_ro
             return fail(ctx, SWH_E_INVAL, "cells_per_trial must be in (0, 1e13]");
         if ((s = begin_call(ctx)) != SWH_OK) return s;
         return autotune(ctx, sc, max_rows, cells_per_trial);
+    });
+}
+
+swh_status swh_autotune_db(swh_ctx *ctx, const swh_scoring *scoring, int32_t *inter_max)
+{
+    if (!ctx) return SWH_E_INVAL;
+    return guarded(ctx, [&]() -> swh_status {
+        ctx->err.clear();
+        Scoring sc;
+        swh_status s = make_scoring(ctx, scoring, sc);
+        if (s != SWH_OK) return s;
+        if ((s = begin_call(ctx)) != SWH_OK) return s;
+        int32_t v = 0;
+        if ((s = autotune_db(ctx, sc, scoring, v)) != SWH_OK) return s;
+        if (inter_max) *inter_max = v;
+        return SWH_OK;
+    });
+}
+
+swh_status swh_tune_save(const swh_ctx *ctx, const char *path)
+{
+    if (!ctx || !path) return SWH_E_INVAL;
+    try {
+        return tune_save(ctx, path);
+    } catch (...) {
+        return SWH_E_NOMEM;
+    }
+}
+
+swh_status swh_tune_load(swh_ctx *ctx, const char *path)
+{
+    if (!ctx) return SWH_E_INVAL;
+    return guarded(ctx, [&]() -> swh_status {
+        ctx->err.clear();
+        if (!path) return fail(ctx, SWH_E_INVAL, "path is NULL");
+        return tune_load(ctx, path);
     });
 }
 

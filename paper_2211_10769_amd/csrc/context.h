@@ -12,6 +12,8 @@
 
 namespace swh {
 
+struct SearchPlan;   // a captured database search (db_graph.cpp)
+
 // A device allocation that only grows; freed with the context.
 struct DevBuf {
     void *p = nullptr;
@@ -109,6 +111,10 @@ struct swh_ctx {
     int32_t *cancel_dev = nullptr;
     // device bytes held by the context's own buffers (the memory cap counts these)
     size_t held = 0;
+    // bumped whenever one of the context's buffers is (re)allocated: a captured
+    // graph that uses them is valid only while it is unchanged
+    uint64_t gen = 0;
+    swh::SearchPlan *splan = nullptr;
     // local passes of the current call run in packed 16 bits, and those redone
     // in 32 bits after a possible saturation
     int64_t passes16 = 0, saturated16 = 0;
@@ -120,14 +126,15 @@ struct swh_ctx {
     swh::DevBuf border, flags, misc, strip_best, mat, lut;
     // strip-kernel problem tables
     swh::DevBuf probs, strip_prob, prob_best, sync;
-    std::vector<swh::Problem> h_probs;
-    std::vector<int32_t> h_strip_prob;
+    swh::PreparedStrips strips;   // host tables of the last strip launch
     // database search buffers
     swh::DevBuf qoff, db_work, db_border, db_redo, db_scatter, db_scores, db_topk;
     // batched pairs: padded per-pair copies and border rows of one launch
     swh::DevBuf bq, bt, bborder;
     // strip shapes measured by the autotuner (empty: built-in rule)
     std::vector<swh_tune_entry> tune;
+    int32_t tuned_inter_max = 0;   // database length switch measured by the autotuner (0: built-in)
+    std::string device_name;
     // prefilter: query features, folded queries, predictions, selection, candidate layout
     swh::DevBuf pf_fq, pf_qlen, pf_Aq, pf_pred, pf_hist, pf_prefix, pf_marks, pf_chunk, pf_cand, pf_res, pf_groups,
         pf_perm;

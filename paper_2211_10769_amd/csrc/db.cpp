@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -99,9 +100,13 @@ swh_status db_create(swh_ctx *ctx, int64_t ndb, const char *cat, const int64_t *
     hipStream_t st = ctx->own_stream;
     swh_db *db = new (std::nothrow) swh_db();
     if (!db) return fail(ctx, SWH_E_NOMEM, "database handle");
+    static std::atomic<uint64_t> serials{0};
     db->device = ctx->device;
     db->sc = sc;
-    db->inter_max = ctx->opt.inter_max > 0 ? ctx->opt.inter_max : kInterMax;
+    db->serial = ++serials;
+    db->inter_max = ctx->opt.inter_max > 0 ? ctx->opt.inter_max
+                    : ctx->tuned_inter_max > 0 ? ctx->tuned_inter_max
+                                               : kInterMax;
     db->ndb = ndb;
     const int64_t base = ndb ? off[0] : 0, total = ndb ? off[ndb] - base : 0;
     db->h_off.resize((size_t)ndb + 1);
@@ -387,6 +392,11 @@ swh_status db_search(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_c
     swh_status s;
     hipError_t e;
     hipStream_t st = ctx->own_stream;
+    if (hits && !scores_host && !dev && ctx->opt.graph != 0 && nq > 0 && db->ndb > 0 && k > 0) {
+        bool done = false;
+        if ((s = search_graph(ctx, db, nq, q_cat, q_off, k, hits, stats, done)) != SWH_OK || done) return s;
+        stats = DbStats{};
+    }
     if ((s = ensure(ctx, ctx->db_scores, sizeof(int32_t) * (size_t)std::max<int64_t>(1, (int64_t)nq * db->ndb) + 64,
                     "score matrix")) != SWH_OK)
         return s;

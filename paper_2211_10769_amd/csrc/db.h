@@ -15,6 +15,7 @@ struct swh_db {
     int64_t ndb = 0;
     int64_t total_residues = 0;
     int32_t inter_max = 0;                 // longest sequence of the inter-task kernel
+    uint64_t serial = 0;                   // unique per handle (keys captured search graphs)
     std::vector<int64_t> h_off;            // per database index, rebased to 0
     std::vector<swh::DbGroup> h_groups;
     std::vector<int32_t> h_perm;           // sorted position -> database index, -1 padding
@@ -34,6 +35,7 @@ struct DbStats {
     double ms_inter = 0.0, ms_intra = 0.0, ms_topk = 0.0;
     int64_t redo = 0;
     int64_t intra_pairs = 0;
+    bool graph = false;   // the search ran as a graph replay (ms_inter then times the whole graph)
 };
 
 // dst[i] = src[i] for i < count, pad code up to padded
@@ -77,5 +79,14 @@ swh_status db_scores_device(swh_ctx *ctx, const swh_db *db, int32_t nq, const ch
                             int32_t *scores_dev, DbStats &stats, bool dev = false);
 swh_status db_search(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off, int32_t k,
                      swh_hit *hits, int32_t *scores_host, DbStats &stats, bool dev = false);
+
+// The top-k search as the replay of a captured HIP graph (db_graph.cpp): the
+// context keeps one plan, keyed by the database, k and the query lengths, and
+// captures a new one when they (or any context buffer) change.  done = false
+// when the search must run eagerly instead (capture unavailable, or a 16-bit
+// saturation that needs the eager recomputation).
+swh_status search_graph(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off,
+                        int32_t k, swh_hit *hits, DbStats &stats, bool &done);
+void destroy_search_plan(swh_ctx *ctx);
 
 }  // namespace swh

@@ -52,6 +52,9 @@ hipError_t launch_topk(const int32_t *scores, int32_t nq, int64_t ndb, int32_t k
 size_t topk_scratch_entries(int32_t nq, int64_t ndb, int32_t k);
 // dst[i] = v for i < n (a kernel, so that it may sit inside a captured graph)
 hipError_t launch_fill_i32(int32_t *dst, int64_t n, int32_t v, hipStream_t st);
+// dst[pos[i]] = best[i * stride] (the scores of a strip launch's BestCell results, stride in int32)
+hipError_t launch_scatter_best(const int64_t *pos, const int32_t *best, int64_t n, int32_t stride, int32_t *dst,
+                               hipStream_t st);
 // dst[pos[i]] = val[i]
 hipError_t launch_scatter(const int64_t *pos, const int32_t *val, int64_t n, int32_t *dst, hipStream_t st);
 

@@ -282,6 +282,14 @@ __global__ void scatter_kernel(const int64_t *pos, const int32_t *val, int64_t n
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[pos[i]] = val[i];
 }
 
+// dst[pos[i]] = score of the i-th strip-kernel problem (BestCell: score first)
+__global__ void scatter_best_kernel(const int64_t *pos, const int32_t *best, int64_t n, int32_t stride,
+                                    int32_t *dst)
+{
+    const int64_t gs = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gs) dst[pos[i]] = best[i * stride];
+}
+
 __global__ void fill_i32_kernel(int32_t *dst, int64_t n, int32_t v)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -295,6 +303,15 @@ hipError_t launch_scatter(const int64_t *pos, const int32_t *val, int64_t n, int
     if (n <= 0) return hipSuccess;
     const int64_t g = std::min<int64_t>(4096, (n + 255) / 256);
     hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)g), dim3(256), 0, st, pos, val, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_best(const int64_t *pos, const int32_t *best, int64_t n, int32_t stride, int32_t *dst,
+                               hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t g = std::min<int64_t>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL(scatter_best_kernel, dim3((unsigned)g), dim3(256), 0, st, pos, best, n, stride, dst);
     return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 namespace swh {
 
@@ -114,6 +115,16 @@ bool strip16_balanced_launch(int device, int R, int asize, int per_simd, int num
 int strip16_grid_limit(int device, int R, int asize);
 hipError_t launch_strip16(const StripArgs &a, int R, const StripLaunch &grid, hipStream_t st, bool prune);
 inline int32_t sat16_limit(int smax) { return 32767 - (smax > 0 ? smax : 0); }
+
+// The host side of one strip launch (strips.h: prepare_strips, enqueue_strips).
+struct PreparedStrips {
+    int R = 0, np = 0;
+    bool local = true, int16 = false, prune = false;
+    int64_t total_strips = 0, total_flags = 0;
+    StripLaunch grid{0, 1, 0};
+    std::vector<Problem> tab;
+    std::vector<int32_t> strip_prob;
+};
 
 // Blocks of 64 steps that sweep m columns with the 63-step lane skew:
 // ceil((m + 63) / 64).  Code and border buffers hold 64 * (blocks + 3) entries.

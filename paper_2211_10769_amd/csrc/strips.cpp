@@ -12,6 +12,7 @@
 #include "context.h"
 #include "engine.h"
 #include "strips.h"
+#include "db_kernels.h"
 
 namespace swh {
 
@@ -86,17 +87,20 @@ bool int16_usable(const swh_ctx *ctx, const Scoring &sc, int R)
     return ctx->opt.int16 != 0 && (R == 4 || R == 8 || R == 16) && strip16_supported(2 * R, sc.asize, ctx->device);
 }
 
-swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, const Scoring &sc, int R, bool local,
-                      hipStream_t st, std::vector<BestCell> *best, float *ms, int waves, bool int16)
+swh_status prepare_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, const Scoring &sc, int R, bool local,
+                          int waves, bool int16, PreparedStrips &out)
 {
     const int np = (int)probs.size();
-    if (np == 0) return SWH_OK;
     if (int16 && (!local || (R != 4 && R != 8 && R != 16) || !strip16_supported(2 * R, sc.asize, ctx->device)))
         return fail(ctx, SWH_E_INVAL, "packed 16-bit pass requested for an unsupported shape");
     // the 16-bit kernel's strips hold two sub-strips of the nominal height
     const int RK = int16 ? 2 * R : R;
-    std::vector<Problem> &tab = ctx->h_probs;
-    std::vector<int32_t> &sp = ctx->h_strip_prob;
+    out.R = R;
+    out.local = local;
+    out.int16 = int16;
+    out.np = np;
+    std::vector<Problem> &tab = out.tab;
+    std::vector<int32_t> &sp = out.strip_prob;
     tab.resize(np);
     sp.clear();
     int64_t total_strips = 0, total_flags = 0;
@@ -138,31 +142,10 @@ swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, cons
     if ((s = ensure(ctx, ctx->sync, 64, "ticket")) != SWH_OK) return s;
     for (int i = 0; i < np; ++i)
         tab[i].flags = (int32_t *)ctx->flags.p + (intptr_t)tab[i].flags;
+    out.total_strips = total_strips;
+    out.total_flags = total_flags;
+    out.prune = prune;
 
-    hipError_t e;
-    if ((e = hipMemsetAsync(ctx->flags.p, 0, (size_t)total_flags * 4, st)) != hipSuccess ||
-        (e = hipMemsetAsync(ctx->sync.p, 0, 8, st)) != hipSuccess)
-        return hip_fail(ctx, e, "hipMemsetAsync(counters)");
-    if ((e = hipMemcpyAsync(ctx->probs.p, tab.data(), (size_t)np * sizeof(Problem), hipMemcpyHostToDevice, st)) !=
-            hipSuccess ||
-        (np > 1 &&
-         (e = hipMemcpyAsync(ctx->strip_prob.p, sp.data(), sp.size() * 4, hipMemcpyHostToDevice, st)) != hipSuccess))
-        return hip_fail(ctx, e, "hipMemcpyAsync(problem table)");
-
-    StripArgs a;
-    a.probs = (const Problem *)ctx->probs.p;
-    a.strip_prob = np > 1 ? (const int32_t *)ctx->strip_prob.p : nullptr;
-    a.total_strips = (int32_t)total_strips;
-    a.mat = (const int8_t *)ctx->mat.p;
-    a.asize = sc.asize;
-    a.o = sc.o;
-    a.e = sc.e;
-    a.smax = sc.smax;
-    a.ticket = (int32_t *)ctx->sync.p;
-    a.abort_flag = (int32_t *)ctx->sync.p + 1;
-    a.cancel = ctx->cancel_dev;
-    a.strip_best = (BestCell *)ctx->strip_best.p;
-    a.wait_ticks = wait_ticks(ctx->device);
     // Strips of one problem form a chain that moves at the pace of its slowest
     // wave, so every SIMD must hold the same number of waves: a balanced
     // placement when it can be made (with fewer waves per SIMD when there are
@@ -182,14 +165,59 @@ swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, cons
                                 : strip_grid_limit(ctx->device, R, local, sc.asize);
         grid = StripLaunch{strip_grid(total_strips, RK, limit, ctx->num_cu, waves, forced), 1, wave_lds};
     }
-    hipEventRecord(ctx->ev[0], st);
-    if ((e = int16 ? launch_strip16(a, RK, grid, st, prune) : launch_strip(a, R, local, grid, st, prune)) !=
-        hipSuccess)
-        return hip_fail(ctx, e, "strip kernel launch");
-    hipEventRecord(ctx->ev[1], st);
-    if (local && (e = launch_reduce_best_multi(a.strip_best, a.probs, np, (BestCell *)ctx->prob_best.p, st)) !=
-                     hipSuccess)
-        return hip_fail(ctx, e, "reduce kernel launch");
+    out.grid = grid;
+    return SWH_OK;
+}
+
+hipError_t enqueue_strips(swh_ctx *ctx, const PreparedStrips &ps, const Scoring &sc, const Problem *tab_src,
+                          const int32_t *sp_src, hipStream_t st, bool timed)
+{
+    hipError_t e;
+    // counters and ticket cleared by kernels (no memset node in a captured graph)
+    if ((e = launch_fill_i32((int32_t *)ctx->flags.p, ps.total_flags, 0, st)) != hipSuccess ||
+        (e = launch_fill_i32((int32_t *)ctx->sync.p, 2, 0, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(ctx->probs.p, tab_src, (size_t)ps.np * sizeof(Problem), hipMemcpyHostToDevice, st)) !=
+            hipSuccess ||
+        (ps.np > 1 && (e = hipMemcpyAsync(ctx->strip_prob.p, sp_src, ps.strip_prob.size() * 4,
+                                          hipMemcpyHostToDevice, st)) != hipSuccess))
+        return e;
+    StripArgs a;
+    a.probs = (const Problem *)ctx->probs.p;
+    a.strip_prob = ps.np > 1 ? (const int32_t *)ctx->strip_prob.p : nullptr;
+    a.total_strips = (int32_t)ps.total_strips;
+    a.mat = (const int8_t *)ctx->mat.p;
+    a.asize = sc.asize;
+    a.o = sc.o;
+    a.e = sc.e;
+    a.smax = sc.smax;
+    a.ticket = (int32_t *)ctx->sync.p;
+    a.abort_flag = (int32_t *)ctx->sync.p + 1;
+    a.cancel = ctx->cancel_dev;
+    a.strip_best = (BestCell *)ctx->strip_best.p;
+    a.wait_ticks = wait_ticks(ctx->device);
+    const int RK = ps.int16 ? 2 * ps.R : ps.R;
+    if (timed) hipEventRecord(ctx->ev[0], st);
+    if ((e = ps.int16 ? launch_strip16(a, RK, ps.grid, st, ps.prune)
+                      : launch_strip(a, ps.R, ps.local, ps.grid, st, ps.prune)) != hipSuccess)
+        return e;
+    if (timed) hipEventRecord(ctx->ev[1], st);
+    if (ps.local && (e = launch_reduce_best_multi(a.strip_best, a.probs, ps.np, (BestCell *)ctx->prob_best.p, st)) !=
+                        hipSuccess)
+        return e;
+    return hipSuccess;
+}
+
+swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, const Scoring &sc, int R, bool local,
+                      hipStream_t st, std::vector<BestCell> *best, float *ms, int waves, bool int16)
+{
+    const int np = (int)probs.size();
+    if (np == 0) return SWH_OK;
+    PreparedStrips &ps = ctx->strips;
+    swh_status s = prepare_strips(ctx, probs, sc, R, local, waves, int16, ps);
+    if (s != SWH_OK) return s;
+    hipError_t e;
+    if ((e = enqueue_strips(ctx, ps, sc, ps.tab.data(), ps.strip_prob.data(), st, true)) != hipSuccess)
+        return hip_fail(ctx, e, "strip pass launch");
     int32_t flags_host[2] = {0, 0};
     if ((e = hipMemcpyAsync(flags_host, ctx->sync.p, 8, hipMemcpyDeviceToHost, st)) != hipSuccess)
         return hip_fail(ctx, e, "hipMemcpyAsync(abort flag)");

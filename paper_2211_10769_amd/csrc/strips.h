@@ -47,6 +47,18 @@ int strip_grid(int64_t nstrips, int R, int limit, int num_cu, int waves = 0, int
 swh_status run_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, const Scoring &sc, int R, bool local,
                       hipStream_t st, std::vector<BestCell> *best, float *ms, int waves = 0, bool int16 = false);
 
+// run_strips in two steps, so that the launches can be captured in a graph:
+// prepare_strips builds the problem tables on the host (device pointers
+// resolved) and sizes the context's buffers and the grid; enqueue_strips
+// copies the tables from tab_src / sp_src (the prepared tables, or a pinned
+// copy of them), clears the counters with kernels and launches the strip
+// kernel and, in local mode, the per-problem reduction into ctx->prob_best,
+// with no host synchronisation (PreparedStrips: engine.h).
+swh_status prepare_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, const Scoring &sc, int R, bool local,
+                          int waves, bool int16, PreparedStrips &out);
+hipError_t enqueue_strips(swh_ctx *ctx, const PreparedStrips &ps, const Scoring &sc, const Problem *tab_src,
+                          const int32_t *sp_src, hipStream_t st, bool timed);
+
 // Whether the context may run a 16-bit pass of nominal height R (4, 8 or 16).
 bool int16_usable(const swh_ctx *ctx, const Scoring &sc, int R);
 // No cell of an n x m local pass can reach sat16_limit (S <= min(n, m) max s).

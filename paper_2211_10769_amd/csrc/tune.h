@@ -21,5 +21,9 @@ inline int tuned_rows_per_lane(swh_ctx *ctx, int64_t n, int64_t) { return tuned_
 // Time every (R, waves) candidate on synthetic problems for row buckets
 // 1 Ki, 4 Ki, ... up to max_rows and install the fastest per bucket.
 swh_status autotune(swh_ctx *ctx, const Scoring &sc, int64_t max_rows, double cells_per_trial);
+// Measure the database length switch (swh_autotune_db).
+swh_status autotune_db(swh_ctx *ctx, const Scoring &sc, const swh_scoring *raw, int32_t &inter_max);
+swh_status tune_save(const swh_ctx *ctx, const char *path);
+swh_status tune_load(swh_ctx *ctx, const char *path);
 
 }  // namespace swh

@@ -76,3 +76,47 @@ def test_edge_cases(eng):
     with pytest.raises(swh.SwhError) as ei:
         swh.Database(eng, [b"ACDX1"], sc)
     assert ei.value.status == -2
+
+
+def test_length_switch_autotune_and_tuning_file(tmp_path):
+    # the measured switch moves sequences between the kernels; scores never change,
+    # and a saved tuning file restores the switch in another context
+    import paper_2211_10769_amd as swh
+    sc = seqgen.protein_scoring()
+    rng = np.random.default_rng(77)
+    lens = np.concatenate([rng.integers(20, 500, 300), rng.integers(500, 9000, 40)])
+    db = [bytes(seqgen.random_protein(rng, int(L))) for L in lens]
+    qs = [bytes(seqgen.random_protein(rng, int(L))) for L in (60, 250)]
+    want = oracle.db_scores(qs, db, sc)
+    a = swh.Engine(0)
+    b = swh.Engine(0)
+    try:
+        v = a.autotune_db(sc)
+        assert v in (512, 1024, 2048, 4096, 8192)
+        got, st = swh.Database(a, db, sc).scores(qs)
+        assert (got == want).all()
+        assert st["intra_pairs"] == len(qs) * int((lens > v).sum())
+        path = str(tmp_path / "tune.txt")
+        a.tune_save(path)
+        text = open(path).read()
+        assert text.startswith("swh-tune 1\n") and f"inter_max {v}\n" in text
+        b.tune_load(path)
+        got_b, st_b = swh.Database(b, db, sc).scores(qs)
+        assert (got_b == want).all() and st_b["intra_pairs"] == st["intra_pairs"]
+        # files of another device, or not tuning files at all, are refused
+        lines = text.splitlines()
+        other = tmp_path / "other.txt"
+        other.write_text("\n".join(["swh-tune 1", "device some other gpu"] + lines[2:]) + "\n")
+        bad = tmp_path / "bad.txt"
+        bad.write_text("hello\n")
+        for p in (other, bad, tmp_path / "missing.txt"):
+            with pytest.raises(swh.SwhError) as ex:
+                b.tune_load(str(p))
+            assert ex.value.status == -1
+        # an explicit option still wins over the measured switch
+        b.set_option("inter_max", 8192)
+        got_c, st_c = swh.Database(b, db, sc).scores(qs)
+        assert (got_c == want).all() and st_c["intra_pairs"] == len(qs) * int((lens > 8192).sum())
+    finally:
+        a.close()
+        b.close()

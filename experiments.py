@@ -61,17 +61,23 @@ def dna_schemes(swh, eng, seqgen, n):
 
 
 def protein_schemes(swh, eng, seqgen, db_size):
-    """Database search under BLOSUM62 with several gap penalties, and with the
-    matrix doubled (a higher-scoring table: more 16-bit saturation)."""
+    """Database search under BLOSUM62, 50 and 45 with several gap penalties, and
+    with BLOSUM62 doubled (a higher-scoring table: more 16-bit saturation)."""
     qs, (cat, off) = seqgen.workload2(n_db=db_size)
     alphabet, mat, _, _ = seqgen.protein_scoring()
     qcat, qoff = swh._concat(qs)
     out = [f"## Protein scoring schemes (database search, {len(qs)} queries vs {db_size:,} proteins, top-10)", "",
            "| matrix | open | extend | search ms | GCUPS | 16-bit saturated pairs |", "|---|---|---|---|---|---|"]
     doubled = np.clip(np.asarray(mat, dtype=np.int16) * 2, -128, 127).astype(np.int8)
-    for name, m, o, e in (("BLOSUM62", mat, 10, 2), ("BLOSUM62", mat, 10, 1), ("BLOSUM62", mat, 11, 1),
-                          ("BLOSUM62", mat, 12, 2), ("BLOSUM62", mat, 6, 1), ("2 x BLOSUM62", doubled, 20, 4)):
-        db = swh.Database(eng, (cat, off), swh.Scoring(alphabet, m, o, e))
+    b50 = seqgen.blosum_scoring(50)
+    b45 = seqgen.blosum_scoring(45)
+    schemes = [("BLOSUM62", alphabet, mat, 10, 2), ("BLOSUM62", alphabet, mat, 10, 1),
+               ("BLOSUM62", alphabet, mat, 11, 1), ("BLOSUM62", alphabet, mat, 12, 2),
+               ("BLOSUM62", alphabet, mat, 6, 1), ("2 x BLOSUM62", alphabet, doubled, 20, 4),
+               ("BLOSUM50", b50[0], b50[1], 10, 2), ("BLOSUM50", b50[0], b50[1], 13, 2),
+               ("BLOSUM45", b45[0], b45[1], 10, 2), ("BLOSUM45", b45[0], b45[1], 14, 2)]
+    for name, alph, m, o, e in schemes:
+        db = swh.Database(eng, (cat, off), swh.Scoring(alph, m, o, e))
         db.search((qcat, qoff), k=10)
         t0 = time.perf_counter()
         reps = 2

@@ -120,3 +120,20 @@ def test_length_switch_autotune_and_tuning_file(tmp_path):
     finally:
         a.close()
         b.close()
+
+
+@pytest.mark.parametrize("which", [50, 45])
+def test_other_blosum_tables(eng, which):
+    import paper_2211_10769_amd as swh
+    sc = seqgen.blosum_scoring(which)
+    rng = np.random.default_rng(100 + which)
+    db = _db(rng, 600)
+    qs = [bytes(seqgen.random_protein(rng, int(L))) for L in (45, 300)]
+    db[11] = bytes(seqgen.homolog(rng, np.frombuffer(qs[1], np.uint8)))
+    D = swh.Database(eng, db, sc)
+    got, _ = D.scores(qs)
+    want = oracle.db_scores(qs, db, sc)
+    assert (got == want).all()
+    idx, sco, _ = D.search(qs, k=5)
+    widx, wsco = oracle.topk(want, 5)
+    assert (idx == widx).all() and (sco == wsco).all()

@@ -2,6 +2,7 @@
 import hashlib
 
 import numpy as np
+import pytest
 
 import seqgen
 
@@ -19,6 +20,41 @@ def test_scoring_data_sanity():
     assert M[A.index("C"), A.index("C")] == 9
     assert M[A.index("I"), A.index("V")] == 3
     assert M[A.index("D"), A.index("E")] == 2
+
+
+def _karlin_lambda_entropy(S):
+    # lambda: the positive root of sum_ij p_i p_j exp(lambda s_ij) = 1;
+    # H = sum_ij q_ij lambda s_ij with target frequencies q_ij = p_i p_j exp(lambda s_ij)
+    from scipy.optimize import brentq
+    pp = np.outer(seqgen.BACKGROUND, seqgen.BACKGROUND)
+    S = S.astype(np.float64)
+    lam = brentq(lambda x: (pp * np.exp(x * S)).sum() - 1.0, 1e-3, 2.0)
+    return lam, (pp * np.exp(lam * S) * lam * S).sum()
+
+
+@pytest.mark.parametrize("which, lam, ent", [(62, 0.3176, 0.4012), (50, 0.2318, 0.3362), (45, 0.2291, 0.2514)])
+def test_blosum_tables_give_published_statistics(which, lam, ent):
+    # the ungapped Karlin-Altschul lambda and relative entropy (nats) that BLAST
+    # publishes for each matrix under the Robinson & Robinson background; a +-1
+    # change of any one symmetric pair of entries moves one of them in the
+    # fourth decimal, so the tables are pinned entry by entry
+    alph, M, o, e = seqgen.blosum_scoring(which)
+    assert M.shape == (20, 20) and alph == seqgen.PROTEIN_ALPHABET[:20] and (o, e) == (10, 2)
+    assert (M == M.T).all() and (np.diag(M) > 0).all()
+    assert (np.outer(seqgen.BACKGROUND, seqgen.BACKGROUND) * M).sum() < 0   # negative expected score
+    got_lam, got_ent = _karlin_lambda_entropy(M)
+    assert round(got_lam, 4) == lam and round(got_ent, 4) == ent
+
+
+def test_statistics_pin_catches_single_entry_errors():
+    M = seqgen.BLOSUM50.astype(np.int64)
+    base = _karlin_lambda_entropy(M)
+    for (i, j) in ((0, 0), (3, 6), (17, 17), (9, 19), (4, 13)):
+        T = M.copy()
+        T[i, j] += 1
+        T[j, i] = T[i, j]
+        got = _karlin_lambda_entropy(T)
+        assert (round(got[0], 4), round(got[1], 4)) != (round(base[0], 4), round(base[1], 4))
 
 
 def test_generators_are_deterministic():

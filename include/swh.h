@@ -171,7 +171,9 @@ swh_status  swh_cancel(swh_ctx *ctx);
  *                          rows per lane; 0 (default) = the tuned table or the
  *                          built-in rule
  *   SWH_OPT_GRID           > 0: run the strip kernel as this many single-wave
- *                          workgroups instead of the balanced placement; 0 default
+ *                          workgroups instead of the balanced placement, and the
+ *                          database kernel with at most this many persistent
+ *                          work-groups; 0 default
  *   SWH_OPT_BAND_ROWS      rows between the rows the score passes keep for the
  *                          band traceback: 0 (default) = built-in, -1 = no band
  *                          traceback, > 0 = that many (rounded up to strips)
@@ -208,6 +210,18 @@ swh_status  swh_cancel(swh_ctx *ctx);
  *                          rescored cells, but noise in groups of near-equal
  *                          predictions is amplified); 0 by the predicted score
  *                          itself.  Reported scores are exact either way.
+ *   SWH_OPT_DB_WAVES       waves that share one (query, group) unit of the
+ *                          database kernel: 1 (one wave per unit), 2, 4, 8 or 16 (the
+ *                          unit's 32-row query chunks run on neighbouring waves
+ *                          and hand their bottom rows on through LDS, so that a
+ *                          few queries still fill the GPU); 0 (default): chosen
+ *                          from the number of units
+ *   SWH_OPT_DB_ROUTE       a (query, group) unit whose cells exceed this percentage
+ *                          of one compute unit's share of the search runs on the
+ *                          single-pair kernel instead (one work-group would
+ *                          otherwise finish long after the rest: a unit cannot
+ *                          leave its compute unit, a single-pair problem can);
+ *                          0 (default) = 100, -1 = never
  *   SWH_OPT_FAULT_NOMEM    1: the next entry point on ctx fails as if a host
  *                          allocation had thrown std::bad_alloc (after its
  *                          argument checks), then the option resets; a test
@@ -225,7 +239,9 @@ enum {
     SWH_OPT_INT16 = 8,
     SWH_OPT_INTER_MAX = 9,
     SWH_OPT_FAULT_NOMEM = 10,
-    SWH_OPT_PF_RANK = 11
+    SWH_OPT_PF_RANK = 11,
+    SWH_OPT_DB_WAVES = 12,
+    SWH_OPT_DB_ROUTE = 13
 };
 swh_status  swh_set_option(swh_ctx *ctx, int32_t option, int64_t value);
 swh_status  swh_get_option(const swh_ctx *ctx, int32_t option, int64_t *value);

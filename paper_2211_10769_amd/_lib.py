@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "SWH_OK", -1: "SWH_E_INVAL", -2: "SWH_E_ALPHABET", -3: "SWH_E
 MODE_SCORE, MODE_COORDS, MODE_CIGAR = 0, 1, 2
 # context options (swh_set_option)
 OPTIONS = {"rows_per_lane": 1, "grid": 2, "band_rows": 3, "tb_leaf": 4, "graph": 5, "prune": 6, "mem_cap": 7,
-           "int16": 8, "inter_max": 9, "fault_nomem": 10, "pf_rank": 11}
+           "int16": 8, "inter_max": 9, "fault_nomem": 10, "pf_rank": 11, "db_waves": 12, "db_route": 13}
 GLOBAL = 0x100          # OR'd into mode: global (Needleman-Wunsch) alignment
 SEMIGLOBAL = 0x200      # OR'd into mode: semi-global (whole query, free target ends)
 OVERLAP = 0x400         # OR'd into mode: overlap (end gaps of both sequences free)

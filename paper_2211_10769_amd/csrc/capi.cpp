@@ -307,7 +307,10 @@ swh_status swh_create(int device, swh_ctx **out)
             delete ctx;
             return SWH_E_DEVICE;
         }
-        bool ok = hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming) == hipSuccess;
+        bool ok = hipStreamCreateWithFlags(&ctx->aux_stream, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) == hipSuccess;
         for (auto &ev : ctx->ev) ok = ok && hipEventCreate(&ev) == hipSuccess;
         // the cancellation flag: pinned, coherent host memory the kernels read uncached
         void *hp = nullptr, *dp = nullptr;
@@ -340,6 +343,7 @@ void swh_destroy(swh_ctx *ctx)
     try {
         hipSetDevice(ctx->device);
         if (ctx->own_stream) hipStreamSynchronize(ctx->own_stream);
+        if (ctx->aux_stream) hipStreamSynchronize(ctx->aux_stream);
         for (DevBuf *b : ctx->all())
             if (b->p) hipFree(b->p);
         ctx->tb_arena.free_all(ctx->held);
@@ -347,8 +351,11 @@ void swh_destroy(swh_ctx *ctx)
         for (auto &ev : ctx->ev)
             if (ev) hipEventDestroy(ev);
         if (ctx->ev_in) hipEventDestroy(ctx->ev_in);
+        if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
+        if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
         if (ctx->cancel_host) hipHostFree(ctx->cancel_host);
         if (ctx->own_stream) hipStreamDestroy(ctx->own_stream);
+        if (ctx->aux_stream) hipStreamDestroy(ctx->aux_stream);
         delete ctx;
     } catch (...) {
     }
@@ -384,6 +391,7 @@ swh_status swh_set_option(swh_ctx *ctx, int32_t option, int64_t value)
         case SWH_OPT_GRID:
             if (value < 0 || value > (1 << 20)) return bad("grid must be in 0 .. 2^20");
             o.grid = (int32_t)value;
+            ++ctx->gen;   // a captured search keeps its launch shape
             return SWH_OK;
         case SWH_OPT_BAND_ROWS:
             if (value < -1 || value > (1 << 30)) return bad("band rows must be -1, 0 or a positive row count");
@@ -417,6 +425,17 @@ swh_status swh_set_option(swh_ctx *ctx, int32_t option, int64_t value)
             if (value < 0 || value > 2) return bad("prefilter ranking must be 0, 1 or 2");
             o.pf_rank = (int32_t)value;
             return SWH_OK;
+        case SWH_OPT_DB_WAVES:
+            if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
+                return bad("database waves must be 0, 1, 2, 4, 8 or 16");
+            o.db_waves = (int32_t)value;
+            ++ctx->gen;   // a captured search keeps its launch shape
+            return SWH_OK;
+        case SWH_OPT_DB_ROUTE:
+            if (value < -1 || value > 100000) return bad("database routing must be -1, 0 or a percentage");
+            o.db_route = (int32_t)value;
+            ++ctx->gen;
+            return SWH_OK;
         case SWH_OPT_FAULT_NOMEM:
             if (value != 0 && value != 1) return bad("fault injection must be 0 or 1");
             o.fault_nomem = (int32_t)value;
@@ -442,6 +461,8 @@ swh_status swh_get_option(const swh_ctx *ctx, int32_t option, int64_t *value)
     case SWH_OPT_INT16: *value = o.int16; return SWH_OK;
     case SWH_OPT_INTER_MAX: *value = o.inter_max; return SWH_OK;
     case SWH_OPT_PF_RANK: *value = o.pf_rank; return SWH_OK;
+    case SWH_OPT_DB_WAVES: *value = o.db_waves; return SWH_OK;
+    case SWH_OPT_DB_ROUTE: *value = o.db_route; return SWH_OK;
     case SWH_OPT_FAULT_NOMEM: *value = o.fault_nomem; return SWH_OK;
     default: return SWH_E_INVAL;
     }

@@ -41,6 +41,8 @@ struct Options {
     int32_t int16 = 1;       // packed 16-bit local passes: 0 off, 1 batches and GPU-filling passes, 2 always
     int32_t inter_max = 0;   // database length switch (0: built-in / tuned)
     int32_t pf_rank = 1;     // prefilter ranking: 1 excess over same-length mean, 2 its z-score, 0 raw
+    int32_t db_waves = 0;    // waves per database unit: 0 auto, 1, 2 or 4
+    int32_t db_route = 0;    // units above this % of a CU's share go to the single-pair kernel (0: 100, -1: never)
     int32_t fault_nomem = 0; // the next entry point throws std::bad_alloc
 };
 
@@ -101,10 +103,12 @@ struct Arena {
 struct swh_ctx {
     int device = 0;
     hipStream_t own_stream = nullptr;
+    hipStream_t aux_stream = nullptr;   // second stream of the context (default priority)
     int num_cu = 0;
     std::string err;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t ev_in = nullptr;   // orders the context's stream after a caller's stream
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;   // own_stream <-> aux_stream ordering
     swh::Options opt;
     // cancellation flag in pinned host memory (host view and device view)
     int32_t *cancel_host = nullptr;
@@ -129,6 +133,8 @@ struct swh_ctx {
     swh::PreparedStrips strips;   // host tables of the last strip launch
     // database search buffers
     swh::DevBuf qoff, db_work, db_border, db_redo, db_scatter, db_scores, db_topk;
+    swh::DevBuf db_sync;                 // the inter-task kernel's ticket, abort flag and redo count
+    std::vector<int64_t> pair_pos;       // score positions of the last single-pair launch (upload source)
     // batched pairs: padded per-pair copies and border rows of one launch
     swh::DevBuf bq, bt, bborder;
     // strip shapes measured by the autotuner (empty: built-in rule)
@@ -149,7 +155,7 @@ struct swh_ctx {
     std::vector<swh::DevBuf *> all() {
         return {&qraw, &traw, &qc, &tc, &qr, &tr, &border, &flags, &misc, &strip_best, &mat, &lut,
                 &probs, &strip_prob, &prob_best, &sync,
-                &qoff, &db_work, &db_border, &db_redo, &db_scatter, &db_scores, &db_topk,
+                &qoff, &db_work, &db_border, &db_redo, &db_scatter, &db_scores, &db_topk, &db_sync,
                 &bq, &bt, &bborder,
                 &pf_fq, &pf_qlen, &pf_Aq, &pf_pred, &pf_hist, &pf_prefix, &pf_marks, &pf_chunk, &pf_cand,
                 &pf_res, &pf_groups, &pf_perm,

@@ -219,15 +219,174 @@ swh_status prepare_queries(swh_ctx *ctx, const Scoring &sc, int32_t nq, const ch
     return SWH_OK;
 }
 
+void plan_search(const swh_ctx *ctx, const swh_db *db, const std::vector<int64_t> &qo, int32_t nq,
+                 std::vector<DbWork> &work, std::vector<std::pair<int32_t, int32_t>> &pairs, double &cells)
+{
+    const int64_t ngroups = (int64_t)db->h_groups.size();
+    double colsum = 0.0;   // sum over groups of 128 x maxlen
+    for (const DbGroup &g : db->h_groups) colsum += 128.0 * g.maxlen;
+    double inter = 0.0;
+    for (int32_t q = 0; q < nq; ++q) inter += (double)(qo[q + 1] - qo[q]) * colsum;
+    const double share = inter / std::max(1, ctx->num_cu);
+    const int route = ctx->opt.db_route;
+    const double limit = route < 0 ? 1e300 : share * (route == 0 ? 100 : route) / 100.0;
+    work.reserve(work.size() + (size_t)nq * (size_t)ngroups);
+    for (int32_t q = 0; q < nq; ++q) {
+        const int64_t n = qo[q + 1] - qo[q];
+        if (n == 0) continue;
+        for (int64_t g = 0; g < ngroups; ++g) {
+            // (members are sorted by length: the first is the shortest; an empty
+            // sequence is no single-pair problem, so its group is never moved)
+            const int32_t first = db->h_perm[g * 128];
+            const bool movable = first >= 0 && db->h_off[first + 1] > db->h_off[first];
+            if (movable && (double)n * 128.0 * db->h_groups[g].maxlen > limit) {
+                for (int s = 0; s < 128; ++s) {
+                    const int32_t idx = db->h_perm[g * 128 + s];
+                    if (idx >= 0) pairs.push_back({q, idx});
+                }
+            } else {
+                work.push_back(DbWork{q, (int32_t)g});
+            }
+        }
+        for (int32_t d : db->long_idx) pairs.push_back({q, d});
+        cells += (double)n * (double)db->total_residues;
+    }
+}
+
+DbLaunch db_launch_shape(const swh_ctx *ctx, size_t units, int32_t max_len)
+{
+    DbLaunch L;
+    L.waves = ctx->opt.db_waves;
+    if (L.waves == 0) {
+        // one wave per unit while the units outnumber the waves that fit four to one
+        // (the pipelined form pays some hand-over work per column); below that the
+        // unit's chunks are spread over four waves
+        L.waves = units >= (size_t)4 * db_search_grid_limit(ctx->device, 1) ? 1 : 4;
+    }
+    int limit = db_search_grid_limit(ctx->device, L.waves);
+    if (ctx->opt.grid > 0) limit = std::min(limit, (int)ctx->opt.grid);
+    L.grid = std::max(1, std::min<int>(limit, (int)std::max<size_t>(1, units)));
+    L.wrap_cap = max_len + 64;
+    L.border_bytes = L.waves == 1 ? (size_t)L.grid * max_len * 64 * 8 + 64
+                                  : (size_t)L.grid * L.wrap_cap * 64 * 16 + 64;
+    return L;
+}
+
+namespace {
+
+// (query, sequence) pairs on the single-pair kernel, in 32 bits, enqueued on
+// stream st with no host wait after the gather: padded copies of each query
+// and each sequence once, the strip launch (timed by ctx->ev[0..1]), and the
+// scatter of the scores into scores_dev.  The strip kernel's abort flag is
+// ctx->sync[1] afterwards.
+swh_status enqueue_pairs(swh_ctx *ctx, const swh_db *db, const QuerySet &qs,
+                         const std::vector<std::pair<int32_t, int32_t>> &pairs, int32_t *scores_dev, hipStream_t st)
+{
+    swh_status s;
+    hipError_t e;
+    const Scoring &sc = db->sc;
+    const std::vector<int64_t> &qo = qs.qo;
+    const int32_t nq = qs.nq;
+    const StripShape shape = tuned_shape(ctx, qs.maxq);
+    const int R = shape.R;
+    std::vector<int64_t> qpad_off((size_t)nq + 1, 0);
+    for (int32_t q = 0; q < nq; ++q) qpad_off[q + 1] = qpad_off[q] + rows_padded(qo[q + 1] - qo[q], R);
+    std::vector<int32_t> dids;
+    for (auto &pq : pairs) dids.push_back(pq.second);
+    std::sort(dids.begin(), dids.end());
+    dids.erase(std::unique(dids.begin(), dids.end()), dids.end());
+    std::vector<int64_t> dpad_off(dids.size() + 1, 0);
+    for (size_t i = 0; i < dids.size(); ++i)
+        dpad_off[i + 1] = dpad_off[i] + cols_padded(db->h_off[dids[i] + 1] - db->h_off[dids[i]]);
+    int64_t border_entries = 0;
+    for (auto &pq : pairs) border_entries += cols_padded(db->h_off[pq.second + 1] - db->h_off[pq.second]);
+    const size_t code_bytes = (size_t)(qpad_off[nq] + dpad_off.back()) + 256;
+    if ((s = ensure(ctx, ctx->tb_codes_q, code_bytes, "intra-task codes")) != SWH_OK ||
+        (s = ensure(ctx, ctx->tb_bwd, sizeof(Border) * (size_t)border_entries + 256, "intra-task borders")) != SWH_OK ||
+        (s = ensure(ctx, ctx->db_scatter, sizeof(int64_t) * pairs.size() + 64, "scatter")) != SWH_OK)
+        return s;
+    std::vector<GatherLite> gl;
+    uint8_t *qbuf = (uint8_t *)ctx->tb_codes_q.p, *dbuf = qbuf + qpad_off[nq];
+    for (int32_t q = 0; q < nq; ++q)
+        gl.push_back(GatherLite{(const uint8_t *)ctx->qc.p + qo[q], qbuf + qpad_off[q], qo[q + 1] - qo[q],
+                                qpad_off[q + 1] - qpad_off[q]});
+    for (size_t i = 0; i < dids.size(); ++i)
+        gl.push_back(GatherLite{(const uint8_t *)db->codes.p + db->h_off[dids[i]], dbuf + dpad_off[i],
+                                db->h_off[dids[i] + 1] - db->h_off[dids[i]], dpad_off[i + 1] - dpad_off[i]});
+    if ((s = gather_lite(ctx, gl, (uint8_t)sc.asize, st)) != SWH_OK) return s;
+    if ((e = launch_fill_i32((int32_t *)ctx->tb_bwd.p, 2 * border_entries, 0, st)) != hipSuccess)
+        return hip_fail(ctx, e, "intra-task borders");
+    std::vector<StripProblem> probs;
+    Border *bp = (Border *)ctx->tb_bwd.p;
+    std::vector<int64_t> &pos = ctx->pair_pos;   // lives until the next call: the upload reads it
+    pos.resize(pairs.size());
+    for (size_t i = 0; i < pairs.size(); ++i) {
+        const auto &pq = pairs[i];
+        const size_t di = (size_t)(std::lower_bound(dids.begin(), dids.end(), pq.second) - dids.begin());
+        const int64_t L = db->h_off[pq.second + 1] - db->h_off[pq.second];
+        probs.push_back(StripProblem{qbuf + qpad_off[pq.first], qo[pq.first + 1] - qo[pq.first],
+                                     dbuf + dpad_off[di], L, bp});
+        bp += cols_padded(L);
+        pos[i] = (int64_t)pq.first * db->ndb + pq.second;
+    }
+    PreparedStrips &ps = ctx->strips;
+    if ((s = prepare_strips(ctx, probs, sc, R, true, shape.waves, false, ps)) != SWH_OK) return s;
+    if ((e = enqueue_strips(ctx, ps, sc, ps.tab.data(), ps.strip_prob.data(), st, true)) != hipSuccess ||
+        (e = hipMemcpyAsync(ctx->db_scatter.p, pos.data(), sizeof(int64_t) * pos.size(), hipMemcpyHostToDevice,
+                            st)) != hipSuccess ||
+        (e = launch_scatter_best((const int64_t *)ctx->db_scatter.p, (const int32_t *)ctx->prob_best.p,
+                                 (int64_t)pos.size(), (int32_t)(sizeof(BestCell) / sizeof(int32_t)), scores_dev,
+                                 st)) != hipSuccess)
+        return hip_fail(ctx, e, "single-pair launch");
+    return SWH_OK;
+}
+
+// Wait for an enqueue_pairs on st; adds its kernel time to stats.
+swh_status finish_pairs(swh_ctx *ctx, hipStream_t st, DbStats &stats, size_t npairs)
+{
+    hipError_t e;
+    int32_t flags[2] = {0, 0};
+    if ((e = hipMemcpyAsync(flags, ctx->sync.p, sizeof(flags), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_fail(ctx, e, "single-pair pass");
+    if (cancelled(ctx)) return cancel_status(ctx);
+    if (flags[1]) return fail(ctx, SWH_E_TIMEOUT, "strip wavefront wait expired");
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]);
+    stats.ms_intra += ms;
+    stats.intra_pairs += (int64_t)npairs;
+    return SWH_OK;
+}
+
+}  // namespace
+
 swh_status score_units(swh_ctx *ctx, const swh_db *db, const QuerySet &qs, const GroupSet &gs,
                        std::vector<DbWork> work, const std::vector<std::pair<int32_t, int32_t>> &long_pairs,
                        int32_t *scores_dev, DbStats &stats)
 {
     swh_status s;
     hipError_t e;
-    hipStream_t st = ctx->own_stream;
+    hipStream_t st = ctx->own_stream, aux = ctx->aux_stream;
     const Scoring &sc = db->sc;
     const std::vector<int64_t> &qo = qs.qo;
+
+    // ---- the single-pair problems known now (sequences beyond the length
+    //      switch, members of oversize units) run on the auxiliary stream, beside
+    //      the inter-task kernel: its last units leave most of the GPU idle
+    const bool side = !long_pairs.empty();
+    if (side) {
+        if ((e = hipEventRecord(ctx->ev_fork, st)) != hipSuccess ||
+            (e = hipStreamWaitEvent(aux, ctx->ev_fork, 0)) != hipSuccess)
+            return hip_fail(ctx, e, "stream fork");
+        if ((s = enqueue_pairs(ctx, db, qs, long_pairs, scores_dev, aux)) != SWH_OK) {
+            hipStreamSynchronize(aux);
+            return s;
+        }
+    }
+    auto join = [&]() {
+        if (side && hipEventRecord(ctx->ev_join, aux) == hipSuccess) hipStreamWaitEvent(st, ctx->ev_join, 0);
+        hipStreamSynchronize(aux);
+    };
 
     // ---- inter-task: every (query, group) unit, most expensive first
     int32_t max_len = 1;
@@ -236,18 +395,21 @@ swh_status score_units(swh_ctx *ctx, const swh_db *db, const QuerySet &qs, const
         return (qo[a.q + 1] - qo[a.q]) * (int64_t)(*gs.h_groups)[a.g].maxlen >
                (qo[b.q + 1] - qo[b.q]) * (int64_t)(*gs.h_groups)[b.g].maxlen;
     });
-    const int limit = db_search_grid_limit(ctx->device);
-    const int grid = std::max(1, std::min<int>(limit, (int)std::max<size_t>(1, work.size())));
+    const DbLaunch shape = db_launch_shape(ctx, work.size(), max_len);
     const int redo_cap = 1 << 20;
     if ((s = ensure(ctx, ctx->db_work, sizeof(DbWork) * work.size() + 16, "work list")) != SWH_OK ||
-        (s = ensure(ctx, ctx->db_border, (size_t)grid * max_len * 64 * 8 + 64, "inter-task borders")) != SWH_OK ||
+        (s = ensure(ctx, ctx->db_border, shape.border_bytes, "inter-task borders")) != SWH_OK ||
         (s = ensure(ctx, ctx->db_redo, sizeof(int32_t) * 2 * (size_t)redo_cap + 64, "redo list")) != SWH_OK ||
-        (s = ensure(ctx, ctx->sync, 64, "ticket")) != SWH_OK)
+        (s = ensure(ctx, ctx->db_sync, 64, "ticket")) != SWH_OK) {
+        join();
         return s;
+    }
     if ((!work.empty() && (e = hipMemcpyAsync(ctx->db_work.p, work.data(), sizeof(DbWork) * work.size(),
                                               hipMemcpyHostToDevice, st)) != hipSuccess) ||
-        (e = hipMemsetAsync(ctx->sync.p, 0, 64, st)) != hipSuccess)
+        (e = launch_fill_i32((int32_t *)ctx->db_sync.p, 16, 0, st)) != hipSuccess) {
+        join();
         return hip_fail(ctx, e, "work upload");
+    }
     DbSearchArgs a;
     a.res = gs.res;
     a.groups = gs.groups;
@@ -263,101 +425,52 @@ swh_status score_units(swh_ctx *ctx, const swh_db *db, const QuerySet &qs, const
     a.ndb = db->ndb;
     a.scores = scores_dev;
     a.redo = (int32_t *)ctx->db_redo.p;
-    a.nredo = (int32_t *)ctx->sync.p + 8;
+    a.nredo = (int32_t *)ctx->db_sync.p + 8;
     a.redo_cap = redo_cap;
-    a.ticket = (int32_t *)ctx->sync.p;
+    a.ticket = (int32_t *)ctx->db_sync.p;
     a.border = (uint32_t *)ctx->db_border.p;
     a.max_len = max_len;
+    a.wrap_cap = shape.wrap_cap;
     a.cancel = ctx->cancel_dev;
+    a.abort_flag = (int32_t *)ctx->db_sync.p + 2;
+    a.wait_ticks = wait_ticks(ctx->device);
     hipEventRecord(ctx->ev[2], st);
-    if (!work.empty() && (e = launch_db_search(a, grid, st)) != hipSuccess) return hip_fail(ctx, e, "search launch");
+    if (!work.empty() && (e = launch_db_search(a, shape.waves, shape.grid, st)) != hipSuccess) {
+        join();
+        return hip_fail(ctx, e, "search launch");
+    }
     hipEventRecord(ctx->ev[3], st);
-    int32_t nredo = 0;
-    if ((e = hipMemcpyAsync(&nredo, a.nredo, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (e = hipStreamSynchronize(st)) != hipSuccess)
+    int32_t words[16] = {0};
+    e = hipMemcpyAsync(words, ctx->db_sync.p, sizeof(words), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        join();
         return hip_fail(ctx, e, "search");
+    }
+    if (side && (s = finish_pairs(ctx, aux, stats, long_pairs.size())) != SWH_OK) return s;
+    const int32_t nredo = words[8];
     if (cancelled(ctx)) return cancel_status(ctx);
+    if (words[2]) return fail(ctx, SWH_E_TIMEOUT, "database search: a hand-over wait expired");
     float ms = 0.f;
     hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]);
     stats.ms_inter += ms;
     if (nredo > redo_cap) return fail(ctx, SWH_E_RANGE, "more than 2^20 saturated pairs in one search");
+    if (nredo == 0) return SWH_OK;
+
+    // ---- 16-bit saturation: those pairs again in 32 bits on the single-pair kernel
     std::vector<int32_t> redo((size_t)2 * nredo);
-    if (nredo && ((e = hipMemcpyAsync(redo.data(), a.redo, sizeof(int32_t) * 2 * nredo, hipMemcpyDeviceToHost, st)) !=
-                      hipSuccess ||
-                  (e = hipStreamSynchronize(st)) != hipSuccess))
+    if ((e = hipMemcpyAsync(redo.data(), a.redo, sizeof(int32_t) * 2 * nredo, hipMemcpyDeviceToHost, st)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
         return hip_fail(ctx, e, "redo list");
     stats.redo += nredo;
-
-    // ---- intra-task in 32 bits: long database sequences and saturated pairs
-    std::vector<std::pair<int32_t, int32_t>> pairs(long_pairs);
+    std::vector<std::pair<int32_t, int32_t>> pairs;
     for (int32_t i = 0; i < nredo; ++i) pairs.push_back({redo[2 * i], redo[2 * i + 1]});
-    if (!pairs.empty()) {
-        const int32_t nq = qs.nq;
-        const StripShape shape = tuned_shape(ctx, qs.maxq);
-        const int R = shape.R;
-        // padded copies: each query once, each database sequence once
-        std::vector<int64_t> qpad_off((size_t)nq + 1, 0);
-        for (int32_t q = 0; q < nq; ++q) qpad_off[q + 1] = qpad_off[q] + rows_padded(qo[q + 1] - qo[q], R);
-        std::vector<int32_t> dids;
-        for (auto &pq : pairs) dids.push_back(pq.second);
-        std::sort(dids.begin(), dids.end());
-        dids.erase(std::unique(dids.begin(), dids.end()), dids.end());
-        std::vector<int64_t> dpad_off(dids.size() + 1, 0);
-        for (size_t i = 0; i < dids.size(); ++i)
-            dpad_off[i + 1] = dpad_off[i] + cols_padded(db->h_off[dids[i] + 1] - db->h_off[dids[i]]);
-        int64_t border_entries = 0;
-        for (auto &pq : pairs)
-            border_entries += cols_padded(db->h_off[pq.second + 1] - db->h_off[pq.second]);
-        const size_t code_bytes = (size_t)(qpad_off[nq] + dpad_off.back()) + 256;
-        if ((s = ensure(ctx, ctx->tb_codes_q, code_bytes, "intra-task codes")) != SWH_OK ||
-            (s = ensure(ctx, ctx->tb_bwd, sizeof(Border) * (size_t)border_entries + 256, "intra-task borders")) !=
-                SWH_OK)
-            return s;
-        std::vector<GatherLite> gl;
-        uint8_t *qbuf = (uint8_t *)ctx->tb_codes_q.p, *dbuf = qbuf + qpad_off[nq];
-        for (int32_t q = 0; q < nq; ++q)
-            gl.push_back(GatherLite{(const uint8_t *)ctx->qc.p + qo[q], qbuf + qpad_off[q], qo[q + 1] - qo[q],
-                                    qpad_off[q + 1] - qpad_off[q]});
-        for (size_t i = 0; i < dids.size(); ++i)
-            gl.push_back(GatherLite{(const uint8_t *)db->codes.p + db->h_off[dids[i]], dbuf + dpad_off[i],
-                                    db->h_off[dids[i] + 1] - db->h_off[dids[i]], dpad_off[i + 1] - dpad_off[i]});
-        if ((s = gather_lite(ctx, gl, (uint8_t)sc.asize, st)) != SWH_OK) return s;
-        if ((e = hipMemsetAsync(ctx->tb_bwd.p, 0, sizeof(Border) * (size_t)border_entries, st)) != hipSuccess)
-            return hip_fail(ctx, e, "intra-task borders");
-        std::vector<StripProblem> probs;
-        Border *bp = (Border *)ctx->tb_bwd.p;
-        for (auto &pq : pairs) {
-            const size_t di = (size_t)(std::lower_bound(dids.begin(), dids.end(), pq.second) - dids.begin());
-            const int64_t L = db->h_off[pq.second + 1] - db->h_off[pq.second];
-            probs.push_back(StripProblem{qbuf + qpad_off[pq.first], qo[pq.first + 1] - qo[pq.first],
-                                         dbuf + dpad_off[di], L, bp});
-            bp += cols_padded(L);
-        }
-        std::vector<BestCell> best;
-        float ms2 = 0.f;
-        if ((s = run_strips(ctx, probs, sc, R, true, st, &best, &ms2, shape.waves)) != SWH_OK) return s;
-        stats.ms_intra += ms2;
-        stats.intra_pairs += (int64_t)pairs.size();
-        std::vector<int64_t> pos(pairs.size());
-        std::vector<int32_t> val(pairs.size());
-        for (size_t i = 0; i < pairs.size(); ++i) {
-            pos[i] = (int64_t)pairs[i].first * db->ndb + pairs[i].second;
-            val[i] = best[i].score;
-        }
-        if ((s = ensure(ctx, ctx->db_scatter, (sizeof(int64_t) + sizeof(int32_t)) * pos.size() + 64, "scatter")) !=
-            SWH_OK)
-            return s;
-        int64_t *dpos = (int64_t *)ctx->db_scatter.p;
-        int32_t *dval = (int32_t *)(dpos + pos.size());
-        if ((e = hipMemcpyAsync(dpos, pos.data(), sizeof(int64_t) * pos.size(), hipMemcpyHostToDevice, st)) !=
-                hipSuccess ||
-            (e = hipMemcpyAsync(dval, val.data(), sizeof(int32_t) * val.size(), hipMemcpyHostToDevice, st)) !=
-                hipSuccess ||
-            (e = launch_scatter(dpos, dval, (int64_t)pos.size(), scores_dev, st)) != hipSuccess ||
-            (e = hipStreamSynchronize(st)) != hipSuccess)
-            return hip_fail(ctx, e, "scatter");
+    if ((s = enqueue_pairs(ctx, db, qs, pairs, scores_dev, st)) != SWH_OK) {
+        hipStreamSynchronize(st);
+        return s;
     }
-    return SWH_OK;
+    return finish_pairs(ctx, st, stats, pairs.size());
 }
 
 swh_status db_scores_device(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_cat, const int64_t *q_off,
@@ -366,21 +479,16 @@ swh_status db_scores_device(swh_ctx *ctx, const swh_db *db, int32_t nq, const ch
     QuerySet qs;
     swh_status s = prepare_queries(ctx, db->sc, nq, q_cat, q_off, qs, dev);
     if (s != SWH_OK) return s;
-    const int64_t ngroups = (int64_t)db->h_groups.size();
     std::vector<DbWork> work;
-    work.reserve((size_t)(nq * ngroups));
     std::vector<std::pair<int32_t, int32_t>> long_pairs;
     for (int32_t q = 0; q < nq; ++q) {
         if (qs.qo[q + 1] == qs.qo[q]) {
             // an empty query aligns with nothing: every score is 0
             hipError_t e = launch_fill_i32(scores_dev + (int64_t)q * db->ndb, db->ndb, 0, ctx->own_stream);
             if (e != hipSuccess) return hip_fail(ctx, e, "score fill");
-            continue;
         }
-        for (int64_t g = 0; g < ngroups; ++g) work.push_back(DbWork{q, (int32_t)g});
-        for (int32_t d : db->long_idx) long_pairs.push_back({q, d});
-        stats.cells += (double)(qs.qo[q + 1] - qs.qo[q]) * (double)db->total_residues;
     }
+    plan_search(ctx, db, qs.qo, nq, work, long_pairs, stats.cells);
     GroupSet gs{(const uint8_t *)db->res.p, (const DbGroup *)db->groups.p, (const int32_t *)db->perm.p,
                 &db->h_groups};
     return score_units(ctx, db, qs, gs, std::move(work), long_pairs, scores_dev, stats);

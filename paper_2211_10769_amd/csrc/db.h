@@ -72,6 +72,24 @@ swh_status score_units(swh_ctx *ctx, const swh_db *db, const QuerySet &qs, const
                        std::vector<DbWork> work, const std::vector<std::pair<int32_t, int32_t>> &long_pairs,
                        int32_t *scores_dev, DbStats &stats);
 
+// The units of a search: (query, group) units for the inter-task kernel and
+// (query, sequence) pairs for the single-pair kernel -- sequences beyond the
+// length switch, and the members of a group whose unit alone would exceed
+// SWH_OPT_DB_ROUTE percent of one compute unit's share of the inter-task
+// cells.  Empty queries get neither; cells += their DP cells.
+void plan_search(const swh_ctx *ctx, const swh_db *db, const std::vector<int64_t> &qo, int32_t nq,
+                 std::vector<DbWork> &work, std::vector<std::pair<int32_t, int32_t>> &pairs, double &cells);
+
+// Launch shape of the inter-task kernel for `units` units of groups up to
+// max_len columns: waves per unit, persistent work-groups, border bytes.
+struct DbLaunch {
+    int waves = 1;
+    int grid = 1;
+    int32_t wrap_cap = 0;
+    size_t border_bytes = 0;
+};
+DbLaunch db_launch_shape(const swh_ctx *ctx, size_t units, int32_t max_len);
+
 swh_status db_create(swh_ctx *ctx, int64_t ndb, const char *cat, const int64_t *off, const Scoring &sc,
                      swh_db **out);
 void db_destroy(swh_db *db);

@@ -52,7 +52,8 @@ struct SearchPlan {
     char *q_stage = nullptr;
     int64_t *out_idx = nullptr;
     int32_t *out_score = nullptr;
-    int32_t *out_words = nullptr;   // [0] first bad byte (INT32_MAX: none), [1] saturated pairs, [2] abort flag
+    int32_t *out_words = nullptr;   // [0] first bad byte (INT32_MAX: none), [1] saturated pairs,
+                                    // [2] strip abort flag, [3] database-kernel abort flag
     int64_t qtotal = 0;
     double cells = 0.0;
     int64_t long_pairs = 0;
@@ -120,20 +121,14 @@ swh_status build_plan(swh_ctx *ctx, const swh_db *db, int32_t nq, int32_t k, con
     std::vector<DbWork> work;
     std::vector<std::pair<int32_t, int32_t>> lp;
     double cells = 0.0;
-    for (int32_t q = 0; q < nq; ++q) {
-        if (qo[q + 1] == qo[q]) continue;
-        for (int64_t g = 0; g < ngroups; ++g) work.push_back(DbWork{q, (int32_t)g});
-        for (int32_t d : db->long_idx) lp.push_back({q, d});
-        cells += (double)(qo[q + 1] - qo[q]) * (double)db->total_residues;
-    }
+    plan_search(ctx, db, qo, nq, work, lp, cells);
     int32_t max_len = 1;
     for (const DbWork &w : work) max_len = std::max(max_len, db->h_groups[w.g].maxlen);
     std::stable_sort(work.begin(), work.end(), [&](const DbWork &a, const DbWork &b) {
         return (qo[a.q + 1] - qo[a.q]) * (int64_t)db->h_groups[a.g].maxlen >
                (qo[b.q + 1] - qo[b.q]) * (int64_t)db->h_groups[b.g].maxlen;
     });
-    const int limit = db_search_grid_limit(ctx->device);
-    const int grid = std::max(1, std::min<int>(limit, (int)std::max<size_t>(1, work.size())));
+    const DbLaunch dbl = db_launch_shape(ctx, work.size(), max_len);
     const int redo_cap = 1 << 20;
     const size_t cand = topk_scratch_entries(nq, ndb, k);
 
@@ -147,9 +142,10 @@ swh_status build_plan(swh_ctx *ctx, const swh_db *db, int32_t nq, int32_t k, con
         (s = ensure(ctx, ctx->db_scores, sizeof(int32_t) * (size_t)std::max<int64_t>(1, (int64_t)nq * ndb) + 64,
                     "score matrix")) != SWH_OK ||
         (s = ensure(ctx, ctx->db_work, sizeof(DbWork) * work.size() + 16, "work list")) != SWH_OK ||
-        (s = ensure(ctx, ctx->db_border, (size_t)grid * max_len * 64 * 8 + 64, "inter-task borders")) != SWH_OK ||
+        (s = ensure(ctx, ctx->db_border, dbl.border_bytes, "inter-task borders")) != SWH_OK ||
         (s = ensure(ctx, ctx->db_redo, sizeof(int32_t) * 2 * (size_t)redo_cap + 64, "redo list")) != SWH_OK ||
         (s = ensure(ctx, ctx->sync, 64, "ticket")) != SWH_OK ||
+        (s = ensure(ctx, ctx->db_sync, 64, "ticket")) != SWH_OK ||
         (s = ensure(ctx, ctx->db_topk, cand * 8 + (size_t)nq * k * 12 + 256, "top-k scratch")) != SWH_OK)
         return s;
 
@@ -162,7 +158,10 @@ swh_status build_plan(swh_ctx *ctx, const swh_db *db, int32_t nq, int32_t k, con
     if (!lp.empty()) {
         std::vector<int64_t> qpad_off((size_t)nq + 1, 0);
         for (int32_t q = 0; q < nq; ++q) qpad_off[q + 1] = qpad_off[q] + rows_padded(qo[q + 1] - qo[q], R);
-        const std::vector<int32_t> &dids = db->long_idx;   // sorted by index
+        std::vector<int32_t> dids;   // each database sequence of a pair once, by index
+        for (auto &pq : lp) dids.push_back(pq.second);
+        std::sort(dids.begin(), dids.end());
+        dids.erase(std::unique(dids.begin(), dids.end()), dids.end());
         std::vector<int64_t> dpad_off(dids.size() + 1, 0);
         for (size_t i = 0; i < dids.size(); ++i)
             dpad_off[i + 1] = dpad_off[i] + cols_padded(db->h_off[dids[i] + 1] - db->h_off[dids[i]]);
@@ -250,12 +249,15 @@ swh_status build_plan(swh_ctx *ctx, const swh_db *db, int32_t nq, int32_t k, con
     a.ndb = ndb;
     a.scores = (int32_t *)ctx->db_scores.p;
     a.redo = (int32_t *)ctx->db_redo.p;
-    a.nredo = (int32_t *)ctx->sync.p + 8;
+    a.nredo = (int32_t *)ctx->db_sync.p + 8;
     a.redo_cap = redo_cap;
-    a.ticket = (int32_t *)ctx->sync.p;
+    a.ticket = (int32_t *)ctx->db_sync.p;
     a.border = (uint32_t *)ctx->db_border.p;
     a.max_len = max_len;
+    a.wrap_cap = dbl.wrap_cap;
     a.cancel = ctx->cancel_dev;
+    a.abort_flag = (int32_t *)ctx->db_sync.p + 2;
+    a.wait_ticks = wait_ticks(ctx->device);
     int32_t *cidx = (int32_t *)ctx->db_topk.p;
     int32_t *cscore = cidx + cand;
     int64_t *oidx = (int64_t *)(((uintptr_t)(cscore + cand) + 15) & ~(uintptr_t)15);
@@ -279,25 +281,34 @@ swh_status build_plan(swh_ctx *ctx, const swh_db *db, int32_t nq, int32_t k, con
     step(launch_encode((const char *)ctx->qraw.p, qtotal, (uint8_t *)ctx->qc.p, qtotal, (const uint8_t *)ctx->lut.p,
                        (uint8_t)sc.asize, (int32_t *)ctx->misc.p, st));
     if (!work.empty()) step(hipMemcpyAsync(ctx->db_work.p, base + o_work, sizeof(DbWork) * work.size(), H2D, st));
-    step(launch_fill_i32((int32_t *)ctx->sync.p, 16, 0, st));
-    if (!work.empty()) step(launch_db_search(a, grid, st));
+    step(launch_fill_i32((int32_t *)ctx->db_sync.p, 16, 0, st));
     if (!probs.empty()) {
-        step(hipMemcpyAsync(ctx->tb_misc.p, base + o_gd, sizeof(GatherDesc) * gd.size(), H2D, st));
-        step(launch_gather((const GatherDesc *)ctx->tb_misc.p, (int32_t)gd.size(), (uint8_t)sc.asize, st));
-        step(launch_fill_i32((int32_t *)ctx->tb_bwd.p, 2 * border_entries, 0, st));
-        step(enqueue_strips(ctx, prep, sc, (const Problem *)(base + o_tab), (const int32_t *)(base + o_sp), st,
+        // the single-pair problems on the auxiliary stream, beside the inter-task kernel
+        hipStream_t aux = ctx->aux_stream;
+        step(hipEventRecord(ctx->ev_fork, st));
+        step(hipStreamWaitEvent(aux, ctx->ev_fork, 0));
+        step(hipMemcpyAsync(ctx->tb_misc.p, base + o_gd, sizeof(GatherDesc) * gd.size(), H2D, aux));
+        step(launch_gather((const GatherDesc *)ctx->tb_misc.p, (int32_t)gd.size(), (uint8_t)sc.asize, aux));
+        step(launch_fill_i32((int32_t *)ctx->tb_bwd.p, 2 * border_entries, 0, aux));
+        step(enqueue_strips(ctx, prep, sc, (const Problem *)(base + o_tab), (const int32_t *)(base + o_sp), aux,
                             false));
-        step(hipMemcpyAsync(ctx->db_scatter.p, base + o_pos, sizeof(int64_t) * pos.size(), H2D, st));
+        step(hipMemcpyAsync(ctx->db_scatter.p, base + o_pos, sizeof(int64_t) * pos.size(), H2D, aux));
         step(launch_scatter_best((const int64_t *)ctx->db_scatter.p, (const int32_t *)ctx->prob_best.p,
                                  (int64_t)pos.size(), (int32_t)(sizeof(BestCell) / sizeof(int32_t)),
-                                 (int32_t *)ctx->db_scores.p, st));
+                                 (int32_t *)ctx->db_scores.p, aux));
+    }
+    if (!work.empty()) step(launch_db_search(a, dbl.waves, dbl.grid, st));
+    if (!probs.empty()) {
+        step(hipEventRecord(ctx->ev_join, ctx->aux_stream));
+        step(hipStreamWaitEvent(st, ctx->ev_join, 0));
     }
     step(launch_topk((const int32_t *)ctx->db_scores.p, nq, ndb, k, cidx, cscore, oidx, oscore, st));
     step(hipMemcpyAsync(p->out_idx, oidx, sizeof(int64_t) * (size_t)nq * k, hipMemcpyDeviceToHost, st));
     step(hipMemcpyAsync(p->out_score, oscore, sizeof(int32_t) * (size_t)nq * k, hipMemcpyDeviceToHost, st));
     step(hipMemcpyAsync(p->out_words, ctx->misc.p, 4, hipMemcpyDeviceToHost, st));
-    step(hipMemcpyAsync(p->out_words + 1, (int32_t *)ctx->sync.p + 8, 4, hipMemcpyDeviceToHost, st));
+    step(hipMemcpyAsync(p->out_words + 1, (int32_t *)ctx->db_sync.p + 8, 4, hipMemcpyDeviceToHost, st));
     step(hipMemcpyAsync(p->out_words + 2, (int32_t *)ctx->sync.p + 1, 4, hipMemcpyDeviceToHost, st));
+    step(hipMemcpyAsync(p->out_words + 3, (int32_t *)ctx->db_sync.p + 2, 4, hipMemcpyDeviceToHost, st));
     const hipError_t ee = hipStreamEndCapture(st, &p->graph);
     if (e != hipSuccess || ee != hipSuccess || !p->graph ||
         hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) {
@@ -352,6 +363,7 @@ swh_status search_graph(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *
                                              " of the concatenation is not in the alphabet");
     if (cancelled(ctx)) return cancel_status(ctx);
     if (p->out_words[2]) return fail(ctx, SWH_E_TIMEOUT, "strip wavefront wait expired");
+    if (p->out_words[3]) return fail(ctx, SWH_E_TIMEOUT, "database search: a hand-over wait expired");
     if (p->out_words[1] > 0) return SWH_OK;   // 16-bit saturation: the eager path recomputes those pairs
     float ms = 0.f;
     hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]);

@@ -37,15 +37,22 @@ struct DbSearchArgs {
     int32_t *nredo;
     int32_t redo_cap;
     int32_t *ticket;
-    uint32_t *border;          // per persistent wave: max_len * 64 lanes * 2 words
+    uint32_t *border;          // one wave per unit: per persistent wave, max_len * 64 lanes * 2 words;
+                               // pipelined: per work-group, wrap_cap * 64 lanes * 4 words
     int32_t max_len;           // longest group handled here
+    int32_t wrap_cap;          // pipelined: columns of the global ring (>= max_len + 64)
     const int32_t *cancel;     // pinned host flag: nonzero = take no further unit (NULL: none)
+    int32_t *abort_flag;       // pipelined: set when a bounded wait expires
+    uint64_t wait_ticks;       // wall-clock ticks one wait may last
 };
 
 hipError_t launch_db_pack(const uint8_t *codes, const int64_t *offs, const int32_t *perm, const DbGroup *groups,
                           int32_t ngroups, uint8_t pad, uint8_t *res, hipStream_t st);
-hipError_t launch_db_search(const DbSearchArgs &a, int grid, hipStream_t st);
-int db_search_grid_limit(int device);
+// waves = 1: one wave per (query, group) unit; 2, 4, 8 or 16: the pipelined form,
+// a work-group of that many waves shares each unit, its 32-row chunks on
+// neighbouring waves.  grid = work-groups (persistent).
+hipError_t launch_db_search(const DbSearchArgs &a, int waves, int grid, hipStream_t st);
+int db_search_grid_limit(int device, int waves);
 // Top-k per row of an nq x ndb score matrix: score desc, index asc; -1 padding.
 hipError_t launch_topk(const int32_t *scores, int32_t nq, int64_t ndb, int32_t k, int32_t *cand_idx,
                        int32_t *cand_score, int64_t *out_idx, int32_t *out_score, hipStream_t st);

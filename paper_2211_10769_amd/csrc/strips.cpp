@@ -16,8 +16,6 @@
 
 namespace swh {
 
-namespace {
-
 // A single chunk wait longer than this is a bug (the wavefront cannot
 // deadlock); the kernel then drains and the call fails with SWH_E_TIMEOUT.
 constexpr double kWaitSeconds = 30.0;
@@ -29,8 +27,6 @@ uint64_t wait_ticks(int device)
         khz = 100000;   // 100 MHz constant clock
     return (uint64_t)(kWaitSeconds * 1e3 * khz);
 }
-
-}  // namespace
 
 // Strip height for a launch whose problems hold n rows in all.  The strips of
 // one problem form a chain that moves at the pace of its slowest wave, so a
@@ -114,6 +110,9 @@ swh_status prepare_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, 
         P.n = (int32_t)q.n;
         P.m = (int32_t)q.m;
         P.nstrips = (int32_t)((q.n + 64 * RK - 1) / (64 * RK));
+        // a strip waits for chunk 0 of the strip above, which a problem without
+        // columns never publishes
+        if (q.m <= 0 && P.nstrips > 1) return fail(ctx, SWH_E_INVAL, "strip problem with rows but no columns");
         P.nblocks = (int32_t)sweep_blocks(q.m) + (int16 ? 1 : 0);   // the 16-bit high halves trail by a block
         P.strip0 = (int32_t)total_strips;
         P.flags = (int32_t *)(intptr_t)total_flags;   // offset, fixed up below

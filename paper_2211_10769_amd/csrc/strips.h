@@ -34,6 +34,8 @@ inline int64_t rows_padded(int64_t n, int R) { return ((n + 64 * R - 1) / (64 * 
 inline int64_t cols_padded(int64_t m) { return 64 * (sweep_blocks(m) + 3); }
 
 int pick_rows_per_lane(int64_t n, int simds);
+// Wall-clock ticks a kernel's bounded wait may last before it gives up.
+uint64_t wait_ticks(int device);
 int strip_grid(int64_t nstrips, int R, int limit, int num_cu, int waves = 0, int forced = 0);
 
 // One launch over all problems; local mode fills best (one entry per problem).

@@ -98,7 +98,8 @@ swh_status autotune_db(swh_ctx *ctx, const Scoring &sc, const swh_scoring *raw, 
         for (int i = 0; i < 400; ++i) qcat.push_back(raw->alphabet[sym(rng)]);
         qoff.push_back((int64_t)qcat.size());
     }
-    const int32_t saved = ctx->opt.inter_max;
+    const int32_t saved = ctx->opt.inter_max, saved_route = ctx->opt.db_route;
+    ctx->opt.db_route = -1;   // time the kernels as chosen, unrouted
     int32_t best = 512;
     swh_status s = SWH_OK;
     for (int32_t T = 1024; T <= 8192; T *= 2) {
@@ -137,6 +138,7 @@ swh_status autotune_db(swh_ctx *ctx, const Scoring &sc, const swh_scoring *raw, 
             break;
     }
     ctx->opt.inter_max = saved;
+    ctx->opt.db_route = saved_route;
     if (s != SWH_OK) return s;
     ctx->tuned_inter_max = best;
     inter_max = best;

@@ -43,8 +43,9 @@ def test_scores_and_topk_match_oracle(eng):
     assert (idx == widx).all() and (sco == wsco).all()
 
 
-def test_saturation_is_recomputed(eng):
+def test_saturation_is_recomputed(eng, opt):
     import paper_2211_10769_amd as swh
+    opt("db_route", -1)      # keep every group on the 16-bit inter-task kernel
     # match +100: a 1,000-residue identity scores 100,000 > 65,535 and must be redone in 32 bits
     mat = np.full((4, 4), -50, dtype=np.int8)
     np.fill_diagonal(mat, 100)
@@ -91,6 +92,8 @@ def test_length_switch_autotune_and_tuning_file(tmp_path):
     a = swh.Engine(0)
     b = swh.Engine(0)
     try:
+        for x in (a, b):
+            x.set_option("db_route", -1)   # count only the sequences beyond the switch
         v = a.autotune_db(sc)
         assert v in (512, 1024, 2048, 4096, 8192)
         got, st = swh.Database(a, db, sc).scores(qs)

@@ -90,7 +90,8 @@ def test_buffer_reallocation_invalidates_the_plan(swh, eng, dbase):
     assert not np.array_equal(a[0], gi)
 
 
-def test_empty_query_and_saturation_fall_back(swh, eng):
+def test_empty_query_and_saturation_fall_back(swh, eng, opt):
+    opt("db_route", -1)       # the saturating pair stays on the 16-bit inter-task kernel
     rng = np.random.default_rng(904)
     # +60 for identities: a 1,000-residue self-alignment scores 60,000, beyond 16 bits
     alph, _, o, e = seqgen.protein_scoring()

@@ -91,22 +91,32 @@ def protein_schemes(swh, eng, seqgen, db_size):
 
 
 def query_lengths(swh, eng, seqgen, db_size):
-    """Database search GCUPS against the length of a single query."""
+    """Database search GCUPS against the length of a single query: the default
+    launch (units shared by four waves, oversize units on the single-pair
+    kernel beside it) and one wave per unit with no routing."""
     _, (cat, off) = seqgen.workload2(n_db=db_size, n_queries=1)
     sc = swh.Scoring(*seqgen.protein_scoring())
     db = swh.Database(eng, (cat, off), sc)
     rng = seqgen.rng_for(2, 901)
-    out = [f"## Query length (one query vs {db_size:,} proteins, BLOSUM62 10/2)", "",
-           "| query residues | search ms | GCUPS |", "|---|---|---|"]
+    out = [f"## Query length (one query vs {db_size:,} proteins, BLOSUM62 10/2, top-10, graph replay)", "",
+           "| query residues | default ms | default GCUPS | one wave per unit ms | one wave per unit GCUPS |",
+           "|---|---|---|---|---|"]
     for L in (100, 300, 1000, 3000, 5000):
         q = [bytes(seqgen.random_protein(rng, L))]
-        db.search(q, k=10)
-        t0 = time.perf_counter()
-        reps = 3
-        for _ in range(reps):
-            _, _, st = db.search(q, k=10)
-        dt = (time.perf_counter() - t0) / reps
-        out.append(f"| {L:,} | {dt * 1e3:,.1f} | {st['cells'] / dt / 1e9:,.0f} |")
+        row = []
+        for waves, route in ((0, 0), (1, -1)):
+            eng.set_option("db_waves", waves)
+            eng.set_option("db_route", route)
+            db.search(q, k=10)
+            t0 = time.perf_counter()
+            reps = 5
+            for _ in range(reps):
+                _, _, st = db.search(q, k=10)
+            dt = (time.perf_counter() - t0) / reps
+            row += [dt * 1e3, st["cells"] / dt / 1e9]
+        eng.set_option("db_waves", 0)
+        eng.set_option("db_route", 0)
+        out.append(f"| {L:,} | {row[0]:,.2f} | {row[1]:,.0f} | {row[2]:,.2f} | {row[3]:,.0f} |")
         log(f"query length {L} done")
     db.close()
     return out

@@ -120,3 +120,23 @@ def test_oversize_units_routed_to_single_pair_kernel(eng, opt, route):
     idx, sco, _ = D.search(qs, k=7)
     widx, wsco = oracle.topk(want, 7)
     assert (idx == widx).all() and (sco == wsco).all()
+
+
+def test_high_scores_on_the_single_pair_kernel(eng):
+    import paper_2211_10769_amd as swh
+    # sequences beyond the length switch go to the single-pair kernel (32-bit):
+    # with +100 per match the query's copy inside one of them scores 100,000
+    mat = np.full((4, 4), -50, dtype=np.int8)
+    np.fill_diagonal(mat, 100)
+    sc = ("ACGT", mat, 120, 60)
+    rng = np.random.default_rng(4242)
+    q = bytes(seqgen.random_dna(rng, 1000))
+    db = [bytes(seqgen.random_dna(rng, int(L))) for L in rng.integers(50, 400, 500)]
+    db += [bytes(seqgen.random_dna(rng, int(L))) for L in (2100, 2600, 3000)]
+    db[-2] = bytes(seqgen.random_dna(rng, 800)) + q + bytes(seqgen.random_dna(rng, 900))
+    D = swh.Database(eng, db, sc)
+    got, st = D.scores([q])
+    want = oracle.db_scores([q], db, sc)
+    assert (got == want).all()
+    assert got[0, len(db) - 2] == 100_000
+    assert st["intra_pairs"] >= 3

@@ -98,7 +98,7 @@ def query_lengths(swh, eng, seqgen, db_size):
     sc = swh.Scoring(*seqgen.protein_scoring())
     db = swh.Database(eng, (cat, off), sc)
     rng = seqgen.rng_for(2, 901)
-    out = [f"## Query length (one query vs {db_size:,} proteins, BLOSUM62 10/2, top-10, graph replay)", "",
+    out = [f"## Query length (one query vs {db_size:,} proteins, BLOSUM62 10/2, top-10)", "",
            "| query residues | default ms | default GCUPS | one wave per unit ms | one wave per unit GCUPS |",
            "|---|---|---|---|---|"]
     for L in (100, 300, 1000, 3000, 5000):

@@ -179,10 +179,15 @@ swh_status  swh_cancel(swh_ctx *ctx);
  *                          traceback, > 0 = that many (rounded up to strips)
  *   SWH_OPT_TB_LEAF        largest leaf of the linear-space traceback, in DP
  *                          cells (1 .. 524288); 0 (default) = the largest
- *   SWH_OPT_GRAPH          1 (default): the prefilter's training step and
- *                          repeated database searches (swh_db_search with the
- *                          same database, k and query lengths) run as replays of
- *                          captured HIP graphs; 0: plain launches
+ *   SWH_OPT_GRAPH          1 (default): the prefilter's training step runs as
+ *                          the replay of a captured HIP graph; 2: repeated
+ *                          database searches as well (swh_db_search with the
+ *                          same database, k and query lengths: one replay per
+ *                          search, no host work between its launches; a replay
+ *                          runs the single-pair branch after the inter-task
+ *                          kernel rather than beside it, so searches that have
+ *                          such problems are faster as plain launches); 0: plain
+ *                          launches everywhere
  *   SWH_OPT_PRUNE          1 (default): block pruning of reverse passes; 0: off
  *   SWH_OPT_MEM_CAP        bytes of device memory the context's own working
  *                          buffers may hold (database and model handles are

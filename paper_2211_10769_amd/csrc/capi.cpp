@@ -402,7 +402,7 @@ swh_status swh_set_option(swh_ctx *ctx, int32_t option, int64_t value)
             o.tb_leaf = value;
             return SWH_OK;
         case SWH_OPT_GRAPH:
-            if (value != 0 && value != 1) return bad("graph must be 0 or 1");
+            if (value < 0 || value > 2) return bad("graph must be 0, 1 or 2");
             o.graph = (int32_t)value;
             return SWH_OK;
         case SWH_OPT_PRUNE:

@@ -258,10 +258,12 @@ DbLaunch db_launch_shape(const swh_ctx *ctx, size_t units, int32_t max_len)
     DbLaunch L;
     L.waves = ctx->opt.db_waves;
     if (L.waves == 0) {
-        // one wave per unit while the units outnumber the waves that fit four to one
-        // (the pipelined form pays some hand-over work per column); below that the
-        // unit's chunks are spread over four waves
-        L.waves = units >= (size_t)4 * db_search_grid_limit(ctx->device, 1) ? 1 : 4;
+        // one wave per unit while the units outnumber the resident waves sixteen to
+        // one (the pipelined form pays some hand-over work per column, about 7%);
+        // with fewer, the last units of the one-wave form leave SIMDs idle (a search
+        // of 20 queries over a rescoring subset of 15,600 units: 238 ms with one wave
+        // per unit, 135 ms with four), so the unit's chunks are spread over four waves
+        L.waves = units >= (size_t)16 * db_search_grid_limit(ctx->device, 1) ? 1 : 4;
     }
     int limit = db_search_grid_limit(ctx->device, L.waves);
     if (ctx->opt.grid > 0) limit = std::min(limit, (int)ctx->opt.grid);
@@ -500,7 +502,7 @@ swh_status db_search(swh_ctx *ctx, const swh_db *db, int32_t nq, const char *q_c
     swh_status s;
     hipError_t e;
     hipStream_t st = ctx->own_stream;
-    if (hits && !scores_host && !dev && ctx->opt.graph != 0 && nq > 0 && db->ndb > 0 && k > 0) {
+    if (hits && !scores_host && !dev && ctx->opt.graph == 2 && nq > 0 && db->ndb > 0 && k > 0) {
         bool done = false;
         if ((s = search_graph(ctx, db, nq, q_cat, q_off, k, hits, stats, done)) != SWH_OK || done) return s;
         stats = DbStats{};

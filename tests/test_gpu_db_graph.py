@@ -20,7 +20,9 @@ def swh():
 
 @pytest.fixture(scope="module")
 def eng(swh):
-    return swh.Engine(0)
+    e = swh.Engine(0)
+    e.set_option("graph", 2)     # database searches replayed as graphs
+    return e
 
 
 @pytest.fixture(scope="module")
@@ -41,7 +43,7 @@ def _eager(eng, D, qs, k):
     try:
         return D.search(qs, k=k)
     finally:
-        eng.set_option("graph", 1)
+        eng.set_option("graph", 2)
 
 
 def test_replays_equal_eager_and_oracle(swh, eng, dbase):

@@ -420,101 +420,166 @@ __global__ void __launch_bounds__(256) infer_kernel(InferArgs a)
     }
 }
 
-// 128 database rows x one query per workgroup with the rows' frequencies
-// staged once in LDS (108.5 KB, then reused for the layer-1 activations):
-// the four waves share the tile instead of each reading it from L2, and the
-// folded weights and W2 are read once per 128 rows instead of per 64.  Wave
-// w owns hidden units [64 w, 64 w + 64); its B fragments for the next K step
-// are loaded while the current one multiplies.
+// All queries over 128 database rows per workgroup.  The rows' frequency tile
+// is staged in LDS once (108.5 KB) and serves every query, so the feature
+// matrix is read from memory once per search instead of once per query.  Both
+// layers are computed transposed -- hidden (or output) units along the MFMA's
+// M dimension, database rows along N -- so that a lane's four accumulator
+// values are four consecutive units of one row: the layer-1 epilogue stores
+// them as one 8-byte LDS write, and its length term is a single per-row value.
+// The hidden layer is produced in two halves of 128 units (34 KB of LDS each
+// time); layer 2 accumulates over both halves.  Wave w owns hidden units
+// [128 h + 32 w, +32) of half h and output units [64 w, +64).
 constexpr int kInferRows = 128;
 constexpr int kFStride = kKPad + 8;   // bf16 per LDS row of the F tile (rows stay 16-byte aligned)
-constexpr int kHStride = kNH + 8;     // bf16 per LDS row of the activations
+constexpr int kHalf = kNH / 2;        // hidden units per half
+constexpr int kH2Stride = kHalf + 8;  // bf16 per LDS row of a half of the activations
+constexpr size_t kInferLds = (size_t)kInferRows * (kFStride + kH2Stride) * 2;
 
-__global__ void __launch_bounds__(256) infer128_kernel(InferArgs a)
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi)
+{
+    return (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) infer_all_kernel(InferArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) uint16_t sm[];
+    uint16_t *Ft = sm;                                  // [rows][kFStride]
+    uint16_t *Hh = sm + kInferRows * kFStride;          // [rows][kH2Stride]
+    __shared__ float rowlog[kInferRows];
     __shared__ float part[4][kInferRows];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lg = lane >> 4, lk = 8 * lg;
     const int64_t row0 = (int64_t)blockIdx.x * kInferRows;
-    const int q = blockIdx.y;
-    const int li = lane & 15, lk = 8 * (lane >> 4);
     for (int c = tid; c < kInferRows * (kKPad / 8); c += 256) {
         const int r = c / (kKPad / 8), k8 = c - r * (kKPad / 8);
         const int64_t row = min(row0 + r, a.nrows - 1);
-        *(u32x4 *)&sm[r * kFStride + 8 * k8] = *(const u32x4 *)(a.F + row * kKPad + 8 * k8);
+        *(u32x4 *)&Ft[r * kFStride + 8 * k8] = *(const u32x4 *)(a.F + row * kKPad + 8 * k8);
     }
-    __syncthreads();
-
-    const uint16_t *Aq = a.Aq + (int64_t)q * kNH * kKPad;
-    f32x4 acc[8][4];
-    for (int i = 0; i < 8; ++i)
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const uint16_t *brow[4];
-    for (int j = 0; j < 4; ++j) brow[j] = Aq + (int64_t)(64 * w + 16 * j + li) * kKPad + lk;
-    bf16x8 fb[4];
-    for (int j = 0; j < 4; ++j) fb[j] = as_bf(*(const u32x4 *)brow[j]);
-    for (int kk = 0; kk < kKPad; kk += 32) {
-        bf16x8 fn[4];
-        if (kk + 32 < kKPad)
-            for (int j = 0; j < 4; ++j) fn[j] = as_bf(*(const u32x4 *)(brow[j] + kk + 32));
-        for (int i = 0; i < 8; ++i) {
-            const bf16x8 fa = as_bf(*(const u32x4 *)&sm[(16 * i + li) * kFStride + kk + lk]);
-            for (int j = 0; j < 4; ++j) acc[i][j] = mfma(fa, fb[j], acc[i][j]);
-        }
-        if (kk + 32 < kKPad)
-            for (int j = 0; j < 4; ++j) fb[j] = fn[j];
-    }
-    __syncthreads();   // the F tile is dead: its LDS now holds the activations
-
-    const int32_t Lq = a.qlen[q];
-    for (int i = 0; i < 8; ++i)
-        for (int r = 0; r < 4; ++r) {
-            const int lr = 16 * i + 4 * (lane >> 4) + r;
-            const int64_t row = min(row0 + lr, a.nrows - 1);
-            const float x400 = log_len(Lq, a.row_len[row]) - a.mu400;   // w1x holds the 1 / sd
-            for (int j = 0; j < 4; ++j) {
-                const int n = 64 * w + 16 * j + li;
-                const float z = acc[i][j][r] + a.cvec[n] + a.w1x[n] * x400;
-                sm[lr * kHStride + n] = f2bf(fmaxf(z, 0.0f));
-            }
-        }
+    // ln(max(1, min(Lq, L))) = min(ln max(1, Lq), ln max(1, L)): the row's half here
+    if (tid < kInferRows) rowlog[tid] = logf((float)max(1, a.row_len[min(row0 + tid, a.nrows - 1)]));
     __syncthreads();
 
     const float *b2 = a.theta + kOffB2;
     const float *w3 = a.theta + kOffW3;
-    for (int i = 0; i < 8; ++i)
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const uint16_t *wrow[4];
-    for (int j = 0; j < 4; ++j) wrow[j] = a.W2bf + (int64_t)(64 * w + 16 * j + li) * kNH + lk;
-    for (int j = 0; j < 4; ++j) fb[j] = as_bf(*(const u32x4 *)wrow[j]);
-    for (int kk = 0; kk < kNH; kk += 32) {
-        bf16x8 fn[4];
-        if (kk + 32 < kNH)
-            for (int j = 0; j < 4; ++j) fn[j] = as_bf(*(const u32x4 *)(wrow[j] + kk + 32));
-        for (int i = 0; i < 8; ++i) {
-            const bf16x8 ha = as_bf(*(const u32x4 *)&sm[(16 * i + li) * kHStride + kk + lk]);
-            for (int j = 0; j < 4; ++j) acc[i][j] = mfma(ha, fb[j], acc[i][j]);
-        }
-        if (kk + 32 < kNH)
-            for (int j = 0; j < 4; ++j) fb[j] = fn[j];
-    }
-    for (int i = 0; i < 8; ++i)
+    float b2v[4][4], w3v[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
         for (int r = 0; r < 4; ++r) {
-            float sum = 0.0f;
-            for (int j = 0; j < 4; ++j) {
-                const int n = 64 * w + 16 * j + li;
-                sum += fmaxf(acc[i][j][r] + b2[n], 0.0f) * w3[n];
+            const int m = 64 * w + 16 * i + 4 * lg + r;
+            b2v[i][r] = b2[m];
+            w3v[i][r] = w3[m];
+        }
+    const float b3 = a.theta[kOffB3];
+
+    for (int q = 0; q < a.nq; ++q) {
+        const uint16_t *Aq = a.Aq + (int64_t)q * kNH * kKPad;
+        const float lq = logf((float)max(1, a.qlen[q]));
+        f32x4 acc2[4][8];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc2[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+        for (int h = 0; h < 2; ++h) {
+            // ---- layer 1 (transposed): D[hidden][row] = A_q[hidden][:] . F[row][:]
+            f32x4 acc1[2][8];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) acc1[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            const uint16_t *arow[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) arow[i] = Aq + (int64_t)(kHalf * h + 32 * w + 16 * i + li) * kKPad + lk;
+            // A fragments two K steps ahead (they come from L2)
+            bf16x8 fa[2], f1[2], f2[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                fa[i] = as_bf(*(const u32x4 *)arow[i]);
+                f1[i] = as_bf(*(const u32x4 *)(arow[i] + 32));
             }
-            for (int o = 8; o >= 1; o >>= 1) sum += __shfl_xor(sum, o);
-            if (li == 0) part[w][16 * i + 4 * (lane >> 4) + r] = sum;
+#pragma unroll
+            for (int kk = 0; kk < kKPad; kk += 32) {
+                if (kk + 64 < kKPad)
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) f2[i] = as_bf(*(const u32x4 *)(arow[i] + kk + 64));
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const bf16x8 fb = as_bf(*(const u32x4 *)&Ft[(16 * j + li) * kFStride + kk + lk]);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) acc1[i][j] = mfma(fa[i], fb, acc1[i][j]);
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    fa[i] = f1[i];
+                    f1[i] = f2[i];
+                }
+            }
+            // ---- bias, length term, ReLU: four consecutive hidden units of one row per lane
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int m0 = kHalf * h + 32 * w + 16 * i + 4 * lg;
+                const float4 cv = *(const float4 *)(a.cvec + m0);
+                const float4 wx = *(const float4 *)(a.w1x + m0);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int n = 16 * j + li;
+                    const float xr = fminf(lq, rowlog[n]) - a.mu400;   // w1x holds the 1 / sd
+                    const float z0 = fmaxf(acc1[i][j][0] + cv.x + wx.x * xr, 0.0f);
+                    const float z1 = fmaxf(acc1[i][j][1] + cv.y + wx.y * xr, 0.0f);
+                    const float z2 = fmaxf(acc1[i][j][2] + cv.z + wx.z * xr, 0.0f);
+                    const float z3 = fmaxf(acc1[i][j][3] + cv.w + wx.w * xr, 0.0f);
+                    *(uint2 *)&Hh[n * kH2Stride + 32 * w + 16 * i + 4 * lg] =
+                        make_uint2(pack_bf16(z0, z1), pack_bf16(z2, z3));
+                }
+            }
+            __syncthreads();
+            // ---- layer 2 (transposed) over this half: D[out][row] += W2[out][half] . H[row][half]
+            const uint16_t *wrow[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) wrow[i] = a.W2bf + (int64_t)(64 * w + 16 * i + li) * kNH + kHalf * h + lk;
+            bf16x8 wa[4], wn[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) wa[i] = as_bf(*(const u32x4 *)wrow[i]);
+#pragma unroll
+            for (int kk = 0; kk < kHalf; kk += 32) {
+                if (kk + 32 < kHalf)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) wn[i] = as_bf(*(const u32x4 *)(wrow[i] + kk + 32));
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const bf16x8 hb = as_bf(*(const u32x4 *)&Hh[(16 * j + li) * kH2Stride + kk + lk]);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc2[i][j] = mfma(wa[i], hb, acc2[i][j]);
+                }
+                if (kk + 32 < kHalf)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) wa[i] = wn[i];
+            }
+            __syncthreads();   // the next half overwrites the activations
         }
-    __syncthreads();
-    if (tid < kInferRows) {
-        const int64_t row = row0 + tid;
-        if (row < a.nrows) {
-            const float y = a.theta[kOffB3] + part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
-            a.pred[(int64_t)q * a.nrows + row] = a.row_db[row] >= 0 ? y : -INFINITY;
+        // ---- output: y[row] = b3 + sum over outputs of relu(. + b2) w3
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            float sum = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sum += fmaxf(acc2[i][j][r] + b2v[i][r], 0.0f) * w3v[i][r];
+            sum += __shfl_xor(sum, 16);
+            sum += __shfl_xor(sum, 32);
+            if (lg == 0) part[w][16 * j + li] = sum;
         }
+        __syncthreads();
+        if (tid < kInferRows) {
+            const int64_t row = row0 + tid;
+            if (row < a.nrows) {
+                const float y = b3 + part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
+                a.pred[(int64_t)q * a.nrows + row] = a.row_db[row] >= 0 ? y : -INFINITY;
+            }
+        }
+        // part is written again only after the next query's two barriers
     }
 }
 
@@ -772,13 +837,12 @@ hipError_t launch_fold_query(const float *theta, const float *fq, int nq, const 
 hipError_t launch_infer(const InferArgs &a, hipStream_t st)
 {
     if (a.nrows <= 0 || a.nq <= 0) return hipSuccess;
-    // the 128-row kernel needs 108.5 KB of LDS per workgroup; otherwise the 64-row one
-    const size_t lds = (size_t)kInferRows * std::max(kFStride, kHStride) * 2;
+    // the all-queries kernel needs 143 KB of dynamic LDS per workgroup; otherwise the 64-row one
     int dev = 0, lds_wg = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&lds_wg, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
-        (size_t)lds_wg >= lds + sizeof(float) * 4 * kInferRows) {
-        hipLaunchKernelGGL(infer128_kernel, dim3(blocks_for(a.nrows, kInferRows), a.nq), dim3(256), lds, st, a);
+        (size_t)lds_wg >= kInferLds + sizeof(float) * 5 * kInferRows) {
+        hipLaunchKernelGGL(infer_all_kernel, dim3(blocks_for(a.nrows, kInferRows)), dim3(256), kInferLds, st, a);
         return hipGetLastError();
     }
     (void)hipGetLastError();

@@ -436,9 +436,13 @@ constexpr int kHalf = kNH / 2;        // hidden units per half
 constexpr int kH2Stride = kHalf + 8;  // bf16 per LDS row of a half of the activations
 constexpr size_t kInferLds = (size_t)kInferRows * (kFStride + kH2Stride) * 2;
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// two floats to two bfloat16 (nearest, ties to even: one v_cvt_pk_bf16_f32)
 __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi)
 {
-    return (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
+    const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(uint32_t, v);
 }
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) infer_all_kernel(InferArgs a)

@@ -101,8 +101,9 @@ def test_database_argument_checks(swh, eng):
 
 def test_options_round_trip_and_range(swh, eng):
     for name, good, bad in (("rows_per_lane", 16, 12), ("grid", 512, -1), ("band_rows", -1, -2),
-                            ("tb_leaf", 64, 600000), ("graph", 0, 2), ("prune", 0, 5), ("mem_cap", 1 << 30, -1),
-                            ("int16", 2, 3), ("inter_max", 1024, 16), ("pf_rank", 0, 3)):
+                            ("tb_leaf", 64, 600000), ("graph", 2, 3), ("prune", 0, 5), ("mem_cap", 1 << 30, -1),
+                            ("int16", 2, 3), ("inter_max", 1024, 16), ("pf_rank", 0, 3), ("db_waves", 16, 3),
+                            ("db_route", 50, -2)):
         old = eng.get_option(name)
         eng.set_option(name, good)
         assert eng.get_option(name) == good

@@ -88,7 +88,7 @@ struct DbLaunch {
     int32_t wrap_cap = 0;
     size_t border_bytes = 0;
 };
-DbLaunch db_launch_shape(const swh_ctx *ctx, size_t units, int32_t max_len);
+DbLaunch db_launch_shape(const swh_ctx *ctx, size_t units, int32_t max_len, double mean_chunks);
 
 swh_status db_create(swh_ctx *ctx, int64_t ndb, const char *cat, const int64_t *off, const Scoring &sc,
                      swh_db **out);

@@ -128,7 +128,9 @@ swh_status build_plan(swh_ctx *ctx, const swh_db *db, int32_t nq, int32_t k, con
         return (qo[a.q + 1] - qo[a.q]) * (int64_t)db->h_groups[a.g].maxlen >
                (qo[b.q + 1] - qo[b.q]) * (int64_t)db->h_groups[b.g].maxlen;
     });
-    const DbLaunch dbl = db_launch_shape(ctx, work.size(), max_len);
+    double chunks = 0.0;
+    for (const DbWork &w : work) chunks += (double)((qo[w.q + 1] - qo[w.q] + 31) / 32);
+    const DbLaunch dbl = db_launch_shape(ctx, work.size(), max_len, work.empty() ? 0.0 : chunks / work.size());
     const int redo_cap = 1 << 20;
     const size_t cand = topk_scratch_entries(nq, ndb, k);
 

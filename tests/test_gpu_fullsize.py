@@ -1,9 +1,9 @@
 """Parity at the benchmark's own sizes, in the launch configurations bench.py
 times: the database search of 20 queries against 500,000 proteins and the
-batch of 20,000 read/reference pairs.  The oracle cannot score everything at
+batch of 200,000 read/reference pairs.  The oracle cannot score everything at
 these sizes, so it checks sampled outputs one by one (every top-10 hit and
 random query/database pairs; random pairs of the batch, CIGARs included), and
-every pair of the batch is checked by properties that hold at any size."""
+pairs of the batch are checked by properties that hold at any size."""
 import re
 
 import numpy as np
@@ -65,16 +65,20 @@ def _rescore(q, t, r, scoring):
 
 
 def test_batch_of_read_pairs_bench_config(eng):
-    pairs = seqgen.workload4(n_pairs=20_000)
+    # all 200,000 pairs of the bench's batched leg in one call (its chunking,
+    # 16-bit passes and kept-row groups as timed)
+    pairs = seqgen.workload4(n_pairs=200_000)
     qs = [bytes(p[0]) for p in pairs]
     ts = [bytes(p[1]) for p in pairs]
     del pairs
     sc = seqgen.dna_scoring()
     got = eng.align_batch(qs, ts, sc, mode="cigar")
-    # properties on every pair: the CIGAR spans the reported rectangle, starts
-    # and ends with a match run, and rescores to the reported optimum
-    for i, r in enumerate(got):
-        assert r["score"] > 0, i
+    assert len(got) == len(qs) and all(r["score"] > 0 for r in got)
+    # properties on 20,000 pairs drawn at random: the CIGAR spans the reported
+    # rectangle, starts and ends with a match run, and rescores to the optimum
+    rng = np.random.default_rng(11)
+    for i in rng.choice(len(qs), size=20_000, replace=False):
+        r = got[i]
         assert r["cigar"][-1] == "M" and re.match(r"^\d+M", r["cigar"]), i
         total, spans = _rescore(qs[i], ts[i], r, sc)
         assert spans and total == r["score"], i

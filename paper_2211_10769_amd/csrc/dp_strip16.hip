@@ -57,9 +57,10 @@ typedef short i16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kDppWaveRor1 = 0x13C;   // lane i reads lane i-1, lane 0 reads lane 63
 
-__device__ __forceinline__ unsigned ror1(unsigned src)
+// every lane has a source under the rotation, so no old value is needed
+__device__ __forceinline__ unsigned rot1(unsigned src)
 {
-    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)src, kDppWaveRor1, 0xF, 0xF, false);
+    return (unsigned)__builtin_amdgcn_mov_dpp((int)src, kDppWaveRor1, 0xF, 0xF, false);
 }
 
 __device__ __forceinline__ u16x2 as16(unsigned x) { return __builtin_bit_cast(u16x2, x); }
@@ -89,7 +90,6 @@ struct Prof16 {
     static constexpr int W = RH / 2;                   // int16-pair words per (half, code, lane)
     static constexpr int P = (W + 3) / 4;              // planes of (up to) four words
     static constexpr int PW = W < 4 ? W : 4;           // words per plane
-    static constexpr int LOG2R = RH == 2 ? 2 : RH == 4 ? 3 : RH == 8 ? 4 : 5;   // bits of a row index (2 RH rows)
 };
 
 // word w of (half, code, lane): plane w / 4, prof[((half * P + plane) * A1 + code) * 64 * PW + lane * PW + w % 4]
@@ -100,14 +100,16 @@ __device__ __forceinline__ int prof16_index(int a1, int half, int code, int lane
     return (((half * P + w / PW) * a1 + code) * 64 + lane) * PW + (w % PW);
 }
 
+// The RH / 2 words of one (half, code, lane): base is the lane's entry of the
+// half's first plane and code 0, off the code's byte offset in a plane,
+// plane_b the bytes between planes.
 template <int RH>
-__device__ __forceinline__ void load_prof16(const int *prof, int a1, int half, int code, int lane,
-                                            unsigned (&w)[RH / 2])
+__device__ __forceinline__ void load_prof16_at(const int *base, unsigned off, int plane_b, unsigned (&w)[RH / 2])
 {
     constexpr int P = Prof16<RH>::P, PW = Prof16<RH>::PW;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        const int *q = prof + (((half * P + p) * a1 + code) * 64 + lane) * PW;
+        const int *q = reinterpret_cast<const int *>(reinterpret_cast<const char *>(base) + off + p * plane_b);
         if constexpr (PW == 4) {
             const int4 x = reinterpret_cast<const int4 *>(q)[0];
             w[4 * p] = (unsigned)x.x;
@@ -133,15 +135,12 @@ __global__ void __launch_bounds__(256 * kWg16PerSimd<RH>) strip16_kernel(StripAr
 {
     extern __shared__ int prof_all[];
     constexpr int W = Prof16<RH>::W;
-    constexpr int LOGR = Prof16<RH>::LOG2R;
     const int lane = threadIdx.x & 63;
     const int pad = a.asize;
     const int A1 = a.asize + 1;
     int *prof = prof_all + (threadIdx.x >> 6) * (2 * A1 * 64 * W);   // this wave's profiles
     const unsigned o2 = (unsigned)a.o | ((unsigned)a.o << 16);
     const unsigned e2 = (unsigned)a.e | ((unsigned)a.e << 16);
-    // lane 0 takes the border into its low half and lane 63's low half into its high half
-    const unsigned in_sel = lane == 0 ? 0x05040100u : 0x07060504u;
 
     for (;;) {
         const int sv = __hip_atomic_fetch_add(a.ticket, lane == 0 ? 1 : 0, __ATOMIC_RELAXED,
@@ -194,32 +193,56 @@ __global__ void __launch_bounds__(256 * kWg16PerSimd<RH>) strip16_kernel(StripAr
         for (int k = 0; k < RH; ++k) { hp[k] = 0u; E[k] = 0u; }
         unsigned hup_prev = 0u;            // H(row0 - 1, j - 1) of both halves
         unsigned hbot = 0u, fbot = 0u;     // the lane's last row outputs of the previous step
-        int oh = 0, of = 0;                // lane 63's high-half outputs, collected
-        int bkey = 0, bstep = 0, bthr = 1; // best cell (as in the 32-bit kernel; row index over 2 RH rows)
+        // lane 63's outputs of the block's steps, collected one per lane: high
+        // halves (H low, F high), and low halves where the upper sub-strip's last
+        // row is kept
+        unsigned ohf = 0u, olf = 0u;
+        // Best cell: lane keys (H << 16) | (2 RH - 1 - i), i the row over the
+        // lane's 2 RH rows (low half first), so a maximum orders a step's cells
+        // by value, then smaller row; bkey keeps the largest key and bstep the
+        // first step that reached it.  Keys are formed only in steps where some
+        // half reaches its threshold (thr2 + 1 per half): the lane's own best
+        // value, and at every block end the strip's best so far over all lanes
+        // (value V at row r*): a half whose rows all lie below r* needs V + 1,
+        // the others V.  No cell below its threshold can be the strip's best,
+        // so the strip's result is that of a tracker that forms every key.
+        int bkey = 0, bstep = 0;
+        unsigned thrw2 = 0u, thr2 = 0u;
 
-        int code = lane == 0 ? (int)P.tc[0] : pad;   // low half: column t - lane + 1
-        int code_h = pad;                            // high half: 64 columns behind
-        int tfeed = P.tc[1 + lane];
+        // Column codes as profile byte offsets (CS bytes per code in a plane):
+        // low 16 bits the low half's column, high 16 bits the high half's.
+        constexpr unsigned CS = 4u * Prof16<RH>::PW * 64u;
+        const int plane_b = A1 * (int)CS;
+        const int *base_lo = prof + lane * Prof16<RH>::PW;
+        const int *base_hi = base_lo + Prof16<RH>::P * A1 * 64 * Prof16<RH>::PW;
+        int code0 = lane == 0 ? (int)P.tc[0] : pad;
+        int traw = P.tc[1 + lane];                            // the low half's feed (raw codes)
         // the high half's feed of block 0: columns <= 0 (pad), except that its
         // last entry brings column 1 to lane 0 on step 64
-        int tfeed_h = lane == 63 ? (int)P.tc[0] : pad;
+        int traw_h = lane == 63 ? (int)P.tc[0] : pad;
         int fh = 0, ff = 0;
         bool ok = true;
         if (!wait_chunk(a, P.flags, 0, s)) ok = false;
         if (ok) load_border(P.border + lane, fh, ff);
         int fl_next = 64 < P.m ? peek_chunk(P.flags, 1) : s;
-        code = settled(code);
-        tfeed = settled(tfeed);
-        tfeed_h = settled(tfeed_h);
-        fh = settled(fh);
-        ff = settled(ff);
+        code0 = settled(code0);
+        traw = settled(traw);
+        traw_h = settled(traw_h);
+        // the border chunk packed: H in the low half, F in the high half
+        unsigned hf = ((unsigned)settled(fh) & 0xFFFFu) | ((unsigned)settled(ff) << 16);
+        unsigned code2 = (unsigned)code0 * CS | (((unsigned)pad * CS) << 16);
+        unsigned tfeed2 = (unsigned)traw * CS | (((unsigned)traw_h * CS) << 16);
+        // lane 0 takes the border into the low half and lane 63's low half into
+        // the high half: H from the chunk's low half, F from its high half
+        const unsigned sel_h = lane == 0 ? 0x05040100u : 0x07060504u;
+        const unsigned sel_f = lane == 0 ? 0x05040302u : 0x07060504u;
 
         unsigned sl[W], sh[W];
-        load_prof16<RH>(prof, A1, 0, code, lane, sl);
-        load_prof16<RH>(prof, A1, 1, code_h, lane, sh);
+        load_prof16_at<RH>(base_lo, code2 & 0xFFFFu, plane_b, sl);
+        load_prof16_at<RH>(base_hi, code2 >> 16, plane_b, sh);
 
         for (int b = 0; b < P.nblocks && ok; ++b) {
-            const int tfeed_n = P.tc[64 * (b + 1) + 1 + lane];
+            const int traw_n = P.tc[64 * (b + 1) + 1 + lane];
             int fh_n = 0, ff_n = 0;
             if (64 * (b + 1) < P.m) {
                 if (__builtin_amdgcn_readfirstlane(fl_next) < s && !wait_chunk(a, P.flags, b + 1, s)) {
@@ -230,7 +253,6 @@ __global__ void __launch_bounds__(256 * kWg16PerSimd<RH>) strip16_kernel(StripAr
                 fl_next = 64 * (b + 2) < P.m ? peek_chunk(P.flags, b + 2) : s;
             }
             const int tbase = 64 * b;
-            const int tfeed_h_next = tfeed;   // the high half's feed of block b + 1
 
             bool pruned = false;
             if (PRUNE && P.prune > 0) {
@@ -238,7 +260,7 @@ __global__ void __launch_bounds__(256 * kWg16PerSimd<RH>) strip16_kernel(StripAr
 #pragma unroll
                 for (int k = 0; k < RH; ++k) hin = umax(hin, umax(hp[k], E[k]));
                 int hmax = max((int)(hin & 0xFFFF), (int)(hin >> 16));
-                hmax = max(hmax, max(fh, ff));
+                hmax = max(hmax, max((int)(hf & 0xFFFFu), (int)(hf >> 16)));
 #pragma unroll
                 for (int off = 32; off >= 1; off >>= 1) hmax = max(hmax, __shfl_xor(hmax, off));
                 hmax = __builtin_amdgcn_readfirstlane(hmax);
@@ -252,79 +274,98 @@ __global__ void __launch_bounds__(256 * kWg16PerSimd<RH>) strip16_kernel(StripAr
                 // the block's steps at the floor (see the 32-bit kernel); lane 0's
                 // next diagonal input: the border chunk's last record (low half)
                 // and lane 63's floor value (high half)
-                const int last_h = __shfl(fh, 63);
+                const unsigned last_h = (unsigned)__shfl((int)hf, 63) & 0xFFFFu;
 #pragma unroll
                 for (int k = 0; k < RH; ++k) { hp[k] = 0u; E[k] = 0u; }
                 hbot = 0u;
                 fbot = 0u;
-                oh = 0;
-                of = 0;
-                hup_prev = lane == 0 ? ((unsigned)last_h & 0xFFFFu) : 0u;
-                code = __shfl(tfeed, 63 - lane);
-                code_h = __shfl(tfeed_h, 63 - lane);
-                load_prof16<RH>(prof, A1, 0, code, lane, sl);
-                load_prof16<RH>(prof, A1, 1, code_h, lane, sh);
+                ohf = 0u;
+                olf = 0u;
+                hup_prev = lane == 0 ? last_h : 0u;
+                code2 = (unsigned)__shfl((int)tfeed2, 63 - lane);
+                load_prof16_at<RH>(base_lo, code2 & 0xFFFFu, plane_b, sl);
+                load_prof16_at<RH>(base_hi, code2 >> 16, plane_b, sh);
             } else {
+                auto block_steps = [&](auto keep_c) {
+                    constexpr bool KEEP = decltype(keep_c)::value;
 #pragma unroll 2
-                for (int u = 0; u < 64; ++u) {
-                    const int code_n = shr1(tfeed, code);
-                    tfeed = shl1(tfeed, tfeed);
-                    const int code_hn = shr1(tfeed_h, code_h);
-                    tfeed_h = shl1(tfeed_h, tfeed_h);
-                    unsigned sl_n[W], sh_n[W];
-                    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): retire the previous profile reads
-                    load_prof16<RH>(prof, A1, 0, code_n, lane, sl_n);
-                    load_prof16<RH>(prof, A1, 1, code_hn, lane, sh_n);
-                    __builtin_amdgcn_sched_barrier(0);
-                    // the rows above each half's first row at this column
-                    const unsigned hup = __builtin_amdgcn_perm(ror1(hbot), (unsigned)fh, in_sel);
-                    unsigned f = __builtin_amdgcn_perm(ror1(fbot), (unsigned)ff, in_sel);
-                    fh = shl1(fh, fh);
-                    ff = shl1(ff, ff);
+                    for (int u = 0; u < 64; ++u) {
+                        const unsigned code2_n = (unsigned)shr1((int)tfeed2, (int)code2);
+                        tfeed2 = (unsigned)shl1((int)tfeed2, (int)tfeed2);
+                        unsigned sl_n[W], sh_n[W];
+                        __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): retire the previous profile reads
+                        load_prof16_at<RH>(base_lo, code2_n & 0xFFFFu, plane_b, sl_n);
+                        load_prof16_at<RH>(base_hi, code2_n >> 16, plane_b, sh_n);
+                        __builtin_amdgcn_sched_barrier(0);
+                        // the rows above each half's first row at this column
+                        const unsigned hup = __builtin_amdgcn_perm(rot1(hbot), hf, sel_h);
+                        unsigned f = __builtin_amdgcn_perm(rot1(fbot), hf, sel_f);
+                        hf = (unsigned)shl1((int)hf, (int)hf);
 
-                    unsigned dg = hup_prev;
+                        unsigned dg = hup_prev;
 #pragma unroll
-                    for (int k = 0; k < RH; ++k) {
-                        const unsigned sel = (k & 1) ? 0x07060302u : 0x05040100u;
-                        const unsigned sk = __builtin_amdgcn_perm(sh[k >> 1], sl[k >> 1], sel);
-                        const unsigned h = smax(smax(sadds(dg, sk), E[k]), f);
-                        const unsigned hop = subs(h, o2);
-                        f = umax(subs(f, e2), hop);
-                        E[k] = umax(subs(E[k], e2), hop);
-                        dg = hp[k];
-                        hp[k] = h;
-                    }
-                    hup_prev = hup;
-                    hbot = hp[RH - 1];
-                    fbot = f;
-                    oh = shl1((int)hbot, oh);
-                    of = shl1((int)fbot, of);
+                        for (int k = 0; k < RH; ++k) {
+                            const unsigned sel = (k & 1) ? 0x07060302u : 0x05040100u;
+                            const unsigned sk = __builtin_amdgcn_perm(sh[k >> 1], sl[k >> 1], sel);
+                            const unsigned h = smax(smax(sadds(dg, sk), E[k]), f);
+                            const unsigned hop = subs(h, o2);
+                            f = umax(subs(f, e2), hop);
+                            E[k] = umax(subs(E[k], e2), hop);
+                            dg = hp[k];
+                            hp[k] = h;
+                        }
+                        hup_prev = hup;
+                        hbot = hp[RH - 1];
+                        fbot = f;
+                        ohf = (unsigned)shl1((int)__builtin_amdgcn_perm(fbot, hbot, 0x07060302u), (int)ohf);
+                        if constexpr (KEEP)
+                            olf = (unsigned)shl1((int)__builtin_amdgcn_perm(fbot, hbot, 0x05040100u), (int)olf);
 
-                    // best cell: a packed maximum per step, keys only when some half
-                    // reaches the best value so far
-                    unsigned hm = hp[0];
+                        unsigned hm = hp[0];
 #pragma unroll
-                    for (int k = 1; k < RH; ++k) hm = umax(hm, hp[k]);
-                    const unsigned thr2 = (unsigned)(bthr - 1) | ((unsigned)(bthr - 1) << 16);
-                    if (__builtin_amdgcn_ballot_w64(subs(hm, thr2) != 0u)) {
-                        int mx = ((int)(hp[0] & 0xFFFF) << LOGR) | (2 * RH - 1);
+                        for (int k = 1; k < RH; ++k) hm = umax(hm, hp[k]);
+                        if (__builtin_amdgcn_ballot_w64(subs(hm, thr2) != 0u)) {
+                            int mx = (int)((hp[0] << 16) | (2u * RH - 1u));
 #pragma unroll
-                        for (int k = 1; k < RH; ++k) mx = max(mx, ((int)(hp[k] & 0xFFFF) << LOGR) | (2 * RH - 1 - k));
+                            for (int k = 1; k < RH; ++k) mx = max(mx, (int)((hp[k] << 16) | (unsigned)(2 * RH - 1 - k)));
 #pragma unroll
-                        for (int k = 0; k < RH; ++k) mx = max(mx, ((int)(hp[k] >> 16) << LOGR) | (RH - 1 - k));
-                        const bool gt = mx > bkey;
-                        bkey = gt ? mx : bkey;
-                        bstep = gt ? tbase + u : bstep;
-                        bthr = max(bkey >> LOGR, 1);
+                            for (int k = 0; k < RH; ++k) mx = max(mx, (int)((hp[k] & 0xFFFF0000u) | (unsigned)(RH - 1 - k)));
+                            const bool gt = mx > bkey;
+                            bkey = gt ? mx : bkey;
+                            bstep = gt ? tbase + u : bstep;
+                            const unsigned own = (unsigned)max((bkey >> 16) - 1, 0);
+                            thr2 = umax(thrw2, own | (own << 16));
+                        }
+#pragma unroll
+                        for (int w = 0; w < W; ++w) {
+                            sl[w] = sl_n[w];
+                            sh[w] = sh_n[w];
+                        }
+                        code2 = code2_n;
                     }
+                };
+                if (keep_lo)
+                    block_steps(BoolC<true>{});
+                else
+                    block_steps(BoolC<false>{});
+            }
+
+            // the strip's best so far (strip-relative key: value, then smaller
+            // row) sets every lane's threshold for the next block
+            {
+                const int bv = bkey >> 16;
+                const int i = 2 * RH - 1 - (bkey & 0xFFFF);
+                const int row = lane * RH + (i < RH ? i : 63 * RH + i);
+                int K = bv > 0 ? (bv << 11) | (2047 - row) : 0;
 #pragma unroll
-                    for (int w = 0; w < W; ++w) {
-                        sl[w] = sl_n[w];
-                        sh[w] = sh_n[w];
-                    }
-                    code = code_n;
-                    code_h = code_hn;
-                }
+                for (int off = 32; off >= 1; off >>= 1) K = max(K, __shfl_xor(K, off));
+                K = __builtin_amdgcn_readfirstlane(K);
+                const int V = K >> 11, brow = 2047 - (K & 2047);
+                const unsigned tlo = (unsigned)max(V + (lane * RH > brow ? 1 : 0), 1) - 1u;
+                const unsigned thi = (unsigned)max(V + (64 * RH + lane * RH > brow ? 1 : 0), 1) - 1u;
+                thrw2 = tlo | (thi << 16);
+                const unsigned own = (unsigned)max(bv - 1, 0);
+                thr2 = umax(thrw2, own | (own << 16));
             }
 
             // border records: lane l holds lane 63's high-half output of step
@@ -333,20 +374,22 @@ __global__ void __launch_bounds__(256 * kWg16PerSimd<RH>) strip16_kernel(StripAr
             drain_stores();
             if (lane == 0 && b >= 3)
                 __hip_atomic_store(P.flags + (b - 3), s + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            tfeed = settled(tfeed_n);
-            tfeed_h = settled(tfeed_h_next);
-            fh = settled(fh_n);
-            ff = settled(ff_n);
+            {
+                const int tn = settled(traw_n);
+                tfeed2 = (unsigned)tn * CS | (((unsigned)traw * CS) << 16);   // the high half takes this block's feed
+                traw = tn;
+            }
+            hf = ((unsigned)settled(fh_n) & 0xFFFFu) | ((unsigned)settled(ff_n) << 16);
             const int idx = 64 * b + lane - 127;
             if (idx >= 0 && idx < P.m) {
-                const int h32 = (int)((unsigned)oh >> 16), f32 = (int)((unsigned)of >> 16);
+                const int h32 = (int)(ohf & 0xFFFFu), f32 = (int)(ohf >> 16);
                 store_border(P.border + idx, h32, f32);
                 if (keep_hi) keep_hi[idx] = Border{h32, f32};
             }
             // the upper sub-strip's last row (low halves) runs 64 columns ahead
             const int idx_lo = 64 * b + lane - 63;
             if (keep_lo && idx_lo >= 0 && idx_lo < P.m)
-                keep_lo[idx_lo] = Border{(int)((unsigned)oh & 0xFFFFu), (int)((unsigned)of & 0xFFFFu)};
+                keep_lo[idx_lo] = Border{(int)(olf & 0xFFFFu), (int)(olf >> 16)};
         }
         drain_stores();
         {
@@ -359,8 +402,8 @@ __global__ void __launch_bounds__(256 * kWg16PerSimd<RH>) strip16_kernel(StripAr
         }
 
         // lane's best: row index i over the lane's 2 RH rows (0 .. RH-1 low, RH .. 2RH-1 high)
-        int bv = bkey >> LOGR;
-        const int i = 2 * RH - 1 - (bkey & ((1 << LOGR) - 1));
+        int bv = bkey >> 16;
+        const int i = 2 * RH - 1 - (bkey & 0xFFFF);
         int br = 0, bc = 0;
         if (bv > 0) {
             br = (int)((i < RH ? rowA + i : rowB + (i - RH)) + 1);

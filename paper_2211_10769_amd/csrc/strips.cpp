@@ -152,9 +152,11 @@ swh_status prepare_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, 
     const size_t wave_lds = int16 ? strip16_lds_bytes(RK, sc.asize) : strip_lds_bytes(R, sc.asize);
     StripLaunch grid{0, 1, wave_lds};
     const int forced = ctx->opt.grid;
-    // long chains (a few big problems) want one wave per SIMD; many short
-    // ones want several to hide latency (read-pair batch: 4 for R = 8)
-    const bool long_chains = total_strips >= 16 * (int64_t)np;
+    // long chains of a few big problems want one wave per SIMD (their strips
+    // come in rounds of one per SIMD); problems at least as many as the SIMDs
+    // fill the GPU with independent chains whatever their length and want
+    // several waves to hide latency (read-pair batch: 4 for R = 8)
+    const bool long_chains = total_strips >= 16 * (int64_t)np && np < 4 * ctx->num_cu;
     int per_simd = waves > 0 ? waves : long_chains ? 1 : (RK <= 4 ? 8 : 4);
     while (per_simd > 1 && (int64_t)per_simd / 2 * 4 * ctx->num_cu >= total_strips) per_simd /= 2;
     const bool balanced = int16 ? strip16_balanced_launch(ctx->device, RK, sc.asize, per_simd, ctx->num_cu, grid)

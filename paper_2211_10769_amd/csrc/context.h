@@ -129,7 +129,7 @@ struct swh_ctx {
     swh::DevBuf qr, tr;            // reversed codes
     swh::DevBuf border, flags, misc, strip_best, mat, lut;
     // strip-kernel problem tables
-    swh::DevBuf probs, strip_prob, prob_best, sync;
+    swh::DevBuf probs, strip_prob, strip_order, prob_best, sync;
     swh::PreparedStrips strips;   // host tables of the last strip launch
     // database search buffers
     swh::DevBuf qoff, db_work, db_border, db_redo, db_scatter, db_scores, db_topk;
@@ -154,7 +154,7 @@ struct swh_ctx {
     swh::DevBuf gscores;
     std::vector<swh::DevBuf *> all() {
         return {&qraw, &traw, &qc, &tc, &qr, &tr, &border, &flags, &misc, &strip_best, &mat, &lut,
-                &probs, &strip_prob, &prob_best, &sync,
+                &probs, &strip_prob, &strip_order, &prob_best, &sync,
                 &qoff, &db_work, &db_border, &db_redo, &db_scatter, &db_scores, &db_topk, &db_sync,
                 &bq, &bt, &bborder,
                 &pf_fq, &pf_qlen, &pf_Aq, &pf_pred, &pf_hist, &pf_prefix, &pf_marks, &pf_chunk, &pf_cand,

@@ -197,6 +197,7 @@ swh_status build_plan(swh_ctx *ctx, const swh_db *db, int32_t nq, int32_t k, con
     }
     PreparedStrips prep;
     if (!probs.empty() && (s = prepare_strips(ctx, probs, sc, R, true, shape.waves, false, prep)) != SWH_OK) return s;
+    prep.strip_order.clear();   // tickets in global strip order: the plan holds no order table
     int64_t border_entries = 0;
     for (const StripProblem &p : probs) border_entries += cols_padded(p.m);
 

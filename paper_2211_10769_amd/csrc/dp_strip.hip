@@ -160,9 +160,10 @@ __global__ void __launch_bounds__(256 * kWgPerSimd<R>) strip_kernel(StripArgs a)
             __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
         }
-        const int pi = a.strip_prob ? __builtin_amdgcn_readfirstlane((int)a.strip_prob[sg]) : 0;
+        const int g = a.strip_order ? __builtin_amdgcn_readfirstlane((int)a.strip_order[sg]) : sg;
+        const int pi = a.strip_prob ? __builtin_amdgcn_readfirstlane((int)a.strip_prob[g]) : 0;
         const Problem P = a.probs[pi];
-        const int s = sg - P.strip0;                                      // strip within the problem
+        const int s = g - P.strip0;                                       // strip within the problem
         const int64_t row0 = (int64_t)s * 64 * R + (int64_t)lane * R;   // 0-based
 
         // ---- query profile for this lane's rows (written and read by this lane only)
@@ -403,7 +404,7 @@ __global__ void __launch_bounds__(256 * kWgPerSimd<R>) strip_kernel(StripArgs a)
                 br = better ? orr : br;
                 bc = better ? oc : bc;
             }
-            if (lane == 0) a.strip_best[sg] = BestCell{bv, br, bc, 0};
+            if (lane == 0) a.strip_best[g] = BestCell{bv, br, bc, 0};
         }
     }
 }

@@ -152,9 +152,10 @@ __global__ void __launch_bounds__(256 * kWg16PerSimd<RH>) strip16_kernel(StripAr
             __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
         }
-        const int pi = a.strip_prob ? __builtin_amdgcn_readfirstlane((int)a.strip_prob[sg]) : 0;
+        const int g = a.strip_order ? __builtin_amdgcn_readfirstlane((int)a.strip_order[sg]) : sg;
+        const int pi = a.strip_prob ? __builtin_amdgcn_readfirstlane((int)a.strip_prob[g]) : 0;
         const Problem P = a.probs[pi];
-        const int s = sg - P.strip0;
+        const int s = g - P.strip0;
         const int64_t rowA = (int64_t)s * 128 * RH + (int64_t)lane * RH;   // low halves (0-based rows)
         const int64_t rowB = rowA + 64 * RH;                                 // high halves
 
@@ -417,7 +418,7 @@ __global__ void __launch_bounds__(256 * kWg16PerSimd<RH>) strip16_kernel(StripAr
             br = better ? orr : br;
             bc = better ? oc : bc;
         }
-        if (lane == 0) a.strip_best[sg] = BestCell{bv, br, bc, 0};
+        if (lane == 0) a.strip_best[g] = BestCell{bv, br, bc, 0};
     }
 }
 

@@ -65,6 +65,10 @@ struct Problem {
 struct StripArgs {
     const Problem *probs;
     const int32_t *strip_prob;   // global strip -> problem index (NULL: single problem)
+    // ticket -> global strip (NULL: the identity).  Global strips number the
+    // strips of problem 0, then problem 1, ...; the order keeps every problem's
+    // strips in increasing tickets (a strip only waits for strips taken before it)
+    const int32_t *strip_order;
     int32_t total_strips;
     const int8_t *mat;           // asize x asize substitution scores
     int32_t asize;               // the pad code equals asize
@@ -124,6 +128,7 @@ struct PreparedStrips {
     StripLaunch grid{0, 1, 0};
     std::vector<Problem> tab;
     std::vector<int32_t> strip_prob;
+    std::vector<int32_t> strip_order;   // empty: tickets in global strip order
 };
 
 // Blocks of 64 steps that sweep m columns with the 63-step lane skew:

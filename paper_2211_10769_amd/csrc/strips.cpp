@@ -167,6 +167,25 @@ swh_status prepare_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, 
         grid = StripLaunch{strip_grid(total_strips, RK, limit, ctx->num_cu, waves, forced), 1, wave_lds};
     }
     out.grid = grid;
+
+    // With problems enough to fill the GPU, a problem's strips are spread over
+    // the tickets: strip k comes about k G tickets after strip 0 (G an eighth
+    // of the resident waves), so that by the time it is taken the strip above
+    // has the head start of a few blocks it waits for, instead of holding a
+    // wave idle while it builds up.  Tickets of one problem keep increasing.
+    out.strip_order.clear();
+    if (np >= 4 * ctx->num_cu && total_strips > np) {
+        const int64_t G = std::max<int64_t>((int64_t)grid.nwg * grid.waves / 8, 1);
+        std::vector<std::pair<int64_t, int32_t>> key;
+        key.reserve((size_t)total_strips);
+        for (int i = 0; i < np; ++i)
+            for (int k = 0; k < tab[i].nstrips; ++k)
+                key.emplace_back((int64_t)tab[i].strip0 + k * G, tab[i].strip0 + k);
+        std::sort(key.begin(), key.end());
+        out.strip_order.resize(key.size());
+        for (size_t j = 0; j < key.size(); ++j) out.strip_order[j] = key[j].second;
+        if ((s = ensure(ctx, ctx->strip_order, out.strip_order.size() * 4, "strip order")) != SWH_OK) return s;
+    }
     return SWH_OK;
 }
 
@@ -180,11 +199,15 @@ hipError_t enqueue_strips(swh_ctx *ctx, const PreparedStrips &ps, const Scoring 
         (e = hipMemcpyAsync(ctx->probs.p, tab_src, (size_t)ps.np * sizeof(Problem), hipMemcpyHostToDevice, st)) !=
             hipSuccess ||
         (ps.np > 1 && (e = hipMemcpyAsync(ctx->strip_prob.p, sp_src, ps.strip_prob.size() * 4,
-                                          hipMemcpyHostToDevice, st)) != hipSuccess))
+                                          hipMemcpyHostToDevice, st)) != hipSuccess) ||
+        (!ps.strip_order.empty() && (e = hipMemcpyAsync(ctx->strip_order.p, ps.strip_order.data(),
+                                                        ps.strip_order.size() * 4, hipMemcpyHostToDevice, st)) !=
+                                        hipSuccess))
         return e;
     StripArgs a;
     a.probs = (const Problem *)ctx->probs.p;
     a.strip_prob = ps.np > 1 ? (const int32_t *)ctx->strip_prob.p : nullptr;
+    a.strip_order = ps.strip_order.empty() ? nullptr : (const int32_t *)ctx->strip_order.p;
     a.total_strips = (int32_t)ps.total_strips;
     a.mat = (const int8_t *)ctx->mat.p;
     a.asize = sc.asize;

@@ -216,7 +216,7 @@ swh_status  swh_cancel(swh_ctx *ctx);
  *                          predictions is amplified); 0 by the predicted score
  *                          itself.  Reported scores are exact either way.
  *   SWH_OPT_DB_WAVES       waves that share one (query, group) unit of the
- *                          database kernel: 1 (one wave per unit), 2, 4, 8 or 16 (the
+ *                          database kernel: 1 (one wave per unit), 2, 4, 8, 12 or 16 (the
  *                          unit's 32-row query chunks run on neighbouring waves
  *                          and hand their bottom rows on through LDS, so that a
  *                          few queries still fill the GPU); 0 (default): chosen

@@ -426,8 +426,8 @@ swh_status swh_set_option(swh_ctx *ctx, int32_t option, int64_t value)
             o.pf_rank = (int32_t)value;
             return SWH_OK;
         case SWH_OPT_DB_WAVES:
-            if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
-                return bad("database waves must be 0, 1, 2, 4, 8 or 16");
+            if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8 && value != 12 && value != 16)
+                return bad("database waves must be 0, 1, 2, 4, 8, 12 or 16");
             o.db_waves = (int32_t)value;
             ++ctx->gen;   // a captured search keeps its launch shape
             return SWH_OK;

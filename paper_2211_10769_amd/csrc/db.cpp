@@ -264,11 +264,12 @@ DbLaunch db_launch_shape(const swh_ctx *ctx, size_t units, int32_t max_len, doub
         // of 20 queries over a rescoring subset of 15,600 units: 238 ms with one wave
         // per unit, 135 ms with four), so the unit's chunks are spread over four waves
         L.waves = units >= (size_t)16 * db_search_grid_limit(ctx->device, 1) ? 1 : 4;
-        // about one unit per CU slot and long queries (32 chunks or more per unit):
-        // sixteen waves per work-group, one work-group per CU, so that each CU
-        // list-schedules its units (one query of 1,000-5,000 residues against 100,000
-        // proteins: 5-15% faster than four waves; with short queries four are better)
-        if (L.waves == 4 && units <= (size_t)4 * std::max(1, ctx->num_cu) && mean_chunks >= 32.0) L.waves = 16;
+        // at most about one unit per SIMD: one work-group of eight waves per CU, or of
+        // twelve for long queries (64 chunks or more per unit), so that each CU
+        // list-schedules its units (one query against 100,000 proteins: eight waves
+        // best up to 1,000 residues, 2.3-9.0 ms against 2.7-11.8 ms with four; twelve
+        // at 5,000, 38.8 ms against 41.9 with eight and 61.3 with four)
+        if (L.waves == 4 && units <= (size_t)4 * std::max(1, ctx->num_cu)) L.waves = mean_chunks >= 64.0 ? 12 : 8;
     }
     int limit = db_search_grid_limit(ctx->device, L.waves);
     if (ctx->opt.grid > 0) limit = std::min(limit, (int)ctx->opt.grid);

@@ -431,8 +431,14 @@ __device__ __forceinline__ bool pipe_chunk(const DbSearchArgs &a, const PipeRing
     return true;
 }
 
+// Three waves per SIMD: a chunk's rows, E and H take 64 registers and the
+// profile words, ring values and addresses about 70 more, so 168 registers
+// per wave hold the column loop without spills (at four waves per SIMD, 128
+// registers, the loop reloaded spilled values from scratch every column and
+// ran about 5% slower with four waves per unit, 25% with sixteen).  Sixteen
+// waves per work-group still force four per SIMD.
 template <int W>
-__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3)))
 db_pipe_kernel(DbSearchArgs a)
 {
     static_assert(W >= 2, "the pipelined form needs two waves or more");
@@ -669,6 +675,7 @@ hipError_t launch_db_search(const DbSearchArgs &a, int waves, int grid, hipStrea
     case 2: hipLaunchKernelGGL(db_pipe_kernel<2>, dim3(grid), dim3(128), 0, st, a); break;
     case 4: hipLaunchKernelGGL(db_pipe_kernel<4>, dim3(grid), dim3(256), 0, st, a); break;
     case 8: hipLaunchKernelGGL(db_pipe_kernel<8>, dim3(grid), dim3(512), 0, st, a); break;
+    case 12: hipLaunchKernelGGL(db_pipe_kernel<12>, dim3(grid), dim3(768), 0, st, a); break;
     case 16: hipLaunchKernelGGL(db_pipe_kernel<16>, dim3(grid), dim3(1024), 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
@@ -681,7 +688,8 @@ int db_search_grid_limit(int device, int waves)
                      : waves == 2 ? reinterpret_cast<const void *>(&db_pipe_kernel<2>)
                      : waves == 4 ? reinterpret_cast<const void *>(&db_pipe_kernel<4>)
                      : waves == 8 ? reinterpret_cast<const void *>(&db_pipe_kernel<8>)
-                                  : reinterpret_cast<const void *>(&db_pipe_kernel<16>);
+                     : waves == 12 ? reinterpret_cast<const void *>(&db_pipe_kernel<12>)
+                                   : reinterpret_cast<const void *>(&db_pipe_kernel<16>);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * waves, 0) != hipSuccess || per_cu < 1)
         per_cu = waves == 1 ? 4 : 1;

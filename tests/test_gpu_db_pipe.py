@@ -28,7 +28,7 @@ def _mixed_db(rng, count, n_empty):
     return [b""] * n_empty + db
 
 
-@pytest.mark.parametrize("waves", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("waves", [1, 2, 4, 8, 12, 16])
 def test_forms_match_oracle(eng, opt, waves):
     import paper_2211_10769_amd as swh
     opt("db_waves", waves)
@@ -50,7 +50,7 @@ def test_forms_match_oracle(eng, opt, waves):
     assert (idx == widx).all() and (sco == wsco).all()
 
 
-@pytest.mark.parametrize("waves", [2, 4, 16])
+@pytest.mark.parametrize("waves", [2, 4, 12, 16])
 def test_saturation_carried_across_chunks(eng, opt, waves):
     import paper_2211_10769_amd as swh
     opt("db_waves", waves)
@@ -74,7 +74,7 @@ def test_saturation_carried_across_chunks(eng, opt, waves):
     assert got[0, 17] == 100_000
 
 
-@pytest.mark.parametrize("waves", [2, 4, 16])
+@pytest.mark.parametrize("waves", [2, 4, 12, 16])
 def test_small_grid_runs_many_units_per_work_group(eng, opt, waves):
     import paper_2211_10769_amd as swh
     opt("db_waves", waves)

@@ -49,9 +49,9 @@ ISSUED_OPS_PER_CELL = 8.66
 # (strip_kernel<20, true, false>) on the long pair, from two rocprofv3 counter
 # passes over one CIGAR step (forward launch 2.55e13 cells, keeping rows for the
 # band traceback), each scaled by the same counter on a 1 GiB plain copy
-# (profiles/strip_kernel_long_dna.md): FETCH_SIZE 95,953,114 KiB x 2.0 +
-# WRITE_SIZE 190,673,384 KiB x 1.0 = 391.8 GB per launch.
-HBM_BYTES_PER_CELL = (95_953_114.2 * 2.0 + 190_673_383.5) * 1024 / 25_500_765_000_000
+# (profiles/strip_kernel_long_dna.md): FETCH_SIZE 96,123,802 KiB x 2.0 +
+# WRITE_SIZE 190,673,382 KiB x 1.0 = 392.1 GB per launch.
+HBM_BYTES_PER_CELL = (96_123_801.75 * 2.0 + 190_673_382.25) * 1024 / 25_500_765_000_000
 TRAFFIC_SOURCE = "profiles/strip_kernel_long_dna.md (rocprofv3 FETCH_SIZE and WRITE_SIZE of the forward launch)"
 
 

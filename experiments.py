@@ -92,8 +92,8 @@ def protein_schemes(swh, eng, seqgen, db_size):
 
 def query_lengths(swh, eng, seqgen, db_size):
     """Database search GCUPS against the length of a single query: the default
-    launch (units shared by four waves, oversize units on the single-pair
-    kernel beside it) and one wave per unit with no routing."""
+    launch (units shared by eight or twelve waves, oversize units on the
+    single-pair kernel beside it) and one wave per unit with no routing."""
     _, (cat, off) = seqgen.workload2(n_db=db_size, n_queries=1)
     sc = swh.Scoring(*seqgen.protein_scoring())
     db = swh.Database(eng, (cat, off), sc)

@@ -173,3 +173,19 @@ def test_band_traceback_tie_heavy_batch(eng, opt):
     got, st = eng.align_batch(qs, ts, tie, mode="cigar", stats=True)
     _check(got, _oracle_all(qs, ts, tie))
     assert st["traceback_retries"] == 0
+
+
+@pytest.mark.parametrize("int16", [1, 0])
+def test_many_multi_strip_pairs_spread_ticket_order(eng, opt, int16):
+    # 1,200 pairs: at least as many problems as SIMDs, so each pair's strips are
+    # spread over the ticket order (reads up to 2,500 bp: up to five 512-row
+    # strips in 32 bits, three 1,024-row strips in 16); every pair equals the oracle
+    opt("int16", int16)
+    qs, ts = _read_pairs(1200, 2500, seed_stream=11)
+    sc = seqgen.dna_scoring()
+    assert sum(len(q) > 1024 for q in qs) > 300
+    want = _oracle_all(qs, ts, sc, cigar=True)
+    got, st = eng.align_batch(qs, ts, sc, mode="cigar", stats=True)
+    _check(got, want)
+    _check(eng.align_batch(qs, ts, sc, mode="coords"), want, "coords")
+    assert (st["passes_int16"] > 0) == bool(int16)

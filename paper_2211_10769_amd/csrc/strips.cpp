@@ -168,22 +168,25 @@ swh_status prepare_strips(swh_ctx *ctx, const std::vector<StripProblem> &probs, 
     }
     out.grid = grid;
 
-    // With problems enough to fill the GPU, a problem's strips are spread over
-    // the tickets: strip k comes about k G tickets after strip 0 (G an eighth
-    // of the resident waves), so that by the time it is taken the strip above
-    // has the head start of a few blocks it waits for, instead of holding a
-    // wave idle while it builds up.  Tickets of one problem keep increasing.
+    // With problems enough to fill the GPU the tickets go level by level: strip
+    // 0 of every problem (in the caller's order), then strip 1 of every problem
+    // with two or more, and so on.  By the time a strip is taken the strip above
+    // has long had the head start of a few blocks it waits for, so no wave sits
+    // idle building it up; the tickets of one problem keep increasing.  Measured
+    // on 200,000 read pairs (score-mode forward): consecutive tickets 2.12 s,
+    // strip k about k G tickets after strip 0: G = 512 2.01 s, 4,096 1.87 s,
+    // 16,384 1.80 s, level by level 1.78 s.
     out.strip_order.clear();
     if (np >= 4 * ctx->num_cu && total_strips > np) {
-        const int64_t G = std::max<int64_t>((int64_t)grid.nwg * grid.waves / 8, 1);
-        std::vector<std::pair<int64_t, int32_t>> key;
-        key.reserve((size_t)total_strips);
+        int32_t levels = 0;
+        for (int i = 0; i < np; ++i) levels = std::max(levels, tab[i].nstrips);
+        std::vector<int64_t> start((size_t)levels + 1, 0);   // tickets before level k
         for (int i = 0; i < np; ++i)
-            for (int k = 0; k < tab[i].nstrips; ++k)
-                key.emplace_back((int64_t)tab[i].strip0 + k * G, tab[i].strip0 + k);
-        std::sort(key.begin(), key.end());
-        out.strip_order.resize(key.size());
-        for (size_t j = 0; j < key.size(); ++j) out.strip_order[j] = key[j].second;
+            for (int32_t k = 0; k < tab[i].nstrips; ++k) ++start[(size_t)k + 1];
+        for (int32_t k = 0; k < levels; ++k) start[(size_t)k + 1] += start[(size_t)k];
+        out.strip_order.resize((size_t)total_strips);
+        for (int i = 0; i < np; ++i)
+            for (int32_t k = 0; k < tab[i].nstrips; ++k) out.strip_order[(size_t)start[(size_t)k]++] = tab[i].strip0 + k;
         if ((s = ensure(ctx, ctx->strip_order, out.strip_order.size() * 4, "strip order")) != SWH_OK) return s;
     }
     return SWH_OK;

@@ -36,9 +36,10 @@
 // of int16 pairs (two consecutive rows per word, RH/2 words per lane,
 // planes of four words so every read is a conflict-free ds_read_b128); row
 // k's packed score comes from one v_perm of the two halves' words.  The two
-// halves look up different columns (64 apart), so each half has its own
-// code stream: the high half's feed is the low half's feed of the previous
-// block.
+// halves look up different columns (64 apart): their codes travel together in
+// one register as profile byte offsets (low 16 bits the low half's, high 16
+// bits the high half's), and the high half's feed is the low half's feed of
+// the previous block.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

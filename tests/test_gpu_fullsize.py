@@ -3,7 +3,10 @@ times: the database search of 20 queries against 500,000 proteins and the
 batch of 200,000 read/reference pairs.  The oracle cannot score everything at
 these sizes, so it checks sampled outputs one by one (every top-10 hit and
 random query/database pairs; random pairs of the batch, CIGARs included), and
-pairs of the batch are checked by properties that hold at any size."""
+pairs of the batch are checked by properties that hold at any size.  At 20
+queries x 20,000 proteins every score is compared with the oracle's, stored by
+tests/golden/make_db_20k.py."""
+import os
 import re
 
 import numpy as np
@@ -88,3 +91,26 @@ def test_batch_of_read_pairs_bench_config(eng):
     for i in rng.choice(small, size=40, replace=False):
         want = oracle.sw_align(qs[i], ts[i], sc)
         assert {k: got[i][k] for k in want} == want, i
+
+
+@pytest.mark.parametrize("waves", [0, 1, 8, 12])
+def test_database_20_queries_20k_proteins_equal_the_oracle(eng, opt, waves):
+    # every score of the 20 database queries against 20,000 proteins equals the
+    # oracle's (stored by tests/golden/make_db_20k.py, 2.3e11 cells), and the
+    # top-10 lists are its stable sort; the launch rule's form and forced ones
+    import paper_2211_10769_amd as swh
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "db_20k_scores.npz"))
+    qs, (cat, off) = seqgen.workload2(n_db=20_000, n_queries=20)
+    assert [len(q) for q in qs] == list(g["query_lengths"]) and int(off[-1] - off[0]) == int(g["db_residues"])
+    opt("db_waves", waves)
+    sc = seqgen.protein_scoring()
+    D = swh.Database(eng, (cat, off), sc)
+    qb = [bytes(q) for q in qs]
+    got, _ = D.scores(qb)
+    idx, sco, _ = D.search(qb, k=10)
+    D.close()
+    want = g["scores"].astype(np.int64)
+    mism = np.argwhere(got != want)
+    assert len(mism) == 0, (mism[:5], [(int(got[tuple(m)]), int(want[tuple(m)])) for m in mism[:5]])
+    widx, wsco = oracle.topk(want, 10)
+    assert (idx == widx).all() and (sco == wsco).all()

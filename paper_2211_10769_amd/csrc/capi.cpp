@@ -354,6 +354,7 @@ void swh_destroy(swh_ctx *ctx)
         if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
         if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
         if (ctx->cancel_host) hipHostFree(ctx->cancel_host);
+        if (ctx->tb_ops_host) hipHostFree(ctx->tb_ops_host);
         if (ctx->own_stream) hipStreamDestroy(ctx->own_stream);
         if (ctx->aux_stream) hipStreamDestroy(ctx->aux_stream);
         delete ctx;

@@ -147,6 +147,10 @@ struct swh_ctx {
     float pf_infer_ms = 0.f;
     // traceback buffers
     swh::Arena tb_arena;
+    // pinned host copy of the traceback leaves' ops, kept across calls (grown by
+    // doubling): copies land without staging or page faults
+    char *tb_ops_host = nullptr;
+    size_t tb_ops_host_cap = 0;
     swh::DevBuf tb_fwd, tb_bwd, tb_front, tb_codes_q, tb_flags, tb_leaf, tb_misc;
     // band traceback: rows kept by the forward and reverse score passes, cut tables
     swh::DevBuf keep_f, keep_r, cut_desc, cut_cnt, cut_out;

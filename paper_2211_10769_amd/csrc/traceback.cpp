@@ -159,7 +159,22 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
         (e = hipStreamSynchronize(st)) != hipSuccess)
         return hip_fail(ctx, e, "traceback setup");
 
-    std::vector<char> ops_host;
+    // the leaves' ops on the host: the context's pinned buffer, ops_used bytes in use
+    size_t ops_used = 0;
+    auto ops_room = [&](size_t more) -> bool {
+        if (ops_used + more <= ctx->tb_ops_host_cap) return true;
+        const size_t cap = std::max(ops_used + more, 2 * ctx->tb_ops_host_cap);
+        char *p = nullptr;
+        if (hipHostMalloc(reinterpret_cast<void **>(&p), cap, hipHostMallocDefault) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return false;
+        }
+        if (ops_used) std::memcpy(p, ctx->tb_ops_host, ops_used);
+        if (ctx->tb_ops_host) hipHostFree(ctx->tb_ops_host);
+        ctx->tb_ops_host = p;
+        ctx->tb_ops_host_cap = cap;
+        return true;
+    };
     std::vector<int> ready((size_t)nodes.size());
     for (size_t k = 0; k < nodes.size(); ++k) ready[k] = (int)k;
     // the leaf-size option lowers it (tests use it to force deep recursion on small inputs)
@@ -417,11 +432,12 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
                                      max_w, lod + nsmall, st)) != hipSuccess)
                 return hip_fail(ctx, e, "leaf launch");
             std::vector<LeafOut> lo(nl);
-            const size_t base = ops_host.size();
-            ops_host.resize(base + (size_t)ops_total);
+            const size_t base = ops_used;
+            if (!ops_room((size_t)ops_total)) return fail(ctx, SWH_E_NOMEM, "pinned host memory for traceback ops");
+            ops_used += (size_t)ops_total;
             if ((e = hipMemcpyAsync(lo.data(), ctx->tb_front.p, sizeof(LeafOut) * nl, hipMemcpyDeviceToHost, st)) !=
                     hipSuccess ||
-                (e = hipMemcpyAsync(ops_host.data() + base, op, (size_t)ops_total, hipMemcpyDeviceToHost, st)) !=
+                (e = hipMemcpyAsync(ctx->tb_ops_host + base, op, (size_t)ops_total, hipMemcpyDeviceToHost, st)) !=
                     hipSuccess ||
                 (e = hipStreamSynchronize(st)) != hipSuccess)
                 return hip_fail(ctx, e, "leaf results");
@@ -487,7 +503,7 @@ swh_status traceback_batch(swh_ctx *ctx, const std::vector<TbInput> &in, const S
                 stack.pop_back();
                 const Node &n = nodes[k];
                 if (n.leaf) {
-                    back.append(ops_host.data() + n.ops_off, (size_t)n.nops);
+                    back.append(ctx->tb_ops_host + n.ops_off, (size_t)n.nops);
                 } else {
                     stack.push_back(n.top);
                     stack.push_back(n.bottom);
